@@ -1,0 +1,196 @@
+"""Pins of the exact-integer query oracle: the paper's worked examples
+(Sec. 3 and Sec. 4), the fixed facts about guarded and unguarded accesses,
+closed-form counts, and exhaustive agreement between the oracle's own CNF
+encoding and brute force over every input tuple.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import cnf_ref, query_ref
+from tests.querygen import random_query
+from workloads import Query, config1, config2, oob_1d, partition_query
+
+
+# ---------------------------------------------------------------- worked examples
+
+def _adv_cubature(wc=3, wn=3):
+    """Fig. 1: id = threadIdx.y*16 + threadIdx.x in a 16x16 block; the
+    buffer holds (cubN+1)^3 * Nelements * 3 elements."""
+    q = Query("advCubature")
+    cubN, nel = q.var("cubN", wc), q.var("Nelements", wn)
+    tx, ty = q.var("tidx", 4), q.var("tidy", 4)      # ids below the 16x16 block
+    q.require(tx < 16)
+    q.require(ty < 16)
+    cubNp = (cubN + 1) * (cubN + 1) * (cubN + 1)
+    size = cubNp * nel * 3
+    idx = ty * 16 + tx
+    q.require(idx >= size)
+    return q
+
+
+def test_t1_adv_cubature_input_dependent_oob():
+    q = _adv_cubature()
+    # the paper's input: cubN = Nelements = 1 gives 24 elements, id up to 255
+    assert query_ref.int_eval_named(q, dict(cubN=1, Nelements=1, tidx=15, tidy=15))
+    vals = query_ref.int_eval_nodes(q, [1, 1, 15, 15])
+    assert 24 in vals and 255 in vals
+    v, wit, _ = query_ref.decide(q)
+    assert v == "SAT" and query_ref.int_eval(q, wit)
+    assert query_ref.int_bruteforce(q)[0] == "SAT"
+
+
+def _saxpy(wm=6):
+    """Fig. 5: index = threadIdx.x + blockDim.x*blockIdx.x with 512-thread
+    blocks, gridDim = multiples, allocation multiples*512 elements."""
+    q = Query("saxpy")
+    mult, bid, tid = q.var("multiples", wm), q.var("blockIdx", wm), q.var("threadIdx", 9)
+    q.require(tid < 512)
+    q.require(bid < mult)
+    q.require(tid + bid * 512 >= mult * 512)
+    return q
+
+
+def test_t2_saxpy_bound_by_relation():
+    q = _saxpy()
+    assert query_ref.int_bruteforce(q)[0] == "UNSAT"
+    assert query_ref.decide(q)[0] == "UNSAT"
+
+
+def test_t3_push_node_loaded_index():
+    """Fig. 2: the index is a value loaded from memory (an unknown)."""
+    q = Query("pushNode")
+    numv, tid, bid, bdim = (q.var(n, 5) for n in ("numv", "tid", "bid", "bdim"))
+    neighbor = q.var("neighbor", 5)
+    q.require(tid < bdim)
+    q.require(bid * bdim + tid < numv)          # if (i < numv)
+    q.require(neighbor >= numv)                 # data1 has numv entries
+    v, wit, _ = query_ref.decide(q)
+    assert v == "SAT" and query_ref.int_eval(q, wit)
+
+
+def test_t4_intra_allocation_partition():
+    """Fig. 3 / Sec. 6.1: an index pushed one past a non-last partition
+    stays inside the allocation yet leaves its partition."""
+    for k_sub, j in ((3, 1), (2, 0)):
+        alloc = partition_query(4, 3, k_sub, j, "t", "le", level="allocation")
+        part = partition_query(4, 3, k_sub, j, "t", "le", level="partition")
+        assert query_ref.int_bruteforce(alloc)[0] == "UNSAT"
+        assert query_ref.int_bruteforce(part)[0] == "SAT"
+        ok = partition_query(4, 3, k_sub, j, "t", "lt", level="partition")
+        assert query_ref.int_bruteforce(ok)[0] == "UNSAT"
+        assert query_ref.root_check(ok) == "UNSAT"
+
+
+def test_t5_local_buffer_loop_bound():
+    """Fig. 4: local arrays of rd entries indexed by a loop i < rd."""
+    for guard, want in (("lt", "UNSAT"), ("le", "SAT")):
+        q = Query("kalman")
+        rd, i = q.var("rd", 6), q.var("i", 6)
+        q.require(i < rd if guard == "lt" else i <= rd)
+        q.require(i >= rd)
+        assert query_ref.int_bruteforce(q)[0] == want
+        assert query_ref.decide(q)[0] == want
+        if want == "SAT":
+            assert query_ref.int_eval_named(q, dict(rd=5, i=5))
+
+
+def test_t6_lu_decomposition_multiple_of_16():
+    """Sec. 6.1: the OOB shows only when N is not a multiple of 16 (grid of
+    ceil(N/16) blocks of 16 threads, no guard)."""
+    q = Query("lud")
+    N, bid, tid = q.var("N", 7), q.var("bid", 4), q.var("tid", 4)
+    q.require(bid < (N + 15) // 16)
+    q.require(tid < 16)
+    q.require(bid * 16 + tid >= N)
+    verdict, cnt, _ = query_ref.int_bruteforce(q)
+    assert verdict == "SAT"
+    for n in range(0, 128, 16):          # every multiple of 16 is safe
+        for b in range(16):
+            for t in range(16):
+                assert not query_ref.int_eval(q, [n, b, t]) if b < (n + 15) // 16 else True
+    # count: for N = 16a + r (r > 0) exactly the 16 - r threads of the
+    # last block past N go out of bounds
+    want = sum(16 - (n % 16) for n in range(128) if n % 16)
+    assert cnt == want
+    v, wit, _ = query_ref.decide(q)
+    assert v == "SAT" and wit[0] % 16 != 0
+
+
+# ---------------------------------------------------------------- fixed facts
+
+def test_guarded_access_is_unsat_and_unguarded_sat():
+    assert query_ref.root_check(config1("lt").query) == "UNSAT"
+    for variant in ("none", "le"):
+        g = config1(variant)
+        assert query_ref.int_eval_named(g.query, g.witness)
+        v, wit, _ = query_ref.decide(g.query)
+        assert v == "SAT" and query_ref.int_eval(g.query, wit)
+
+
+@pytest.mark.parametrize("w", [2, 3, 4, 5])
+def test_unguarded_count_closed_form(w):
+    """#{(N, bdim, bid, tid) : tid < bdim, bid*bdim + tid >= N}: for each
+    (bdim, tid, bid) the admissible N are 0 .. min(2^w - 1, idx)."""
+    top = 1 << w
+    b = np.arange(top)[:, None, None]
+    t = np.arange(top)[None, :, None]
+    i = np.arange(top)[None, None, :]
+    idx = i * b + t
+    want = int(np.where(t < b, np.minimum(top, idx + 1), 0).sum())
+    q = oob_1d(w, "none", scale=4)
+    assert query_ref.int_bruteforce(q)[1] == want
+    if w <= 3:
+        cnf, _ = query_ref.encode(q)
+        assert cnf_ref.count(cnf) == want
+
+
+@pytest.mark.parametrize("w", [2, 3, 4])
+def test_guarded_small_widths_unsat(w):
+    for s, c in ((1, 0), (4, 3), (8, 16)):
+        q = oob_1d(w, "lt", scale=s, header=c)
+        assert query_ref.int_bruteforce(q)[0] == "UNSAT"
+        cnf, _ = query_ref.encode(q)
+        assert cnf_ref.solve(cnf)[0] == "UNSAT"
+
+
+def test_config2_labels_by_construction():
+    gens = config2()
+    assert sum(g.label == "UNSAT" for g in gens) == 128
+    for g in gens:
+        if g.label == "UNSAT":
+            assert query_ref.root_check(g.query) == "UNSAT"
+        else:
+            assert query_ref.int_eval_named(g.query, g.witness)
+            assert query_ref.root_check(g.query) is None
+
+
+def test_config2_sat_decided_at_full_width():
+    gens = [g for g in config2() if g.label == "SAT"][:12]
+    for g in gens:
+        v, wit, _ = query_ref.decide(g.query)
+        assert v == "SAT" and query_ref.int_eval(g.query, wit), g.query.name
+
+
+# ---------------------------------------------------------------- encoder + root check
+
+def test_encoder_counts_match_brute_force():
+    rng = np.random.Generator(np.random.PCG64(21))
+    for i in range(150):
+        q = random_query(rng, max_bits=9, name=f"r{i}")
+        verdict, cnt, _ = query_ref.int_bruteforce(q)
+        cnf, inputs = query_ref.encode(q)
+        assert cnf_ref.count(cnf) == cnt, q.nodes
+        v, model, _ = cnf_ref.solve(cnf)
+        assert v == verdict
+        if model is not None:
+            assert query_ref.int_eval(q, query_ref.decode_inputs(model, inputs))
+
+
+def test_root_check_is_sound():
+    rng = np.random.Generator(np.random.PCG64(22))
+    hits = 0
+    for i in range(400):
+        q = random_query(rng, max_bits=10, ops=("add", "sub", "mul", "shl", "const"))
+        if query_ref.root_check(q) == "UNSAT":
+            hits += 1
+            assert query_ref.int_bruteforce(q)[0] == "UNSAT", q.nodes
+    assert hits > 10
