@@ -1,0 +1,290 @@
+/*
+ * scuba.h - C ABI of the MI355X OOB-query decision library.
+ *
+ * What is decided.  For every static memory access the bounds analysis
+ * builds one constraint set (paper Sec. 4.1 "three kinds of constraints",
+ * Sec. 5.2): thread/block ids below their dimensions (kind 1), the access
+ * offset reaching the allocation or partition size (kind 2), and the
+ * equalities that define offset, size, grid dimensions and asserts through
+ * expression trees (kind 3, Sec. 5.1, Fig. 8, Fig. 9).  The set is
+ * satisfiable iff some legal input makes the access out of bounds; the paper
+ * hands each set to a SAT solver and reports the satisfying ones (Sec. 5.2).
+ * Here each set is a *query*; SCUBA_SAT means "OOB possible", with a witness
+ * input, SCUBA_UNSAT means "in bounds for every input".
+ *
+ * Path: scuba_bitblast (word-level normalisation + Tseitin CNF, host)
+ *       -> scuba_split (unit propagation + cube splitting, host)
+ *       -> device unit propagation and bit-sliced leaf evaluation (HIP,
+ *          gfx950) -> results (verdict, verified witness, leaf counts).
+ * scuba_decide runs the whole loop, splitting lazily until every query is
+ * decided or out of budget; scuba_solve evaluates a given cube list.
+ *
+ * Conventions
+ *  - Every call returns scuba_status (0 = OK, < 0 = error).  Out-parameters
+ *    are written only on SCUBA_OK.  No C++ exception crosses the ABI; the
+ *    text of the last error of a context is returned by scuba_last_error.
+ *  - Inputs are copied; the library never keeps a caller pointer after a
+ *    call returns.  Handles (scuba_cnf, scuba_cubes, scuba_results) are owned
+ *    by the caller and released with their *_free function.  Pointers inside
+ *    a view are borrowed and stay valid until the handle is freed.
+ *  - One context per host thread.  A context owns pinned host staging
+ *    buffers and is bound to one HIP device, which is opened at the first
+ *    call that needs it (the host-only calls work without a GPU).
+ *  - Device memory is supplied by the caller as one workspace (device
+ *    pointer + size); its required size comes from the *_workspace calls.
+ *    Streams are hipStream_t passed as void* (0 = the null stream).  Calls
+ *    that take a stream return after that stream has been synchronised.
+ *  - CNF: variables 1..n_vars, DIMACS literals (+v / -v), clause c of query
+ *    q spans lits[clause_off[c] .. clause_off[c+1]).  A clause may not repeat
+ *    a variable.  An empty clause makes the query UNSAT.
+ */
+#ifndef SCUBA_H
+#define SCUBA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
+typedef int32_t scuba_status;
+#define SCUBA_OK 0
+#define SCUBA_E_INVALID (-1)   /* malformed input or argument            */
+#define SCUBA_E_WIDTH (-2)     /* input width outside 1..64              */
+#define SCUBA_E_NOMEM (-3)     /* host allocation failed                 */
+#define SCUBA_E_DEVICE (-4)    /* a HIP call or a device check failed    */
+#define SCUBA_E_CAPACITY (-5)  /* workspace or a fixed limit too small   */
+#define SCUBA_E_STATE (-6)     /* call not valid for this handle         */
+#define SCUBA_E_INTERNAL (-7)  /* unexpected internal error              */
+
+typedef int32_t scuba_verdict;
+#define SCUBA_UNSAT 0    /* no input makes the access out of bounds */
+#define SCUBA_SAT 1      /* some input does; a witness is available  */
+#define SCUBA_UNKNOWN 2  /* a budget ran out before a decision        */
+
+/* ---------------------------------------------------------------- queries
+ * A query is a DAG in topological order (Sec. 5.1: leaves are constants or
+ * unknown inputs, inner nodes operators; an input used by several trees is
+ * one node).  a/b index earlier nodes of the same query.
+ *   VAR   width 1..64, imm = declaration number (0,1,2,... in node order);
+ *         value range 0 .. 2^width - 1.
+ *   CONST imm = unsigned value.
+ *   ADD SUB MUL                 exact integers (no wrap-around)
+ *   SHL imm<=64, UDIV/UREM imm>0 (operand must be >= 0 for every input)
+ *   LT LE GT GE EQ NE           integer comparison -> boolean
+ *   AND OR (a, b)  NOT (a)      boolean connectives
+ * roots: boolean nodes that must all hold.                                   */
+#define SCUBA_OP_VAR 0
+#define SCUBA_OP_CONST 1
+#define SCUBA_OP_ADD 2
+#define SCUBA_OP_SUB 3
+#define SCUBA_OP_MUL 4
+#define SCUBA_OP_SHL 5
+#define SCUBA_OP_UDIV 6
+#define SCUBA_OP_UREM 7
+#define SCUBA_OP_LT 8
+#define SCUBA_OP_LE 9
+#define SCUBA_OP_GT 10
+#define SCUBA_OP_GE 11
+#define SCUBA_OP_EQ 12
+#define SCUBA_OP_NE 13
+#define SCUBA_OP_AND 14
+#define SCUBA_OP_OR 15
+#define SCUBA_OP_NOT 16
+
+typedef struct {
+  uint32_t op, a, b, width;
+  uint64_t imm;
+} scuba_node; /* 24 bytes */
+
+typedef struct scuba_ctx scuba_ctx;
+typedef struct scuba_cnf scuba_cnf;
+typedef struct scuba_cubes scuba_cubes;
+typedef struct scuba_results scuba_results;
+
+/* Context for HIP device `device` (checked at the first device call). */
+scuba_status scuba_ctx_create(int32_t device, scuba_ctx** out);
+void scuba_ctx_destroy(scuba_ctx* ctx);
+const char* scuba_last_error(const scuba_ctx* ctx);
+const char* scuba_status_str(scuba_status s);
+/* Library version and the number of exported entry points (self check). */
+uint32_t scuba_abi_version(void);
+
+/* ---------------------------------------------------------------- bit-blast
+ * Word-level normalisation, then Tseitin encoding (host).
+ * Normalisation writes every comparison as a bound on a polynomial over the
+ * inputs with coprime integer coefficients (this cancels common additive
+ * terms and common positive factors), intersects the bounds the roots put on
+ * the same polynomial, and marks the query UNSAT at the root when an
+ * intersection is empty.  It keeps the set of satisfying inputs unchanged.
+ * Encoding: exact two's-complement widths from value ranges; gates are
+ * full equivalences, so auxiliary variables are functions of the inputs and
+ * the CNF has exactly one model per satisfying input tuple.  Input bits get
+ * the first CNF variables: declared variable i, bit j (LSB first) is
+ * variable first_var[i] + j.
+ * nodes/roots: concatenated per query; node_start/root_start: nq+1 offsets.
+ * flags: SCUBA_BB_NO_REWRITE encodes the DAG as given (no normalisation).
+ * Errors: SCUBA_E_INVALID (bad op, order, type, negative division operand),
+ * SCUBA_E_WIDTH (width outside 1..64).                                      */
+#define SCUBA_BB_NO_REWRITE 1u
+scuba_status scuba_bitblast(scuba_ctx* ctx, uint32_t nq, const scuba_node* nodes,
+                            const uint64_t* node_start, const uint32_t* roots,
+                            const uint64_t* root_start, uint32_t flags, scuba_cnf** out);
+
+/* A CNF batch from raw arrays (random k-SAT, pigeonhole, ...).
+ * n_vars[nq]; q_clause_start[nq+1] indexes clauses; clause_off[C+1] indexes
+ * lits (global, non-decreasing).  Rejects repeated variables in a clause and
+ * literals outside 1..n_vars (SCUBA_E_INVALID).                              */
+scuba_status scuba_cnf_from_arrays(scuba_ctx* ctx, uint32_t nq, const uint32_t* n_vars,
+                                   const uint64_t* q_clause_start, const uint64_t* clause_off,
+                                   const int32_t* lits, scuba_cnf** out);
+
+typedef struct {
+  uint32_t n_vars;
+  uint32_t n_inputs;          /* declared input variables (0 for raw CNF)   */
+  uint64_t n_clauses;
+  uint64_t n_lits;
+  const uint64_t* clause_off; /* n_clauses+1, relative to lits below        */
+  const int32_t* lits;
+  int32_t root_unsat;         /* 1: normalisation proved UNSAT              */
+} scuba_cnf_view;
+
+uint32_t scuba_cnf_count(const scuba_cnf* cnf);
+scuba_status scuba_cnf_view_get(const scuba_cnf* cnf, uint32_t qi, scuba_cnf_view* out);
+/* first_var[i], width[i] for each declared input (cap entries at most). */
+scuba_status scuba_cnf_input_map(const scuba_cnf* cnf, uint32_t qi, uint32_t* first_var,
+                                 uint32_t* width, uint32_t cap);
+void scuba_cnf_free(scuba_cnf* cnf);
+
+/* ---------------------------------------------------------------- split
+ * Cube splitting (host).  From the root, unit propagation runs to its
+ * fixpoint; a node whose propagation conflicts is a refuted cube; a node
+ * with at most k active variables (unassigned and occurring in a clause not
+ * yet satisfied) becomes a leaf; otherwise the scorer picks a branching
+ * variable and the 0-child is explored before the 1-child.  The static
+ * scorer takes the active variable with the most literal occurrences in the
+ * original CNF, ties to the lowest index.  Cubes hold the branching literals
+ * only.  A query whose tree exceeds max_cubes is cut (UNKNOWN).             */
+#define SCUBA_SCORER_STATIC 0u
+typedef struct {
+  uint32_t k;            /* max active variables per leaf (<= 38)            */
+  uint32_t scorer;       /* SCUBA_SCORER_*                                   */
+  uint64_t max_cubes;    /* per query, leaves + refuted                       */
+  uint32_t max_residual; /* a leaf must also have at most this many residual
+                            clauses (0 = the device limit)                   */
+  uint32_t reserved;
+} scuba_split_opts;
+
+#define SCUBA_CUBE_LEAF 0
+#define SCUBA_CUBE_REFUTED 1
+scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split_opts* opts,
+                         scuba_cubes** out);
+/* Cubes from arrays: q_cube_start[nq+1] indexes cubes, cube_off[ncubes+1]
+ * indexes cube_lits.  Every cube is evaluated as given (no validation of
+ * completeness; clashing literals make a refuted cube).                     */
+scuba_status scuba_cubes_from_arrays(scuba_ctx* ctx, const scuba_cnf* cnf,
+                                     const uint64_t* q_cube_start, const uint64_t* cube_off,
+                                     const int32_t* cube_lits, scuba_cubes** out);
+typedef struct {
+  uint64_t n_cubes;
+  const uint64_t* cube_off;  /* n_cubes+1, relative to lits                  */
+  const int32_t* lits;
+  const int32_t* kind;       /* SCUBA_CUBE_LEAF / SCUBA_CUBE_REFUTED (host)   */
+  const int32_t* f;          /* active variables of leaves (host), -1 refuted */
+  int32_t complete;          /* 1 if the tree was not cut by max_cubes        */
+} scuba_cubes_view;
+scuba_status scuba_cubes_view_get(const scuba_cubes* cubes, uint32_t qi, scuba_cubes_view* out);
+void scuba_cubes_free(scuba_cubes* cubes);
+
+/* ---------------------------------------------------------------- solve */
+#define SCUBA_MODE_DECIDE 0u   /* stop a query at its first satisfying leaf  */
+#define SCUBA_MODE_COUNT 1u    /* count every leaf's satisfying assignments   */
+typedef struct {
+  uint32_t mode;             /* SCUBA_MODE_*                                  */
+  uint32_t k;                /* split bound for scuba_decide (<= 38)          */
+  uint64_t max_cubes;        /* per query budget for scuba_decide             */
+  uint32_t leaves_per_round; /* lazily split leaves per query per round       */
+  uint32_t chunk_log2;       /* leaf work item = 2^chunk_log2 blocks of 4096
+                                assignments                                   */
+  uint32_t grid;             /* persistent workgroups (0 = 8 per CU)          */
+  uint32_t max_rounds;       /* scuba_decide rounds (0 = unbounded)           */
+  uint32_t scorer;           /* SCUBA_SCORER_*                                */
+  uint32_t reserved[3];
+} scuba_solve_opts;
+
+/* Device bytes scuba_solve / scuba_decide need for this batch. */
+scuba_status scuba_solve_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes* cubes,
+                                   const scuba_solve_opts* opts, size_t* bytes);
+scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf,
+                                    const scuba_solve_opts* opts, size_t* bytes);
+
+/* Evaluate every cube of `cubes` on the device: unit propagation, then
+ * the bit-sliced exhaustive leaf evaluation.  COUNT mode fills per-cube
+ * (refuted, f, m, count, first satisfying index); DECIDE mode stops a query
+ * at its first satisfying leaf (smallest cube index, then smallest
+ * assignment index).  Verdict: SAT if a leaf is satisfiable, UNSAT if the
+ * cube list is complete and no leaf is, else UNKNOWN.
+ * dev_ws: device memory of at least scuba_solve_workspace bytes.           */
+scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes* cubes,
+                         const scuba_solve_opts* opts, void* dev_ws, size_t ws_bytes,
+                         void* hip_stream, scuba_results** out);
+
+/* The whole path for a batch: split lazily (leaves_per_round per query per
+ * round, DFS order), evaluate each round's leaves on the device, drop the
+ * queries that are decided, repeat until every query is decided, its tree
+ * is exhausted, or its budget is spent.                                    */
+scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
+                          void* dev_ws, size_t ws_bytes, void* hip_stream, scuba_results** out);
+
+/* ---------------------------------------------------------------- results */
+#define SCUBA_HOW_ROOT 0    /* decided by normalisation / root propagation */
+#define SCUBA_HOW_DEVICE 1  /* decided by device leaves                      */
+#define SCUBA_HOW_BUDGET 2  /* undecided: budget                             */
+typedef struct {
+  scuba_verdict verdict;
+  int32_t how;               /* SCUBA_HOW_*                                   */
+  uint64_t cubes_total;      /* leaves + refuted cubes produced               */
+  uint64_t cubes_refuted;    /* refuted by host propagation                   */
+  uint64_t leaves_sent;      /* leaves evaluated on the device                */
+  uint64_t leaves_refuted;   /* leaves the device propagation refuted         */
+  uint64_t blocks_evaluated; /* 4096-assignment blocks evaluated              */
+  uint64_t clause_blocks;    /* clause x block evaluations on the VALU        */
+  uint32_t rounds;
+  int32_t witness_checked;   /* 1: model satisfies every clause and (for
+                                bit-blasted queries) the exact integer query */
+} scuba_query_result;
+
+typedef struct {
+  int32_t refuted;           /* 1: device propagation conflicted             */
+  int32_t f, m;              /* active / other unassigned variables          */
+  int32_t reserved;
+  uint64_t count;            /* satisfying assignments of the active vars    */
+  int64_t first;             /* smallest satisfying index (-1 none; DECIDE:
+                                only the deciding leaf)                      */
+} scuba_leaf_result;
+
+scuba_status scuba_result_get(const scuba_results* r, uint32_t qi, scuba_query_result* out);
+/* Integer value of each declared input for a SAT query (n <= 64 bits each). */
+scuba_status scuba_witness_get(const scuba_results* r, uint32_t qi, uint64_t* values, uint32_t n);
+/* Full CNF model (n_vars+1 bytes, index 0 unused) of a SAT query. */
+scuba_status scuba_model_get(const scuba_results* r, uint32_t qi, uint8_t* bits, uint32_t n);
+/* Per-cube results of scuba_solve (cube order of the input list). */
+scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube,
+                            scuba_leaf_result* out);
+/* Stage times in ms: [0] bitblast-free host split, [1] upload, [2] device
+ * kernels (HIP events), [3] download, [4] verify, [5] total wall,
+ * [6] UP kernel, [7] leaf kernel.  n <= 8.                                  */
+scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n);
+void scuba_results_free(scuba_results* r);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCUBA_H */

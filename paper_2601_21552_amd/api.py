@@ -1,0 +1,241 @@
+"""Python binding of the C ABI: the same steps under the same names
+(bitblast, cnf_from_arrays, split, cubes_from_arrays, solve, decide and the
+result getters).  Only argument marshalling happens here; every step runs in
+``libscuba.so`` (host C++ and gfx950 kernels).  torch provides the device
+workspace and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+_P = C.c_void_p
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P) if a is not None and a.size else None
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self, ctx: "Context", h):
+        self.ctx, self.h = ctx, h
+
+    def __del__(self):
+        if getattr(self, "h", None) and self._free:
+            getattr(L.load(), self._free)(self.h)
+            self.h = None
+
+
+class Cnf(_Handle):
+    _free = "scuba_cnf_free"
+
+    def __len__(self):
+        return L.load().scuba_cnf_count(self.h)
+
+    def view(self, qi: int) -> dict:
+        v = L.CnfView()
+        self.ctx._check(L.load().scuba_cnf_view_get(self.h, qi, C.byref(v)))
+        off = np.ctypeslib.as_array(v.clause_off, shape=(v.n_clauses + 1,)).copy()
+        lits = (np.ctypeslib.as_array(v.lits, shape=(v.n_lits,)).copy()
+                if v.n_lits else np.zeros(0, np.int32))
+        return dict(n_vars=v.n_vars, n_inputs=v.n_inputs, n_clauses=v.n_clauses,
+                    clause_off=off, lits=lits, root_unsat=bool(v.root_unsat))
+
+    def input_map(self, qi: int):
+        n = self.view(qi)["n_inputs"]
+        first = np.zeros(max(n, 1), np.uint32)
+        width = np.zeros(max(n, 1), np.uint32)
+        self.ctx._check(L.load().scuba_cnf_input_map(self.h, qi, _ptr(first), _ptr(width), n))
+        return first[:n], width[:n]
+
+
+class Cubes(_Handle):
+    _free = "scuba_cubes_free"
+
+    def view(self, qi: int) -> dict:
+        v = L.CubesView()
+        self.ctx._check(L.load().scuba_cubes_view_get(self.h, qi, C.byref(v)))
+        n = v.n_cubes
+        off = np.ctypeslib.as_array(v.cube_off, shape=(n + 1,)).copy()
+        nl = int(off[-1])
+        lits = np.ctypeslib.as_array(v.lits, shape=(nl,)).copy() if nl else np.zeros(0, np.int32)
+        kind = np.ctypeslib.as_array(v.kind, shape=(n,)).copy() if n else np.zeros(0, np.int32)
+        f = np.ctypeslib.as_array(v.f, shape=(n,)).copy() if n else np.zeros(0, np.int32)
+        return dict(cube_off=off, lits=lits, kind=kind, f=f, complete=bool(v.complete),
+                    cubes=[lits[off[i]:off[i + 1]].tolist() for i in range(n)])
+
+
+class Results(_Handle):
+    _free = "scuba_results_free"
+
+    def __init__(self, ctx, h, nq):
+        super().__init__(ctx, h)
+        self.nq = nq
+
+    def result(self, qi: int) -> dict:
+        r = L.QueryResult()
+        self.ctx._check(L.load().scuba_result_get(self.h, qi, C.byref(r)))
+        return dict(verdict=L.VERDICT[r.verdict], how=L.HOW[r.how], cubes_total=r.cubes_total,
+                    cubes_refuted=r.cubes_refuted, leaves_sent=r.leaves_sent,
+                    leaves_refuted=r.leaves_refuted, blocks_evaluated=r.blocks_evaluated,
+                    clause_blocks=r.clause_blocks, rounds=r.rounds,
+                    witness_checked=bool(r.witness_checked))
+
+    def verdicts(self):
+        return [self.result(i)["verdict"] for i in range(self.nq)]
+
+    def witness(self, qi: int, n_inputs: int):
+        vals = np.zeros(max(n_inputs, 1), np.uint64)
+        self.ctx._check(L.load().scuba_witness_get(self.h, qi, _ptr(vals), n_inputs))
+        return [int(x) for x in vals[:n_inputs]]
+
+    def model(self, qi: int, n_vars: int):
+        bits = np.zeros(n_vars + 1, np.uint8)
+        self.ctx._check(L.load().scuba_model_get(self.h, qi, _ptr(bits), n_vars + 1))
+        return bits
+
+    def leaf(self, qi: int, cube: int) -> dict:
+        r = L.LeafResult()
+        self.ctx._check(L.load().scuba_leaf_get(self.h, qi, cube, C.byref(r)))
+        return dict(refuted=bool(r.refuted), f=r.f, m=r.m, count=int(r.count), first=int(r.first))
+
+    def timing(self) -> dict:
+        ms = np.zeros(8, np.float64)
+        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 8))
+        keys = ["split", "h2d", "kernels", "d2h", "verify", "total", "up", "leaf"]
+        return dict(zip(keys, ms.tolist()))
+
+
+def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_log2=0,
+                grid=0, max_rounds=0, scorer=0):
+    o = L.SolveOpts()
+    o.mode, o.k, o.max_cubes = mode, k, max_cubes
+    o.leaves_per_round, o.chunk_log2, o.grid = leaves_per_round, chunk_log2, grid
+    o.max_rounds, o.scorer = max_rounds, scorer
+    return o
+
+
+class Context:
+    """One library context bound to a HIP device (opened lazily)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        h = _P()
+        st = self.lib.scuba_ctx_create(device, C.byref(h))
+        if st != L.OK:
+            raise L.ScubaError(st, "scuba_ctx_create")
+        self.h = h
+        self.device = device
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.scuba_ctx_destroy(self.h)
+            self.h = None
+
+    def _check(self, st):
+        if st != L.OK:
+            raise L.ScubaError(st, self.lib.scuba_last_error(self.h).decode())
+
+    # ------------------------------------------------------------ CNF
+    def bitblast(self, queries, flags: int = 0) -> Cnf:
+        """queries: iterable of (nodes: NODE_DTYPE array, roots: uint32 array)."""
+        nodes, roots, ns, rs = [], [], [0], [0]
+        for n, r in queries:
+            n = np.asarray(n)
+            assert n.dtype.itemsize == L.NODE_DTYPE.itemsize
+            nodes.append(n.view(L.NODE_DTYPE) if n.dtype != L.NODE_DTYPE else n)
+            roots.append(np.asarray(r, dtype=np.uint32))
+            ns.append(ns[-1] + len(n))
+            rs.append(rs[-1] + len(r))
+        nq = len(ns) - 1
+        an = np.ascontiguousarray(np.concatenate(nodes)) if nodes else np.zeros(0, L.NODE_DTYPE)
+        ar = np.ascontiguousarray(np.concatenate(roots)) if roots else np.zeros(0, np.uint32)
+        ans, ars = np.array(ns, np.uint64), np.array(rs, np.uint64)
+        h = _P()
+        self._check(self.lib.scuba_bitblast(self.h, nq, _ptr(an), _ptr(ans), _ptr(ar), _ptr(ars),
+                                            flags, C.byref(h)))
+        return Cnf(self, h)
+
+    def cnf_from_arrays(self, n_vars, q_clause_start, clause_off, lits) -> Cnf:
+        n_vars = np.ascontiguousarray(n_vars, dtype=np.uint32)
+        qs = np.ascontiguousarray(q_clause_start, dtype=np.uint64)
+        co = np.ascontiguousarray(clause_off, dtype=np.uint64)
+        li = np.ascontiguousarray(lits, dtype=np.int32)
+        h = _P()
+        self._check(self.lib.scuba_cnf_from_arrays(self.h, len(n_vars), _ptr(n_vars), _ptr(qs),
+                                                   _ptr(co), _ptr(li), C.byref(h)))
+        return Cnf(self, h)
+
+    # ------------------------------------------------------------ cubes
+    def split(self, cnf: Cnf, k: int, max_cubes: int = 0, max_residual: int = 0,
+              scorer: int = 0) -> Cubes:
+        o = L.SplitOpts()
+        o.k, o.scorer, o.max_cubes, o.max_residual = k, scorer, max_cubes, max_residual
+        h = _P()
+        self._check(self.lib.scuba_split(self.h, cnf.h, C.byref(o), C.byref(h)))
+        return Cubes(self, h)
+
+    def cubes_from_arrays(self, cnf: Cnf, cubes_per_query) -> Cubes:
+        qs, off, lits = [0], [0], []
+        for cubes in cubes_per_query:
+            for c in cubes:
+                lits.extend(int(x) for x in c)
+                off.append(len(lits))
+            qs.append(len(off) - 1)
+        aq = np.array(qs, np.uint64)
+        ao = np.array(off, np.uint64)
+        al = np.array(lits or [0], np.int32)
+        h = _P()
+        self._check(self.lib.scuba_cubes_from_arrays(self.h, cnf.h, _ptr(aq), _ptr(ao), _ptr(al),
+                                                     C.byref(h)))
+        return Cubes(self, h)
+
+    # ------------------------------------------------------------ device
+    def _workspace(self, nbytes: int, workspace=None):
+        import torch
+        if workspace is not None:
+            assert workspace.numel() * workspace.element_size() >= nbytes
+            return workspace
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8,
+                                   device=f"cuda:{self.device}")
+        return self._ws
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return _P(s.cuda_stream)
+
+    def solve_workspace(self, cnf: Cnf, cubes: Cubes, **opts) -> int:
+        o = _solve_opts(**opts)
+        n = C.c_size_t()
+        self._check(self.lib.scuba_solve_workspace(self.h, cnf.h, cubes.h, C.byref(o), C.byref(n)))
+        return n.value
+
+    def decide_workspace(self, cnf: Cnf, **opts) -> int:
+        o = _solve_opts(**opts)
+        n = C.c_size_t()
+        self._check(self.lib.scuba_decide_workspace(self.h, cnf.h, C.byref(o), C.byref(n)))
+        return n.value
+
+    def solve(self, cnf: Cnf, cubes: Cubes, workspace=None, stream=None, **opts) -> Results:
+        o = _solve_opts(**opts)
+        ws = self._workspace(self.solve_workspace(cnf, cubes, **opts), workspace)
+        h = _P()
+        self._check(self.lib.scuba_solve(self.h, cnf.h, cubes.h, C.byref(o), _P(ws.data_ptr()),
+                                         ws.numel(), self._stream(stream), C.byref(h)))
+        return Results(self, h, len(cnf))
+
+    def decide(self, cnf: Cnf, workspace=None, stream=None, **opts) -> Results:
+        o = _solve_opts(**opts)
+        ws = self._workspace(self.decide_workspace(cnf, **opts), workspace)
+        h = _P()
+        self._check(self.lib.scuba_decide(self.h, cnf.h, C.byref(o), _P(ws.data_ptr()), ws.numel(),
+                                          self._stream(stream), C.byref(h)))
+        return Results(self, h, len(cnf))

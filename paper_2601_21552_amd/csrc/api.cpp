@@ -1,0 +1,707 @@
+// C ABI of the library: handles, the split/solve/decide drivers and results.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "bigint.hpp"
+#include "common.hpp"
+#include "device.hpp"
+#include "split.hpp"
+
+using namespace scuba;
+
+struct scuba_ctx {
+  int32_t device = 0;
+  bool dev_ready = false;
+  DeviceInfo dev;
+  std::string err;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+
+  void ensure_device() {
+    if (!dev_ready) {
+      dev_init(&dev, device);
+      dev_ready = true;
+    }
+  }
+  void* staging(size_t bytes) {
+    if (bytes > pinned_bytes) {
+      dev_pinned_free(pinned);
+      pinned = nullptr;
+      pinned_bytes = 0;
+      size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+      pinned = dev_pinned(want);
+      pinned_bytes = want;
+    }
+    return pinned;
+  }
+  ~scuba_ctx() { dev_pinned_free(pinned); }
+};
+
+struct scuba_cubes {
+  struct Q {
+    std::vector<uint64_t> off{0};
+    std::vector<int32_t> lits;
+    std::vector<int32_t> kind, f;
+    std::vector<uint32_t> nres;
+    bool complete = true;
+  };
+  std::vector<Q> q;
+};
+
+struct scuba_results {
+  struct Q {
+    scuba_query_result r{};
+    std::vector<uint8_t> model;
+    std::vector<uint64_t> witness;
+    std::vector<scuba_leaf_result> leaves;
+  };
+  std::vector<Q> q;
+  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+template <typename F>
+scuba_status guard(scuba_ctx* ctx, F&& f) {
+  try {
+    f();
+    return SCUBA_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "out of host memory";
+    return SCUBA_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return SCUBA_E_INTERNAL;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return SCUBA_E_INTERNAL;
+  }
+}
+
+constexpr uint32_t kDefaultK = 30;
+constexpr uint32_t kDefaultLeavesPerRound = 4;
+constexpr uint32_t kDefaultChunkLog2 = 8;
+constexpr uint64_t kDefaultMaxCubes = 100000;
+constexpr uint32_t kMaxCubeLen = 4096;
+
+struct Opts {
+  uint32_t mode, k, lpr, chunk_log2, grid, max_rounds, scorer;
+  uint64_t max_cubes;
+};
+Opts resolve(const scuba_solve_opts* o) {
+  Opts r{SCUBA_MODE_DECIDE, kDefaultK, kDefaultLeavesPerRound, kDefaultChunkLog2, 0, 0, 0, kDefaultMaxCubes};
+  if (o) {
+    r.mode = o->mode;
+    if (o->k) r.k = o->k;
+    if (o->leaves_per_round) r.lpr = o->leaves_per_round;
+    if (o->chunk_log2) r.chunk_log2 = o->chunk_log2;
+    r.grid = o->grid;
+    r.max_rounds = o->max_rounds;
+    r.scorer = o->scorer;
+    if (o->max_cubes) r.max_cubes = o->max_cubes;
+  }
+  if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
+  if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
+  if (r.chunk_log2 > 26) fail(SCUBA_E_INVALID, "chunk_log2 above 26");
+  if (r.scorer != SCUBA_SCORER_STATIC) fail(SCUBA_E_INVALID, "unknown scorer");
+  return r;
+}
+
+CnfHost cnf_host(const scuba_cnf* cnf) {
+  CnfHost h;
+  for (const CnfQuery& q : cnf->q) {
+    DevQueryDesc d;
+    d.coff_base = h.coff.size();
+    d.lit_base = h.lits.size();
+    if (q.n_clauses() >= (uint64_t(1) << 32) || q.lits.size() >= (uint64_t(1) << 32))
+      fail(SCUBA_E_CAPACITY, "query with 2^32 or more clauses or literals");
+    d.n_clauses = uint32_t(q.n_clauses());
+    d.n_vars = q.n_vars;
+    for (uint64_t o : q.off) h.coff.push_back(uint32_t(o));
+    h.lits.insert(h.lits.end(), q.lits.begin(), q.lits.end());
+    h.q.push_back(d);
+  }
+  return h;
+}
+
+uint64_t blocks_of(int32_t f) { return f >= 12 ? (uint64_t(1) << (f - 12)) : 1; }
+
+// Append one cube to a round; returns its index within the round.  A cube
+// the host refuted is sent too (its device refutation is checked) but gets
+// no leaf work.
+uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint32_t chunk_log2,
+                  uint32_t n_vars) {
+  if (c.lits.size() > kMaxCubeLen) fail(SCUBA_E_CAPACITY, "cube longer than 4096 literals");
+  if (!c.refuted && (c.f < 0 || uint32_t(c.f) > kMaxLeafVars))
+    fail(SCUBA_E_CAPACITY, "leaf with more than 38 active variables");
+  DevCubeDesc d;
+  d.qid = qid;
+  d.lit_off = uint32_t(rh.cube_lits.size());
+  d.n_lits = uint32_t(c.lits.size());
+  d.seq = seq;
+  d.f_expect = c.refuted ? -1 : c.f;
+  d.nres_cap = c.refuted ? 0 : c.nres;
+  d.res_base = rh.res_records;
+  rh.res_records += d.nres_cap;
+  rh.tile_max = std::max(rh.tile_max, d.nres_cap);
+  rh.nw_max = std::max(rh.nw_max, (n_vars >> 5) + 1);
+  rh.cube_lits.insert(rh.cube_lits.end(), c.lits.begin(), c.lits.end());
+  uint32_t ci = uint32_t(rh.cubes.size());
+  rh.cubes.push_back(d);
+  if (!c.refuted) {
+    uint64_t nb = blocks_of(c.f), chunk = uint64_t(1) << chunk_log2;
+    for (uint64_t lo = 0; lo < nb; lo += chunk)
+      rh.items.push_back({ci, uint32_t(lo), uint32_t(std::min(nb, lo + chunk)), 0});
+  }
+  return ci;
+}
+
+size_t round_bound(const scuba_cnf* cnf, size_t n_cubes, const Opts& o, uint32_t max_res) {
+  uint32_t max_vars = 0;
+  for (const CnfQuery& q : cnf->q) max_vars = std::max(max_vars, q.n_vars);
+  size_t lits = n_cubes * std::min<uint32_t>(max_vars + 1, kMaxCubeLen);
+  uint64_t nb = blocks_of(int32_t(o.k));
+  uint64_t per = (nb + (uint64_t(1) << o.chunk_log2) - 1) >> o.chunk_log2;
+  return dev_round_bytes(n_cubes, lits, n_cubes * per, uint64_t(n_cubes) * max_res);
+}
+
+// Model of a SAT leaf: propagation of the cube, slot j = bit j of `a`,
+// remaining unassigned variables 0.  Then the checks of the result stage.
+void assemble_witness(const CnfQuery& q, const std::vector<int32_t>& cube, uint64_t a,
+                      scuba_results::Q& out) {
+  Splitter sp(q, 0, 0, 1);
+  std::vector<int8_t> assign;
+  std::vector<int32_t> active;
+  uint32_t nres = 0;
+  if (!sp.leaf_of(cube, &assign, &active, &nres)) fail(SCUBA_E_INTERNAL, "witness cube conflicts on the host");
+  for (size_t j = 0; j < active.size(); j++) assign[active[j]] = int8_t((a >> j) & 1);
+  out.model.assign(size_t(q.n_vars) + 1, 0);
+  for (uint32_t v = 1; v <= q.n_vars; v++) out.model[v] = assign[v] > 0 ? 1 : 0;
+  // every clause must hold
+  for (uint64_t c = 0; c < q.n_clauses(); c++) {
+    bool sat = false;
+    for (uint64_t i = q.off[c]; i < q.off[c + 1] && !sat; i++) {
+      int32_t l = q.lits[i];
+      sat = (out.model[std::abs(l)] == 1) == (l > 0);
+    }
+    if (!sat) fail(SCUBA_E_INTERNAL, "device witness violates a clause");
+  }
+  out.witness.clear();
+  for (size_t i = 0; i < q.in_first.size(); i++) {
+    uint64_t v = 0;
+    for (uint32_t b = 0; b < q.in_width[i]; b++)
+      if (out.model[q.in_first[i] + b]) v |= uint64_t(1) << b;
+    out.witness.push_back(v);
+  }
+  if (!int_check_query(q, out.witness)) fail(SCUBA_E_INTERNAL, "witness fails the exact integer query");
+  out.r.witness_checked = 1;
+}
+
+// The device's propagation must reach the host's fixpoint: the same
+// refutation, active count and number of unsatisfied clauses.
+void check_out(const DevCubeOut& o, const Cube& host) {
+  if (host.refuted) {
+    if (o.status != 1) fail(SCUBA_E_DEVICE, "device kept a cube the host propagation refuted");
+    return;
+  }
+  if (o.status == 2) fail(SCUBA_E_DEVICE, "device propagation disagrees with the host (active count)");
+  if (o.status == 3) fail(SCUBA_E_DEVICE, "device residual exceeds the host's count");
+  if (o.status == 1) fail(SCUBA_E_DEVICE, "device refuted a leaf the host propagation kept");
+  if (o.f != host.f || uint32_t(o.nres) != host.nres)
+    fail(SCUBA_E_DEVICE, "device leaf disagrees with the host (active count or residual)");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+
+extern "C" {
+
+uint32_t scuba_abi_version(void) { return 1; }
+
+scuba_status scuba_ctx_create(int32_t device, scuba_ctx** out) {
+  if (!out) return SCUBA_E_INVALID;
+  try {
+    auto* c = new scuba_ctx();
+    c->device = device;
+    *out = c;
+    return SCUBA_OK;
+  } catch (...) {
+    return SCUBA_E_NOMEM;
+  }
+}
+
+void scuba_ctx_destroy(scuba_ctx* ctx) { delete ctx; }
+
+const char* scuba_last_error(const scuba_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+const char* scuba_status_str(scuba_status s) {
+  switch (s) {
+    case SCUBA_OK: return "ok";
+    case SCUBA_E_INVALID: return "invalid input";
+    case SCUBA_E_WIDTH: return "input width outside 1..64";
+    case SCUBA_E_NOMEM: return "out of host memory";
+    case SCUBA_E_DEVICE: return "device error";
+    case SCUBA_E_CAPACITY: return "capacity exceeded";
+    case SCUBA_E_STATE: return "invalid state";
+    case SCUBA_E_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+// ---------------------------------------------------------------- CNF
+
+scuba_status scuba_bitblast(scuba_ctx* ctx, uint32_t nq, const scuba_node* nodes, const uint64_t* node_start,
+                            const uint32_t* roots, const uint64_t* root_start, uint32_t flags,
+                            scuba_cnf** out) {
+  if (!ctx || !out || (nq && (!node_start || !root_start))) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    auto cnf = std::make_unique<scuba_cnf>();
+    cnf->q.reserve(nq);
+    for (uint32_t i = 0; i < nq; i++) {
+      uint64_t n0 = node_start[i], n1 = node_start[i + 1], r0 = root_start[i], r1 = root_start[i + 1];
+      if (n1 < n0 || r1 < r0) fail(SCUBA_E_INVALID, "offsets must not decrease");
+      try {
+        cnf->q.push_back(bitblast_query(nodes + n0, n1 - n0, roots + r0, r1 - r0, flags));
+      } catch (const Error& e) {
+        throw Error(e.code, "query " + std::to_string(i) + ": " + e.what());
+      }
+    }
+    *out = cnf.release();
+  });
+}
+
+scuba_status scuba_cnf_from_arrays(scuba_ctx* ctx, uint32_t nq, const uint32_t* n_vars,
+                                   const uint64_t* q_clause_start, const uint64_t* clause_off,
+                                   const int32_t* lits, scuba_cnf** out) {
+  if (!ctx || !out || (nq && (!n_vars || !q_clause_start || !clause_off))) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    auto cnf = std::make_unique<scuba_cnf>();
+    for (uint32_t i = 0; i < nq; i++) {
+      CnfQuery q;
+      q.n_vars = n_vars[i];
+      uint64_t c0 = q_clause_start[i], c1 = q_clause_start[i + 1];
+      if (c1 < c0) fail(SCUBA_E_INVALID, "clause ranges must not decrease");
+      std::vector<uint32_t> seen(size_t(q.n_vars) + 1, 0);
+      uint32_t stamp = 0;
+      for (uint64_t c = c0; c < c1; c++) {
+        if (clause_off[c + 1] < clause_off[c]) fail(SCUBA_E_INVALID, "clause offsets must not decrease");
+        stamp++;
+        for (uint64_t j = clause_off[c]; j < clause_off[c + 1]; j++) {
+          int32_t l = lits[j];
+          uint32_t v = uint32_t(l > 0 ? l : -int64_t(l));
+          if (l == 0 || v > q.n_vars) fail(SCUBA_E_INVALID, "query " + std::to_string(i) + ": literal out of range");
+          if (seen[v] == stamp) fail(SCUBA_E_INVALID, "query " + std::to_string(i) + ": clause repeats a variable");
+          seen[v] = stamp;
+          q.lits.push_back(l);
+        }
+        q.off.push_back(q.lits.size());
+      }
+      cnf->q.push_back(std::move(q));
+    }
+    *out = cnf.release();
+  });
+}
+
+uint32_t scuba_cnf_count(const scuba_cnf* cnf) { return cnf ? uint32_t(cnf->q.size()) : 0; }
+
+scuba_status scuba_cnf_view_get(const scuba_cnf* cnf, uint32_t qi, scuba_cnf_view* out) {
+  if (!cnf || !out || qi >= cnf->q.size()) return SCUBA_E_INVALID;
+  const CnfQuery& q = cnf->q[qi];
+  out->n_vars = q.n_vars;
+  out->n_inputs = uint32_t(q.in_first.size());
+  out->n_clauses = q.n_clauses();
+  out->n_lits = q.lits.size();
+  out->clause_off = q.off.data();
+  out->lits = q.lits.data();
+  out->root_unsat = q.root_unsat ? 1 : 0;
+  return SCUBA_OK;
+}
+
+scuba_status scuba_cnf_input_map(const scuba_cnf* cnf, uint32_t qi, uint32_t* first_var, uint32_t* width,
+                                 uint32_t cap) {
+  if (!cnf || qi >= cnf->q.size()) return SCUBA_E_INVALID;
+  const CnfQuery& q = cnf->q[qi];
+  if (cap < q.in_first.size() || (!q.in_first.empty() && (!first_var || !width))) return SCUBA_E_CAPACITY;
+  for (size_t i = 0; i < q.in_first.size(); i++) {
+    first_var[i] = q.in_first[i];
+    width[i] = q.in_width[i];
+  }
+  return SCUBA_OK;
+}
+
+void scuba_cnf_free(scuba_cnf* cnf) { delete cnf; }
+
+// ---------------------------------------------------------------- cubes
+
+scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split_opts* opts, scuba_cubes** out) {
+  if (!ctx || !cnf || !opts || !out) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    if (opts->k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
+    if (opts->scorer != SCUBA_SCORER_STATIC) fail(SCUBA_E_INVALID, "unknown scorer");
+    uint32_t max_res = opts->max_residual ? opts->max_residual : kDefaultMaxResidual;
+    uint64_t max_cubes = opts->max_cubes ? opts->max_cubes : kDefaultMaxCubes;
+    auto cubes = std::make_unique<scuba_cubes>();
+    for (const CnfQuery& q : cnf->q) {
+      scuba_cubes::Q cq;
+      Splitter sp(q, opts->k, max_res, max_cubes);
+      std::vector<Cube> all;
+      Splitter::State st;
+      do st = sp.next(UINT32_MAX, all, true);
+      while (st == Splitter::kRunning);
+      cq.complete = st == Splitter::kExhausted;
+      for (const Cube& c : all) {
+        cq.lits.insert(cq.lits.end(), c.lits.begin(), c.lits.end());
+        cq.off.push_back(cq.lits.size());
+        cq.kind.push_back(c.refuted ? SCUBA_CUBE_REFUTED : SCUBA_CUBE_LEAF);
+        cq.f.push_back(c.refuted ? -1 : c.f);
+        cq.nres.push_back(c.nres);
+      }
+      cubes->q.push_back(std::move(cq));
+    }
+    *out = cubes.release();
+  });
+}
+
+scuba_status scuba_cubes_from_arrays(scuba_ctx* ctx, const scuba_cnf* cnf, const uint64_t* q_cube_start,
+                                     const uint64_t* cube_off, const int32_t* cube_lits, scuba_cubes** out) {
+  if (!ctx || !cnf || !q_cube_start || !cube_off || !out) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    auto cubes = std::make_unique<scuba_cubes>();
+    for (size_t i = 0; i < cnf->q.size(); i++) {
+      const CnfQuery& q = cnf->q[i];
+      scuba_cubes::Q cq;
+      Splitter sp(q, 0, 0, 1);
+      if (q_cube_start[i + 1] < q_cube_start[i]) fail(SCUBA_E_INVALID, "cube ranges must not decrease");
+      for (uint64_t c = q_cube_start[i]; c < q_cube_start[i + 1]; c++) {
+        if (cube_off[c + 1] < cube_off[c]) fail(SCUBA_E_INVALID, "cube offsets must not decrease");
+        std::vector<int32_t> lits(cube_lits + cube_off[c], cube_lits + cube_off[c + 1]);
+        for (int32_t l : lits)
+          if (l == 0 || uint32_t(std::abs(l)) > q.n_vars) fail(SCUBA_E_INVALID, "cube literal out of range");
+        std::vector<int8_t> assign;
+        std::vector<int32_t> active;
+        uint32_t nres = 0;
+        bool ok = sp.leaf_of(lits, &assign, &active, &nres);
+        cq.lits.insert(cq.lits.end(), lits.begin(), lits.end());
+        cq.off.push_back(cq.lits.size());
+        // every given cube goes to the device; host-conflicting ones are
+        // marked so that the device's refutation can be checked
+        cq.kind.push_back(ok ? SCUBA_CUBE_LEAF : SCUBA_CUBE_REFUTED);
+        cq.f.push_back(ok ? int32_t(active.size()) : -1);
+        cq.nres.push_back(ok ? nres : 0);
+      }
+      cq.complete = false;
+      cubes->q.push_back(std::move(cq));
+    }
+    *out = cubes.release();
+  });
+}
+
+scuba_status scuba_cubes_view_get(const scuba_cubes* cubes, uint32_t qi, scuba_cubes_view* out) {
+  if (!cubes || !out || qi >= cubes->q.size()) return SCUBA_E_INVALID;
+  const auto& q = cubes->q[qi];
+  out->n_cubes = q.kind.size();
+  out->cube_off = q.off.data();
+  out->lits = q.lits.data();
+  out->kind = q.kind.data();
+  out->f = q.f.data();
+  out->complete = q.complete ? 1 : 0;
+  return SCUBA_OK;
+}
+
+void scuba_cubes_free(scuba_cubes* cubes) { delete cubes; }
+
+// ---------------------------------------------------------------- solve
+
+scuba_status scuba_solve_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes* cubes,
+                                   const scuba_solve_opts* opts, size_t* bytes) {
+  if (!ctx || !cnf || !cubes || !bytes || cubes->q.size() != cnf->q.size()) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    Opts o = resolve(opts);
+    CnfHost h = cnf_host(cnf);
+    size_t n_cubes = 0, n_lits = 0, n_items = 0;
+    uint64_t res = 0;
+    // every cube is sent (refuted ones too, to check the device agrees);
+    // only leaves get residual records and work items
+    for (const auto& q : cubes->q)
+      for (size_t c = 0; c < q.kind.size(); c++) {
+        n_cubes++;
+        n_lits += q.off[c + 1] - q.off[c];
+        if (q.kind[c] != SCUBA_CUBE_LEAF) continue;
+        res += q.nres[c];
+        uint64_t nb = blocks_of(std::max(q.f[c], 0));
+        n_items += size_t((nb + (uint64_t(1) << o.chunk_log2) - 1) >> o.chunk_log2);
+      }
+    *bytes = dev_cnf_bytes(h) + dev_round_bytes(n_cubes, n_lits, n_items, res);
+  });
+}
+
+scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
+                                    size_t* bytes) {
+  if (!ctx || !cnf || !bytes) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    Opts o = resolve(opts);
+    CnfHost h = cnf_host(cnf);
+    *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, kDefaultMaxResidual);
+  });
+}
+
+scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes* cubes,
+                         const scuba_solve_opts* opts, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                         scuba_results** out) {
+  if (!ctx || !cnf || !cubes || !out || !dev_ws || cubes->q.size() != cnf->q.size()) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    auto t0 = Clock::now();
+    Opts o = resolve(opts);
+    ctx->ensure_device();
+    CnfHost h = cnf_host(cnf);
+    auto res = std::make_unique<scuba_results>();
+    res->q.resize(cnf->q.size());
+    RoundHost rh;
+    std::vector<std::pair<uint32_t, uint64_t>> where;   // round cube -> (query, cube)
+    std::vector<Cube> host_leaf;
+    for (size_t qi = 0; qi < cnf->q.size(); qi++) {
+      const auto& cq = cubes->q[qi];
+      auto& rq = res->q[qi];
+      rq.leaves.assign(cq.kind.size(), scuba_leaf_result{});
+      for (auto& l : rq.leaves) { l.first = -1; l.refuted = 0; }
+      rq.r.cubes_total = cq.kind.size();
+      for (size_t c = 0; c < cq.kind.size(); c++) {
+        Cube cube;
+        cube.lits.assign(cq.lits.begin() + cq.off[c], cq.lits.begin() + cq.off[c + 1]);
+        cube.refuted = cq.kind[c] != SCUBA_CUBE_LEAF;
+        if (cube.refuted) rq.r.cubes_refuted++;
+        cube.f = cq.f[c];
+        cube.nres = cq.nres[c];
+        add_cube(rh, uint32_t(qi), uint32_t(c), cube, o.chunk_log2, cnf->q[qi].n_vars);
+        where.push_back({uint32_t(qi), c});
+        host_leaf.push_back(cube);
+      }
+    }
+    size_t cnf_b = dev_cnf_bytes(h);
+    size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);
+    if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than scuba_solve_workspace");
+    void* stg = ctx->staging(std::max(cnf_b, round_b) + 4096 + rh.cubes.size() * sizeof(DevCubeOut) + h.q.size() * 8);
+    RoundTimes rt;
+    dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->pinned_bytes);
+    std::vector<DevCubeOut> outs;
+    std::vector<uint64_t> qkeys;
+    dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, o.mode, o.grid, hip_stream, stg, ctx->pinned_bytes, &outs,
+              &qkeys, &rt);
+    auto tv = Clock::now();
+    for (size_t i = 0; i < outs.size(); i++) {
+      check_out(outs[i], host_leaf[i]);
+      auto [qi, c] = where[i];
+      auto& rq = res->q[qi];
+      scuba_leaf_result& lr = rq.leaves[c];
+      lr.refuted = outs[i].status == 1;
+      lr.f = lr.refuted ? -1 : outs[i].f;
+      lr.m = lr.refuted ? -1 : outs[i].m;
+      lr.count = outs[i].count;
+      lr.first = outs[i].first == ~0ull ? -1 : int64_t(outs[i].first);
+      if (host_leaf[i].refuted) continue;
+      rq.r.leaves_sent++;
+      rq.r.leaves_refuted += lr.refuted;
+      rq.r.blocks_evaluated += outs[i].blocks;
+      rq.r.clause_blocks += outs[i].clause_blocks;
+    }
+    for (size_t qi = 0; qi < cnf->q.size(); qi++) {
+      auto& rq = res->q[qi];
+      rq.r.rounds = 1;
+      rq.r.how = SCUBA_HOW_DEVICE;
+      // first satisfying leaf in cube order
+      int64_t sat_cube = -1;
+      for (size_t c = 0; c < rq.leaves.size(); c++)
+        if (rq.leaves[c].first >= 0) { sat_cube = int64_t(c); break; }
+      if (sat_cube >= 0) {
+        rq.r.verdict = SCUBA_SAT;
+        const auto& cq = cubes->q[qi];
+        std::vector<int32_t> lits(cq.lits.begin() + cq.off[sat_cube], cq.lits.begin() + cq.off[sat_cube + 1]);
+        assemble_witness(cnf->q[qi], lits, uint64_t(rq.leaves[sat_cube].first), rq);
+      } else {
+        rq.r.verdict = cubes->q[qi].complete ? SCUBA_UNSAT : SCUBA_UNKNOWN;
+        if (cnf->q[qi].root_unsat) { rq.r.verdict = SCUBA_UNSAT; rq.r.how = SCUBA_HOW_ROOT; }
+      }
+    }
+    res->ms[1] = rt.h2d_ms;
+    res->ms[2] = rt.up_ms + rt.leaf_ms;
+    res->ms[3] = rt.d2h_ms;
+    res->ms[4] = ms_since(tv);
+    res->ms[5] = ms_since(t0);
+    res->ms[6] = rt.up_ms;
+    res->ms[7] = rt.leaf_ms;
+    *out = res.release();
+  });
+}
+
+scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts, void* dev_ws,
+                          size_t ws_bytes, void* hip_stream, scuba_results** out) {
+  if (!ctx || !cnf || !out || !dev_ws) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    auto t0 = Clock::now();
+    Opts o = resolve(opts);
+    if (o.mode != SCUBA_MODE_DECIDE) fail(SCUBA_E_INVALID, "scuba_decide runs in DECIDE mode");
+    ctx->ensure_device();
+    const size_t nq = cnf->q.size();
+    CnfHost h = cnf_host(cnf);
+    auto res = std::make_unique<scuba_results>();
+    res->q.resize(nq);
+    std::vector<std::unique_ptr<Splitter>> sp(nq);
+    std::vector<char> open(nq, 0);
+    std::vector<uint32_t> seq(nq, 0);
+    double split_ms = 0, verify_ms = 0;
+    auto ts = Clock::now();
+    for (size_t qi = 0; qi < nq; qi++) {
+      auto& r = res->q[qi].r;
+      if (cnf->q[qi].root_unsat) {
+        r.verdict = SCUBA_UNSAT;
+        r.how = SCUBA_HOW_ROOT;
+        continue;
+      }
+      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
+      open[qi] = 1;
+    }
+    split_ms += ms_since(ts);
+    size_t cnf_b = dev_cnf_bytes(h);
+    if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
+    bool uploaded = false;
+    RoundTimes rt;
+    for (uint32_t round = 0; o.max_rounds == 0 || round < o.max_rounds; round++) {
+      ts = Clock::now();
+      RoundHost rh;
+      std::vector<std::pair<uint32_t, Cube>> sent;
+      for (size_t qi = 0; qi < nq; qi++) {
+        if (!open[qi]) continue;
+        std::vector<Cube> leaves;
+        Splitter::State st = sp[qi]->next(o.lpr, leaves, false);
+        auto& r = res->q[qi].r;
+        r.rounds++;
+        for (Cube& c : leaves) {
+          add_cube(rh, uint32_t(qi), seq[qi]++, c, o.chunk_log2, cnf->q[qi].n_vars);
+          sent.push_back({uint32_t(qi), std::move(c)});
+        }
+        r.cubes_total = sp[qi]->cubes_total();
+        r.cubes_refuted = sp[qi]->cubes_refuted();
+        if (leaves.empty()) {
+          // nothing left for the device: the tree is done or cut
+          open[qi] = 0;
+          r.verdict = st == Splitter::kExhausted ? SCUBA_UNSAT : SCUBA_UNKNOWN;
+          r.how = st == Splitter::kExhausted ? (r.leaves_sent ? SCUBA_HOW_DEVICE : SCUBA_HOW_ROOT)
+                                              : SCUBA_HOW_BUDGET;
+        }
+      }
+      split_ms += ms_since(ts);
+      if (rh.cubes.empty()) break;
+      size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);
+      if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than this round needs");
+      void* stg = ctx->staging(std::max(cnf_b, round_b) + 4096 + rh.cubes.size() * sizeof(DevCubeOut) + nq * 8);
+      if (!uploaded) {
+        dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->pinned_bytes);
+        uploaded = true;
+      }
+      std::vector<DevCubeOut> outs;
+      std::vector<uint64_t> qkeys;
+      dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
+                ctx->pinned_bytes, &outs, &qkeys, &rt);
+      auto tv = Clock::now();
+      for (size_t i = 0; i < outs.size(); i++) {
+        check_out(outs[i], sent[i].second);
+        auto& r = res->q[sent[i].first].r;
+        r.leaves_sent++;
+        r.leaves_refuted += outs[i].status == 1;
+        r.blocks_evaluated += outs[i].blocks;
+        r.clause_blocks += outs[i].clause_blocks;
+      }
+      // queries with a witness are SAT; the witness is from this round
+      std::vector<size_t> first_of(nq, SIZE_MAX);
+      for (size_t i = 0; i < sent.size(); i++)
+        if (first_of[sent[i].first] == SIZE_MAX) first_of[sent[i].first] = i;
+      for (size_t qi = 0; qi < nq; qi++) {
+        if (qkeys[qi] == ~0ull || res->q[qi].r.verdict == SCUBA_SAT) continue;
+        uint32_t s = uint32_t(qkeys[qi] >> 38);
+        uint64_t a = qkeys[qi] & ((uint64_t(1) << 38) - 1);
+        // locate the cube with that sequence number among this round's leaves
+        const Cube* cube = nullptr;
+        for (size_t i = first_of[qi]; i < sent.size() && sent[i].first == qi; i++) {
+          uint32_t si = rh.cubes[i].seq;
+          if (si == s) { cube = &sent[i].second; break; }
+        }
+        if (!cube) fail(SCUBA_E_INTERNAL, "witness from an unknown cube");
+        auto& rq = res->q[qi];
+        rq.r.verdict = SCUBA_SAT;
+        rq.r.how = SCUBA_HOW_DEVICE;
+        open[qi] = 0;
+        assemble_witness(cnf->q[qi], cube->lits, a, rq);
+      }
+      verify_ms += ms_since(tv);
+    }
+    for (size_t qi = 0; qi < nq; qi++)
+      if (open[qi]) {  // round limit reached
+        res->q[qi].r.verdict = SCUBA_UNKNOWN;
+        res->q[qi].r.how = SCUBA_HOW_BUDGET;
+      }
+    res->ms[0] = split_ms;
+    res->ms[1] = rt.h2d_ms;
+    res->ms[2] = rt.up_ms + rt.leaf_ms;
+    res->ms[3] = rt.d2h_ms;
+    res->ms[4] = verify_ms;
+    res->ms[5] = ms_since(t0);
+    res->ms[6] = rt.up_ms;
+    res->ms[7] = rt.leaf_ms;
+    *out = res.release();
+  });
+}
+
+// ---------------------------------------------------------------- results
+
+scuba_status scuba_result_get(const scuba_results* r, uint32_t qi, scuba_query_result* out) {
+  if (!r || !out || qi >= r->q.size()) return SCUBA_E_INVALID;
+  *out = r->q[qi].r;
+  return SCUBA_OK;
+}
+
+scuba_status scuba_witness_get(const scuba_results* r, uint32_t qi, uint64_t* values, uint32_t n) {
+  if (!r || qi >= r->q.size()) return SCUBA_E_INVALID;
+  const auto& q = r->q[qi];
+  if (q.r.verdict != SCUBA_SAT) return SCUBA_E_STATE;
+  if (n < q.witness.size() || (!q.witness.empty() && !values)) return SCUBA_E_CAPACITY;
+  std::copy(q.witness.begin(), q.witness.end(), values);
+  return SCUBA_OK;
+}
+
+scuba_status scuba_model_get(const scuba_results* r, uint32_t qi, uint8_t* bits, uint32_t n) {
+  if (!r || qi >= r->q.size()) return SCUBA_E_INVALID;
+  const auto& q = r->q[qi];
+  if (q.r.verdict != SCUBA_SAT) return SCUBA_E_STATE;
+  if (n < q.model.size() || !bits) return SCUBA_E_CAPACITY;
+  std::copy(q.model.begin(), q.model.end(), bits);
+  return SCUBA_OK;
+}
+
+scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube, scuba_leaf_result* out) {
+  if (!r || !out || qi >= r->q.size()) return SCUBA_E_INVALID;
+  if (cube >= r->q[qi].leaves.size()) return SCUBA_E_STATE;
+  *out = r->q[qi].leaves[cube];
+  return SCUBA_OK;
+}
+
+scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n) {
+  if (!r || !ms || n > 8) return SCUBA_E_INVALID;
+  std::copy(r->ms, r->ms + n, ms);
+  return SCUBA_OK;
+}
+
+void scuba_results_free(scuba_results* r) { delete r; }
+
+}  // extern "C"

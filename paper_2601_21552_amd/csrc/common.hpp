@@ -1,0 +1,50 @@
+// Shared host-side types of the library (not part of the C ABI).
+#pragma once
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/scuba.h"
+
+namespace scuba {
+
+struct Error : std::runtime_error {
+  scuba_status code;
+  Error(scuba_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(scuba_status c, const std::string& m) { throw Error(c, m); }
+
+// One query's CNF plus what the result stage needs to decode witnesses.
+struct CnfQuery {
+  uint32_t n_vars = 0;
+  std::vector<uint64_t> off{0};      // clause offsets into lits
+  std::vector<int32_t> lits;
+  std::vector<uint32_t> in_first;    // declared inputs: first CNF variable
+  std::vector<uint32_t> in_width;    //                  width in bits
+  bool root_unsat = false;
+  // original query, kept for the exact integer witness check
+  bool has_query = false;
+  std::vector<scuba_node> nodes;
+  std::vector<uint32_t> roots;
+
+  uint64_t n_clauses() const { return off.size() - 1; }
+};
+
+// Limits shared by host and device code paths.
+constexpr uint32_t kMaxLeafVars = 38;       // f <= 38: high slots fit 26 bits
+constexpr uint32_t kDefaultMaxResidual = 2048;
+
+// Builds the CNF of one query (normalisation + Tseitin).
+CnfQuery bitblast_query(const scuba_node* nodes, uint64_t n_nodes, const uint32_t* roots,
+                        uint64_t n_roots, uint32_t flags);
+
+// Exact integer check of a witness against the original query.
+bool int_check_query(const CnfQuery& q, const std::vector<uint64_t>& values);
+
+}  // namespace scuba
+
+struct scuba_cnf {
+  std::vector<scuba::CnfQuery> q;
+};

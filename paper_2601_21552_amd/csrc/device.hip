@@ -1,0 +1,521 @@
+// Device side for gfx950 (CDNA4, wave64): batched unit propagation and the
+// bit-sliced exhaustive leaf evaluator.
+//
+// Unit propagation kernel: one workgroup per cube (persistent: workgroups
+// pull cube indices from a counter).  The assignment lives in LDS as two
+// bitmaps (variable true / variable false).  Each round every lane scans a
+// slice of the query's clauses; a clause with one open literal sets it with
+// an atomic OR (a variable set both ways is a conflict); rounds repeat until
+// nothing changes.  The fixpoint is unique, so the order does not matter.
+// Then the active variables (unassigned and in an unsatisfied clause) get
+// slots 0..f-1 in increasing variable order and every unsatisfied clause is
+// compiled, in clause order, into a 16-byte record:
+//   x,y : 64-bit word, OR of the literal patterns of slots 0..5
+//   z   : bits 0..25 positive literals of slots 12..37, bits 26..31 of 6..11
+//   w   : the same for negative literals
+//
+// Leaf kernel: assignment index a = 4096*block + 64*lane + bit.  Slot j < 6
+// is bit j of `bit` (a constant 64-bit pattern), slot 6..11 is bit j-6 of
+// the lane id, slot >= 12 is bit j-12 of the block (the same for the whole
+// wave).  A wave evaluates one block (64 lanes x 64 bits) per step: a clause
+// satisfied by a block-level literal is skipped with a scalar test; else a
+// lane whose lane-level literals satisfy it keeps its word, other lanes AND
+// the clause's pattern word in.  A block dies when every lane's word is 0.
+// DECIDE takes the smallest (cube, index) witness per query with atomicMin
+// and lets later work of that query stop early; COUNT sums popcounts.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace scuba {
+
+#define HIP_OK(x)                                                                       \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess) fail(SCUBA_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 waves)
+constexpr uint32_t kHighMask = (1u << 26) - 1;
+
+__device__ __forceinline__ uint64_t slot_pattern(uint32_t j) {
+  switch (j) {
+    case 0: return 0xAAAAAAAAAAAAAAAAull;
+    case 1: return 0xCCCCCCCCCCCCCCCCull;
+    case 2: return 0xF0F0F0F0F0F0F0F0ull;
+    case 3: return 0xFF00FF00FF00FF00ull;
+    case 4: return 0xFFFF0000FFFF0000ull;
+    default: return 0xFFFFFFFF00000000ull;
+  }
+}
+
+// wave-uniform copy of a 32-bit value (the builtin returns a signed int:
+// widen through uint32_t so that 64-bit values are zero-extended)
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) {
+  return uint32_t(__builtin_amdgcn_readfirstlane(int(x)));
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  return (uint64_t(uniform_u32(uint32_t(x >> 32))) << 32) | uniform_u32(uint32_t(x));
+}
+
+// exclusive scan of one value per thread over the workgroup
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) s_wave[wave] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (uint32_t w = 0; w < kBlock / 64; w++) {
+    if (w < wave) base += s_wave[w];
+    tot += s_wave[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+__device__ __forceinline__ bool clause_satisfied(const int32_t* L, uint32_t b, uint32_t e,
+                                                 const uint32_t* T, const uint32_t* F) {
+  for (uint32_t i = b; i < e; i++) {
+    int32_t l = L[i];
+    uint32_t v = uint32_t(l > 0 ? l : -l);
+    uint32_t bit = 1u << (v & 31);
+    if ((l > 0 ? T[v >> 5] : F[v >> 5]) & bit) return true;
+  }
+  return false;
+}
+
+__global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restrict__ qd,
+                                                   const uint32_t* __restrict__ coff,
+                                                   const int32_t* __restrict__ lits,
+                                                   const DevCubeDesc* __restrict__ cubes,
+                                                   const int32_t* __restrict__ cube_lits,
+                                                   uint32_t n_cubes, DevCubeOut* __restrict__ out,
+                                                   uint4* __restrict__ res, uint32_t* head,
+                                                   uint32_t nw_max) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* T = smem;
+  uint32_t* F = T + nw_max;
+  uint32_t* A = F + nw_max;
+  uint32_t* P = A + nw_max;
+  __shared__ uint32_t s_item, s_conflict, s_flags[3], s_wave[kBlock / 64];
+  __shared__ uint32_t s_error;
+  const uint32_t tid = threadIdx.x;
+
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(head, 1u);
+    __syncthreads();
+    const uint32_t ci = s_item;
+    __syncthreads();
+    if (ci >= n_cubes) break;
+
+    const DevCubeDesc cd = cubes[ci];
+    const DevQueryDesc q = qd[cd.qid];
+    const uint32_t nv = q.n_vars, nc = q.n_clauses;
+    const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
+    const uint32_t* co = coff + q.coff_base;
+    const int32_t* L = lits + q.lit_base;
+
+    for (uint32_t w = tid; w < nw; w += kBlock) { T[w] = 0; F[w] = 0; A[w] = 0; }
+    if (tid == 0) { s_conflict = 0; s_error = 0; s_flags[0] = 0; s_flags[1] = 0; s_flags[2] = 0; }
+    __syncthreads();
+    for (uint32_t j = tid; j < cd.n_lits; j += kBlock) {
+      int32_t l = cube_lits[cd.lit_off + j];
+      uint32_t v = uint32_t(l > 0 ? l : -l);
+      if (v == 0 || v > nv) { s_error = 1; continue; }
+      atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], 1u << (v & 31));
+    }
+    __syncthreads();
+
+    // ---- propagation rounds; at most 2*(nv+1) rounds change something
+    const uint32_t max_rounds = 2 * nv + 4;
+    for (uint32_t r = 0;; r++) {
+      if (tid == 0) s_flags[(r + 1) % 3] = 0;
+      for (uint32_t w = tid; w < nw; w += kBlock)
+        if (T[w] & F[w]) s_conflict = 1;
+      for (uint32_t c = tid; c < nc; c += kBlock) {
+        const uint32_t b = co[c], e = co[c + 1];
+        bool sat = false;
+        uint32_t open = 0;
+        int32_t last = 0;
+        for (uint32_t i = b; i < e; i++) {
+          int32_t l = L[i];
+          uint32_t v = uint32_t(l > 0 ? l : -l);
+          uint32_t bit = 1u << (v & 31);
+          uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
+          if (l > 0 ? t : f) { sat = true; break; }
+          if (!(t | f)) { open++; last = l; }
+        }
+        if (sat) continue;
+        if (open == 0) {
+          s_conflict = 1;
+        } else if (open == 1) {
+          uint32_t v = uint32_t(last > 0 ? last : -last);
+          uint32_t bit = 1u << (v & 31);
+          uint32_t old = atomicOr(last > 0 ? &T[v >> 5] : &F[v >> 5], bit);
+          if (!(old & bit)) s_flags[r % 3] = 1;
+        }
+      }
+      __syncthreads();
+      const uint32_t changed = s_flags[r % 3], conflict = s_conflict;
+      __syncthreads();   // every thread has read the flags of this round
+      if (conflict || !changed) break;
+      if (r >= max_rounds) {   // cannot happen: every changing round sets a new bit
+        if (tid == 0) s_error = 1;
+        break;
+      }
+    }
+    __syncthreads();
+    for (uint32_t w = tid; w < nw; w += kBlock)
+      if (T[w] & F[w]) s_conflict = 1;
+    __syncthreads();
+    if (s_conflict || s_error) {
+      if (tid == 0) {
+        out[ci].status = s_error ? 2 : 1;
+        out[ci].f = out[ci].m = out[ci].nres = 0;
+      }
+      __syncthreads();
+      continue;
+    }
+
+    // ---- active variables
+    for (uint32_t c = tid; c < nc; c += kBlock) {
+      const uint32_t b = co[c], e = co[c + 1];
+      if (clause_satisfied(L, b, e, T, F)) continue;
+      for (uint32_t i = b; i < e; i++) {
+        int32_t l = L[i];
+        uint32_t v = uint32_t(l > 0 ? l : -l);
+        uint32_t bit = 1u << (v & 31);
+        if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
+      }
+    }
+    __syncthreads();
+
+    // ---- slot prefix per bitmap word (contiguous words per thread)
+    const uint32_t wpt = (nw + kBlock - 1) / kBlock;
+    const uint32_t w0 = tid * wpt, w1 = min(nw, w0 + wpt);
+    uint32_t my_act = 0, my_free = 0;
+    for (uint32_t w = w0; w < w1; w++) {
+      uint32_t valid = 0xFFFFFFFFu;
+      if (w == 0) valid &= ~1u;                      // no variable 0
+      if (w == (nv >> 5)) valid &= (nv & 31) == 31 ? 0xFFFFFFFFu : ((2u << (nv & 31)) - 1);
+      my_act += __popc(A[w]);
+      my_free += __popc(~(T[w] | F[w]) & valid);
+    }
+    uint32_t f_total, free_total;
+    uint32_t base = block_exclusive_scan(my_act, s_wave, &f_total);
+    block_exclusive_scan(my_free, s_wave, &free_total);
+    for (uint32_t w = w0; w < w1; w++) { P[w] = base; base += __popc(A[w]); }
+    __syncthreads();
+
+    const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
+
+    // ---- residual records, in clause order (contiguous clauses per thread)
+    const uint32_t cpt = (nc + kBlock - 1) / kBlock;
+    const uint32_t c0 = tid * cpt, c1 = min(nc, c0 + cpt);
+    uint32_t my_unsat = 0;
+    for (uint32_t c = c0; c < c1; c++)
+      if (!clause_satisfied(L, co[c], co[c + 1], T, F)) my_unsat++;
+    uint32_t n_unsat;
+    uint32_t pos = block_exclusive_scan(my_unsat, s_wave, &n_unsat);
+    const bool cap_ok = n_unsat <= cd.nres_cap;
+    if (f_ok && cap_ok) {
+      for (uint32_t c = c0; c < c1; c++) {
+        const uint32_t b = co[c], e = co[c + 1];
+        if (clause_satisfied(L, b, e, T, F)) continue;
+        uint64_t low = 0;
+        uint32_t hp = 0, hn = 0, mp = 0, mn = 0;
+        for (uint32_t i = b; i < e; i++) {
+          int32_t l = L[i];
+          uint32_t v = uint32_t(l > 0 ? l : -l);
+          uint32_t bit = 1u << (v & 31);
+          if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
+          uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
+          bool neg = l < 0;
+          if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
+          else if (slot < 12) (neg ? mn : mp) |= 1u << (slot - 6);
+          else (neg ? hn : hp) |= 1u << (slot - 12);
+        }
+        res[cd.res_base + pos] = make_uint4(uint32_t(low), uint32_t(low >> 32), hp | (mp << 26),
+                                            hn | (mn << 26));
+        pos++;
+      }
+    }
+    if (tid == 0) {
+      out[ci].status = !f_ok ? 2 : (!cap_ok ? 3 : 0);
+      out[ci].f = int32_t(f_total);
+      out[ci].m = int32_t(free_total - f_total);
+      out[ci].nres = int32_t(n_unsat);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict__ items,
+                                                     uint32_t n_items,
+                                                     const DevCubeDesc* __restrict__ cubes,
+                                                     DevCubeOut* __restrict__ out,
+                                                     const uint4* __restrict__ res,
+                                                     unsigned long long* __restrict__ qkey,
+                                                     uint32_t* head, uint32_t mode) {
+  extern __shared__ uint4 tile[];
+  __shared__ uint32_t s_item, s_skip;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr uint32_t kWaves = kBlock / 64;
+
+  for (;;) {
+    // thread 0 takes the next item and decides for the whole workgroup
+    // whether it is still useful (device-refuted leaf, or a witness of the
+    // query that precedes every assignment of the item)
+    if (tid == 0) {
+      const uint32_t i = atomicAdd(head + 1, 1u);
+      uint32_t skip = 0;
+      if (i < n_items) {
+        const DevItem it0 = items[i];
+        if (out[it0.cube].status != 0) skip = 1;
+        else if (mode == SCUBA_MODE_DECIDE) {
+          const DevCubeDesc c0 = cubes[it0.cube];
+          const uint64_t k = __hip_atomic_load(&qkey[c0.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (k <= (uint64_t(c0.seq) << 38) + (uint64_t(it0.it_lo) << 12)) skip = 1;
+        }
+      }
+      s_item = i;
+      s_skip = skip;
+    }
+    __syncthreads();
+    const uint32_t item = s_item, skip_item = s_skip;
+    __syncthreads();
+    if (item >= n_items) break;
+    if (skip_item) continue;
+
+    const DevItem it = items[item];
+    const DevCubeDesc cd = cubes[it.cube];
+    const uint32_t f = uint32_t(out[it.cube].f);
+    const uint32_t nres = uint32_t(out[it.cube].nres);
+    const uint64_t key_base = uint64_t(cd.seq) << 38;
+
+    for (uint32_t j = tid; j < nres; j += kBlock) tile[j] = res[cd.res_base + j];
+    __syncthreads();
+
+    uint64_t valid;
+    if (f >= 12) valid = ~0ull;
+    else if (f >= 6) valid = lane < (1u << (f - 6)) ? ~0ull : 0ull;
+    else valid = lane == 0 ? ((2ull << ((1u << f) - 1)) - 1) : 0ull;
+
+    uint64_t count = 0, blocks = 0, evals = 0, first = ~0ull;
+    uint32_t steps = 0;
+    for (uint32_t blk = it.it_lo + wave; blk < it.it_hi; blk += kWaves) {
+      if (mode == SCUBA_MODE_DECIDE && (steps++ & 7) == 0) {
+        const uint64_t k = uniform_u64(
+            __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (k <= key_base + (uint64_t(blk) << 12)) break;
+      }
+      const uint32_t H = blk;
+      uint64_t acc = valid;
+      uint32_t done = 0;
+      for (uint32_t c = 0; c < nres; c++) {
+        const uint4 r = tile[c];
+        const uint32_t z = uniform_u32(r.z);
+        const uint32_t w = uniform_u32(r.w);
+        if (((H & z) | (~H & w)) & kHighMask) continue;
+        const uint32_t mn = w >> 26, mm = (z >> 26) | mn;
+        const uint64_t low = (uint64_t(uniform_u32(r.y)) << 32) | uniform_u32(r.x);
+        acc &= ((lane ^ mn) & mm) ? ~0ull : low;
+        done++;
+        if ((done & 3) == 0 && !__any(acc != 0)) break;
+      }
+      blocks++;
+      evals += done;
+      if (mode == SCUBA_MODE_COUNT) count += __popcll(acc);
+      const uint64_t hit = __ballot(acc != 0);
+      if (hit) {
+        const uint32_t fl = __builtin_ctzll(hit);
+        const uint64_t acc_fl = __shfl(acc, int(fl), 64);
+        const uint64_t a = (uint64_t(blk) << 12) | (uint64_t(fl) << 6) | uint64_t(__builtin_ctzll(acc_fl));
+        if (lane == 0) {
+          if (a < first) first = a;
+          if (mode == SCUBA_MODE_DECIDE) atomicMin(&qkey[cd.qid], (unsigned long long)(key_base | a));
+        }
+        if (mode == SCUBA_MODE_DECIDE) break;
+      }
+    }
+    // wave totals
+    for (uint32_t d = 32; d >= 1; d >>= 1) count += __shfl_xor(count, int(d), 64);
+    if (lane == 0) {
+      if (mode == SCUBA_MODE_COUNT && count) atomicAdd((unsigned long long*)&out[it.cube].count, (unsigned long long)count);
+      if (first != ~0ull) atomicMin((unsigned long long*)&out[it.cube].first, (unsigned long long)first);
+      atomicAdd((unsigned long long*)&out[it.cube].blocks, (unsigned long long)blocks);
+      atomicAdd((unsigned long long*)&out[it.cube].clause_blocks, (unsigned long long)evals);
+    }
+    __syncthreads();
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct CnfLayout {
+  size_t q, coff, lits, qkey, end;
+};
+CnfLayout cnf_layout(const CnfHost& c) {
+  CnfLayout l;
+  l.q = 0;
+  l.coff = align256(l.q + c.q.size() * sizeof(DevQueryDesc));
+  l.lits = align256(l.coff + c.coff.size() * 4);
+  l.qkey = align256(l.lits + c.lits.size() * 4);
+  l.end = align256(l.qkey + c.q.size() * 8);
+  return l;
+}
+struct RoundLayout {
+  size_t head, cubes, lits, items, outs, res, end;
+};
+RoundLayout round_layout(size_t base, size_t n_cubes, size_t n_lits, size_t n_items, uint64_t nres) {
+  RoundLayout l;
+  l.head = base;
+  l.cubes = align256(l.head + 256);
+  l.lits = align256(l.cubes + n_cubes * sizeof(DevCubeDesc));
+  l.items = align256(l.lits + n_lits * 4);
+  l.outs = align256(l.items + n_items * sizeof(DevItem));
+  l.res = align256(l.outs + n_cubes * sizeof(DevCubeOut));
+  l.end = align256(l.res + size_t(nres) * 16);
+  return l;
+}
+
+}  // namespace
+
+void dev_init(DeviceInfo* info, int device) {
+  int n = 0;
+  HIP_OK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) fail(SCUBA_E_DEVICE, "no such HIP device");
+  HIP_OK(hipSetDevice(device));
+  hipDeviceProp_t p;
+  HIP_OK(hipGetDeviceProperties(&p, device));
+  info->device = device;
+  info->cus = p.multiProcessorCount;
+  info->max_lds = p.sharedMemPerBlock;
+}
+
+void* dev_pinned(size_t bytes) {
+  void* p = nullptr;
+  HIP_OK(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+  return p;
+}
+void dev_pinned_free(void* p) {
+  if (p) (void)hipHostFree(p);
+}
+
+size_t dev_cnf_bytes(const CnfHost& cnf) { return cnf_layout(cnf).end; }
+size_t dev_round_bytes(size_t n_cubes, size_t n_cube_lits, size_t n_items, uint64_t res_records) {
+  return round_layout(0, n_cubes, n_cube_lits, n_items, res_records).end;
+}
+
+void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, void* stream,
+                    void* staging, size_t staging_bytes) {
+  HIP_OK(hipSetDevice(info.device));
+  CnfLayout l = cnf_layout(cnf);
+  if (l.end > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
+  if (l.end > staging_bytes) fail(SCUBA_E_INTERNAL, "staging too small");
+  char* s = static_cast<char*>(staging);
+  std::memcpy(s + l.q, cnf.q.data(), cnf.q.size() * sizeof(DevQueryDesc));
+  std::memcpy(s + l.coff, cnf.coff.data(), cnf.coff.size() * 4);
+  std::memcpy(s + l.lits, cnf.lits.data(), cnf.lits.size() * 4);
+  std::memset(s + l.qkey, 0xFF, cnf.q.size() * 8);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_OK(hipMemcpyAsync(ws, s, l.end, hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+}
+
+void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
+               uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
+               std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys, RoundTimes* times) {
+  HIP_OK(hipSetDevice(info.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CnfLayout cl = cnf_layout(cnf);
+  const size_t nc = rh.cubes.size(), ni = rh.items.size();
+  RoundLayout rl = round_layout(cl.end, nc, rh.cube_lits.size(), ni, rh.res_records);
+  if (rl.end > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for this round");
+  const size_t up_bytes = rl.res - rl.head;
+  if (up_bytes > staging_bytes || align256(nc * sizeof(DevCubeOut)) + cnf.q.size() * 8 > staging_bytes)
+    fail(SCUBA_E_INTERNAL, "staging too small");
+  // host-side checks of what the kernels assume
+  const size_t up_lds = size_t(rh.nw_max) * 4 * 4;
+  const size_t leaf_lds = size_t(std::max<uint32_t>(rh.tile_max, 1)) * 16;
+  if (up_lds + 1024 > info.max_lds) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
+  if (leaf_lds + 64 > info.max_lds) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");
+  for (const DevCubeDesc& c : rh.cubes) {
+    if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + c.n_lits > rh.cube_lits.size() ||
+        c.res_base + c.nres_cap > rh.res_records || c.nres_cap > rh.tile_max ||
+        (cnf.q[c.qid].n_vars >> 5) + 1 > rh.nw_max)
+      fail(SCUBA_E_INTERNAL, "cube descriptor out of range");
+  }
+  for (const DevItem& it : rh.items)
+    if (it.cube >= nc || it.it_lo >= it.it_hi) fail(SCUBA_E_INTERNAL, "work item out of range");
+
+  char* s = static_cast<char*>(staging);
+  const size_t b = rl.head;
+  std::memset(s + (rl.head - b), 0, 256);
+  std::memcpy(s + (rl.cubes - b), rh.cubes.data(), nc * sizeof(DevCubeDesc));
+  std::memcpy(s + (rl.lits - b), rh.cube_lits.data(), rh.cube_lits.size() * 4);
+  std::memcpy(s + (rl.items - b), rh.items.data(), ni * sizeof(DevItem));
+  DevCubeOut init{};
+  init.first = ~0ull;
+  for (size_t i = 0; i < nc; i++) std::memcpy(s + (rl.outs - b) + i * sizeof(DevCubeOut), &init, sizeof(init));
+
+  char* w = static_cast<char*>(ws);
+  hipEvent_t ev[6];
+  for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+  HIP_OK(hipEventRecord(ev[0], st));
+  HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(ev[1], st));
+  const uint32_t g = grid ? grid : uint32_t(info.cus) * 8;
+  if (nc) {
+    uint32_t gu = std::min<uint32_t>(g, uint32_t(nc));
+    hipLaunchKernelGGL(up_kernel, dim3(gu), dim3(kBlock), up_lds, st,
+                       reinterpret_cast<const DevQueryDesc*>(w + cl.q),
+                       reinterpret_cast<const uint32_t*>(w + cl.coff),
+                       reinterpret_cast<const int32_t*>(w + cl.lits),
+                       reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
+                       reinterpret_cast<const int32_t*>(w + rl.lits), uint32_t(nc),
+                       reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
+                       reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
+    HIP_OK(hipGetLastError());
+  }
+  HIP_OK(hipEventRecord(ev[2], st));
+  if (ni) {
+    uint32_t gl = std::min<uint32_t>(g, uint32_t(ni));
+    hipLaunchKernelGGL(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, st,
+                       reinterpret_cast<const DevItem*>(w + rl.items), uint32_t(ni),
+                       reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
+                       reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
+                       reinterpret_cast<unsigned long long*>(w + cl.qkey),
+                       reinterpret_cast<uint32_t*>(w + rl.head), mode);
+    HIP_OK(hipGetLastError());
+  }
+  HIP_OK(hipEventRecord(ev[3], st));
+  HIP_OK(hipMemcpyAsync(s, w + rl.outs, nc * sizeof(DevCubeOut), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(s + align256(nc * sizeof(DevCubeOut)), w + cl.qkey, cnf.q.size() * 8,
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipEventRecord(ev[4], st));
+  HIP_OK(hipStreamSynchronize(st));
+  outs->resize(nc);
+  std::memcpy(outs->data(), s, nc * sizeof(DevCubeOut));
+  qkeys->resize(cnf.q.size());
+  std::memcpy(qkeys->data(), s + align256(nc * sizeof(DevCubeOut)), cnf.q.size() * 8);
+  float ms;
+  HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1])); times->h2d_ms += ms;
+  HIP_OK(hipEventElapsedTime(&ms, ev[1], ev[2])); times->up_ms += ms;
+  HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->leaf_ms += ms;
+  HIP_OK(hipEventElapsedTime(&ms, ev[3], ev[4])); times->d2h_ms += ms;
+  for (auto& e : ev) (void)hipEventDestroy(e);
+}
+
+}  // namespace scuba

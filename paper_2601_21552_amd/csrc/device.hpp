@@ -1,0 +1,90 @@
+// Plain C++ interface between the host library and the HIP code.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+namespace scuba {
+
+// One query's CNF on the device.
+struct DevQueryDesc {
+  uint64_t coff_base;   // index into the clause-offset array (u32, relative)
+  uint64_t lit_base;    // index into the literal array
+  uint32_t n_clauses;
+  uint32_t n_vars;
+};
+
+// One cube to evaluate.
+struct DevCubeDesc {
+  uint32_t qid;
+  uint32_t lit_off;     // into the round's cube literal array
+  uint32_t n_lits;
+  uint32_t seq;         // position of the cube in its query's cube order
+  int32_t f_expect;     // host propagation's active count (-1: unknown)
+  uint32_t nres_cap;    // residual records reserved for this cube
+  uint64_t res_base;    // first residual record
+};
+
+// Per-cube device results.
+struct DevCubeOut {
+  int32_t status;       // 0 ok, 1 refuted, 2 host/device mismatch, 3 capacity
+  int32_t f, m, nres;
+  uint64_t count;       // satisfying assignments (COUNT mode)
+  uint64_t first;       // smallest satisfying index (~0: none found)
+  uint64_t blocks;      // 4096-assignment blocks evaluated
+  uint64_t clause_blocks;  // clause x block evaluations on the VALU
+};
+
+// A slice of one leaf: blocks [it_lo, it_hi) of 4096 assignments.
+struct DevItem {
+  uint32_t cube, it_lo, it_hi, pad;
+};
+
+struct RoundTimes {
+  double up_ms = 0, leaf_ms = 0, h2d_ms = 0, d2h_ms = 0;
+};
+
+// Device context: a device id, its CU count and events.
+struct DeviceInfo {
+  int device = 0;
+  int cus = 256;
+  size_t max_lds = 65536;
+};
+
+// Host staging for one launch pair; the layout inside the workspace is
+// computed by the device code.
+struct RoundHost {
+  std::vector<DevCubeDesc> cubes;
+  std::vector<int32_t> cube_lits;
+  std::vector<DevItem> items;
+  uint64_t res_records = 0;   // residual records to reserve
+  uint32_t tile_max = 0;      // largest residual of a cube
+  uint32_t nw_max = 0;        // largest bitmap (32-bit words) of a query
+};
+
+struct CnfHost {
+  std::vector<DevQueryDesc> q;
+  std::vector<uint32_t> coff;
+  std::vector<int32_t> lits;
+};
+
+void dev_init(DeviceInfo* info, int device);
+void* dev_pinned(size_t bytes);          // pinned host memory (or throws)
+void dev_pinned_free(void* p);
+
+// Workspace layout.  The CNF region persists across rounds of one call.
+size_t dev_cnf_bytes(const CnfHost& cnf);
+size_t dev_round_bytes(size_t n_cubes, size_t n_cube_lits, size_t n_items, uint64_t res_records);
+
+// Upload the CNF and reset the per-query witness keys (stream-ordered).
+void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
+                    void* stream, void* staging, size_t staging_bytes);
+
+// Run one round: upload, unit propagation kernel, leaf kernel, download.
+// outs (n_cubes) and qkeys (nq) are filled; the stream is synchronised.
+void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
+               const RoundHost& round, uint32_t mode, uint32_t grid, void* stream, void* staging,
+               size_t staging_bytes, std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys,
+               RoundTimes* times);
+
+}  // namespace scuba

@@ -1,0 +1,172 @@
+"""Parity of the GPU path (C ABI -> gfx950 kernels) with the CPU oracle.
+
+* COUNT mode: for every cube, the device's (refuted, f, m, count of
+  satisfying assignments of the active variables, smallest satisfying
+  index) equals the oracle's canonical leaf, bit for bit; over a complete
+  cube set the counts add up to the oracle's #DPLL model count.
+* DECIDE mode: verdicts equal the oracle's (and the generators' labels);
+  every SAT witness satisfies the original query under exact integers.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnf_ref, query_ref
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2601_21552_amd import api
+    return api.Context(0)
+
+
+def _raw(ctx, cnfs):
+    return ctx.cnf_from_arrays(*w.concat(cnfs))
+
+
+def _check_leaves(cnfs, cubes_per_query, out, complete=True):
+    for qi, (f, cubes) in enumerate(zip(cnfs, cubes_per_query)):
+        total = 0
+        for c, cube in enumerate(cubes):
+            lf = out.leaf(qi, c)
+            ref = cnf_ref.leaf(f, cube)
+            assert lf["refuted"] == ref["refuted"], (f.name, c, cube, lf, ref)
+            if ref["refuted"]:
+                continue
+            got = (lf["f"], lf["m"], lf["count"], lf["first"])
+            want = (ref["f"], ref["m"], ref["count"], ref["first"])
+            assert got == want, (f.name, c, cube, got, want)
+            total += lf["count"] << lf["m"]
+        if complete:
+            assert total == cnf_ref.count(f), f.name
+
+
+def test_count_mode_split_cubes(ctx):
+    rng = np.random.Generator(np.random.PCG64(101))
+    cnfs = []
+    for n, ratio in ((24, 3.0), (30, 4.26), (40, 4.26), (48, 3.5), (36, 2.0), (60, 4.26)):
+        cnfs.append(w.random_ksat(n, int(round(ratio * n)), 3, rng))
+    raw = _raw(ctx, cnfs)
+    for k in (8, 14, 20):
+        cubes = ctx.split(raw, k=k)
+        out = ctx.solve(raw, cubes, mode=1)
+        per_q = [cubes.view(i)["cubes"] for i in range(len(cnfs))]
+        for i in range(len(cnfs)):
+            assert cubes.view(i)["complete"]
+        _check_leaves(cnfs, per_q, out)
+
+
+def test_count_mode_oracle_cubes(ctx):
+    """Cubes drawn on the test side (random partial assignments, some of
+    them clashing), not by the library's splitter."""
+    rng = np.random.Generator(np.random.PCG64(102))
+    cnfs, cubes = [], []
+    for n in (16, 20, 26, 33):
+        f = w.random_ksat(n, int(round(3.8 * n)), 3, rng)
+        cnfs.append(f)
+        qc = [[]]
+        for _ in range(12):
+            size = int(rng.integers(0, n // 2))
+            vs = rng.choice(n, size=size, replace=False) + 1
+            qc.append([int(v) if rng.integers(2) else -int(v) for v in vs])
+        v = int(rng.integers(1, n + 1))
+        qc.append([v, -v])                       # a clashing cube
+        cubes.append(qc)
+    raw = _raw(ctx, cnfs)
+    cb = ctx.cubes_from_arrays(raw, cubes)
+    out = ctx.solve(raw, cb, mode=1)
+    _check_leaves(cnfs, cubes, out, complete=False)
+
+
+@pytest.mark.parametrize("pigeons,holes,want", [(3, 3, 6), (4, 4, 24), (5, 5, 120),
+                                                (5, 4, 0), (6, 5, 0)])
+def test_pigeonhole_single_leaf(ctx, pigeons, holes, want):
+    f = w.pigeonhole(pigeons, holes)
+    raw = _raw(ctx, [f])
+    cubes = ctx.cubes_from_arrays(raw, [[[]]])
+    out = ctx.solve(raw, cubes, mode=1)
+    lf = out.leaf(0, 0)
+    assert not lf["refuted"] and lf["f"] == pigeons * holes
+    assert lf["count"] << lf["m"] == want
+
+
+def test_degenerate_formulas(ctx):
+    cnfs = [w.CNF.from_clauses(3, []),                 # no clauses: SAT, 8 models
+            w.CNF.from_clauses(2, [[1], []]),          # empty clause: UNSAT
+            w.CNF.from_clauses(4, [[1], [-1, 2]]),     # decided by propagation
+            w.CNF.from_clauses(5, [[1, 2], [-1, -2]]),  # f = 2 < 6
+            w.CNF.from_clauses(9, [[1, 2, 3], [4, 5, 6], [7, 8, 9], [-1, -4, -7]])]  # 6 < f < 12
+    raw = _raw(ctx, cnfs)
+    cubes = ctx.split(raw, k=20)
+    out = ctx.solve(raw, cubes, mode=1)
+    per_q = [cubes.view(i)["cubes"] for i in range(len(cnfs))]
+    _check_leaves(cnfs, per_q, out)
+    dec = ctx.decide(raw, k=20)
+    assert dec.verdicts() == ["SAT", "UNSAT", "SAT", "SAT", "SAT"]
+
+
+def test_product_cnf_counts_small_widths(ctx):
+    """Model counts of the library's own CNFs (split + COUNT leaves) equal
+    the number of satisfying input tuples by brute force."""
+    from tests.querygen import random_query
+    rng = np.random.Generator(np.random.PCG64(103))
+    qs = [random_query(rng, max_bits=10, name=f"r{i}") for i in range(40)]
+    qs += [w.oob_1d(3, g, scale=s, header=c) for g in ("lt", "le", "none")
+           for (s, c) in ((1, 0), (4, 3))]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs])
+    cubes = ctx.split(cnf, k=14)
+    out = ctx.solve(cnf, cubes, mode=1)
+    for i, q in enumerate(qs):
+        cv = cubes.view(i)
+        assert cv["complete"]
+        total = 0
+        for c in range(len(cv["cubes"])):
+            lf = out.leaf(i, c)
+            if not lf["refuted"]:
+                total += lf["count"] << lf["m"]
+        assert total == query_ref.int_bruteforce(q)[1], q.name
+
+
+def test_decide_config1(ctx):
+    gens = [w.config1("lt"), w.config1("none"), w.config1("le")]
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    res = ctx.decide(cnf, k=30)
+    for i, g in enumerate(gens):
+        r = res.result(i)
+        assert r["verdict"] == g.label
+        if g.label == "SAT":
+            assert r["witness_checked"]
+            assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
+
+
+def test_decide_config2_full(ctx):
+    gens = w.config2()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    res = ctx.decide(cnf, k=30)
+    for i, g in enumerate(gens):
+        r = res.result(i)
+        assert r["verdict"] == g.label, (g.query.name, r)
+        ov, _, _ = query_ref.decide(g.query)
+        assert ov == r["verdict"], g.query.name
+        if g.label == "SAT":
+            assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
+
+
+def test_decide_small_queries_brute_force(ctx):
+    from tests.querygen import random_query
+    rng = np.random.Generator(np.random.PCG64(104))
+    qs = [random_query(rng, max_bits=12, name=f"d{i}") for i in range(60)]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs])
+    for k in (6, 16):
+        res = ctx.decide(cnf, k=k, leaves_per_round=2)
+        for i, q in enumerate(qs):
+            want = query_ref.int_bruteforce(q)[0]
+            r = res.result(i)
+            assert r["verdict"] == want, (q.name, k, r)
+            if want == "SAT":
+                assert query_ref.int_eval(q, res.witness(i, q.n_vars))
