@@ -275,9 +275,10 @@ scuba_status scuba_model_get(const scuba_results* r, uint32_t qi, uint8_t* bits,
 /* Per-cube results of scuba_solve (cube order of the input list). */
 scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube,
                             scuba_leaf_result* out);
-/* Stage times in ms: [0] bitblast-free host split, [1] upload, [2] device
- * kernels (HIP events), [3] download, [4] verify, [5] total wall,
- * [6] UP kernel, [7] leaf kernel.  n <= 8.                                  */
+/* Stage times in ms: [0] host split, [1] upload, [2] device kernels (HIP
+ * events on the caller's stream), [3] download, [4] verify, [5] total wall,
+ * [6] propagation kernel, [7] leaf kernel; then launch counts: [8]
+ * propagation kernel, [9] leaf kernel.  n <= 10.                            */
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n);
 void scuba_results_free(scuba_results* r);
 

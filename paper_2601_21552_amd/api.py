@@ -104,9 +104,10 @@ class Results(_Handle):
         return dict(refuted=bool(r.refuted), f=r.f, m=r.m, count=int(r.count), first=int(r.first))
 
     def timing(self) -> dict:
-        ms = np.zeros(8, np.float64)
-        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 8))
-        keys = ["split", "h2d", "kernels", "d2h", "verify", "total", "up", "leaf"]
+        ms = np.zeros(10, np.float64)
+        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 10))
+        keys = ["split", "h2d", "kernels", "d2h", "verify", "total", "up", "leaf",
+                "up_launches", "leaf_launches"]
         return dict(zip(keys, ms.tolist()))
 
 

@@ -59,7 +59,7 @@ struct scuba_results {
     std::vector<scuba_leaf_result> leaves;
   };
   std::vector<Q> q;
-  double ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double ms[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -541,6 +541,8 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     res->ms[5] = ms_since(t0);
     res->ms[6] = rt.up_ms;
     res->ms[7] = rt.leaf_ms;
+    res->ms[8] = rt.up_launches;
+    res->ms[9] = rt.leaf_launches;
     *out = res.release();
   });
 }
@@ -659,6 +661,8 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
     res->ms[5] = ms_since(t0);
     res->ms[6] = rt.up_ms;
     res->ms[7] = rt.leaf_ms;
+    res->ms[8] = rt.up_launches;
+    res->ms[9] = rt.leaf_launches;
     *out = res.release();
   });
 }
@@ -697,7 +701,7 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube, 
 }
 
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n) {
-  if (!r || !ms || n > 8) return SCUBA_E_INVALID;
+  if (!r || !ms || n > 10) return SCUBA_E_INVALID;
   std::copy(r->ms, r->ms + n, ms);
   return SCUBA_OK;
 }

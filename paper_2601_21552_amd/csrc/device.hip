@@ -488,6 +488,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                        reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
                        reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
     HIP_OK(hipGetLastError());
+    times->up_launches++;
   }
   HIP_OK(hipEventRecord(ev[2], st));
   if (ni) {
@@ -499,6 +500,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                        reinterpret_cast<unsigned long long*>(w + cl.qkey),
                        reinterpret_cast<uint32_t*>(w + rl.head), mode);
     HIP_OK(hipGetLastError());
+    times->leaf_launches++;
   }
   HIP_OK(hipEventRecord(ev[3], st));
   HIP_OK(hipMemcpyAsync(s, w + rl.outs, nc * sizeof(DevCubeOut), hipMemcpyDeviceToHost, st));

@@ -42,6 +42,7 @@ struct DevItem {
 
 struct RoundTimes {
   double up_ms = 0, leaf_ms = 0, h2d_ms = 0, d2h_ms = 0;
+  uint32_t up_launches = 0, leaf_launches = 0;
 };
 
 // Device context: a device id, its CU count and events.

@@ -1,0 +1,169 @@
+"""Host-side checks of the library (no GPU): every declared entry point is
+exported, the CNF of every query has exactly one model per satisfying input
+tuple (against brute force), malformed input is rejected, and the cube
+splitter's trees are complete and disjoint with leaves matching the
+oracle's canonical leaves."""
+import re
+from fractions import Fraction
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+from oracle import cnf_ref, query_ref
+from tests.querygen import random_query
+import workloads as w
+from workloads import CNF, Query
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2601_21552_amd import _lib, api as api_mod
+    import os
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2601_21552_amd import build
+        build.build()
+    return api_mod
+
+
+@pytest.fixture(scope="module")
+def ctx(api):
+    return api.Context(0)
+
+
+def _cnf(view):
+    return CNF(view["n_vars"], view["clause_off"], view["lits"])
+
+
+def test_every_declared_symbol_is_exported(api):
+    import ctypes
+    from paper_2601_21552_amd import _lib
+    with open(_lib.os.path.join(_lib.HERE, "..", "include", "scuba.h")) as f:
+        header = f.read()
+    declared = set(re.findall(
+        r"^(?:scuba_status|void|const char\*|uint32_t)\s+(scuba_[a-z_0-9]+)\s*\(", header, re.M))
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert declared == set(_lib.SIGNATURES), declared ^ set(_lib.SIGNATURES)
+    assert _lib.load().scuba_abi_version() == 1
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_cnf_counts_equal_integer_solutions(ctx, flags):
+    rng = np.random.Generator(np.random.PCG64(201 + flags))
+    qs = [random_query(rng, max_bits=9, name=f"r{i}") for i in range(80)]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs], flags=flags)
+    for i, q in enumerate(qs):
+        v = cnf.view(i)
+        assert cnf_ref.count(_cnf(v)) == query_ref.int_bruteforce(q)[1], q.nodes
+
+
+def test_input_map_and_witness_decoding(ctx):
+    g = w.config1("none")
+    cnf = ctx.bitblast([g.query.arrays()[:2]])
+    first, width = cnf.input_map(0)
+    assert list(width) == [12, 12, 12, 12]
+    assert list(first) == [1, 13, 25, 37]          # inputs take the first variables
+    v = cnf.view(0)
+    verdict, model, _ = cnf_ref.solve(_cnf(v))
+    assert verdict == "SAT"
+    vals = [sum(int(model[f + b]) << b for b in range(wd)) for f, wd in zip(first, width)]
+    assert query_ref.int_eval(g.query, vals)
+
+
+def test_root_unsat_on_guarded_queries(ctx):
+    gens = w.config2()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    for i, g in enumerate(gens):
+        assert cnf.view(i)["root_unsat"] == (g.label == "UNSAT"), g.query.name
+    one = ctx.bitblast([w.config1("lt").query.arrays()[:2]]).view(0)
+    assert one["root_unsat"] and one["n_clauses"] == 1
+
+
+def _status(api, fn):
+    from paper_2601_21552_amd import _lib
+    with pytest.raises(_lib.ScubaError) as e:
+        fn()
+    return e.value.status
+
+
+def test_malformed_queries_are_rejected(api, ctx):
+    q = Query("wide")
+    q.var("x", 8)
+    nodes, roots, _ = q.arrays()
+    bad = nodes.copy()
+    bad["width"][0] = 65
+    assert _status(api, lambda: ctx.bitblast([(bad, np.array([0], np.uint32))])) == -2
+    q = Query("fwd")
+    x = q.var("x", 4)
+    q.require(x < 3)
+    nodes, roots, _ = q.arrays()
+    fwd = nodes.copy()
+    fwd["a"][-1] = len(fwd)                      # operand after the node
+    assert _status(api, lambda: ctx.bitblast([(fwd, roots)])) == -1
+    # an integer node as a root
+    assert _status(api, lambda: ctx.bitblast([(nodes, np.array([0], np.uint32))])) == -1
+    # division of a value that can be negative
+    q = Query("negdiv")
+    x, y = q.var("x", 3), q.var("y", 3)
+    q.require(((x - y) // 2) < 1)
+    assert _status(api, lambda: ctx.bitblast([q.arrays()[:2]])) == -1
+
+
+def test_raw_cnf_validation(api, ctx):
+    ok = ctx.cnf_from_arrays([3], [0, 2], [0, 2, 3], [1, -2, 3])
+    assert ok.view(0)["n_clauses"] == 2
+    rep = lambda: ctx.cnf_from_arrays([3], [0, 1], [0, 2], [1, -1])
+    assert _status(api, rep) == -1
+    rng = lambda: ctx.cnf_from_arrays([3], [0, 1], [0, 1], [4])
+    assert _status(api, rng) == -1
+
+
+def _kraft_and_disjoint(cubes):
+    total = sum(Fraction(1, 2 ** len(c)) for c in cubes)
+    assert total == 1
+    for a, b in combinations(cubes, 2):
+        sa = set(a)
+        assert any(-l in sa for l in b), (a, b)
+
+
+def test_split_trees_complete_disjoint_and_canonical(ctx):
+    rng = np.random.Generator(np.random.PCG64(202))
+    cnfs = [w.random_ksat(n, int(r * n), 3, rng) for n, r in ((14, 4.3), (18, 3.0), (22, 4.26))]
+    cnfs.append(w.pigeonhole(4, 3))
+    raw = ctx.cnf_from_arrays(*w.concat(cnfs))
+    for k in (3, 7, 12):
+        cubes = ctx.split(raw, k=k)
+        for i, f in enumerate(cnfs):
+            cv = cubes.view(i)
+            assert cv["complete"]
+            _kraft_and_disjoint(cv["cubes"])
+            total = 0
+            for c, cube in enumerate(cv["cubes"]):
+                ref = cnf_ref.leaf(f, cube)
+                if cv["kind"][c] == 1:
+                    assert ref["refuted"]
+                else:
+                    assert not ref["refuted"] and ref["f"] == cv["f"][c] <= k
+                    total += ref["count"] << ref["m"]
+            assert total == cnf_ref.count(f)
+
+
+def test_split_budget_marks_incomplete(ctx):
+    g = w.config1("none")
+    cnf = ctx.bitblast([g.query.arrays()[:2]])
+    cv = ctx.split(cnf, k=20, max_cubes=10).view(0)
+    assert not cv["complete"] and len(cv["cubes"]) == 10
+
+
+def test_decide_needs_a_device(api, ctx):
+    """Without a GPU the device entry points fail loudly (no CPU fallback)."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cnf = ctx.bitblast([w.config1("none").query.arrays()[:2]])
+    from paper_2601_21552_amd import _lib
+    with pytest.raises(Exception):
+        ctx.decide(cnf, k=30)
+    assert _lib.load() is not None
