@@ -8,6 +8,7 @@
 #include "bigint.hpp"
 #include "common.hpp"
 #include "device.hpp"
+#include "parallel.hpp"
 #include "split.hpp"
 
 using namespace scuba;
@@ -118,30 +119,43 @@ Opts resolve(const scuba_solve_opts* o) {
   return r;
 }
 
-CnfHost cnf_host(const scuba_cnf* cnf) {
+// Device image of the CNF batch.  A query whose CNF fits the LDS left over
+// by the propagation kernel's bitmaps (16-bit literals and offsets) is
+// marked for staging; lds_limit = 0 disables staging.
+CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
   CnfHost h;
+  uint32_t nw_all = 0;
+  for (const CnfQuery& q : cnf->q) nw_all = std::max(nw_all, (q.n_vars >> 5) + 1);
+  const size_t bitmaps = size_t(nw_all) * 16 + 2048;   // + static LDS
+  const size_t budget = lds_limit > bitmaps ? lds_limit - bitmaps : 0;
   for (const CnfQuery& q : cnf->q) {
-    DevQueryDesc d;
+    DevQueryDesc d{};
     d.coff_base = h.coff.size();
     d.lit_base = h.lits.size();
     if (q.n_clauses() >= (uint64_t(1) << 32) || q.lits.size() >= (uint64_t(1) << 32))
       fail(SCUBA_E_CAPACITY, "query with 2^32 or more clauses or literals");
     d.n_clauses = uint32_t(q.n_clauses());
     d.n_vars = q.n_vars;
+    const size_t bytes = ((q.n_clauses() + 1 + q.lits.size()) * 2 + 3) & ~size_t(3);
+    if (q.n_vars < 32768 && q.lits.size() < 65536 && bytes <= budget) {
+      d.staged = 1;
+      h.stage_bytes = std::max(h.stage_bytes, bytes);
+    }
     for (uint64_t o : q.off) h.coff.push_back(uint32_t(o));
     h.lits.insert(h.lits.end(), q.lits.begin(), q.lits.end());
     h.q.push_back(d);
   }
   return h;
 }
+// LDS the propagation kernel may use (64 KB: no launch attribute needed)
+size_t up_lds_limit(const scuba_ctx* ctx) { return std::min<size_t>(ctx->dev.max_lds, 65536); }
 
 uint64_t blocks_of(int32_t f) { return f >= 12 ? (uint64_t(1) << (f - 12)) : 1; }
 
 // Append one cube to a round; returns its index within the round.  A cube
 // the host refuted is sent too (its device refutation is checked) but gets
-// no leaf work.
-uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint32_t chunk_log2,
-                  uint32_t n_vars) {
+// no leaf work.  Work items are made afterwards by make_items.
+uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint32_t n_vars) {
   if (c.lits.size() > kMaxCubeLen) fail(SCUBA_E_CAPACITY, "cube longer than 4096 literals");
   if (!c.refuted && (c.f < 0 || uint32_t(c.f) > kMaxLeafVars))
     fail(SCUBA_E_CAPACITY, "leaf with more than 38 active variables");
@@ -159,28 +173,76 @@ uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint
   rh.cube_lits.insert(rh.cube_lits.end(), c.lits.begin(), c.lits.end());
   uint32_t ci = uint32_t(rh.cubes.size());
   rh.cubes.push_back(d);
-  if (!c.refuted) {
-    uint64_t nb = blocks_of(c.f), chunk = uint64_t(1) << chunk_log2;
-    for (uint64_t lo = 0; lo < nb; lo += chunk)
-      rh.items.push_back({ci, uint32_t(lo), uint32_t(std::min(nb, lo + chunk)), 0});
-  }
   return ci;
+}
+
+// Item sizes in 4096-assignment blocks.  DECIDE: sizes grow geometrically
+// from 4 blocks (one per wave) to the cap, so that the first blocks of every
+// leaf are reached early (witnesses tend to sit at small indices), and the
+// items of all leaves are ordered by their first block.  COUNT: every item
+// has the cap size, the cap chosen so that the round has a few items per
+// workgroup.
+template <typename F>
+void for_each_item(uint64_t nb, uint64_t cap, bool geometric, F&& emit) {
+  uint64_t lo = 0, size = geometric ? std::min<uint64_t>(4, cap) : cap;
+  while (lo < nb) {
+    uint64_t hi = std::min(nb, lo + size);
+    emit(lo, hi);
+    lo = hi;
+    if (geometric) size = std::min(size * 2, cap);
+  }
+}
+uint64_t count_items(uint64_t nb, uint64_t cap, bool geometric) {
+  uint64_t n = 0;
+  for_each_item(nb, cap, geometric, [&](uint64_t, uint64_t) { n++; });
+  return n;
+}
+uint64_t item_cap(const RoundHost& rh, uint32_t mode, uint32_t chunk_log2, uint32_t grid) {
+  const uint64_t cap = uint64_t(1) << chunk_log2;
+  uint64_t total = 0;
+  for (const DevCubeDesc& d : rh.cubes)
+    if (d.f_expect >= 0) total += blocks_of(d.f_expect);
+  if (mode == SCUBA_MODE_DECIDE) {
+    // items past the geometric ramp: at least the configured size, larger
+    // when the round holds far more blocks than a few per workgroup (so that
+    // skipping the items of decided queries stays cheap)
+    const uint64_t want = total / (uint64_t(16) * std::max<uint32_t>(grid, 1));
+    uint64_t c = cap;
+    while (c * 2 <= want && c < (uint64_t(1) << 16)) c *= 2;
+    return c;
+  }
+  const uint64_t want = total / (uint64_t(4) * std::max<uint32_t>(grid, 1));
+  uint64_t c = 4;
+  while (c * 2 <= want && c * 2 <= cap) c *= 2;
+  return std::min(c, cap);
+}
+void make_items(RoundHost& rh, uint32_t mode, uint32_t chunk_log2, uint32_t grid) {
+  const bool geometric = mode == SCUBA_MODE_DECIDE;
+  const uint64_t cap = item_cap(rh, mode, chunk_log2, grid);
+  rh.items.clear();
+  for (uint32_t ci = 0; ci < rh.cubes.size(); ci++) {
+    if (rh.cubes[ci].f_expect < 0) continue;
+    for_each_item(blocks_of(rh.cubes[ci].f_expect), cap, geometric, [&](uint64_t lo, uint64_t hi) {
+      rh.items.push_back({ci, uint32_t(lo), uint32_t(hi), 0});
+    });
+  }
+  if (geometric)
+    std::stable_sort(rh.items.begin(), rh.items.end(),
+                     [](const DevItem& a, const DevItem& b) { return a.it_lo < b.it_lo; });
 }
 
 size_t round_bound(const scuba_cnf* cnf, size_t n_cubes, const Opts& o, uint32_t max_res) {
   uint32_t max_vars = 0;
   for (const CnfQuery& q : cnf->q) max_vars = std::max(max_vars, q.n_vars);
   size_t lits = n_cubes * std::min<uint32_t>(max_vars + 1, kMaxCubeLen);
-  uint64_t nb = blocks_of(int32_t(o.k));
-  uint64_t per = (nb + (uint64_t(1) << o.chunk_log2) - 1) >> o.chunk_log2;
+  uint64_t per = count_items(blocks_of(int32_t(o.k)), uint64_t(1) << o.chunk_log2, true);
   return dev_round_bytes(n_cubes, lits, n_cubes * per, uint64_t(n_cubes) * max_res);
 }
 
 // Model of a SAT leaf: propagation of the cube, slot j = bit j of `a`,
 // remaining unassigned variables 0.  Then the checks of the result stage.
-void assemble_witness(const CnfQuery& q, const std::vector<int32_t>& cube, uint64_t a,
+void assemble_witness(const CnfQuery& q, Splitter& sp, const std::vector<int32_t>& cube, uint64_t a,
                       scuba_results::Q& out) {
-  Splitter sp(q, 0, 0, 1);
   std::vector<int8_t> assign;
   std::vector<int32_t> active;
   uint32_t nres = 0;
@@ -268,16 +330,19 @@ scuba_status scuba_bitblast(scuba_ctx* ctx, uint32_t nq, const scuba_node* nodes
   if (!ctx || !out || (nq && (!node_start || !root_start))) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     auto cnf = std::make_unique<scuba_cnf>();
-    cnf->q.reserve(nq);
-    for (uint32_t i = 0; i < nq; i++) {
+    cnf->q.resize(nq);
+    for (uint32_t i = 0; i < nq; i++)
+      if (node_start[i + 1] < node_start[i] || root_start[i + 1] < root_start[i])
+        fail(SCUBA_E_INVALID, "offsets must not decrease");
+    // queries are independent: encode them on the host thread pool
+    parallel_for(nq, [&](size_t i) {
       uint64_t n0 = node_start[i], n1 = node_start[i + 1], r0 = root_start[i], r1 = root_start[i + 1];
-      if (n1 < n0 || r1 < r0) fail(SCUBA_E_INVALID, "offsets must not decrease");
       try {
-        cnf->q.push_back(bitblast_query(nodes + n0, n1 - n0, roots + r0, r1 - r0, flags));
+        cnf->q[i] = bitblast_query(nodes + n0, n1 - n0, roots + r0, r1 - r0, flags);
       } catch (const Error& e) {
         throw Error(e.code, "query " + std::to_string(i) + ": " + e.what());
       }
-    }
+    });
     *out = cnf.release();
   });
 }
@@ -353,9 +418,10 @@ scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split
     uint32_t max_res = opts->max_residual ? opts->max_residual : kDefaultMaxResidual;
     uint64_t max_cubes = opts->max_cubes ? opts->max_cubes : kDefaultMaxCubes;
     auto cubes = std::make_unique<scuba_cubes>();
-    for (const CnfQuery& q : cnf->q) {
-      scuba_cubes::Q cq;
-      Splitter sp(q, opts->k, max_res, max_cubes);
+    cubes->q.resize(cnf->q.size());
+    parallel_for(cnf->q.size(), [&](size_t qi) {
+      scuba_cubes::Q& cq = cubes->q[qi];
+      Splitter sp(cnf->q[qi], opts->k, max_res, max_cubes);
       std::vector<Cube> all;
       Splitter::State st;
       do st = sp.next(UINT32_MAX, all, true);
@@ -368,8 +434,7 @@ scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split
         cq.f.push_back(c.refuted ? -1 : c.f);
         cq.nres.push_back(c.nres);
       }
-      cubes->q.push_back(std::move(cq));
-    }
+    });
     *out = cubes.release();
   });
 }
@@ -378,17 +443,25 @@ scuba_status scuba_cubes_from_arrays(scuba_ctx* ctx, const scuba_cnf* cnf, const
                                      const uint64_t* cube_off, const int32_t* cube_lits, scuba_cubes** out) {
   if (!ctx || !cnf || !q_cube_start || !cube_off || !out) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
-    auto cubes = std::make_unique<scuba_cubes>();
     for (size_t i = 0; i < cnf->q.size(); i++) {
-      const CnfQuery& q = cnf->q[i];
-      scuba_cubes::Q cq;
-      Splitter sp(q, 0, 0, 1);
       if (q_cube_start[i + 1] < q_cube_start[i]) fail(SCUBA_E_INVALID, "cube ranges must not decrease");
       for (uint64_t c = q_cube_start[i]; c < q_cube_start[i + 1]; c++) {
         if (cube_off[c + 1] < cube_off[c]) fail(SCUBA_E_INVALID, "cube offsets must not decrease");
+        for (uint64_t j = cube_off[c]; j < cube_off[c + 1]; j++) {
+          int32_t l = cube_lits[j];
+          if (l == 0 || uint32_t(l > 0 ? l : -int64_t(l)) > cnf->q[i].n_vars)
+            fail(SCUBA_E_INVALID, "cube literal out of range");
+        }
+      }
+    }
+    auto cubes = std::make_unique<scuba_cubes>();
+    cubes->q.resize(cnf->q.size());
+    parallel_for(cnf->q.size(), [&](size_t i) {
+      const CnfQuery& q = cnf->q[i];
+      scuba_cubes::Q& cq = cubes->q[i];
+      Splitter sp(q, 0, 0, 1);
+      for (uint64_t c = q_cube_start[i]; c < q_cube_start[i + 1]; c++) {
         std::vector<int32_t> lits(cube_lits + cube_off[c], cube_lits + cube_off[c + 1]);
-        for (int32_t l : lits)
-          if (l == 0 || uint32_t(std::abs(l)) > q.n_vars) fail(SCUBA_E_INVALID, "cube literal out of range");
         std::vector<int8_t> assign;
         std::vector<int32_t> active;
         uint32_t nres = 0;
@@ -402,8 +475,7 @@ scuba_status scuba_cubes_from_arrays(scuba_ctx* ctx, const scuba_cnf* cnf, const
         cq.nres.push_back(ok ? nres : 0);
       }
       cq.complete = false;
-      cubes->q.push_back(std::move(cq));
-    }
+    });
     *out = cubes.release();
   });
 }
@@ -424,26 +496,43 @@ void scuba_cubes_free(scuba_cubes* cubes) { delete cubes; }
 
 // ---------------------------------------------------------------- solve
 
+// Round of a given cube list (every cube of every query, in order).
+struct SolveRound {
+  RoundHost rh;
+  std::vector<std::pair<uint32_t, uint64_t>> where;   // round cube -> (query, cube)
+  std::vector<Cube> host;
+};
+SolveRound solve_round(const scuba_cnf* cnf, const scuba_cubes* cubes, const Opts& o, uint32_t grid) {
+  SolveRound sr;
+  for (size_t qi = 0; qi < cnf->q.size(); qi++) {
+    const auto& cq = cubes->q[qi];
+    for (size_t c = 0; c < cq.kind.size(); c++) {
+      Cube cube;
+      cube.lits.assign(cq.lits.begin() + cq.off[c], cq.lits.begin() + cq.off[c + 1]);
+      cube.refuted = cq.kind[c] != SCUBA_CUBE_LEAF;
+      cube.f = cq.f[c];
+      cube.nres = cq.nres[c];
+      add_cube(sr.rh, uint32_t(qi), uint32_t(c), cube, cnf->q[qi].n_vars);
+      sr.where.push_back({uint32_t(qi), c});
+      sr.host.push_back(std::move(cube));
+    }
+  }
+  make_items(sr.rh, o.mode, o.chunk_log2, grid);
+  return sr;
+}
+
+uint32_t grid_of(const scuba_ctx* ctx, const Opts& o) { return o.grid ? o.grid : uint32_t(ctx->dev.cus) * 8; }
+
 scuba_status scuba_solve_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes* cubes,
                                    const scuba_solve_opts* opts, size_t* bytes) {
   if (!ctx || !cnf || !cubes || !bytes || cubes->q.size() != cnf->q.size()) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     Opts o = resolve(opts);
+    ctx->ensure_device();
     CnfHost h = cnf_host(cnf);
-    size_t n_cubes = 0, n_lits = 0, n_items = 0;
-    uint64_t res = 0;
-    // every cube is sent (refuted ones too, to check the device agrees);
-    // only leaves get residual records and work items
-    for (const auto& q : cubes->q)
-      for (size_t c = 0; c < q.kind.size(); c++) {
-        n_cubes++;
-        n_lits += q.off[c + 1] - q.off[c];
-        if (q.kind[c] != SCUBA_CUBE_LEAF) continue;
-        res += q.nres[c];
-        uint64_t nb = blocks_of(std::max(q.f[c], 0));
-        n_items += size_t((nb + (uint64_t(1) << o.chunk_log2) - 1) >> o.chunk_log2);
-      }
-    *bytes = dev_cnf_bytes(h) + dev_round_bytes(n_cubes, n_lits, n_items, res);
+    SolveRound sr = solve_round(cnf, cubes, o, grid_of(ctx, o));
+    *bytes = dev_cnf_bytes(h) +
+             dev_round_bytes(sr.rh.cubes.size(), sr.rh.cube_lits.size(), sr.rh.items.size(), sr.rh.res_records);
   });
 }
 
@@ -465,30 +554,19 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     auto t0 = Clock::now();
     Opts o = resolve(opts);
     ctx->ensure_device();
-    CnfHost h = cnf_host(cnf);
+    CnfHost h = cnf_host(cnf, up_lds_limit(ctx));
     auto res = std::make_unique<scuba_results>();
     res->q.resize(cnf->q.size());
-    RoundHost rh;
-    std::vector<std::pair<uint32_t, uint64_t>> where;   // round cube -> (query, cube)
-    std::vector<Cube> host_leaf;
     for (size_t qi = 0; qi < cnf->q.size(); qi++) {
-      const auto& cq = cubes->q[qi];
       auto& rq = res->q[qi];
+      const auto& cq = cubes->q[qi];
       rq.leaves.assign(cq.kind.size(), scuba_leaf_result{});
       for (auto& l : rq.leaves) { l.first = -1; l.refuted = 0; }
       rq.r.cubes_total = cq.kind.size();
-      for (size_t c = 0; c < cq.kind.size(); c++) {
-        Cube cube;
-        cube.lits.assign(cq.lits.begin() + cq.off[c], cq.lits.begin() + cq.off[c + 1]);
-        cube.refuted = cq.kind[c] != SCUBA_CUBE_LEAF;
-        if (cube.refuted) rq.r.cubes_refuted++;
-        cube.f = cq.f[c];
-        cube.nres = cq.nres[c];
-        add_cube(rh, uint32_t(qi), uint32_t(c), cube, o.chunk_log2, cnf->q[qi].n_vars);
-        where.push_back({uint32_t(qi), c});
-        host_leaf.push_back(cube);
-      }
+      for (int32_t k : cq.kind) rq.r.cubes_refuted += k != SCUBA_CUBE_LEAF;
     }
+    SolveRound sr = solve_round(cnf, cubes, o, grid_of(ctx, o));
+    const RoundHost& rh = sr.rh;
     size_t cnf_b = dev_cnf_bytes(h);
     size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);
     if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than scuba_solve_workspace");
@@ -501,8 +579,8 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
               &qkeys, &rt);
     auto tv = Clock::now();
     for (size_t i = 0; i < outs.size(); i++) {
-      check_out(outs[i], host_leaf[i]);
-      auto [qi, c] = where[i];
+      check_out(outs[i], sr.host[i]);
+      auto [qi, c] = sr.where[i];
       auto& rq = res->q[qi];
       scuba_leaf_result& lr = rq.leaves[c];
       lr.refuted = outs[i].status == 1;
@@ -510,13 +588,13 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
       lr.m = lr.refuted ? -1 : outs[i].m;
       lr.count = outs[i].count;
       lr.first = outs[i].first == ~0ull ? -1 : int64_t(outs[i].first);
-      if (host_leaf[i].refuted) continue;
+      if (sr.host[i].refuted) continue;
       rq.r.leaves_sent++;
       rq.r.leaves_refuted += lr.refuted;
       rq.r.blocks_evaluated += outs[i].blocks;
       rq.r.clause_blocks += outs[i].clause_blocks;
     }
-    for (size_t qi = 0; qi < cnf->q.size(); qi++) {
+    parallel_for(cnf->q.size(), [&](size_t qi) {
       auto& rq = res->q[qi];
       rq.r.rounds = 1;
       rq.r.how = SCUBA_HOW_DEVICE;
@@ -528,12 +606,13 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
         rq.r.verdict = SCUBA_SAT;
         const auto& cq = cubes->q[qi];
         std::vector<int32_t> lits(cq.lits.begin() + cq.off[sat_cube], cq.lits.begin() + cq.off[sat_cube + 1]);
-        assemble_witness(cnf->q[qi], lits, uint64_t(rq.leaves[sat_cube].first), rq);
+        Splitter sp(cnf->q[qi], 0, 0, 1);
+        assemble_witness(cnf->q[qi], sp, lits, uint64_t(rq.leaves[sat_cube].first), rq);
       } else {
         rq.r.verdict = cubes->q[qi].complete ? SCUBA_UNSAT : SCUBA_UNKNOWN;
         if (cnf->q[qi].root_unsat) { rq.r.verdict = SCUBA_UNSAT; rq.r.how = SCUBA_HOW_ROOT; }
       }
-    }
+    });
     res->ms[1] = rt.h2d_ms;
     res->ms[2] = rt.up_ms + rt.leaf_ms;
     res->ms[3] = rt.d2h_ms;
@@ -556,7 +635,7 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
     if (o.mode != SCUBA_MODE_DECIDE) fail(SCUBA_E_INVALID, "scuba_decide runs in DECIDE mode");
     ctx->ensure_device();
     const size_t nq = cnf->q.size();
-    CnfHost h = cnf_host(cnf);
+    CnfHost h = cnf_host(cnf, up_lds_limit(ctx));
     auto res = std::make_unique<scuba_results>();
     res->q.resize(nq);
     std::vector<std::unique_ptr<Splitter>> sp(nq);
@@ -571,38 +650,46 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
         r.how = SCUBA_HOW_ROOT;
         continue;
       }
-      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
       open[qi] = 1;
     }
+    parallel_for(nq, [&](size_t qi) {
+      if (open[qi]) sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
+    });
     split_ms += ms_since(ts);
     size_t cnf_b = dev_cnf_bytes(h);
     if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
     bool uploaded = false;
     RoundTimes rt;
+    const uint32_t grid = grid_of(ctx, o);
     for (uint32_t round = 0; o.max_rounds == 0 || round < o.max_rounds; round++) {
       ts = Clock::now();
+      // each open query's walk advances on the host pool
+      std::vector<std::vector<Cube>> leaves(nq);
+      std::vector<Splitter::State> state(nq, Splitter::kRunning);
+      parallel_for(nq, [&](size_t qi) {
+        if (open[qi]) state[qi] = sp[qi]->next(o.lpr, leaves[qi], false);
+      });
       RoundHost rh;
       std::vector<std::pair<uint32_t, Cube>> sent;
       for (size_t qi = 0; qi < nq; qi++) {
         if (!open[qi]) continue;
-        std::vector<Cube> leaves;
-        Splitter::State st = sp[qi]->next(o.lpr, leaves, false);
         auto& r = res->q[qi].r;
         r.rounds++;
-        for (Cube& c : leaves) {
-          add_cube(rh, uint32_t(qi), seq[qi]++, c, o.chunk_log2, cnf->q[qi].n_vars);
+        for (Cube& c : leaves[qi]) {
+          add_cube(rh, uint32_t(qi), seq[qi]++, c, cnf->q[qi].n_vars);
           sent.push_back({uint32_t(qi), std::move(c)});
         }
         r.cubes_total = sp[qi]->cubes_total();
         r.cubes_refuted = sp[qi]->cubes_refuted();
-        if (leaves.empty()) {
+        if (leaves[qi].empty()) {
           // nothing left for the device: the tree is done or cut
           open[qi] = 0;
-          r.verdict = st == Splitter::kExhausted ? SCUBA_UNSAT : SCUBA_UNKNOWN;
-          r.how = st == Splitter::kExhausted ? (r.leaves_sent ? SCUBA_HOW_DEVICE : SCUBA_HOW_ROOT)
-                                              : SCUBA_HOW_BUDGET;
+          r.verdict = state[qi] == Splitter::kExhausted ? SCUBA_UNSAT : SCUBA_UNKNOWN;
+          r.how = state[qi] == Splitter::kExhausted ? (r.leaves_sent ? SCUBA_HOW_DEVICE : SCUBA_HOW_ROOT)
+                                                     : SCUBA_HOW_BUDGET;
         }
       }
+      make_items(rh, SCUBA_MODE_DECIDE, o.chunk_log2, grid);
       split_ms += ms_since(ts);
       if (rh.cubes.empty()) break;
       size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);
@@ -629,23 +716,25 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
       std::vector<size_t> first_of(nq, SIZE_MAX);
       for (size_t i = 0; i < sent.size(); i++)
         if (first_of[sent[i].first] == SIZE_MAX) first_of[sent[i].first] = i;
-      for (size_t qi = 0; qi < nq; qi++) {
-        if (qkeys[qi] == ~0ull || res->q[qi].r.verdict == SCUBA_SAT) continue;
+      std::vector<uint32_t> sat_q;
+      for (size_t qi = 0; qi < nq; qi++)
+        if (qkeys[qi] != ~0ull && res->q[qi].r.verdict != SCUBA_SAT && first_of[qi] != SIZE_MAX)
+          sat_q.push_back(uint32_t(qi));
+      parallel_for(sat_q.size(), [&](size_t j) {
+        const uint32_t qi = sat_q[j];
         uint32_t s = uint32_t(qkeys[qi] >> 38);
         uint64_t a = qkeys[qi] & ((uint64_t(1) << 38) - 1);
         // locate the cube with that sequence number among this round's leaves
         const Cube* cube = nullptr;
-        for (size_t i = first_of[qi]; i < sent.size() && sent[i].first == qi; i++) {
-          uint32_t si = rh.cubes[i].seq;
-          if (si == s) { cube = &sent[i].second; break; }
-        }
+        for (size_t i = first_of[qi]; i < sent.size() && sent[i].first == qi; i++)
+          if (rh.cubes[i].seq == s) { cube = &sent[i].second; break; }
         if (!cube) fail(SCUBA_E_INTERNAL, "witness from an unknown cube");
         auto& rq = res->q[qi];
         rq.r.verdict = SCUBA_SAT;
         rq.r.how = SCUBA_HOW_DEVICE;
-        open[qi] = 0;
-        assemble_witness(cnf->q[qi], cube->lits, a, rq);
-      }
+        assemble_witness(cnf->q[qi], *sp[qi], cube->lits, a, rq);   // ends this query's walk
+      });
+      for (uint32_t qi : sat_q) open[qi] = 0;
       verify_ms += ms_since(tv);
     }
     for (size_t qi = 0; qi < nq; qi++)

@@ -84,15 +84,186 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t*
   return base + x - v;
 }
 
-__device__ __forceinline__ bool clause_satisfied(const int32_t* L, uint32_t b, uint32_t e,
-                                                 const uint32_t* T, const uint32_t* F) {
-  for (uint32_t i = b; i < e; i++) {
-    int32_t l = L[i];
-    uint32_t v = uint32_t(l > 0 ? l : -l);
-    uint32_t bit = 1u << (v & 31);
-    if ((l > 0 ? T[v >> 5] : F[v >> 5]) & bit) return true;
+// Clause access for the propagation kernel: the query's CNF either read
+// from global memory (DIMACS literals, 32-bit offsets) or staged in LDS as
+// 16-bit literals (variable << 1 | negated) with 16-bit offsets.
+struct GlobalCnf {
+  const uint32_t* co;
+  const int32_t* L;
+  __device__ __forceinline__ uint32_t beg(uint32_t c) const { return co[c]; }
+  __device__ __forceinline__ uint32_t end(uint32_t c) const { return co[c + 1]; }
+  __device__ __forceinline__ void lit(uint32_t i, uint32_t* v, bool* neg) const {
+    const int32_t l = L[i];
+    *v = uint32_t(l > 0 ? l : -l);
+    *neg = l < 0;
+  }
+};
+struct LdsCnf {
+  const uint16_t* co;
+  const uint16_t* L;
+  __device__ __forceinline__ uint32_t beg(uint32_t c) const { return co[c]; }
+  __device__ __forceinline__ uint32_t end(uint32_t c) const { return co[c + 1]; }
+  __device__ __forceinline__ void lit(uint32_t i, uint32_t* v, bool* neg) const {
+    const uint32_t x = L[i];
+    *v = x >> 1;
+    *neg = x & 1;
+  }
+};
+
+template <class Cnf>
+__device__ __forceinline__ bool clause_satisfied(const Cnf& cnf, uint32_t c, const uint32_t* T, const uint32_t* F) {
+  for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+    uint32_t v;
+    bool neg;
+    cnf.lit(i, &v, &neg);
+    if ((neg ? F[v >> 5] : T[v >> 5]) & (1u << (v & 31))) return true;
   }
   return false;
+}
+
+struct UpShared {
+  uint32_t conflict, flags[3], wave[kBlock / 64], error;
+};
+
+// Unit propagation of one cube, then its active variables, slots and
+// residual records.  Called by the whole workgroup (uniform control flow).
+template <class Cnf>
+__device__ void propagate_cube(const Cnf& cnf, const DevCubeDesc& cd, uint32_t ci, uint32_t nv, uint32_t nc,
+                               const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
+                               uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
+                               UpShared& sh) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
+  for (uint32_t w = tid; w < nw; w += kBlock) { T[w] = 0; F[w] = 0; A[w] = 0; }
+  if (tid == 0) { sh.conflict = 0; sh.error = 0; sh.flags[0] = 0; sh.flags[1] = 0; sh.flags[2] = 0; }
+  __syncthreads();
+  for (uint32_t j = tid; j < cd.n_lits; j += kBlock) {
+    int32_t l = cube_lits[cd.lit_off + j];
+    uint32_t v = uint32_t(l > 0 ? l : -l);
+    if (v == 0 || v > nv) { sh.error = 1; continue; }
+    atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], 1u << (v & 31));
+  }
+  __syncthreads();
+
+  // ---- propagation rounds; at most 2*(nv+1) rounds change something
+  const uint32_t max_rounds = 2 * nv + 4;
+  for (uint32_t r = 0;; r++) {
+    if (tid == 0) sh.flags[(r + 1) % 3] = 0;
+    for (uint32_t w = tid; w < nw; w += kBlock)
+      if (T[w] & F[w]) sh.conflict = 1;
+    for (uint32_t c = tid; c < nc; c += kBlock) {
+      bool sat = false;
+      uint32_t open = 0, last_v = 0;
+      bool last_neg = false;
+      for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+        uint32_t v;
+        bool neg;
+        cnf.lit(i, &v, &neg);
+        const uint32_t bit = 1u << (v & 31);
+        const uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
+        if (neg ? f : t) { sat = true; break; }
+        if (!(t | f)) { open++; last_v = v; last_neg = neg; }
+      }
+      if (sat) continue;
+      if (open == 0) {
+        sh.conflict = 1;
+      } else if (open == 1) {
+        const uint32_t bit = 1u << (last_v & 31);
+        const uint32_t old = atomicOr(last_neg ? &F[last_v >> 5] : &T[last_v >> 5], bit);
+        if (!(old & bit)) sh.flags[r % 3] = 1;
+      }
+    }
+    __syncthreads();
+    const uint32_t changed = sh.flags[r % 3], conflict = sh.conflict;
+    __syncthreads();   // every thread has read the flags of this round
+    if (conflict || !changed) break;
+    if (r >= max_rounds) {   // cannot happen: every changing round sets a new bit
+      if (tid == 0) sh.error = 1;
+      break;
+    }
+  }
+  __syncthreads();
+  for (uint32_t w = tid; w < nw; w += kBlock)
+    if (T[w] & F[w]) sh.conflict = 1;
+  __syncthreads();
+  if (sh.conflict || sh.error) {
+    if (tid == 0) {
+      out[ci].status = sh.error ? 2 : 1;
+      out[ci].f = out[ci].m = out[ci].nres = 0;
+    }
+    __syncthreads();
+    return;
+  }
+
+  // ---- active variables
+  for (uint32_t c = tid; c < nc; c += kBlock) {
+    if (clause_satisfied(cnf, c, T, F)) continue;
+    for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+      uint32_t v;
+      bool neg;
+      cnf.lit(i, &v, &neg);
+      const uint32_t bit = 1u << (v & 31);
+      if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
+    }
+  }
+  __syncthreads();
+
+  // ---- slot prefix per bitmap word (contiguous words per thread)
+  const uint32_t wpt = (nw + kBlock - 1) / kBlock;
+  const uint32_t w0 = tid * wpt, w1 = min(nw, w0 + wpt);
+  uint32_t my_act = 0, my_free = 0;
+  for (uint32_t w = w0; w < w1; w++) {
+    uint32_t valid = 0xFFFFFFFFu;
+    if (w == 0) valid &= ~1u;                      // no variable 0
+    if (w == (nv >> 5)) valid &= (nv & 31) == 31 ? 0xFFFFFFFFu : ((2u << (nv & 31)) - 1);
+    my_act += __popc(A[w]);
+    my_free += __popc(~(T[w] | F[w]) & valid);
+  }
+  uint32_t f_total, free_total;
+  uint32_t base = block_exclusive_scan(my_act, sh.wave, &f_total);
+  block_exclusive_scan(my_free, sh.wave, &free_total);
+  for (uint32_t w = w0; w < w1; w++) { P[w] = base; base += __popc(A[w]); }
+  __syncthreads();
+
+  const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
+
+  // ---- residual records, in clause order (contiguous clauses per thread)
+  const uint32_t cpt = (nc + kBlock - 1) / kBlock;
+  const uint32_t c0 = tid * cpt, c1 = min(nc, c0 + cpt);
+  uint32_t my_unsat = 0;
+  for (uint32_t c = c0; c < c1; c++)
+    if (!clause_satisfied(cnf, c, T, F)) my_unsat++;
+  uint32_t n_unsat;
+  uint32_t pos = block_exclusive_scan(my_unsat, sh.wave, &n_unsat);
+  const bool cap_ok = n_unsat <= cd.nres_cap;
+  if (f_ok && cap_ok) {
+    for (uint32_t c = c0; c < c1; c++) {
+      if (clause_satisfied(cnf, c, T, F)) continue;
+      uint64_t low = 0;
+      uint32_t hp = 0, hn = 0, mp = 0, mn = 0;
+      for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+        uint32_t v;
+        bool neg;
+        cnf.lit(i, &v, &neg);
+        const uint32_t bit = 1u << (v & 31);
+        if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
+        const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
+        if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
+        else if (slot < 12) (neg ? mn : mp) |= 1u << (slot - 6);
+        else (neg ? hn : hp) |= 1u << (slot - 12);
+      }
+      res[cd.res_base + pos] = make_uint4(uint32_t(low), uint32_t(low >> 32), hp | (mp << 26),
+                                          hn | (mn << 26));
+      pos++;
+    }
+  }
+  if (tid == 0) {
+    out[ci].status = !f_ok ? 2 : (!cap_ok ? 3 : 0);
+    out[ci].f = int32_t(f_total);
+    out[ci].m = int32_t(free_total - f_total);
+    out[ci].nres = int32_t(n_unsat);
+  }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restrict__ qd,
@@ -103,13 +274,16 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
                                                    uint32_t n_cubes, DevCubeOut* __restrict__ out,
                                                    uint4* __restrict__ res, uint32_t* head,
                                                    uint32_t nw_max) {
+  // LDS: four bitmaps of nw_max words, then (for staged queries) the CNF
+  // as 16-bit offsets and 16-bit literals
   extern __shared__ uint32_t smem[];
   uint32_t* T = smem;
   uint32_t* F = T + nw_max;
   uint32_t* A = F + nw_max;
   uint32_t* P = A + nw_max;
-  __shared__ uint32_t s_item, s_conflict, s_flags[3], s_wave[kBlock / 64];
-  __shared__ uint32_t s_error;
+  uint16_t* stage = reinterpret_cast<uint16_t*>(P + nw_max);
+  __shared__ UpShared sh;
+  __shared__ uint32_t s_item;
   const uint32_t tid = threadIdx.x;
 
   for (;;) {
@@ -121,143 +295,22 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
 
     const DevCubeDesc cd = cubes[ci];
     const DevQueryDesc q = qd[cd.qid];
-    const uint32_t nv = q.n_vars, nc = q.n_clauses;
-    const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
     const uint32_t* co = coff + q.coff_base;
     const int32_t* L = lits + q.lit_base;
-
-    for (uint32_t w = tid; w < nw; w += kBlock) { T[w] = 0; F[w] = 0; A[w] = 0; }
-    if (tid == 0) { s_conflict = 0; s_error = 0; s_flags[0] = 0; s_flags[1] = 0; s_flags[2] = 0; }
-    __syncthreads();
-    for (uint32_t j = tid; j < cd.n_lits; j += kBlock) {
-      int32_t l = cube_lits[cd.lit_off + j];
-      uint32_t v = uint32_t(l > 0 ? l : -l);
-      if (v == 0 || v > nv) { s_error = 1; continue; }
-      atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], 1u << (v & 31));
-    }
-    __syncthreads();
-
-    // ---- propagation rounds; at most 2*(nv+1) rounds change something
-    const uint32_t max_rounds = 2 * nv + 4;
-    for (uint32_t r = 0;; r++) {
-      if (tid == 0) s_flags[(r + 1) % 3] = 0;
-      for (uint32_t w = tid; w < nw; w += kBlock)
-        if (T[w] & F[w]) s_conflict = 1;
-      for (uint32_t c = tid; c < nc; c += kBlock) {
-        const uint32_t b = co[c], e = co[c + 1];
-        bool sat = false;
-        uint32_t open = 0;
-        int32_t last = 0;
-        for (uint32_t i = b; i < e; i++) {
-          int32_t l = L[i];
-          uint32_t v = uint32_t(l > 0 ? l : -l);
-          uint32_t bit = 1u << (v & 31);
-          uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
-          if (l > 0 ? t : f) { sat = true; break; }
-          if (!(t | f)) { open++; last = l; }
-        }
-        if (sat) continue;
-        if (open == 0) {
-          s_conflict = 1;
-        } else if (open == 1) {
-          uint32_t v = uint32_t(last > 0 ? last : -last);
-          uint32_t bit = 1u << (v & 31);
-          uint32_t old = atomicOr(last > 0 ? &T[v >> 5] : &F[v >> 5], bit);
-          if (!(old & bit)) s_flags[r % 3] = 1;
-        }
+    if (q.staged) {
+      const uint32_t nl = co[q.n_clauses];
+      uint16_t* sco = stage;
+      uint16_t* sl = stage + q.n_clauses + 1;
+      for (uint32_t c = tid; c <= q.n_clauses; c += kBlock) sco[c] = uint16_t(co[c]);
+      for (uint32_t i = tid; i < nl; i += kBlock) {
+        const int32_t l = L[i];
+        sl[i] = uint16_t((uint32_t(l > 0 ? l : -l) << 1) | (l < 0 ? 1u : 0u));
       }
       __syncthreads();
-      const uint32_t changed = s_flags[r % 3], conflict = s_conflict;
-      __syncthreads();   // every thread has read the flags of this round
-      if (conflict || !changed) break;
-      if (r >= max_rounds) {   // cannot happen: every changing round sets a new bit
-        if (tid == 0) s_error = 1;
-        break;
-      }
+      propagate_cube(LdsCnf{sco, sl}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P, sh);
+    } else {
+      propagate_cube(GlobalCnf{co, L}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P, sh);
     }
-    __syncthreads();
-    for (uint32_t w = tid; w < nw; w += kBlock)
-      if (T[w] & F[w]) s_conflict = 1;
-    __syncthreads();
-    if (s_conflict || s_error) {
-      if (tid == 0) {
-        out[ci].status = s_error ? 2 : 1;
-        out[ci].f = out[ci].m = out[ci].nres = 0;
-      }
-      __syncthreads();
-      continue;
-    }
-
-    // ---- active variables
-    for (uint32_t c = tid; c < nc; c += kBlock) {
-      const uint32_t b = co[c], e = co[c + 1];
-      if (clause_satisfied(L, b, e, T, F)) continue;
-      for (uint32_t i = b; i < e; i++) {
-        int32_t l = L[i];
-        uint32_t v = uint32_t(l > 0 ? l : -l);
-        uint32_t bit = 1u << (v & 31);
-        if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
-      }
-    }
-    __syncthreads();
-
-    // ---- slot prefix per bitmap word (contiguous words per thread)
-    const uint32_t wpt = (nw + kBlock - 1) / kBlock;
-    const uint32_t w0 = tid * wpt, w1 = min(nw, w0 + wpt);
-    uint32_t my_act = 0, my_free = 0;
-    for (uint32_t w = w0; w < w1; w++) {
-      uint32_t valid = 0xFFFFFFFFu;
-      if (w == 0) valid &= ~1u;                      // no variable 0
-      if (w == (nv >> 5)) valid &= (nv & 31) == 31 ? 0xFFFFFFFFu : ((2u << (nv & 31)) - 1);
-      my_act += __popc(A[w]);
-      my_free += __popc(~(T[w] | F[w]) & valid);
-    }
-    uint32_t f_total, free_total;
-    uint32_t base = block_exclusive_scan(my_act, s_wave, &f_total);
-    block_exclusive_scan(my_free, s_wave, &free_total);
-    for (uint32_t w = w0; w < w1; w++) { P[w] = base; base += __popc(A[w]); }
-    __syncthreads();
-
-    const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
-
-    // ---- residual records, in clause order (contiguous clauses per thread)
-    const uint32_t cpt = (nc + kBlock - 1) / kBlock;
-    const uint32_t c0 = tid * cpt, c1 = min(nc, c0 + cpt);
-    uint32_t my_unsat = 0;
-    for (uint32_t c = c0; c < c1; c++)
-      if (!clause_satisfied(L, co[c], co[c + 1], T, F)) my_unsat++;
-    uint32_t n_unsat;
-    uint32_t pos = block_exclusive_scan(my_unsat, s_wave, &n_unsat);
-    const bool cap_ok = n_unsat <= cd.nres_cap;
-    if (f_ok && cap_ok) {
-      for (uint32_t c = c0; c < c1; c++) {
-        const uint32_t b = co[c], e = co[c + 1];
-        if (clause_satisfied(L, b, e, T, F)) continue;
-        uint64_t low = 0;
-        uint32_t hp = 0, hn = 0, mp = 0, mn = 0;
-        for (uint32_t i = b; i < e; i++) {
-          int32_t l = L[i];
-          uint32_t v = uint32_t(l > 0 ? l : -l);
-          uint32_t bit = 1u << (v & 31);
-          if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
-          uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
-          bool neg = l < 0;
-          if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
-          else if (slot < 12) (neg ? mn : mp) |= 1u << (slot - 6);
-          else (neg ? hn : hp) |= 1u << (slot - 12);
-        }
-        res[cd.res_base + pos] = make_uint4(uint32_t(low), uint32_t(low >> 32), hp | (mp << 26),
-                                            hn | (mn << 26));
-        pos++;
-      }
-    }
-    if (tid == 0) {
-      out[ci].status = !f_ok ? 2 : (!cap_ok ? 3 : 0);
-      out[ci].f = int32_t(f_total);
-      out[ci].m = int32_t(free_total - f_total);
-      out[ci].nres = int32_t(n_unsat);
-    }
-    __syncthreads();
   }
 }
 
@@ -447,7 +500,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   if (up_bytes > staging_bytes || align256(nc * sizeof(DevCubeOut)) + cnf.q.size() * 8 > staging_bytes)
     fail(SCUBA_E_INTERNAL, "staging too small");
   // host-side checks of what the kernels assume
-  const size_t up_lds = size_t(rh.nw_max) * 4 * 4;
+  const size_t up_lds = size_t(rh.nw_max) * 4 * 4 + cnf.stage_bytes;
   const size_t leaf_lds = size_t(std::max<uint32_t>(rh.tile_max, 1)) * 16;
   if (up_lds + 1024 > info.max_lds) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
   if (leaf_lds + 64 > info.max_lds) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");

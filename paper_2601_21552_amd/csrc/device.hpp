@@ -12,6 +12,8 @@ struct DevQueryDesc {
   uint64_t lit_base;    // index into the literal array
   uint32_t n_clauses;
   uint32_t n_vars;
+  uint32_t staged;      // 1: the propagation kernel copies the CNF to LDS
+  uint32_t pad;
 };
 
 // One cube to evaluate.
@@ -67,6 +69,7 @@ struct CnfHost {
   std::vector<DevQueryDesc> q;
   std::vector<uint32_t> coff;
   std::vector<int32_t> lits;
+  size_t stage_bytes = 0;     // LDS for the largest staged CNF (16-bit form)
 };
 
 void dev_init(DeviceInfo* info, int device);

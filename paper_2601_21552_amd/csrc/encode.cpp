@@ -57,20 +57,28 @@ class Gates {
 
   int32_t fresh() { return int32_t(++q_.n_vars); }
 
-  void clause(std::initializer_list<int32_t> ls) { clause(std::vector<int32_t>(ls)); }
-  void clause(std::vector<int32_t> ls) {
-    std::vector<int32_t> c;
-    for (int32_t l : ls) {
-      if (l == kTrue) return;
+  static void sort3(int32_t* x, int n) {
+    for (int i = 1; i < n; i++)
+      for (int j = i; j > 0 && x[j - 1] > x[j]; j--) std::swap(x[j - 1], x[j]);
+  }
+
+  void clause(std::initializer_list<int32_t> ls) { clause(ls.begin(), ls.size()); }
+  void clause(const std::vector<int32_t>& ls) { clause(ls.data(), ls.size()); }
+  // Appends the clause after dropping false constants and repeated
+  // literals; a true constant or a complementary pair drops the clause.
+  void clause(const int32_t* ls, size_t n) {
+    const size_t start = q_.lits.size();
+    for (size_t i = 0; i < n; i++) {
+      int32_t l = ls[i];
+      if (l == kTrue) { q_.lits.resize(start); return; }
       if (l == kFalse) continue;
       bool dup = false;
-      for (int32_t x : c) {
-        if (x == l) dup = true;
-        if (x == -l) return;  // tautology
+      for (size_t j = start; j < q_.lits.size(); j++) {
+        if (q_.lits[j] == l) dup = true;
+        if (q_.lits[j] == -l) { q_.lits.resize(start); return; }  // tautology
       }
-      if (!dup) c.push_back(l);
+      if (!dup) q_.lits.push_back(l);
     }
-    for (int32_t l : c) q_.lits.push_back(l);
     q_.off.push_back(q_.lits.size());
   }
 
@@ -128,19 +136,21 @@ class Gates {
       if (x == kTrue) { x = kFalse; flip = !flip; }
       else if (x < 0 && x != kFalse) { x = -x; flip = !flip; }
     }
-    std::vector<int32_t> xs;
-    for (int32_t x : v) if (x != kFalse) xs.push_back(x);
-    std::sort(xs.begin(), xs.end());
+    int32_t xs[3];
+    int nx = 0;
+    for (int32_t x : v) if (x != kFalse) xs[nx++] = x;
+    sort3(xs, nx);
     // cancel equal pairs
-    std::vector<int32_t> ys;
-    for (size_t i = 0; i < xs.size();) {
-      if (i + 1 < xs.size() && xs[i] == xs[i + 1]) { i += 2; continue; }
-      ys.push_back(xs[i++]);
+    int32_t ys[3];
+    int ny = 0;
+    for (int i = 0; i < nx;) {
+      if (i + 1 < nx && xs[i] == xs[i + 1]) { i += 2; continue; }
+      ys[ny++] = xs[i++];
     }
     int32_t r;
-    if (ys.empty()) r = kFalse;
-    else if (ys.size() == 1) r = ys[0];
-    else if (ys.size() == 2) r = XOR(ys[0], ys[1]);
+    if (ny == 0) r = kFalse;
+    else if (ny == 1) r = ys[0];
+    else if (ny == 2) r = XOR(ys[0], ys[1]);
     else {
       GateKey k{3, ys[0], ys[1], ys[2]};
       auto it = cache_.find(k);
@@ -175,7 +185,10 @@ class Gates {
     bool flip = false;
     if (neg >= 2) { a = -a; b = -b; c = -c; flip = true; }
     int32_t s[3] = {a, b, c};
-    std::sort(s, s + 3, [](int32_t x, int32_t y) { return std::abs(x) < std::abs(y); });
+    auto by_var = [](int32_t& x, int32_t& y) { if (std::abs(x) > std::abs(y)) std::swap(x, y); };
+    by_var(s[0], s[1]);
+    by_var(s[1], s[2]);
+    by_var(s[0], s[1]);
     GateKey k{4, s[0], s[1], s[2]};
     int32_t r;
     auto it = cache_.find(k);

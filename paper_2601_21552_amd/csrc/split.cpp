@@ -199,21 +199,22 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
 
 bool Splitter::leaf_of(const std::vector<int32_t>& cube, std::vector<int8_t>* assign,
                        std::vector<int32_t>* active, uint32_t* nres) {
-  Splitter t(q_, k_, max_res_, max_cubes_);
-  t.reset_state();
-  bool ok = t.root_propagate();
-  for (size_t i = 0; ok && i < cube.size(); i++) ok = t.enqueue_and_propagate(cube[i]);
+  started_ = true;
+  state_ = kExhausted;
+  reset_state();
+  bool ok = root_propagate();
+  for (size_t i = 0; ok && i < cube.size(); i++) ok = enqueue_and_propagate(cube[i]);
   if (!ok) return false;
-  *assign = t.assign_;
+  *assign = assign_;
   active->clear();
   std::vector<char> act(size_t(n_) + 1, 0);
   uint32_t unsat = 0;
   for (uint64_t c = 0; c < q_.n_clauses(); c++) {
-    if (t.ntrue_[c]) continue;
+    if (ntrue_[c]) continue;
     unsat++;
     for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
       int32_t v = std::abs(q_.lits[i]);
-      if (t.assign_[v] < 0) act[v] = 1;
+      if (assign_[v] < 0) act[v] = 1;
     }
   }
   for (uint32_t v = 1; v <= n_; v++)

@@ -37,10 +37,10 @@ class Splitter {
   uint64_t cubes_refuted() const { return n_refuted_; }
   bool root_conflict() const { return root_conflict_; }
 
-  // Propagation fixpoint of (F, cube) from scratch on a fresh copy of the
-  // counters: assignment (-1/0/1 per variable, index 0 unused), active
-  // variables in increasing order, and the number of unsatisfied clauses.
-  // Returns false on a conflict.
+  // Propagation fixpoint of (F, cube) from the root: assignment (-1/0/1 per
+  // variable, index 0 unused), active variables in increasing order, and the
+  // number of unsatisfied clauses.  Returns false on a conflict.  This
+  // abandons the depth-first walk (next() returns kExhausted afterwards).
   bool leaf_of(const std::vector<int32_t>& cube, std::vector<int8_t>* assign,
                std::vector<int32_t>* active, uint32_t* nres);
 
