@@ -165,11 +165,27 @@ void scuba_cnf_free(scuba_cnf* cnf);
  * fixpoint; a node whose propagation conflicts is a refuted cube; a node
  * with at most k active variables (unassigned and occurring in a clause not
  * yet satisfied) becomes a leaf; otherwise the scorer picks a branching
- * variable and the 0-child is explored before the 1-child.  The static
+ * variable and the 0-child is explored before the 1-child; backjumping
+ * prunes a 1-child when every failure below its 0-sibling was a host
+ * conflict that does not involve the branching variable.  The static
  * scorer takes the active variable with the most literal occurrences in the
  * original CNF, ties to the lowest index.  Cubes hold the branching literals
  * only.  A query whose tree exceeds max_cubes is cut (UNKNOWN).             */
 #define SCUBA_SCORER_STATIC 0u
+#define SCUBA_SCORER_LEARNED 1u
+/* Learned ordering: at a decision node the top `candidates` active variables
+ * of the static order are scored by the perceptron below (scuba_mlp_*),
+ * batched over all queries on the device; the ranking orders the decisions
+ * of that node and of `rescore` levels below it.  Non-finite scores fall
+ * back to the static order.  master / wbf16: device parameter block and its
+ * bf16 copy (see the learned-scorer section). */
+typedef struct {
+  const float* master;
+  const uint16_t* wbf16;
+  uint32_t candidates;   /* 2..64 */
+  uint32_t rescore;      /* >= 1 */
+} scuba_learned_scorer;
+
 typedef struct {
   uint32_t k;            /* max active variables per leaf (<= 38)            */
   uint32_t scorer;       /* SCUBA_SCORER_*                                   */
@@ -177,10 +193,23 @@ typedef struct {
   uint32_t max_residual; /* a leaf must also have at most this many residual
                             clauses (0 = the device limit)                   */
   uint32_t reserved;
+  /* SCUBA_SCORER_LEARNED only: the scorer, device memory of at least
+     scuba_scorer_workspace(cnf, candidates) bytes, and the stream         */
+  const scuba_learned_scorer* learned;
+  void* dev_ws;
+  size_t ws_bytes;
+  void* hip_stream;
 } scuba_split_opts;
+/* Device bytes the learned scorer needs for a batch (one row per candidate
+ * of every query). */
+size_t scuba_scorer_workspace(const scuba_cnf* cnf, uint32_t candidates);
 
 #define SCUBA_CUBE_LEAF 0
-#define SCUBA_CUBE_REFUTED 1
+#define SCUBA_CUBE_REFUTED 1   /* unit propagation of the cube conflicts        */
+#define SCUBA_CUBE_PRUNED 2    /* a 1-branch whose 0-sibling failed by host
+                                  conflicts independent of the branching
+                                  variable (backjumping): no model, but not
+                                  necessarily refuted by propagation alone   */
 scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split_opts* opts,
                          scuba_cubes** out);
 /* Cubes from arrays: q_cube_start[nq+1] indexes cubes, cube_off[ncubes+1]
@@ -200,6 +229,24 @@ typedef struct {
 scuba_status scuba_cubes_view_get(const scuba_cubes* cubes, uint32_t qi, scuba_cubes_view* out);
 void scuba_cubes_free(scuba_cubes* cubes);
 
+/* Traces for training the scorer: the static walk of every query, and at
+ * every `every`-th decision node above depth `depth` the features of the top
+ * `candidates` variables with a one-step lookahead label: log2(1 + f - f0)
+ * + log2(1 + f - f1), f the node's active count and f0 / f1 those after
+ * propagating the variable to 0 / 1 (0 for a conflict).  Rows of a node are
+ * contiguous; node = query index << 32 | decision number. */
+typedef struct scuba_trace scuba_trace;
+typedef struct {
+  uint32_t k, candidates, every, depth;
+  uint64_t max_cubes;
+} scuba_trace_opts;
+scuba_status scuba_trace_run(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_trace_opts* opts,
+                             scuba_trace** out);
+/* Borrowed arrays: features[rows * 16], labels[rows], nodes[rows]. */
+scuba_status scuba_trace_view(const scuba_trace* t, uint64_t* rows, const float** features,
+                              const float** labels, const uint64_t** nodes);
+void scuba_trace_free(scuba_trace* t);
+
 /* ---------------------------------------------------------------- solve */
 #define SCUBA_MODE_DECIDE 0u   /* stop a query at its first satisfying leaf  */
 #define SCUBA_MODE_COUNT 1u    /* count every leaf's satisfying assignments   */
@@ -213,7 +260,9 @@ typedef struct {
   uint32_t grid;             /* persistent workgroups (0 = 8 per CU)          */
   uint32_t max_rounds;       /* scuba_decide rounds (0 = unbounded)           */
   uint32_t scorer;           /* SCUBA_SCORER_*                                */
-  uint32_t reserved[3];
+  uint32_t reserved;
+  const scuba_learned_scorer* learned;   /* SCUBA_SCORER_LEARNED only; its
+                                 buffers come from the end of the workspace */
 } scuba_solve_opts;
 
 /* Device bytes scuba_solve / scuba_decide need for this batch. */
@@ -239,6 +288,29 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
  * is exhausted, or its budget is spent.                                    */
 scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
                           void* dev_ws, size_t ws_bytes, void* hip_stream, scuba_results** out);
+
+/* ---------------------------------------------------------------- learned scorer
+ * A perceptron scoring candidate branching variables: 16 features -> 128 ->
+ * 128 -> 1, ReLU, bf16 weights and activations, fp32 accumulation on the
+ * matrix cores; trained by mean squared error with Adam on fp32 master
+ * weights.  Parameter block (fp32, scuba_mlp_param_count() values):
+ *   W1[16][128] | b1[128] | W2[128][128] | b2[128] | w3[128] | b3[1]
+ * and a bf16 copy with the same offsets.  All pointers below are device
+ * pointers (row-major); the calls queue work on the stream and return
+ * without synchronising it.  x: batch x 16 bf16; a1, a2, dz1, dz2:
+ * batch x 128 bf16; y, target: batch fp32; grad/m/v: parameter-sized fp32. */
+#define SCUBA_MLP_FEATURES 16
+#define SCUBA_MLP_HIDDEN 128
+uint32_t scuba_mlp_param_count(void);
+scuba_status scuba_mlp_sync(scuba_ctx* ctx, const float* master, uint16_t* wbf16, void* hip_stream);
+scuba_status scuba_mlp_forward(scuba_ctx* ctx, const uint16_t* wbf16, const float* master, const uint16_t* x,
+                               uint32_t batch, uint16_t* a1, uint16_t* a2, float* y, void* hip_stream);
+scuba_status scuba_mlp_backward(scuba_ctx* ctx, const uint16_t* wbf16, const uint16_t* x, const uint16_t* a1,
+                                const uint16_t* a2, const float* y, const float* target, uint32_t batch,
+                                uint16_t* dz1, uint16_t* dz2, float* grad, void* hip_stream);
+scuba_status scuba_mlp_adam(scuba_ctx* ctx, float* master, const float* grad, float* m, float* v,
+                            uint16_t* wbf16, uint32_t step, float lr, float beta1, float beta2, float eps,
+                            void* hip_stream);
 
 /* ---------------------------------------------------------------- results */
 #define SCUBA_HOW_ROOT 0    /* decided by normalisation / root propagation */

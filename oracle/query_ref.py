@@ -442,6 +442,30 @@ def _poly_range(q, p, polys):
     return lo, hi
 
 
+def _substitute(p, atom, expr):
+    """p with every occurrence of atom replaced by the polynomial expr."""
+    out = {}
+    for m, c in p.items():
+        k = m.count(atom)
+        term = {tuple(x for x in m if x != atom): c}
+        for _ in range(k):
+            nxt = {}
+            for m1, c1 in term.items():
+                for m2, c2 in expr.items():
+                    mm = tuple(sorted(m1 + m2))
+                    nxt[mm] = nxt.get(mm, 0) + c1 * c2
+            term = nxt
+        for mm, cc in term.items():
+            out[mm] = out.get(mm, 0) + cc
+    return {m: c for m, c in out.items() if c != 0}
+
+
+def _substitute_all(p, subs):
+    for atom, expr in subs:
+        p = _substitute(p, atom, expr)
+    return p
+
+
 def root_check(q):
     """UNSAT if the root conjunction bounds one polynomial by an empty
     interval; else None (undecided)."""
@@ -489,6 +513,29 @@ def root_check(q):
     for r in q.roots:
         collect(r, True)
 
+    # Root equalities that define an atom linearly (coefficient +-1, the
+    # atom in no other monomial) are used to eliminate it from every fact;
+    # the rewritten facts are implied by the originals and join them.
+    subs = []                       # (atom, polynomial free of pivots)
+    for p, kind in facts:
+        if kind != "eq":
+            continue
+        p = _substitute_all(p, subs)
+        pivot = None
+        for m, c in p.items():
+            if len(m) == 1 and abs(c) == 1 and \
+                    all(m[0] not in m2 for m2 in p if m2 != m):
+                pivot = (m[0], c)
+                break
+        if pivot is None:
+            continue
+        atom, c = pivot
+        # atom = -(p - c*atom) / c
+        expr = {m: -cc * c for m, cc in p.items() if m != (atom,)}
+        subs = [(a, _substitute(e, atom, expr)) for a, e in subs]
+        subs.append((atom, expr))
+    facts = facts + [(_substitute_all(p, subs), kind) for p, kind in facts]
+
     bounds = {}   # normalised polynomial -> [lo, hi] (None = unbounded)
     for p, kind in facts:
         c0 = p.get((), 0)
@@ -530,14 +577,21 @@ def root_check(q):
 
 # ------------------------------------------------------------ decide
 
-def decide(q, max_nodes: int = cnf_ref.DEFAULT_NODES):
-    """(verdict, witness input values or None, how) for one query."""
+def decide(q, max_nodes: int = cnf_ref.DEFAULT_NODES, candidate=None):
+    """(verdict, witness input values or None, how) for one query.
+
+    Root check, else DPLL on the oracle's own encoding.  When DPLL runs out
+    of its node budget and a candidate input tuple is given, the candidate
+    decides by the definition itself: SAT iff it satisfies every root under
+    exact integer arithmetic ("checked"); otherwise the verdict is UNKNOWN."""
     if root_check(q) == UNSAT:
         return UNSAT, None, "root"
     cnf, inputs = encode(q)
     verdict, model, _ = cnf_ref.solve(cnf, max_nodes)
     if verdict == SAT:
         return SAT, decode_inputs(model, inputs), "dpll"
+    if verdict == UNKNOWN and candidate is not None and int_eval(q, candidate):
+        return SAT, list(candidate), "checked"
     return verdict, None, "dpll"
 
 

@@ -18,7 +18,8 @@ SAT, UNSAT, UNKNOWN = 1, 0, 2
 VERDICT = {1: "SAT", 0: "UNSAT", 2: "UNKNOWN"}
 HOW = {0: "root", 1: "device", 2: "budget"}
 MODE_DECIDE, MODE_COUNT = 0, 1
-CUBE_LEAF, CUBE_REFUTED = 0, 1
+SCORER_STATIC, SCORER_LEARNED = 0, 1
+CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2
 BB_NO_REWRITE = 1
 
 # scuba_node: {u32 op, a, b, width; u64 imm} (24 bytes)
@@ -33,9 +34,21 @@ class CnfView(C.Structure):
                 ("root_unsat", C.c_int32)]
 
 
+class LearnedScorer(C.Structure):
+    _fields_ = [("master", C.c_void_p), ("wbf16", C.c_void_p),
+                ("candidates", C.c_uint32), ("rescore", C.c_uint32)]
+
+
 class SplitOpts(C.Structure):
     _fields_ = [("k", C.c_uint32), ("scorer", C.c_uint32), ("max_cubes", C.c_uint64),
-                ("max_residual", C.c_uint32), ("reserved", C.c_uint32)]
+                ("max_residual", C.c_uint32), ("reserved", C.c_uint32),
+                ("learned", C.POINTER(LearnedScorer)), ("dev_ws", C.c_void_p),
+                ("ws_bytes", C.c_size_t), ("hip_stream", C.c_void_p)]
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("candidates", C.c_uint32), ("every", C.c_uint32),
+                ("depth", C.c_uint32), ("max_cubes", C.c_uint64)]
 
 
 class CubesView(C.Structure):
@@ -48,7 +61,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("k", C.c_uint32), ("max_cubes", C.c_uint64),
                 ("leaves_per_round", C.c_uint32), ("chunk_log2", C.c_uint32),
                 ("grid", C.c_uint32), ("max_rounds", C.c_uint32), ("scorer", C.c_uint32),
-                ("reserved", C.c_uint32 * 3)]
+                ("reserved", C.c_uint32), ("learned", C.POINTER(LearnedScorer))]
 
 
 class QueryResult(C.Structure):
@@ -78,7 +91,13 @@ SIGNATURES = {
     "scuba_cnf_view_get": (C.c_int32, [P, C.c_uint32, C.POINTER(CnfView)]),
     "scuba_cnf_input_map": (C.c_int32, [P, C.c_uint32, P, P, C.c_uint32]),
     "scuba_cnf_free": (None, [P]),
+    "scuba_scorer_workspace": (C.c_size_t, [P, C.c_uint32]),
     "scuba_split": (C.c_int32, [P, P, C.POINTER(SplitOpts), C.POINTER(P)]),
+    "scuba_trace_run": (C.c_int32, [P, P, C.POINTER(TraceOpts), C.POINTER(P)]),
+    "scuba_trace_view": (C.c_int32, [P, C.POINTER(C.c_uint64), C.POINTER(C.POINTER(C.c_float)),
+                                     C.POINTER(C.POINTER(C.c_float)),
+                                     C.POINTER(C.POINTER(C.c_uint64))]),
+    "scuba_trace_free": (None, [P]),
     "scuba_cubes_from_arrays": (C.c_int32, [P, P, P, P, P, C.POINTER(P)]),
     "scuba_cubes_view_get": (C.c_int32, [P, C.c_uint32, C.POINTER(CubesView)]),
     "scuba_cubes_free": (None, [P]),
@@ -92,6 +111,12 @@ SIGNATURES = {
     "scuba_leaf_get": (C.c_int32, [P, C.c_uint32, C.c_uint64, C.POINTER(LeafResult)]),
     "scuba_results_timing": (C.c_int32, [P, P, C.c_uint32]),
     "scuba_results_free": (None, [P]),
+    "scuba_mlp_param_count": (C.c_uint32, []),
+    "scuba_mlp_sync": (C.c_int32, [P, P, P, P]),
+    "scuba_mlp_forward": (C.c_int32, [P, P, P, P, C.c_uint32, P, P, P, P]),
+    "scuba_mlp_backward": (C.c_int32, [P, P, P, P, P, P, P, C.c_uint32, P, P, P, P]),
+    "scuba_mlp_adam": (C.c_int32, [P, P, P, P, P, P, C.c_uint32, C.c_float, C.c_float,
+                                   C.c_float, C.c_float, P]),
 }
 
 _lib = None

@@ -25,8 +25,9 @@ class _Handle:
         self.ctx, self.h = ctx, h
 
     def __del__(self):
-        if getattr(self, "h", None) and self._free:
-            getattr(L.load(), self._free)(self.h)
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and self._free and L is not None and L._lib is not None:
+            getattr(L._lib, self._free)(self.h)
             self.h = None
 
 
@@ -112,11 +113,16 @@ class Results(_Handle):
 
 
 def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_log2=0,
-                grid=0, max_rounds=0, scorer=0):
+                grid=0, max_rounds=0, learned=None):
+    """learned: an L.LearnedScorer (Mlp.scorer()) selects the learned
+    ordering; None the static one."""
     o = L.SolveOpts()
     o.mode, o.k, o.max_cubes = mode, k, max_cubes
     o.leaves_per_round, o.chunk_log2, o.grid = leaves_per_round, chunk_log2, grid
-    o.max_rounds, o.scorer = max_rounds, scorer
+    o.max_rounds = max_rounds
+    if learned is not None:
+        o.scorer = L.SCORER_LEARNED
+        o.learned = C.pointer(learned)
     return o
 
 
@@ -174,12 +180,45 @@ class Context:
 
     # ------------------------------------------------------------ cubes
     def split(self, cnf: Cnf, k: int, max_cubes: int = 0, max_residual: int = 0,
-              scorer: int = 0) -> Cubes:
+              learned=None, workspace=None, stream=None) -> Cubes:
+        """Host cube splitting; learned (an L.LearnedScorer) scores the
+        branching candidates on the device."""
         o = L.SplitOpts()
-        o.k, o.scorer, o.max_cubes, o.max_residual = k, scorer, max_cubes, max_residual
+        o.k, o.max_cubes, o.max_residual = k, max_cubes, max_residual
+        if learned is not None:
+            nbytes = self.lib.scuba_scorer_workspace(cnf.h, learned.candidates)
+            ws = self._workspace(nbytes, workspace)
+            o.scorer = L.SCORER_LEARNED
+            o.learned = C.pointer(learned)
+            o.dev_ws, o.ws_bytes = ws.data_ptr(), ws.numel()
+            o.hip_stream = self._stream(stream).value
         h = _P()
         self._check(self.lib.scuba_split(self.h, cnf.h, C.byref(o), C.byref(h)))
         return Cubes(self, h)
+
+    def trace(self, cnf: Cnf, k: int, candidates: int = 16, every: int = 1, depth: int = 64,
+              max_cubes: int = 0):
+        """Training rows of the static walks: (features [rows, 16] float32,
+        labels [rows] float32, nodes [rows] uint64 = query << 32 | decision)."""
+        o = L.TraceOpts(k, candidates, every, depth, max_cubes)
+        h = _P()
+        self._check(self.lib.scuba_trace_run(self.h, cnf.h, C.byref(o), C.byref(h)))
+        try:
+            rows = C.c_uint64()
+            fp, lp = C.POINTER(C.c_float)(), C.POINTER(C.c_float)()
+            npp = C.POINTER(C.c_uint64)()
+            self._check(self.lib.scuba_trace_view(h, C.byref(rows), C.byref(fp), C.byref(lp),
+                                                  C.byref(npp)))
+            n = rows.value
+            if n == 0:
+                return (np.zeros((0, 16), np.float32), np.zeros(0, np.float32),
+                        np.zeros(0, np.uint64))
+            f = np.ctypeslib.as_array(fp, shape=(n * 16,)).reshape(n, 16).copy()
+            lab = np.ctypeslib.as_array(lp, shape=(n,)).copy()
+            nodes = np.ctypeslib.as_array(npp, shape=(n,)).copy()
+            return f, lab, nodes
+        finally:
+            self.lib.scuba_trace_free(h)
 
     def cubes_from_arrays(self, cnf: Cnf, cubes_per_query) -> Cubes:
         qs, off, lits = [0], [0], []
@@ -240,3 +279,100 @@ class Context:
         self._check(self.lib.scuba_decide(self.h, cnf.h, C.byref(o), _P(ws.data_ptr()), ws.numel(),
                                           self._stream(stream), C.byref(h)))
         return Results(self, h, len(cnf))
+
+
+class Mlp:
+    """Device state of the learned scorer (fp32 master parameters, their
+    bf16 copy, Adam moments) and the calls of the C ABI on it.  torch
+    tensors carry the device memory; every operation runs in libscuba.so."""
+
+    F = 16
+    H = 128
+
+    def __init__(self, ctx: Context, params=None, device=None):
+        import torch
+        self.ctx = ctx
+        self.torch = torch
+        self.dev = device or f"cuda:{ctx.device}"
+        n = ctx.lib.scuba_mlp_param_count()
+        self.n_params = n
+        if params is None:
+            params = np.zeros(n, np.float32)
+        params = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        assert params.size == n
+        self.master = torch.tensor(params, device=self.dev)
+        self.wb = torch.empty(n, dtype=torch.bfloat16, device=self.dev)
+        self.m = torch.zeros(n, dtype=torch.float32, device=self.dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=self.dev)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=self.dev)
+        self.step_count = 0
+        self.sync()
+
+    def _s(self):
+        return _P(self.torch.cuda.current_stream().cuda_stream)
+
+    @staticmethod
+    def _p(t):
+        return _P(t.data_ptr())
+
+    def sync(self):
+        self.ctx._check(self.ctx.lib.scuba_mlp_sync(self.ctx.h, self._p(self.master), self._p(self.wb),
+                                                     self._s()))
+
+    def forward(self, x):
+        """x: [B, 16] bf16 device tensor -> (y [B] fp32, a1, a2)."""
+        torch = self.torch
+        B = x.shape[0]
+        a1 = torch.empty((B, self.H), dtype=torch.bfloat16, device=self.dev)
+        a2 = torch.empty((B, self.H), dtype=torch.bfloat16, device=self.dev)
+        y = torch.empty(B, dtype=torch.float32, device=self.dev)
+        x = x.contiguous()
+        self.ctx._check(self.ctx.lib.scuba_mlp_forward(self.ctx.h, self._p(self.wb), self._p(self.master),
+                                                        self._p(x), B, self._p(a1), self._p(a2),
+                                                        self._p(y), self._s()))
+        return y, a1, a2
+
+    def backward(self, x, a1, a2, y, target):
+        """Gradient of the mean squared error into self.grad."""
+        torch = self.torch
+        B = x.shape[0]
+        dz1 = torch.empty((B, self.H), dtype=torch.bfloat16, device=self.dev)
+        dz2 = torch.empty((B, self.H), dtype=torch.bfloat16, device=self.dev)
+        target = target.contiguous().float()
+        self.ctx._check(self.ctx.lib.scuba_mlp_backward(
+            self.ctx.h, self._p(self.wb), self._p(x.contiguous()), self._p(a1), self._p(a2), self._p(y),
+            self._p(target), B, self._p(dz1), self._p(dz2), self._p(self.grad), self._s()))
+        return self.grad
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        self.ctx._check(self.ctx.lib.scuba_mlp_adam(
+            self.ctx.h, self._p(self.master), self._p(self.grad), self._p(self.m), self._p(self.v),
+            self._p(self.wb), self.step_count, lr, beta1, beta2, eps, self._s()))
+
+    def params(self) -> np.ndarray:
+        return self.master.detach().cpu().numpy().copy()
+
+    def scorer(self, candidates: int = 16, rescore: int = 1) -> "L.LearnedScorer":
+        """The learned-ordering option for split/decide (keeps this Mlp's
+        device parameters alive while it is referenced)."""
+        s = L.LearnedScorer(self.master.data_ptr(), self.wb.data_ptr(), candidates, rescore)
+        s._owner = self
+        return s
+
+
+def mlp_flatten(p: dict) -> np.ndarray:
+    """Parameter dict (W1, b1, W2, b2, w3, b3) -> the C ABI's flat layout."""
+    return np.concatenate([np.asarray(p[k], np.float32).reshape(-1)
+                           for k in ("W1", "b1", "W2", "b2", "w3", "b3")])
+
+
+def mlp_unflatten(v: np.ndarray, F: int = 16, H: int = 128) -> dict:
+    v = np.asarray(v, np.float32)
+    sizes = [("W1", (F, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))]
+    out, o = {}, 0
+    for k, shp in sizes:
+        n = int(np.prod(shp))
+        out[k] = v[o:o + n].reshape(shp).copy()
+        o += n
+    return out

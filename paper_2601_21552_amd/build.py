@@ -16,7 +16,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SRCS = ["api.cpp", "encode.cpp", "split.cpp", "verify.cpp"]
-HIP_SRCS = ["device.hip"]
+HIP_SRCS = ["device.hip", "mlp.hip"]
 
 CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
             "-fvisibility=hidden"]

@@ -8,6 +8,7 @@
 #include "bigint.hpp"
 #include "common.hpp"
 #include "device.hpp"
+#include "mlp.hpp"
 #include "parallel.hpp"
 #include "split.hpp"
 
@@ -99,9 +100,11 @@ constexpr uint32_t kMaxCubeLen = 4096;
 struct Opts {
   uint32_t mode, k, lpr, chunk_log2, grid, max_rounds, scorer;
   uint64_t max_cubes;
+  const scuba_learned_scorer* learned;
 };
 Opts resolve(const scuba_solve_opts* o) {
-  Opts r{SCUBA_MODE_DECIDE, kDefaultK, kDefaultLeavesPerRound, kDefaultChunkLog2, 0, 0, 0, kDefaultMaxCubes};
+  Opts r{SCUBA_MODE_DECIDE, kDefaultK, kDefaultLeavesPerRound, kDefaultChunkLog2, 0, 0, 0, kDefaultMaxCubes,
+         nullptr};
   if (o) {
     r.mode = o->mode;
     if (o->k) r.k = o->k;
@@ -111,11 +114,20 @@ Opts resolve(const scuba_solve_opts* o) {
     r.max_rounds = o->max_rounds;
     r.scorer = o->scorer;
     if (o->max_cubes) r.max_cubes = o->max_cubes;
+    r.learned = o->learned;
   }
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
   if (r.chunk_log2 > 26) fail(SCUBA_E_INVALID, "chunk_log2 above 26");
-  if (r.scorer != SCUBA_SCORER_STATIC) fail(SCUBA_E_INVALID, "unknown scorer");
+  if (r.scorer > SCUBA_SCORER_LEARNED) fail(SCUBA_E_INVALID, "unknown scorer");
+  if (r.scorer == SCUBA_SCORER_LEARNED) {
+    const scuba_learned_scorer* l = r.learned;
+    if (!l || !l->master || !l->wbf16) fail(SCUBA_E_INVALID, "learned scorer without parameters");
+    if (l->candidates < 2 || l->candidates > 64) fail(SCUBA_E_INVALID, "scorer candidates outside 2..64");
+    if (l->rescore < 1) fail(SCUBA_E_INVALID, "scorer rescore must be >= 1");
+  } else {
+    r.learned = nullptr;
+  }
   return r;
 }
 
@@ -157,15 +169,15 @@ uint64_t blocks_of(int32_t f) { return f >= 12 ? (uint64_t(1) << (f - 12)) : 1; 
 // no leaf work.  Work items are made afterwards by make_items.
 uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint32_t n_vars) {
   if (c.lits.size() > kMaxCubeLen) fail(SCUBA_E_CAPACITY, "cube longer than 4096 literals");
-  if (!c.refuted && (c.f < 0 || uint32_t(c.f) > kMaxLeafVars))
+  if (!c.refuted() && (c.f < 0 || uint32_t(c.f) > kMaxLeafVars))
     fail(SCUBA_E_CAPACITY, "leaf with more than 38 active variables");
   DevCubeDesc d;
   d.qid = qid;
   d.lit_off = uint32_t(rh.cube_lits.size());
   d.n_lits = uint32_t(c.lits.size());
   d.seq = seq;
-  d.f_expect = c.refuted ? -1 : c.f;
-  d.nres_cap = c.refuted ? 0 : c.nres;
+  d.f_expect = c.refuted() ? -1 : c.f;
+  d.nres_cap = c.refuted() ? 0 : c.nres;
   d.res_base = rh.res_records;
   rh.res_records += d.nres_cap;
   rh.tile_max = std::max(rh.tile_max, d.nres_cap);
@@ -273,7 +285,7 @@ void assemble_witness(const CnfQuery& q, Splitter& sp, const std::vector<int32_t
 // The device's propagation must reach the host's fixpoint: the same
 // refutation, active count and number of unsatisfied clauses.
 void check_out(const DevCubeOut& o, const Cube& host) {
-  if (host.refuted) {
+  if (host.refuted()) {
     if (o.status != 1) fail(SCUBA_E_DEVICE, "device kept a cube the host propagation refuted");
     return;
   }
@@ -282,6 +294,100 @@ void check_out(const DevCubeOut& o, const Cube& host) {
   if (o.status == 1) fail(SCUBA_E_DEVICE, "device refuted a leaf the host propagation kept");
   if (o.f != host.f || uint32_t(o.nres) != host.nres)
     fail(SCUBA_E_DEVICE, "device leaf disagrees with the host (active count or residual)");
+}
+
+// Batched device scoring for learned orderings: the candidates of every
+// waiting walk go through the perceptron in one pass.  Workspace layout:
+// x bf16 [cap x 16] | a1 bf16 [cap x 128] | a2 bf16 [cap x 128] | y f32 [cap].
+size_t scorer_bytes(size_t rows) {
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  return al(rows * kMlpF * 2) + 2 * al(rows * kMlpH * 2) + al(rows * 4);
+}
+uint16_t to_bf16(float f) {   // round to nearest, ties to even
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return uint16_t((u >> 16) | 0x40);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+struct ScorerRunner {
+  scuba_ctx* ctx;
+  const scuba_learned_scorer* s;
+  char* ws;
+  size_t rows_cap;
+  void* stream;
+  uint64_t rows_scored = 0, passes = 0;
+
+  void score(const std::vector<Splitter*>& waiting) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t i = 0;
+    while (i < waiting.size()) {
+      // as many whole requests as fit
+      size_t j = i, rows = 0;
+      while (j < waiting.size() && rows + waiting[j]->request_vars().size() <= rows_cap) {
+        rows += waiting[j]->request_vars().size();
+        j++;
+      }
+      if (j == i) fail(SCUBA_E_CAPACITY, "scorer workspace smaller than one request");
+      void* stg = ctx->staging(std::max(rows * kMlpF * 2, rows * 4) + 256);
+      uint16_t* xh = static_cast<uint16_t*>(stg);
+      size_t r = 0;
+      for (size_t q = i; q < j; q++) {
+        const std::vector<float>& fe = waiting[q]->request_features();
+        for (float v : fe) xh[r++] = to_bf16(v);
+      }
+      uint16_t* x = reinterpret_cast<uint16_t*>(ws);
+      uint16_t* a1 = reinterpret_cast<uint16_t*>(ws + al(rows_cap * kMlpF * 2));
+      uint16_t* a2 = reinterpret_cast<uint16_t*>(ws + al(rows_cap * kMlpF * 2) + al(rows_cap * kMlpH * 2));
+      float* y = reinterpret_cast<float*>(ws + al(rows_cap * kMlpF * 2) + 2 * al(rows_cap * kMlpH * 2));
+      dev_copy_h2d(x, xh, rows * kMlpF * 2, stream);
+      mlp_forward(s->wbf16, s->master, x, uint32_t(rows), a1, a2, y, stream);
+      dev_copy_d2h(stg, y, rows * 4, stream);
+      dev_sync(stream);
+      const float* yh = static_cast<const float*>(stg);
+      size_t off = 0;
+      for (size_t q = i; q < j; q++) {
+        waiting[q]->provide_scores(yh + off);
+        off += waiting[q]->request_vars().size();
+      }
+      rows_scored += rows;
+      passes++;
+      i = j;
+    }
+  }
+};
+
+// Advance every walk until it has produced max_leaves leaves (or ended),
+// scoring on the device whenever walks wait for a learned decision.
+void run_walks(std::vector<Splitter*>& walks, uint32_t max_leaves, std::vector<std::vector<Cube>>& out,
+               bool keep, std::vector<Splitter::State>& state, ScorerRunner* runner) {
+  std::vector<size_t> todo(walks.size());
+  for (size_t i = 0; i < todo.size(); i++) todo[i] = i;
+  while (!todo.empty()) {
+    parallel_for(todo.size(), [&](size_t t) {
+      const size_t i = todo[t];
+      state[i] = walks[i]->next(max_leaves, out[i], keep);
+    });
+    std::vector<Splitter*> waiting;
+    std::vector<size_t> next;
+    for (size_t i : todo)
+      if (state[i] == Splitter::kNeedScore) {
+        waiting.push_back(walks[i]);
+        next.push_back(i);
+      }
+    if (waiting.empty()) break;
+    if (!runner) fail(SCUBA_E_INTERNAL, "learned walk without a scorer");
+    runner->score(waiting);
+    todo.swap(next);
+  }
+}
+
+void check_learned(const scuba_learned_scorer* l) {
+  scuba_solve_opts so{};
+  so.scorer = SCUBA_SCORER_LEARNED;
+  so.learned = l;
+  resolve(&so);
 }
 
 }  // namespace
@@ -410,34 +516,104 @@ void scuba_cnf_free(scuba_cnf* cnf) { delete cnf; }
 
 // ---------------------------------------------------------------- cubes
 
+size_t scuba_scorer_workspace(const scuba_cnf* cnf, uint32_t candidates) {
+  return cnf ? scorer_bytes(size_t(cnf->q.size()) * std::max<uint32_t>(candidates, 1)) : 0;
+}
+
 scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split_opts* opts, scuba_cubes** out) {
   if (!ctx || !cnf || !opts || !out) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     if (opts->k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
-    if (opts->scorer != SCUBA_SCORER_STATIC) fail(SCUBA_E_INVALID, "unknown scorer");
+    if (opts->scorer > SCUBA_SCORER_LEARNED) fail(SCUBA_E_INVALID, "unknown scorer");
+    const bool learned = opts->scorer == SCUBA_SCORER_LEARNED;
     uint32_t max_res = opts->max_residual ? opts->max_residual : kDefaultMaxResidual;
     uint64_t max_cubes = opts->max_cubes ? opts->max_cubes : kDefaultMaxCubes;
+    const size_t nq = cnf->q.size();
+    std::unique_ptr<ScorerRunner> runner;
+    if (learned) {
+      check_learned(opts->learned);
+      if (!opts->dev_ws || opts->ws_bytes < scorer_bytes(nq * opts->learned->candidates))
+        fail(SCUBA_E_CAPACITY, "scorer workspace smaller than scuba_scorer_workspace");
+      ctx->ensure_device();
+      runner.reset(new ScorerRunner{ctx, opts->learned, static_cast<char*>(opts->dev_ws),
+                                    nq * opts->learned->candidates, opts->hip_stream});
+    }
+    std::vector<std::unique_ptr<Splitter>> sp(nq);
+    std::vector<Splitter*> walks(nq);
+    parallel_for(nq, [&](size_t qi) {
+      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], opts->k, max_res, max_cubes);
+      if (learned) sp[qi]->set_learned(opts->learned->candidates, opts->learned->rescore);
+      walks[qi] = sp[qi].get();
+    });
+    std::vector<std::vector<Cube>> all(nq);
+    std::vector<Splitter::State> state(nq, Splitter::kRunning);
+    run_walks(walks, UINT32_MAX, all, true, state, runner.get());
     auto cubes = std::make_unique<scuba_cubes>();
-    cubes->q.resize(cnf->q.size());
-    parallel_for(cnf->q.size(), [&](size_t qi) {
+    cubes->q.resize(nq);
+    parallel_for(nq, [&](size_t qi) {
       scuba_cubes::Q& cq = cubes->q[qi];
-      Splitter sp(cnf->q[qi], opts->k, max_res, max_cubes);
-      std::vector<Cube> all;
-      Splitter::State st;
-      do st = sp.next(UINT32_MAX, all, true);
-      while (st == Splitter::kRunning);
-      cq.complete = st == Splitter::kExhausted;
-      for (const Cube& c : all) {
+      cq.complete = state[qi] == Splitter::kExhausted;
+      for (const Cube& c : all[qi]) {
         cq.lits.insert(cq.lits.end(), c.lits.begin(), c.lits.end());
         cq.off.push_back(cq.lits.size());
-        cq.kind.push_back(c.refuted ? SCUBA_CUBE_REFUTED : SCUBA_CUBE_LEAF);
-        cq.f.push_back(c.refuted ? -1 : c.f);
+        cq.kind.push_back(c.kind == CubeKind::kLeaf ? SCUBA_CUBE_LEAF
+                          : c.kind == CubeKind::kRefuted ? SCUBA_CUBE_REFUTED : SCUBA_CUBE_PRUNED);
+        cq.f.push_back(c.refuted() ? -1 : c.f);
         cq.nres.push_back(c.nres);
       }
     });
     *out = cubes.release();
   });
 }
+
+struct scuba_trace {
+  std::vector<float> feats, labels;
+  std::vector<uint64_t> nodes;
+};
+
+scuba_status scuba_trace_run(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_trace_opts* opts,
+                             scuba_trace** out) {
+  if (!ctx || !cnf || !opts || !out) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    if (opts->k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
+    if (opts->candidates < 1 || opts->candidates > 64) fail(SCUBA_E_INVALID, "trace candidates outside 1..64");
+    const size_t nq = cnf->q.size();
+    const uint64_t max_cubes = opts->max_cubes ? opts->max_cubes : kDefaultMaxCubes;
+    std::vector<std::unique_ptr<Splitter>> sp(nq);
+    parallel_for(nq, [&](size_t qi) {
+      if (cnf->q[qi].root_unsat) return;
+      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], opts->k, kDefaultMaxResidual, max_cubes);
+      sp[qi]->set_trace(opts->candidates, opts->every, opts->depth);
+      std::vector<Cube> sink;
+      while (sp[qi]->next(4096, sink, false) == Splitter::kRunning) sink.clear();
+    });
+    auto t = std::make_unique<scuba_trace>();
+    for (size_t qi = 0; qi < nq; qi++) {
+      if (!sp[qi]) continue;
+      const auto& f = sp[qi]->trace_features();
+      const auto& l = sp[qi]->trace_labels();
+      const auto& n = sp[qi]->trace_nodes();
+      t->feats.insert(t->feats.end(), f.begin(), f.end());
+      t->labels.insert(t->labels.end(), l.begin(), l.end());
+      for (uint32_t d : n) t->nodes.push_back(uint64_t(qi) << 32 | d);
+      sp[qi].reset();
+    }
+    *out = t.release();
+  });
+}
+
+scuba_status scuba_trace_view(const scuba_trace* t, uint64_t* rows, const float** features,
+                              const float** labels, const uint64_t** nodes) {
+  if (!t || !rows || !features || !labels || !nodes) return SCUBA_E_INVALID;
+  *rows = t->labels.size();
+  *features = t->feats.data();
+  *labels = t->labels.data();
+  *nodes = t->nodes.data();
+  return SCUBA_OK;
+}
+
+void scuba_trace_free(scuba_trace* t) { delete t; }
+
 
 scuba_status scuba_cubes_from_arrays(scuba_ctx* ctx, const scuba_cnf* cnf, const uint64_t* q_cube_start,
                                      const uint64_t* cube_off, const int32_t* cube_lits, scuba_cubes** out) {
@@ -509,7 +685,10 @@ SolveRound solve_round(const scuba_cnf* cnf, const scuba_cubes* cubes, const Opt
     for (size_t c = 0; c < cq.kind.size(); c++) {
       Cube cube;
       cube.lits.assign(cq.lits.begin() + cq.off[c], cq.lits.begin() + cq.off[c + 1]);
-      cube.refuted = cq.kind[c] != SCUBA_CUBE_LEAF;
+      // pruned cubes are refuted through their sibling's subtree, not by
+      // propagation alone: they are not sent
+      if (cq.kind[c] == SCUBA_CUBE_PRUNED) continue;
+      cube.kind = cq.kind[c] == SCUBA_CUBE_LEAF ? CubeKind::kLeaf : CubeKind::kRefuted;
       cube.f = cq.f[c];
       cube.nres = cq.nres[c];
       add_cube(sr.rh, uint32_t(qi), uint32_t(c), cube, cnf->q[qi].n_vars);
@@ -543,6 +722,8 @@ scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const 
     Opts o = resolve(opts);
     CnfHost h = cnf_host(cnf);
     *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, kDefaultMaxResidual);
+    if (o.scorer == SCUBA_SCORER_LEARNED)
+      *bytes += scorer_bytes(size_t(cnf->q.size()) * o.learned->candidates) + 256;
   });
 }
 
@@ -561,7 +742,11 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
       auto& rq = res->q[qi];
       const auto& cq = cubes->q[qi];
       rq.leaves.assign(cq.kind.size(), scuba_leaf_result{});
-      for (auto& l : rq.leaves) { l.first = -1; l.refuted = 0; }
+      for (size_t c = 0; c < cq.kind.size(); c++) {
+        rq.leaves[c].first = -1;
+        rq.leaves[c].refuted = cq.kind[c] == SCUBA_CUBE_PRUNED;
+        if (rq.leaves[c].refuted) rq.leaves[c].f = rq.leaves[c].m = -1;
+      }
       rq.r.cubes_total = cq.kind.size();
       for (int32_t k : cq.kind) rq.r.cubes_refuted += k != SCUBA_CUBE_LEAF;
     }
@@ -588,7 +773,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
       lr.m = lr.refuted ? -1 : outs[i].m;
       lr.count = outs[i].count;
       lr.first = outs[i].first == ~0ull ? -1 : int64_t(outs[i].first);
-      if (sr.host[i].refuted) continue;
+      if (sr.host[i].refuted()) continue;
       rq.r.leaves_sent++;
       rq.r.leaves_refuted += lr.refuted;
       rq.r.blocks_evaluated += outs[i].blocks;
@@ -652,11 +837,24 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
       }
       open[qi] = 1;
     }
+    const bool learned = o.scorer == SCUBA_SCORER_LEARNED;
     parallel_for(nq, [&](size_t qi) {
-      if (open[qi]) sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
+      if (!open[qi]) return;
+      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
+      if (learned) sp[qi]->set_learned(o.learned->candidates, o.learned->rescore);
     });
     split_ms += ms_since(ts);
     size_t cnf_b = dev_cnf_bytes(h);
+    // the scorer's buffers sit at the end of the workspace
+    std::unique_ptr<ScorerRunner> runner;
+    if (learned) {
+      const size_t sb = scorer_bytes(nq * o.learned->candidates);
+      if (sb + 256 + cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the scorer");
+      uintptr_t base = (reinterpret_cast<uintptr_t>(dev_ws) + ws_bytes - sb) & ~uintptr_t(255);
+      ws_bytes = base - reinterpret_cast<uintptr_t>(dev_ws);
+      runner.reset(new ScorerRunner{ctx, o.learned, reinterpret_cast<char*>(base), nq * o.learned->candidates,
+                                    hip_stream});
+    }
     if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
     bool uploaded = false;
     RoundTimes rt;
@@ -666,9 +864,20 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
       // each open query's walk advances on the host pool
       std::vector<std::vector<Cube>> leaves(nq);
       std::vector<Splitter::State> state(nq, Splitter::kRunning);
-      parallel_for(nq, [&](size_t qi) {
-        if (open[qi]) state[qi] = sp[qi]->next(o.lpr, leaves[qi], false);
-      });
+      std::vector<Splitter*> walks;
+      std::vector<size_t> wq;
+      for (size_t qi = 0; qi < nq; qi++)
+        if (open[qi]) {
+          walks.push_back(sp[qi].get());
+          wq.push_back(qi);
+        }
+      std::vector<std::vector<Cube>> wl(walks.size());
+      std::vector<Splitter::State> ws(walks.size(), Splitter::kRunning);
+      run_walks(walks, o.lpr, wl, false, ws, runner.get());
+      for (size_t i = 0; i < wq.size(); i++) {
+        leaves[wq[i]].swap(wl[i]);
+        state[wq[i]] = ws[i];
+      }
       RoundHost rh;
       std::vector<std::pair<uint32_t, Cube>> sent;
       for (size_t qi = 0; qi < nq; qi++) {
@@ -753,6 +962,48 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
     res->ms[8] = rt.up_launches;
     res->ms[9] = rt.leaf_launches;
     *out = res.release();
+  });
+}
+
+// ---------------------------------------------------------------- learned scorer
+
+uint32_t scuba_mlp_param_count(void) { return uint32_t(kMlpParams); }
+
+scuba_status scuba_mlp_sync(scuba_ctx* ctx, const float* master, uint16_t* wbf16, void* hip_stream) {
+  if (!ctx || !master || !wbf16) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    ctx->ensure_device();
+    mlp_sync(master, wbf16, hip_stream);
+  });
+}
+
+scuba_status scuba_mlp_forward(scuba_ctx* ctx, const uint16_t* wbf16, const float* master, const uint16_t* x,
+                               uint32_t batch, uint16_t* a1, uint16_t* a2, float* y, void* hip_stream) {
+  if (!ctx || !wbf16 || !master || (batch && (!x || !a1 || !a2 || !y))) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    ctx->ensure_device();
+    mlp_forward(wbf16, master, x, batch, a1, a2, y, hip_stream);
+  });
+}
+
+scuba_status scuba_mlp_backward(scuba_ctx* ctx, const uint16_t* wbf16, const uint16_t* x, const uint16_t* a1,
+                                const uint16_t* a2, const float* y, const float* target, uint32_t batch,
+                                uint16_t* dz1, uint16_t* dz2, float* grad, void* hip_stream) {
+  if (!ctx || !wbf16 || !grad || (batch && (!x || !a1 || !a2 || !y || !target || !dz1 || !dz2)))
+    return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    ctx->ensure_device();
+    mlp_backward(wbf16, x, a1, a2, y, target, batch, dz1, dz2, grad, hip_stream);
+  });
+}
+
+scuba_status scuba_mlp_adam(scuba_ctx* ctx, float* master, const float* grad, float* m, float* v,
+                            uint16_t* wbf16, uint32_t step, float lr, float beta1, float beta2, float eps,
+                            void* hip_stream) {
+  if (!ctx || !master || !grad || !m || !v || !wbf16 || step == 0) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    ctx->ensure_device();
+    mlp_adam(master, grad, m, v, wbf16, step, lr, beta1, beta2, eps, hip_stream);
   });
 }
 

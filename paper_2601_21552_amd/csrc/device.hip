@@ -457,6 +457,14 @@ void dev_init(DeviceInfo* info, int device) {
   info->max_lds = p.sharedMemPerBlock;
 }
 
+void dev_copy_h2d(void* dst, const void* src, size_t bytes, void* stream) {
+  HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream)));
+}
+void dev_copy_d2h(void* dst, const void* src, size_t bytes, void* stream) {
+  HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, static_cast<hipStream_t>(stream)));
+}
+void dev_sync(void* stream) { HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(stream))); }
+
 void* dev_pinned(size_t bytes) {
   void* p = nullptr;
   HIP_OK(hipHostMalloc(&p, bytes, hipHostMallocDefault));

@@ -458,10 +458,40 @@ class Encoder {
     // kept as a boolean formula and encoded with gates
     std::vector<std::pair<uint32_t, bool>> complex_roots;
     for (uint64_t r = 0; r < nr_; r++) collect(roots_[r], true, complex_roots);
-    for (auto& f : div_facts_) add_fact(f.first, f.second);
+    for (auto& f : div_facts_) facts_.push_back(f);
+    // the facts as given are what gets encoded
+    for (auto& [p, rel] : facts_) add_fact(bounds_, p, rel);
+
+    // Root equalities that define an atom linearly (coefficient +-1, the atom
+    // in no other monomial) eliminate it from every fact; the rewritten facts
+    // are implied by the originals and only join the UNSAT check.
+    std::map<Poly, Bound> check = bounds_;
+    std::vector<std::pair<uint32_t, Poly>> subs;
+    for (auto& [p0, rel] : facts_) {
+      if (rel != Rel::EQ0) continue;
+      Poly p = substitute_all(p0, subs);
+      const Mono* pivot = nullptr;
+      for (auto& [m, c] : p) {
+        if (m.size() != 1 || c.abs() != BigInt(1)) continue;
+        bool alone = true;
+        for (auto& [m2, c2] : p)
+          if (&m2 != &m && std::find(m2.begin(), m2.end(), m[0]) != m2.end()) alone = false;
+        if (alone) { pivot = &m; break; }
+      }
+      if (!pivot) continue;
+      const uint32_t atom = (*pivot)[0];
+      const BigInt c = p.at(*pivot);
+      Poly expr;   // atom = -(p - c*atom)/c = -c*(p - c*atom) since c = +-1
+      for (auto& [m, cc] : p)
+        if (&m != pivot) expr[m] = -(cc * c);
+      for (auto& [a, e] : subs) e = substitute(e, atom, expr);
+      subs.push_back({atom, expr});
+    }
+    if (!subs.empty())
+      for (auto& [p, rel] : facts_) add_fact(check, substitute_all(p, subs), rel);
 
     if (!unsat_) {
-      for (auto& [key, b] : bounds_) {
+      for (auto& [key, b] : check) {
         Range kr = poly_range(key);
         BigInt lo = b.has_lo && b.lo > kr.lo ? b.lo : kr.lo;
         BigInt hi = b.has_hi && b.hi < kr.hi ? b.hi : kr.hi;
@@ -533,8 +563,28 @@ class Encoder {
     return r;
   }
 
+  static Poly substitute(const Poly& p, uint32_t atom, const Poly& expr) {
+    Poly out;
+    for (auto& [m, c] : p) {
+      Mono rest;
+      size_t k = 0;
+      for (uint32_t a : m) {
+        if (a == atom) k++;
+        else rest.push_back(a);
+      }
+      Poly term{{rest, c}};
+      for (size_t i = 0; i < k; i++) term = poly_mul(term, expr);
+      poly_add_into(out, term, BigInt(1));
+    }
+    return out;
+  }
+  static Poly substitute_all(Poly p, const std::vector<std::pair<uint32_t, Poly>>& subs) {
+    for (auto& [a, e] : subs) p = substitute(p, a, e);
+    return p;
+  }
+
   // p >= 0 or p == 0  ->  bound on the canonical key
-  void add_fact(const Poly& p, Rel rel) {
+  void add_fact(std::map<Poly, Bound>& bounds, const Poly& p, Rel rel) {
     BigInt c0;
     Poly rest;
     for (auto& [m, c] : p) {
@@ -550,7 +600,7 @@ class Encoder {
     int s = rest.begin()->second.sign();
     Poly key;
     for (auto& [m, c] : rest) key[m] = BigInt::floor_div(c, g) * BigInt(s);
-    Bound& b = bounds_[key];
+    Bound& b = bounds[key];
     // rest = s*g*key ; fact: s*g*key + c0 (>= | ==) 0
     if (rel == Rel::EQ0) {
       BigInt q, r;
@@ -596,7 +646,7 @@ class Encoder {
     }
     Poly p;
     Rel rel;
-    if (comparison_fact(i, pos, &p, &rel)) { add_fact(p, rel); return; }
+    if (comparison_fact(i, pos, &p, &rel)) { facts_.push_back({p, rel}); return; }
     complex_roots.push_back({i, pos});
   }
 
@@ -844,6 +894,7 @@ class Encoder {
   std::vector<Poly> polys_;
   std::map<std::pair<Poly, uint64_t>, std::pair<uint32_t, uint32_t>> div_pairs_;
   std::vector<std::pair<Poly, Rel>> div_facts_;
+  std::vector<std::pair<Poly, Rel>> facts_;
   std::map<Poly, Bound> bounds_;
   std::map<Poly, BitVec> key_cache_;
   std::map<std::pair<Mono, uint32_t>, BitVec> mono_cache_;

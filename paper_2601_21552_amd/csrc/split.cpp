@@ -1,8 +1,9 @@
-// Host unit propagation (eager clause counters with a trail) and the
-// resumable depth-first cube splitter.
+// Host unit propagation (eager clause counters with a trail and reasons)
+// and the resumable depth-first cube splitter with backjumping.
 #include "split.hpp"
 
 #include <algorithm>
+#include <cmath>
 
 namespace scuba {
 
@@ -21,19 +22,141 @@ Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_
     }
   // static order: literal occurrences in the original CNF, most first,
   // ties to the lowest variable
-  order_.resize(n_);
-  for (uint32_t v = 1; v <= n_; v++) order_[v - 1] = int32_t(v);
   auto occurrences = [&](int32_t v) {
     return (occ_off_[2 * v + 1] - occ_off_[2 * v]) + (occ_off_[2 * v + 2] - occ_off_[2 * v + 1]);
   };
+  order_.resize(n_);
+  for (uint32_t v = 1; v <= n_; v++) order_[v - 1] = int32_t(v);
   std::stable_sort(order_.begin(), order_.end(), [&](int32_t a, int32_t b) {
     uint32_t oa = occurrences(a), ob = occurrences(b);
     return oa != ob ? oa > ob : a < b;
   });
+  static_rank_.assign(size_t(n_) + 1, 0);
+  occurrences_.assign(size_t(n_) + 1, 0);
+  for (uint32_t i = 0; i < n_; i++) static_rank_[order_[i]] = i;
+  for (uint32_t v = 1; v <= n_; v++) occurrences_[v] = occurrences(int32_t(v));
+  bit_pos_.assign(size_t(n_) + 1, 0);
+  bit_width_.assign(size_t(n_) + 1, 0);
+  for (size_t i = 0; i < q_.in_first.size(); i++)
+    for (uint32_t b = 0; b < q_.in_width[i]; b++) {
+      bit_pos_[q_.in_first[i] + b] = b;
+      bit_width_[q_.in_first[i] + b] = q_.in_width[i];
+    }
+}
+
+void Splitter::set_learned(uint32_t candidates, uint32_t rescore) {
+  learned_ = true;
+  n_cands_ = std::max<uint32_t>(candidates, 1);
+  rescore_ = std::max<uint32_t>(rescore, 1);
+}
+
+void Splitter::set_trace(uint32_t candidates, uint32_t every, uint32_t depth) {
+  trace_ = true;
+  n_cands_ = std::max<uint32_t>(candidates, 1);
+  trace_every_ = std::max<uint32_t>(every, 1);
+  trace_depth_ = depth;
+}
+
+// The first m active variables of the static order.
+std::vector<int32_t> Splitter::candidates(uint32_t m) const {
+  std::vector<int32_t> c;
+  for (int32_t v : order_) {
+    if (c.size() >= m) break;
+    if (assign_[v] < 0 && act_cnt_[v] > 0) c.push_back(v);
+  }
+  return c;
+}
+
+// Features of each candidate at the current node (kFeatures per variable):
+// positive / negative occurrences in unsatisfied clauses, occurrences in
+// unsatisfied clauses with 2, 3 and more open literals, the Jeroslow-Wang
+// weight (sum of 2^-open), static occurrences, input-bit flag and relative
+// bit position, the node's active count, unsatisfied-clause fraction and
+// depth, log occurrences, neighbour count, static rank, and a constant.
+void Splitter::features(const std::vector<int32_t>& cands, std::vector<float>* out) const {
+  out->assign(cands.size() * kFeatures, 0.f);
+  const float nc = float(std::max<uint64_t>(q_.n_clauses(), 1));
+  for (size_t r = 0; r < cands.size(); r++) {
+    const int32_t v = cands[r];
+    float pos = 0, neg = 0, bin = 0, ter = 0, lng = 0, jw = 0, nb = 0;
+    for (int side = 0; side < 2; side++) {
+      const size_t li = 2 * size_t(v) + side;
+      for (uint32_t j = occ_off_[li]; j < occ_off_[li + 1]; j++) {
+        const uint32_t c = occ_[j];
+        if (ntrue_[c]) continue;
+        const uint32_t open = uint32_t(q_.off[c + 1] - q_.off[c]) - nfalse_[c];
+        (side ? neg : pos) += 1;
+        if (open == 2) bin += 1;
+        else if (open == 3) ter += 1;
+        else lng += 1;
+        jw += std::ldexp(1.f, -int(std::min<uint32_t>(open, 60)));
+        nb += float(open) - 1.f;
+      }
+    }
+    float* f = out->data() + r * kFeatures;
+    f[0] = pos / 32.f;
+    f[1] = neg / 32.f;
+    f[2] = bin / 16.f;
+    f[3] = ter / 16.f;
+    f[4] = lng / 16.f;
+    f[5] = jw;
+    f[6] = float(occurrences_[v]) / 64.f;
+    f[7] = bit_width_[v] ? 1.f : 0.f;
+    f[8] = bit_width_[v] ? (float(bit_pos_[v]) + 0.5f) / float(bit_width_[v]) : 0.f;
+    f[9] = float(f_) / 256.f;
+    f[10] = float(n_unsat_) / nc;
+    f[11] = float(stack_.size()) / 64.f;
+    f[12] = std::log2(1.f + pos + neg);
+    f[13] = nb / 64.f;
+    f[14] = float(r) / float(cands.size());
+    f[15] = 1.f;
+  }
+}
+
+// One-step lookahead: active counts after propagating v = 0 and v = 1 (a
+// conflicting branch counts as 0); label log2(1 + reduction) summed over
+// the two branches, so that balanced large reductions score highest.
+float Splitter::lookahead_label(int32_t v) {
+  const size_t pos = trail_.size();
+  const uint32_t f = f_;
+  auto branch = [&](int32_t lit) {
+    const bool ok = propagate(lit);
+    const uint32_t fb = ok ? f_ : 0;
+    undo_to(pos);
+    return fb;
+  };
+  const uint32_t f0 = branch(-v), f1 = branch(v);
+  return std::log2(1.f + float(f - f0)) + std::log2(1.f + float(f - f1));
+}
+
+void Splitter::provide_scores(const float* scores) {
+  ranking_ = req_vars_;
+  bool finite = true;
+  for (size_t i = 0; i < req_vars_.size(); i++) finite &= std::isfinite(scores[i]);
+  if (finite) {
+    std::vector<size_t> idx(req_vars_.size());
+    for (size_t i = 0; i < idx.size(); i++) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return scores[a] > scores[b]; });
+    for (size_t i = 0; i < idx.size(); i++) ranking_[i] = req_vars_[idx[i]];
+  }
+  have_scores_ = true;
+}
+
+// The best-ranked active variable while the last ranking applies (the node
+// it was made at and `rescore` levels below), else 0.
+int32_t Splitter::choose_learned() {
+  if (!rank_valid_ || stack_.size() < rank_depth_ || stack_.size() >= rank_depth_ + rescore_) return 0;
+  for (int32_t v : ranking_)
+    if (assign_[v] < 0 && act_cnt_[v] > 0) return v;
+  return 0;
 }
 
 void Splitter::reset_state() {
   assign_.assign(size_t(n_) + 1, -1);
+  reason_.assign(size_t(n_) + 1, -1);
+  level_.assign(size_t(n_) + 1, 0);
+  seen_.assign(size_t(n_) + 1, 0);
+  seen_stamp_ = 0;
   ntrue_.assign(q_.n_clauses(), 0);
   nfalse_.assign(q_.n_clauses(), 0);
   act_cnt_.assign(size_t(n_) + 1, 0);
@@ -45,20 +168,30 @@ void Splitter::reset_state() {
   stack_.clear();
 }
 
-bool Splitter::enqueue_and_propagate(int32_t lit) {
+// Assign `lit` (reason -1) and everything unit propagation implies.  On a
+// conflict, conflict_clause_ holds a clause whose literals are all false
+// (-1 when a decision clashes with an earlier assignment).
+bool Splitter::propagate(int32_t lit) {
   queue_.clear();
-  queue_.push_back(lit);
+  queue_.push_back({lit, -1});
+  conflict_clause_ = -1;
   bool conflict = false;
+  const uint32_t lvl = uint32_t(stack_.size());
   for (size_t qi = 0; qi < queue_.size() && !conflict; qi++) {
-    int32_t l = queue_[qi];
-    int32_t v = std::abs(l);
-    int8_t val = l > 0;
+    const int32_t l = queue_[qi].first, why = queue_[qi].second;
+    const int32_t v = std::abs(l);
+    const int8_t val = l > 0;
     if (assign_[v] >= 0) {
-      if (assign_[v] != val) conflict = true;
+      if (assign_[v] != val) {
+        conflict = true;
+        conflict_clause_ = why;   // every literal of the implying clause is now false
+      }
       continue;
     }
     if (act_cnt_[v] > 0) f_--;
     assign_[v] = val;
+    reason_[v] = why;
+    level_[v] = lvl;
     trail_.push_back(v);
     size_t li = 2 * size_t(v) + (val ? 0 : 1), lf = 2 * size_t(v) + (val ? 1 : 0);
     for (uint32_t j = occ_off_[li]; j < occ_off_[li + 1]; j++) {
@@ -77,10 +210,11 @@ bool Splitter::enqueue_and_propagate(int32_t lit) {
       if (ntrue_[c] != 0) continue;
       uint64_t size = q_.off[c + 1] - q_.off[c];
       if (nfalse_[c] == size) {
+        if (!conflict) conflict_clause_ = int64_t(c);
         conflict = true;
       } else if (nfalse_[c] + 1 == size) {
         for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++)
-          if (assign_[std::abs(q_.lits[i])] < 0) { queue_.push_back(q_.lits[i]); break; }
+          if (assign_[std::abs(q_.lits[i])] < 0) { queue_.push_back({q_.lits[i], int32_t(c)}); break; }
       }
     }
   }
@@ -105,15 +239,45 @@ void Splitter::undo_to(size_t pos) {
       }
     }
     assign_[v] = -1;
+    reason_[v] = -1;
     if (act_cnt_[v] > 0) f_++;
   }
+}
+
+// Decision levels (1-based) that the last conflict depends on: walk the
+// implication graph back from the conflicting clause to decisions.
+std::vector<uint32_t> Splitter::analyze() {
+  std::vector<uint32_t> levels;
+  if (conflict_clause_ < 0) {   // no clause to blame: depend on every decision
+    for (uint32_t l = 1; l <= stack_.size(); l++) levels.push_back(l);
+    return levels;
+  }
+  if (++seen_stamp_ == 0) { std::fill(seen_.begin(), seen_.end(), 0); seen_stamp_ = 1; }
+  std::vector<int32_t> work;
+  auto push_clause = [&](uint64_t c) {
+    for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
+      int32_t u = std::abs(q_.lits[i]);
+      if (seen_[u] != seen_stamp_) { seen_[u] = seen_stamp_; work.push_back(u); }
+    }
+  };
+  push_clause(uint64_t(conflict_clause_));
+  while (!work.empty()) {
+    int32_t u = work.back();
+    work.pop_back();
+    if (assign_[u] < 0 || level_[u] == 0) continue;   // root facts need no decision
+    if (reason_[u] < 0) levels.push_back(level_[u]);
+    else push_clause(uint64_t(reason_[u]));
+  }
+  std::sort(levels.begin(), levels.end());
+  levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
+  return levels;
 }
 
 bool Splitter::root_propagate() {
   for (uint64_t c = 0; c < q_.n_clauses(); c++) {
     uint64_t size = q_.off[c + 1] - q_.off[c];
     if (size == 0) return false;
-    if (size == 1 && !enqueue_and_propagate(q_.lits[q_.off[c]])) return false;
+    if (size == 1 && !propagate(q_.lits[q_.off[c]])) return false;
   }
   return true;
 }
@@ -124,13 +288,23 @@ int32_t Splitter::choose_static() const {
   return 0;
 }
 
-void Splitter::emit(bool refuted, std::vector<Cube>& out, bool keep) {
+// The branch explored first: v = 0.
+int32_t Splitter::first_literal(int32_t v) const { return -v; }
+
+std::vector<int32_t> Splitter::path() const {
+  std::vector<int32_t> lits;
+  lits.reserve(stack_.size());
+  for (const Decision& d : stack_) lits.push_back(d.phase ? -d.lit : d.lit);
+  return lits;
+}
+
+void Splitter::emit(CubeKind kind, std::vector<int32_t> lits, std::vector<Cube>& out, bool keep) {
   Cube c;
-  c.refuted = refuted;
-  c.lits.reserve(stack_.size());
-  for (const Decision& d : stack_) c.lits.push_back(d.phase ? d.var : -d.var);
-  if (refuted) {
+  c.kind = kind;
+  c.lits = std::move(lits);
+  if (kind != CubeKind::kLeaf) {
     n_refuted_++;
+    n_pruned_ += kind == CubeKind::kPruned;
     if (keep) out.push_back(std::move(c));
   } else {
     c.f = int32_t(f_);
@@ -140,60 +314,111 @@ void Splitter::emit(bool refuted, std::vector<Cube>& out, bool keep) {
   }
 }
 
+// The current branch of the deepest decision is done and failed as `r`
+// (for a leaf: outcome unknown).  Moves to the next branch to walk and
+// returns true, or returns false when the tree is exhausted.
+bool Splitter::finish_branch(Failure r, std::vector<Cube>& out, bool keep) {
+  while (!stack_.empty()) {
+    Decision& d = stack_.back();
+    const uint32_t lvl = uint32_t(stack_.size());
+    undo_to(d.trail_pos);
+    const bool depends = r.unknown || std::binary_search(r.levels.begin(), r.levels.end(), lvl);
+    d.acc.unknown |= r.unknown;
+    for (uint32_t l : r.levels)
+      if (l < lvl) d.acc.levels.push_back(l);
+    std::sort(d.acc.levels.begin(), d.acc.levels.end());
+    d.acc.levels.erase(std::unique(d.acc.levels.begin(), d.acc.levels.end()), d.acc.levels.end());
+    if (d.phase == 0) {
+      if (!depends) {
+        // the 1-branch fails for the same reasons: prune it
+        std::vector<int32_t> lits = path();
+        lits.back() = -d.lit;
+        emit(CubeKind::kPruned, std::move(lits), out, keep);
+      } else {
+        d.phase = 1;
+        if (propagate(-d.lit)) return true;
+        Failure f1;
+        f1.levels = analyze();
+        emit(CubeKind::kRefuted, path(), out, keep);
+        r = std::move(f1);
+        if (cubes_total() >= max_cubes_) return true;   // the caller stops on the budget
+        continue;   // this decision's 1-branch is done too
+      }
+    }
+    r = std::move(d.acc);
+    stack_.pop_back();
+    if (stack_.size() <= rank_depth_) rank_valid_ = false;   // the ranked node is done
+    if (cubes_total() >= max_cubes_ && !stack_.empty()) return true;
+  }
+  return false;
+}
+
 Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool keep_refuted) {
   if (state_ != kRunning) return state_;
+  if (!awaiting_) produced_ = 0;   // a call that resumes after scores keeps counting
+  awaiting_ = false;
   if (!started_) {
     started_ = true;
     reset_state();
     if (!root_propagate()) {
       root_conflict_ = true;
-      emit(true, out, keep_refuted);
+      emit(CubeKind::kRefuted, {}, out, keep_refuted);
       state_ = kExhausted;
       return state_;
     }
     at_fresh_node_ = true;
   }
-  uint32_t produced = 0;
   for (;;) {
+    Failure r;
     if (at_fresh_node_) {
-      if (f_ <= k_ && n_unsat_ <= max_res_) {
-        emit(false, out, keep_refuted);
-        produced++;
-        at_fresh_node_ = false;
-      } else {
-        int32_t v = choose_static();
-        if (v == 0) {  // no active variable: every clause is satisfied
-          emit(false, out, keep_refuted);
-          produced++;
-          at_fresh_node_ = false;
-        } else {
-          stack_.push_back({v, 0, trail_.size()});
-          if (!enqueue_and_propagate(-v)) {
-            emit(true, out, keep_refuted);
-            at_fresh_node_ = false;
+      int32_t v = 0;
+      if (f_ > k_ || n_unsat_ > max_res_) {
+        if (learned_) {
+          v = choose_learned();
+          if (!v && have_scores_) {   // scores for this node arrived
+            have_scores_ = false;
+            rank_valid_ = true;
+            rank_depth_ = stack_.size();
+            v = choose_learned();
+          } else if (!v) {
+            req_vars_ = candidates(n_cands_);
+            if (req_vars_.size() > 1) {
+              features(req_vars_, &req_feats_);
+              awaiting_ = true;
+              return kNeedScore;
+            }
           }
-          if (at_fresh_node_ && cubes_total() < max_cubes_) continue;
+        }
+        if (!v) v = choose_static();
+        if (trace_ && stack_.size() < trace_depth_ && decisions_++ % trace_every_ == 0) {
+          const std::vector<int32_t> cands = candidates(n_cands_);
+          std::vector<float> fe;
+          features(cands, &fe);
+          tr_feats_.insert(tr_feats_.end(), fe.begin(), fe.end());
+          for (int32_t c : cands) {
+            tr_labels_.push_back(lookahead_label(c));
+            tr_nodes_.push_back(decisions_);
+          }
         }
       }
-    }
-    // backtrack to the next unexplored 1-branch
-    bool moved = false;
-    while (!stack_.empty()) {
-      Decision& d = stack_.back();
-      undo_to(d.trail_pos);
-      if (d.phase == 0) {
-        d.phase = 1;
-        if (enqueue_and_propagate(d.var)) { moved = true; break; }
-        emit(true, out, keep_refuted);
-        if (cubes_total() >= max_cubes_) break;
+      if (v == 0) {   // a leaf (v == 0 with f > k cannot happen: f > 0 needs an active variable)
+        emit(CubeKind::kLeaf, path(), out, keep_refuted);
+        produced_++;
+        r.unknown = true;
       } else {
-        stack_.pop_back();
+        const int32_t lit = first_literal(v);
+        stack_.push_back({lit, 0, trail_.size(), Failure{}});
+        if (propagate(lit)) continue;
+        r.levels = analyze();
+        emit(CubeKind::kRefuted, path(), out, keep_refuted);
       }
+      at_fresh_node_ = false;
     }
-    if (!moved && stack_.empty()) { state_ = kExhausted; return state_; }
+    const bool moved = finish_branch(std::move(r), out, keep_refuted);
+    if (!moved) { state_ = kExhausted; return state_; }
     if (cubes_total() >= max_cubes_) { state_ = kBudget; return state_; }
     at_fresh_node_ = true;
-    if (produced >= max_leaves) return kRunning;
+    if (produced_ >= max_leaves) return kRunning;
   }
 }
 
@@ -203,7 +428,7 @@ bool Splitter::leaf_of(const std::vector<int32_t>& cube, std::vector<int8_t>* as
   state_ = kExhausted;
   reset_state();
   bool ok = root_propagate();
-  for (size_t i = 0; ok && i < cube.size(); i++) ok = enqueue_and_propagate(cube[i]);
+  for (size_t i = 0; ok && i < cube.size(); i++) ok = propagate(cube[i]);
   if (!ok) return false;
   *assign = assign_;
   active->clear();

@@ -1,11 +1,18 @@
 // Host unit propagation and the cube splitter.
 //
-// The splitter walks a DPLL tree in depth-first order (0-branch first).  At
-// each node unit propagation runs to its fixpoint; a conflicting node is a
+// The splitter walks a DPLL tree in depth-first order (0-branch first).
+// At each node unit propagation runs to its fixpoint; a conflicting node is a
 // refuted cube; a node with at most k active variables (unassigned and in
 // some clause not yet satisfied) and at most max_residual unsatisfied
 // clauses is a leaf for the device; otherwise the scorer picks the branching
 // variable.  The walk is resumable, so leaves can be produced lazily.
+//
+// Backjumping: every propagation records the clause that implied each
+// variable, so a conflict names the decisions it depends on.  When every
+// failure below the 0-branch of a decision is a host conflict that does not
+// depend on that decision, the 1-branch fails for the same reasons; it is
+// emitted as a pruned cube instead of being walked.  Leaves count as
+// failures that depend on every decision (their outcome is not known here).
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -14,27 +21,52 @@
 
 namespace scuba {
 
+enum class CubeKind : int32_t { kLeaf = 0, kRefuted = 1, kPruned = 2 };
+
 struct Cube {
   std::vector<int32_t> lits;  // branching literals, root first
   int32_t f = -1;             // active variables (leaves)
   uint32_t nres = 0;          // unsatisfied clauses at the fixpoint (leaves)
-  bool refuted = false;
+  CubeKind kind = CubeKind::kLeaf;
+  bool refuted() const { return kind != CubeKind::kLeaf; }
 };
+
+constexpr int kFeatures = 16;   // per candidate variable, see features()
 
 class Splitter {
  public:
-  enum State { kRunning = 0, kExhausted = 1, kBudget = 2 };
+  // kNeedScore: the walk waits for scores of the candidates in request()
+  enum State { kRunning = 0, kExhausted = 1, kBudget = 2, kNeedScore = 3 };
 
   Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_t max_cubes);
 
+  // Learned ordering: at a decision node the walk stops with kNeedScore and
+  // asks for scores of the top `candidates` active variables of the static
+  // order; the ranking by score then orders the decisions of that node and
+  // of its descendants up to `rescore` levels below.  Non-finite scores fall
+  // back to the static order.
+  void set_learned(uint32_t candidates, uint32_t rescore);
+  // Trace mode (static ordering): at every `every`-th decision node above
+  // depth `depth`, record features and one-step lookahead labels of the top
+  // `candidates` variables.
+  void set_trace(uint32_t candidates, uint32_t every, uint32_t depth);
+  const std::vector<int32_t>& request_vars() const { return req_vars_; }
+  const std::vector<float>& request_features() const { return req_feats_; }
+  void provide_scores(const float* scores);
+  // trace rows: features (kFeatures each), label, node number
+  const std::vector<float>& trace_features() const { return tr_feats_; }
+  const std::vector<float>& trace_labels() const { return tr_labels_; }
+  const std::vector<uint32_t>& trace_nodes() const { return tr_nodes_; }
+
   // Produce up to max_leaves more leaves, appended to `out` in depth-first
-  // order; refuted cubes are counted, and appended too when keep_refuted.
-  // Returns the state after the call.
+  // order; refuted and pruned cubes are counted, and appended too when
+  // keep_refuted.  Returns the state after the call.
   State next(uint32_t max_leaves, std::vector<Cube>& out, bool keep_refuted);
 
   State state() const { return state_; }
   uint64_t cubes_total() const { return n_leaves_ + n_refuted_; }
   uint64_t cubes_refuted() const { return n_refuted_; }
+  uint64_t cubes_pruned() const { return n_pruned_; }
   bool root_conflict() const { return root_conflict_; }
 
   // Propagation fixpoint of (F, cube) from the root: assignment (-1/0/1 per
@@ -45,12 +77,31 @@ class Splitter {
                std::vector<int32_t>* active, uint32_t* nres);
 
  private:
-  bool enqueue_and_propagate(int32_t lit);
+  struct Failure {
+    std::vector<uint32_t> levels;  // decision levels the failure depends on
+    bool unknown = false;          // a leaf below: depends on everything
+  };
+  struct Decision {
+    int32_t lit;                   // literal of the branch explored first
+    int phase;                     // 0: first branch, 1: its negation
+    size_t trail_pos;
+    Failure acc;                   // failures of the branches done so far
+  };
+
+  bool propagate(int32_t lit);     // a decision (or cube literal)
   void undo_to(size_t trail_pos);
   int32_t choose_static() const;
-  void emit(bool refuted, std::vector<Cube>& out, bool keep);
+  int32_t first_literal(int32_t v) const;
+  std::vector<uint32_t> analyze();
+  void emit(CubeKind kind, std::vector<int32_t> lits, std::vector<Cube>& out, bool keep);
+  std::vector<int32_t> path() const;
+  bool finish_branch(Failure r, std::vector<Cube>& out, bool keep);
   void reset_state();
   bool root_propagate();
+  std::vector<int32_t> candidates(uint32_t m) const;
+  void features(const std::vector<int32_t>& cands, std::vector<float>* out) const;
+  float lookahead_label(int32_t v);
+  int32_t choose_learned();
 
   const CnfQuery& q_;
   uint32_t k_, max_res_;
@@ -58,20 +109,40 @@ class Splitter {
   uint32_t n_;
   std::vector<uint32_t> occ_off_;   // literal index 2v+neg -> clause list
   std::vector<uint32_t> occ_;
-  std::vector<int32_t> order_;      // static order: occurrences desc, index asc
+  std::vector<int32_t> order_;      // static branching order
   // search state
   std::vector<int8_t> assign_;
+  std::vector<int32_t> reason_;     // implying clause, -1 for decisions
+  std::vector<uint32_t> level_;     // decision level of the assignment
   std::vector<uint32_t> ntrue_, nfalse_;
   std::vector<uint32_t> act_cnt_;
   uint32_t f_ = 0;
   uint64_t n_unsat_ = 0;
   std::vector<int32_t> trail_;
-  std::vector<int32_t> queue_;
-  struct Decision { int32_t var; int phase; size_t trail_pos; };
+  std::vector<std::pair<int32_t, int32_t>> queue_;   // (literal, reason)
+  int64_t conflict_clause_ = -1;
+  std::vector<uint32_t> seen_;
+  uint32_t seen_stamp_ = 0;
   std::vector<Decision> stack_;
+  std::vector<uint32_t> static_rank_;   // position of each variable in order_
+  std::vector<uint32_t> occurrences_;
+  std::vector<uint32_t> bit_pos_, bit_width_;   // input bits: position and width
+  // learned ordering
+  bool learned_ = false, have_scores_ = false, rank_valid_ = false;
+  uint32_t n_cands_ = 32, rescore_ = 1;
+  std::vector<int32_t> req_vars_, ranking_;
+  std::vector<float> req_feats_;
+  size_t rank_depth_ = 0;
+  // traces
+  bool trace_ = false;
+  uint32_t trace_every_ = 1, trace_depth_ = 0, decisions_ = 0;
+  std::vector<float> tr_feats_, tr_labels_;
+  std::vector<uint32_t> tr_nodes_;
+  uint32_t produced_ = 0;
+  bool awaiting_ = false;
   bool started_ = false, root_conflict_ = false, at_fresh_node_ = false;
   State state_ = kRunning;
-  uint64_t n_leaves_ = 0, n_refuted_ = 0;
+  uint64_t n_leaves_ = 0, n_refuted_ = 0, n_pruned_ = 0;
 };
 
 }  // namespace scuba

@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(api):
     with open(_lib.os.path.join(_lib.HERE, "..", "include", "scuba.h")) as f:
         header = f.read()
     declared = set(re.findall(
-        r"^(?:scuba_status|void|const char\*|uint32_t)\s+(scuba_[a-z_0-9]+)\s*\(", header, re.M))
+        r"^(?:scuba_status|void|const char\*|uint32_t|size_t)\s+(scuba_[a-z_0-9]+)\s*\(", header, re.M))
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for name in sorted(declared):
         assert hasattr(lib, name), name
@@ -132,6 +132,7 @@ def test_split_trees_complete_disjoint_and_canonical(ctx):
     rng = np.random.Generator(np.random.PCG64(202))
     cnfs = [w.random_ksat(n, int(r * n), 3, rng) for n, r in ((14, 4.3), (18, 3.0), (22, 4.26))]
     cnfs.append(w.pigeonhole(4, 3))
+    cnfs.append(w.pigeonhole(5, 4))     # backjumping prunes here
     raw = ctx.cnf_from_arrays(*w.concat(cnfs))
     for k in (3, 7, 12):
         cubes = ctx.split(raw, k=k)
@@ -144,6 +145,8 @@ def test_split_trees_complete_disjoint_and_canonical(ctx):
                 ref = cnf_ref.leaf(f, cube)
                 if cv["kind"][c] == 1:
                     assert ref["refuted"]
+                elif cv["kind"][c] == 2:      # pruned by backjumping: no model
+                    assert ref["refuted"] or ref["count"] == 0
                 else:
                     assert not ref["refuted"] and ref["f"] == cv["f"][c] <= k
                     total += ref["count"] << ref["m"]
@@ -167,3 +170,65 @@ def test_decide_needs_a_device(api, ctx):
     with pytest.raises(Exception):
         ctx.decide(cnf, k=30)
     assert _lib.load() is not None
+
+
+def _active_count(cnf, assign):
+    """Unassigned variables occurring in a clause that no literal satisfies."""
+    act = set()
+    for c in range(cnf.n_clauses):
+        lits = cnf.lits[cnf.clause_off[c]:cnf.clause_off[c + 1]]
+        if any((l > 0 and assign[l] == 1) or (l < 0 and assign[-l] == 0) for l in lits):
+            continue
+        act.update(abs(int(l)) for l in lits if assign[abs(l)] < 0)
+    return len(act)
+
+
+def test_trace_root_labels_match_lookahead(api, ctx):
+    """Rows of the root node: the candidates are the first active variables of
+    the static order (most literal occurrences, ties to the lowest index) and
+    each label is log2(1 + f - f0) + log2(1 + f - f1), with f0 / f1 the active
+    counts after propagating the variable to 0 / 1 (0 on a conflict)."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    cnfs = [w.random_ksat(36, 150, 3, rng) for _ in range(4)]
+    batch = ctx.cnf_from_arrays(*w.concat(cnfs))
+    m = 6
+    feats, labels, nodes = ctx.trace(batch, k=6, candidates=m, every=1, depth=64)
+    assert feats.shape == (len(labels), 16) and len(nodes) == len(labels)
+    for qi, c in enumerate(cnfs):
+        sel = nodes == ((qi << 32) | 1)
+        conflict, a = cnf_ref.up(c)
+        assert not conflict
+        f = _active_count(c, a)
+        occ = np.zeros(c.n_vars + 1, np.int64)
+        np.add.at(occ, np.abs(c.lits), 1)
+        active = {abs(int(l)) for j in range(c.n_clauses)
+                  for l in c.lits[c.clause_off[j]:c.clause_off[j + 1]]
+                  if a[abs(l)] < 0}
+        order = sorted(range(1, c.n_vars + 1), key=lambda v: (-occ[v], v))
+        cands = [v for v in order if v in active][:m]
+        assert sel.sum() == len(cands)
+        want = []
+        for v in cands:
+            fb = []
+            for lit in (-v, v):
+                cf, ab = cnf_ref.up(c, [lit])
+                fb.append(0 if cf else _active_count(c, ab))
+            want.append(np.log2(1 + f - fb[0]) + np.log2(1 + f - fb[1]))
+        np.testing.assert_allclose(labels[sel], want, rtol=1e-5, atol=1e-5)
+        np.testing.assert_allclose(feats[sel][:, 6], occ[cands] / 64.0, rtol=1e-6)
+        np.testing.assert_allclose(feats[sel][:, 9], f / 256.0, rtol=1e-6)
+        assert np.all(feats[sel][:, 15] == 1.0)
+
+
+def test_learned_options_are_validated(api, ctx):
+    from paper_2601_21552_amd import _lib
+    rng = np.random.Generator(np.random.PCG64(78))
+    c = w.random_ksat(20, 80, 3, rng)
+    batch = ctx.cnf_from_arrays(*w.concat([c]))
+    bad = _lib.LearnedScorer(None, None, 16, 1)
+    with pytest.raises(_lib.ScubaError):
+        ctx.decide_workspace(batch, learned=bad)
+    ok_ptrs = _lib.LearnedScorer(1 << 20, 1 << 20, 1, 1)   # candidates below 2
+    with pytest.raises(_lib.ScubaError):
+        ctx.decide_workspace(batch, learned=ok_ptrs)
+    assert ctx.lib.scuba_scorer_workspace(batch.h, 16) >= 16 * (16 + 2 * 128) * 2

@@ -151,3 +151,44 @@ def partition_query(width: int, lens_w: int, k_sub: int, target: int,
     else:
         q.require(starts[target] + idx >= S)
     return q
+
+
+def config5(seed: int = 5, n: int = 1024, width: int = 20):
+    """Intra-allocation partition queries: one allocation of `width`-bit
+    size split into k_sub ~ U{2..8} parts at prefix-sum offsets, partition
+    sizes by subtraction, a guarded access into part j ~ U{0..k_sub-1}.
+    Half use the correct guard idx < len_j (UNSAT); half are buggy: idx <=
+    len_j (the one-past-the-end index), or a guard against a neighbour's
+    length (SAT).  Index idx = t, or t*W + i with i < W."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    kinds = ["lt"] * (n // 2) + ["bug"] * (n - n // 2)
+    kinds = [kinds[i] for i in rng.permutation(n)]
+    for qi, kind in enumerate(kinds):
+        k_sub = int(rng.integers(2, 9))
+        j = int(rng.integers(0, k_sub))
+        index = "t" if rng.integers(2) == 0 else "tw"
+        if kind == "lt":
+            guard = "lt"
+        else:
+            guard = ["le", "next", "prev"][int(rng.integers(3))]
+        q = partition_query(width, width, k_sub, j, index, guard, level="partition",
+                            name=f"c5_{qi}_k{k_sub}_j{j}_{index}_{guard}")
+        if guard == "lt":
+            out.append(GenQuery(q, UNSAT, kind="partition_guarded"))
+            continue
+        # a witness by construction: every part holds one element, except
+        # that a neighbour guard's part holds three; the index is one past
+        # the end of part j, which the buggy guard still admits
+        lens = [1] * k_sub
+        if guard != "le":
+            lens[(j + 1) % k_sub if guard == "next" else (j - 1) % k_sub] = 3
+        idx = 1
+        wit = {f"len{i}": lens[i] for i in range(k_sub)}
+        wit["S"] = sum(lens)
+        if index == "t":
+            wit["t"] = idx
+        else:
+            wit.update(t=idx, W=1, i=0)
+        out.append(GenQuery(q, SAT, wit, kind=f"partition_{guard}"))
+    return out
