@@ -173,6 +173,11 @@ void scuba_cnf_free(scuba_cnf* cnf);
  * only.  A query whose tree exceeds max_cubes is cut (UNKNOWN).             */
 #define SCUBA_SCORER_STATIC 0u
 #define SCUBA_SCORER_LEARNED 1u
+/* Word ordering (bit-blasted queries): the active input bit of highest
+ * significance first, ties to the lowest variable, so that each decision
+ * halves one input's value range and small inputs are tried first; the
+ * static order for auxiliary variables and raw CNFs. */
+#define SCUBA_SCORER_WORD 2u
 /* Learned ordering: at a decision node the top `candidates` active variables
  * of the static order are scored by the perceptron below (scuba_mlp_*),
  * batched over all queries on the device; the ranking orders the decisions

@@ -15,13 +15,17 @@ Contents
   re-derivation of the CNF route, used to decide queries at full width.
 * ``root_check``      - the oracle's word-level reasoning: every comparison
   is brought to a polynomial normal form and the bounds asserted on the same
-  polynomial are intersected; an empty intersection proves UNSAT.
+  polynomial are intersected; an empty intersection proves UNSAT.  Failing
+  that, the root facts, their products with single atoms (kept when every
+  monomial they produce already occurs in the facts) and the value range of
+  every monomial form a linear system over the monomials; if it has no
+  rational solution (Fourier-Motzkin elimination) the query is UNSAT.
 * ``decide``          - root check, else encode + DPLL.
 """
 from __future__ import annotations
 
 import itertools
-from fractions import Fraction  # noqa: F401  (documented exactness)
+from fractions import Fraction
 from math import gcd
 
 import numpy as np
@@ -466,6 +470,104 @@ def _substitute_all(p, subs):
     return p
 
 
+# Linear relaxation.  A constraint is (coefs, const) meaning
+# sum(coefs[m] * m) + const >= 0 over monomials m, coefs coprime integers,
+# const a Fraction.  Rational feasibility is what Fourier-Motzkin decides;
+# every derived constraint is a non-negative combination of the inputs.
+FM_CAP = 20000
+
+
+def _fm_norm(coefs, const):
+    coefs = {m: c for m, c in coefs.items() if c != 0}
+    g = 0
+    for c in coefs.values():
+        g = gcd(g, abs(c))
+    if g > 1:
+        coefs = {m: c // g for m, c in coefs.items()}
+        const = Fraction(const) / g
+    return coefs, Fraction(const)
+
+
+def fm_infeasible(constraints):
+    """True iff the system {sum c_m m + c0 >= 0} has no rational solution.
+    None when the elimination exceeds FM_CAP constraints (undecided)."""
+    best = {}
+
+    def add(pool, coefs, const):
+        coefs, const = _fm_norm(coefs, const)
+        if not coefs:
+            return const < 0            # a contradiction
+        key = tuple(sorted(coefs.items()))
+        if key not in pool or const < pool[key]:
+            pool[key] = const
+        return False
+
+    for coefs, const in constraints:
+        if add(best, coefs, const):
+            return True
+    pool = best
+    while pool:
+        if len(pool) > FM_CAP:
+            return None
+        vars_ = sorted({m for key in pool for m, _ in key})
+        if not vars_:
+            return False
+
+        def cost(x):
+            pos = sum(1 for key in pool if dict(key).get(x, 0) > 0)
+            neg = sum(1 for key in pool if dict(key).get(x, 0) < 0)
+            return pos * neg - pos - neg
+        x = min(vars_, key=lambda v: (cost(v), v))
+        pos, neg, nxt = [], [], {}
+        for key, const in pool.items():
+            c = dict(key).get(x, 0)
+            if c > 0:
+                pos.append((dict(key), const))
+            elif c < 0:
+                neg.append((dict(key), const))
+            else:
+                nxt[key] = const
+        for pc, pk in pos:
+            a = pc[x]
+            for nc, nk in neg:
+                b = -nc[x]
+                comb = {}
+                for m, c in pc.items():
+                    comb[m] = comb.get(m, 0) + b * c
+                for m, c in nc.items():
+                    comb[m] = comb.get(m, 0) + a * c
+                comb.pop(x, None)
+                if add(nxt, comb, b * pk + a * nk):
+                    return True
+        pool = nxt
+    return False
+
+
+def _lp_check(q, polys, facts):
+    """Facts (poly, 'ge'|'eq') -> True if their linear relaxation with atom
+    products and monomial ranges is infeasible over the rationals."""
+    present = {m for p, _ in facts for m in p if m != ()}
+    atoms = sorted({a for m in present for a in m})
+    rows = []
+    for p, kind in facts:
+        prods = [p]
+        for z in atoms:
+            zp = {tuple(sorted(m + (z,))): c for m, c in p.items()}
+            if all(m in present for m in zp):
+                prods.append(zp)
+        for r in prods:
+            coefs = {m: c for m, c in r.items() if m != ()}
+            const = r.get((), 0)
+            rows.append((coefs, const))
+            if kind == "eq":
+                rows.append(({m: -c for m, c in coefs.items()}, -const))
+    for m in present:
+        lo, hi = _poly_range(q, {m: 1}, polys)
+        rows.append(({m: 1}, -lo))
+        rows.append(({m: -1}, hi))
+    return fm_infeasible(rows) is True
+
+
 def root_check(q):
     """UNSAT if the root conjunction bounds one polynomial by an empty
     interval; else None (undecided)."""
@@ -572,6 +674,8 @@ def root_check(q):
         hi = rhi if hi is None else min(hi, rhi)
         if lo > hi:
             return UNSAT
+    if _lp_check(q, polys, facts):
+        return UNSAT
     return None
 
 

@@ -18,7 +18,7 @@ SAT, UNSAT, UNKNOWN = 1, 0, 2
 VERDICT = {1: "SAT", 0: "UNSAT", 2: "UNKNOWN"}
 HOW = {0: "root", 1: "device", 2: "budget"}
 MODE_DECIDE, MODE_COUNT = 0, 1
-SCORER_STATIC, SCORER_LEARNED = 0, 1
+SCORER_STATIC, SCORER_LEARNED, SCORER_WORD = 0, 1, 2
 CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2
 BB_NO_REWRITE = 1
 

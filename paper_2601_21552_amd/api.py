@@ -112,14 +112,22 @@ class Results(_Handle):
         return dict(zip(keys, ms.tolist()))
 
 
+_SCORERS = {"static": L.SCORER_STATIC, "learned": L.SCORER_LEARNED, "word": L.SCORER_WORD}
+
+
+def _scorer(scorer) -> int:
+    return _SCORERS[scorer] if isinstance(scorer, str) else int(scorer)
+
+
 def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_log2=0,
-                grid=0, max_rounds=0, learned=None):
+                grid=0, max_rounds=0, learned=None, scorer="static"):
     """learned: an L.LearnedScorer (Mlp.scorer()) selects the learned
-    ordering; None the static one."""
+    ordering; otherwise scorer is "static" or "word"."""
     o = L.SolveOpts()
     o.mode, o.k, o.max_cubes = mode, k, max_cubes
     o.leaves_per_round, o.chunk_log2, o.grid = leaves_per_round, chunk_log2, grid
     o.max_rounds = max_rounds
+    o.scorer = _scorer(scorer)
     if learned is not None:
         o.scorer = L.SCORER_LEARNED
         o.learned = C.pointer(learned)
@@ -180,11 +188,12 @@ class Context:
 
     # ------------------------------------------------------------ cubes
     def split(self, cnf: Cnf, k: int, max_cubes: int = 0, max_residual: int = 0,
-              learned=None, workspace=None, stream=None) -> Cubes:
+              learned=None, workspace=None, stream=None, scorer="static") -> Cubes:
         """Host cube splitting; learned (an L.LearnedScorer) scores the
         branching candidates on the device."""
         o = L.SplitOpts()
         o.k, o.max_cubes, o.max_residual = k, max_cubes, max_residual
+        o.scorer = _scorer(scorer)
         if learned is not None:
             nbytes = self.lib.scuba_scorer_workspace(cnf.h, learned.candidates)
             ws = self._workspace(nbytes, workspace)

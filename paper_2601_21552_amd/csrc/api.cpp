@@ -119,7 +119,7 @@ Opts resolve(const scuba_solve_opts* o) {
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
   if (r.chunk_log2 > 26) fail(SCUBA_E_INVALID, "chunk_log2 above 26");
-  if (r.scorer > SCUBA_SCORER_LEARNED) fail(SCUBA_E_INVALID, "unknown scorer");
+  if (r.scorer > SCUBA_SCORER_WORD) fail(SCUBA_E_INVALID, "unknown scorer");
   if (r.scorer == SCUBA_SCORER_LEARNED) {
     const scuba_learned_scorer* l = r.learned;
     if (!l || !l->master || !l->wbf16) fail(SCUBA_E_INVALID, "learned scorer without parameters");
@@ -524,7 +524,7 @@ scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split
   if (!ctx || !cnf || !opts || !out) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     if (opts->k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
-    if (opts->scorer > SCUBA_SCORER_LEARNED) fail(SCUBA_E_INVALID, "unknown scorer");
+    if (opts->scorer > SCUBA_SCORER_WORD) fail(SCUBA_E_INVALID, "unknown scorer");
     const bool learned = opts->scorer == SCUBA_SCORER_LEARNED;
     uint32_t max_res = opts->max_residual ? opts->max_residual : kDefaultMaxResidual;
     uint64_t max_cubes = opts->max_cubes ? opts->max_cubes : kDefaultMaxCubes;
@@ -543,6 +543,7 @@ scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split
     parallel_for(nq, [&](size_t qi) {
       sp[qi] = std::make_unique<Splitter>(cnf->q[qi], opts->k, max_res, max_cubes);
       if (learned) sp[qi]->set_learned(opts->learned->candidates, opts->learned->rescore);
+      if (opts->scorer == SCUBA_SCORER_WORD) sp[qi]->set_word_order();
       walks[qi] = sp[qi].get();
     });
     std::vector<std::vector<Cube>> all(nq);
@@ -842,6 +843,7 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
       if (!open[qi]) return;
       sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
       if (learned) sp[qi]->set_learned(o.learned->candidates, o.learned->rescore);
+      if (o.scorer == SCUBA_SCORER_WORD) sp[qi]->set_word_order();
     });
     split_ms += ms_since(ts);
     size_t cnf_b = dev_cnf_bytes(h);

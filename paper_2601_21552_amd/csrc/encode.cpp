@@ -22,6 +22,7 @@
 // bits directly (no auxiliary variables).
 #include <algorithm>
 #include <map>
+#include <set>
 #include <unordered_map>
 
 #include "bigint.hpp"
@@ -410,6 +411,104 @@ struct Bound {
 
 enum class Rel { GE0, EQ0 };
 
+// ---------------------------------------------------------------- relaxation
+//
+// Rational feasibility of a system of linear constraints over monomials,
+// each  dir . m + c >= 0  with dir a primitive integer vector and c a
+// reduced fraction.  Fourier-Motzkin elimination decides it exactly; for a
+// given direction only the tightest constant is kept.  Every derived
+// constraint is a non-negative combination of the inputs, so "infeasible"
+// is a proof that the integer system has no solution either.
+class Relaxation {
+ public:
+  static constexpr size_t kCap = 20000;   // constraints; beyond it: undecided
+
+  // dir . m + num/den >= 0 ; returns false on an immediate contradiction
+  bool add(Poly dir, BigInt num, BigInt den = BigInt(1)) { return insert(pool_, std::move(dir), num, den); }
+
+  // true: infeasible; false: feasible or undecided (cap)
+  bool infeasible() {
+    if (contradiction_) return true;
+    for (;;) {
+      if (pool_.size() > kCap) return false;
+      // variable with the fewest new constraints, ties to the smallest
+      std::map<Mono, std::pair<size_t, size_t>> occ;
+      for (auto& [dir, c] : pool_)
+        for (auto& [m, a] : dir) (a.sign() > 0 ? occ[m].first : occ[m].second)++;
+      if (occ.empty()) return false;
+      const Mono* best = nullptr;
+      long long best_cost = 0;
+      for (auto& [m, pn] : occ) {
+        long long cost = (long long)pn.first * (long long)pn.second - (long long)pn.first - (long long)pn.second;
+        if (!best || cost < best_cost) { best = &m; best_cost = cost; }
+      }
+      const Mono x = *best;
+      std::vector<const std::pair<const Poly, Frac>*> pos, neg;
+      Pool next;
+      for (auto& e : pool_) {
+        auto it = e.first.find(x);
+        if (it == e.first.end()) next.emplace(e.first, e.second);
+        else (it->second.sign() > 0 ? pos : neg).push_back(&e);
+      }
+      for (auto* p : pos) {
+        const BigInt a = p->first.at(x);
+        for (auto* q : neg) {
+          const BigInt b = -q->first.at(x);
+          Poly dir;
+          for (auto& [m, c] : p->first) if (m != x) dir[m] = c * b;
+          for (auto& [m, c] : q->first) {
+            if (m == x) continue;
+            BigInt v = dir[m] + c * a;
+            if (v.is_zero()) dir.erase(m);
+            else dir[m] = v;
+          }
+          // b*(pn/pd) + a*(qn/qd)
+          BigInt num = b * p->second.num * q->second.den + a * q->second.num * p->second.den;
+          BigInt den = p->second.den * q->second.den;
+          if (!insert(next, std::move(dir), num, den)) return true;
+        }
+      }
+      pool_.swap(next);
+    }
+  }
+
+ private:
+  struct Frac {
+    BigInt num, den;   // den > 0, reduced
+  };
+  using Pool = std::map<Poly, Frac>;
+
+  bool insert(Pool& pool, Poly dir, BigInt num, BigInt den) {
+    for (auto it = dir.begin(); it != dir.end();) {
+      if (it->second.is_zero()) it = dir.erase(it);
+      else ++it;
+    }
+    if (dir.empty()) {
+      if (num.sign() * den.sign() < 0) contradiction_ = true;
+      return !contradiction_;
+    }
+    BigInt g;
+    for (auto& [m, c] : dir) g = BigInt::gcd(g, c);
+    if (g != BigInt(1)) {
+      for (auto& [m, c] : dir) c = BigInt::floor_div(c, g);
+      den = den * g;
+    }
+    if (den.sign() < 0) { num = -num; den = -den; }
+    BigInt r = BigInt::gcd(num, den);
+    if (!r.is_zero() && r != BigInt(1)) {
+      num = BigInt::floor_div(num, r);
+      den = BigInt::floor_div(den, r);
+    }
+    auto it = pool.find(dir);
+    if (it == pool.end()) pool.emplace(std::move(dir), Frac{num, den});
+    else if (num * it->second.den < it->second.num * den) it->second = Frac{num, den};
+    return true;
+  }
+
+  Pool pool_;
+  bool contradiction_ = false;
+};
+
 class Encoder {
  public:
   Encoder(const scuba_node* nodes, uint64_t n, const uint32_t* roots, uint64_t nr, uint32_t flags,
@@ -498,6 +597,12 @@ class Encoder {
         if (lo > hi) { unsat_ = true; break; }
       }
     }
+    if (!unsat_) {
+      std::vector<std::pair<Poly, Rel>> all = facts_;
+      if (!subs.empty())
+        for (auto& [p, rel] : facts_) all.push_back({substitute_all(p, subs), rel});
+      unsat_ = relaxation_infeasible(all);
+    }
     if (unsat_) {
       out_.root_unsat = true;
       g_.clause(std::vector<int32_t>{});  // the empty clause
@@ -508,6 +613,57 @@ class Encoder {
       int32_t l = bool_lit(node);
       g_.clause({pos ? l : -l});
     }
+  }
+
+  // Linear relaxation of the root facts: every fact, its product with each
+  // atom when all monomials of the product already occur in the facts
+  // (z >= 0 and p >= 0 give z*p >= 0; p == 0 gives z*p == 0), and the value
+  // range of every monomial.  Infeasible over the rationals -> UNSAT.
+  bool relaxation_infeasible(const std::vector<std::pair<Poly, Rel>>& facts) const {
+    std::set<Mono> present;
+    for (auto& [p, rel] : facts)
+      for (auto& [m, c] : p)
+        if (!m.empty()) present.insert(m);
+    if (present.empty()) return false;
+    std::set<uint32_t> atoms;
+    for (const Mono& m : present) atoms.insert(m.begin(), m.end());
+    Relaxation lp;
+    auto add_row = [&](const Poly& p, Rel rel) {
+      Poly dir;
+      BigInt c0;
+      for (auto& [m, c] : p) {
+        if (m.empty()) c0 = c;
+        else dir[m] = c;
+      }
+      bool ok = true;
+      if (rel == Rel::EQ0) {
+        Poly neg;
+        for (auto& [m, c] : dir) neg[m] = -c;
+        ok = lp.add(std::move(neg), -c0);
+      }
+      return lp.add(std::move(dir), c0) && ok;
+    };
+    for (auto& [p, rel] : facts) {
+      if (!add_row(p, rel)) return true;
+      for (uint32_t z : atoms) {
+        if (atoms_[z].range.lo < BigInt(0)) continue;
+        Poly zp;
+        bool inside = true;
+        for (auto& [m, c] : p) {
+          Mono mz = m;
+          mz.insert(std::upper_bound(mz.begin(), mz.end(), z), z);
+          if (!present.count(mz)) { inside = false; break; }
+          zp[mz] = c;
+        }
+        if (inside && !add_row(zp, rel)) return true;
+      }
+    }
+    for (const Mono& m : present) {
+      Range r = mono_range(m);
+      if (!lp.add(Poly{{m, BigInt(1)}}, -r.lo)) return true;
+      if (!lp.add(Poly{{m, BigInt(-1)}}, r.hi)) return true;
+    }
+    return lp.infeasible();
   }
 
   Poly div_atom(uint64_t i) {

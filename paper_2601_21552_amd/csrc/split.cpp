@@ -44,6 +44,15 @@ Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_
     }
 }
 
+void Splitter::set_word_order() {
+  word_ = true;
+  word_order_.clear();
+  for (uint32_t v = 1; v <= n_; v++)
+    if (bit_width_[v]) word_order_.push_back(int32_t(v));
+  std::stable_sort(word_order_.begin(), word_order_.end(),
+                   [&](int32_t a, int32_t b) { return bit_pos_[a] > bit_pos_[b]; });
+}
+
 void Splitter::set_learned(uint32_t candidates, uint32_t rescore) {
   learned_ = true;
   n_cands_ = std::max<uint32_t>(candidates, 1);
@@ -282,6 +291,12 @@ bool Splitter::root_propagate() {
   return true;
 }
 
+int32_t Splitter::choose_word() const {
+  for (int32_t v : word_order_)
+    if (assign_[v] < 0 && act_cnt_[v] > 0) return v;
+  return choose_static();
+}
+
 int32_t Splitter::choose_static() const {
   for (int32_t v : order_)
     if (assign_[v] < 0 && act_cnt_[v] > 0) return v;
@@ -389,7 +404,7 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
             }
           }
         }
-        if (!v) v = choose_static();
+        if (!v) v = word_ ? choose_word() : choose_static();
         if (trace_ && stack_.size() < trace_depth_ && decisions_++ % trace_every_ == 0) {
           const std::vector<int32_t> cands = candidates(n_cands_);
           std::vector<float> fe;

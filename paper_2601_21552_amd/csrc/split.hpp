@@ -46,6 +46,10 @@ class Splitter {
   // of its descendants up to `rescore` levels below.  Non-finite scores fall
   // back to the static order.
   void set_learned(uint32_t candidates, uint32_t rescore);
+  // Word ordering: among active input bits the most significant first (ties
+  // to the lowest variable), which halves an input's value range per
+  // decision; then the static order for the remaining (auxiliary) variables.
+  void set_word_order();
   // Trace mode (static ordering): at every `every`-th decision node above
   // depth `depth`, record features and one-step lookahead labels of the top
   // `candidates` variables.
@@ -91,6 +95,7 @@ class Splitter {
   bool propagate(int32_t lit);     // a decision (or cube literal)
   void undo_to(size_t trail_pos);
   int32_t choose_static() const;
+  int32_t choose_word() const;
   int32_t first_literal(int32_t v) const;
   std::vector<uint32_t> analyze();
   void emit(CubeKind kind, std::vector<int32_t> lits, std::vector<Cube>& out, bool keep);
@@ -110,6 +115,8 @@ class Splitter {
   std::vector<uint32_t> occ_off_;   // literal index 2v+neg -> clause list
   std::vector<uint32_t> occ_;
   std::vector<int32_t> order_;      // static branching order
+  std::vector<int32_t> word_order_; // input bits by significance (word ordering)
+  bool word_ = false;
   // search state
   std::vector<int8_t> assign_;
   std::vector<int32_t> reason_;     // implying clause, -1 for decisions

@@ -81,6 +81,15 @@ def test_root_unsat_on_guarded_queries(ctx):
     assert one["root_unsat"] and one["n_clauses"] == 1
 
 
+def test_root_unsat_on_2d_queries(ctx):
+    """The library's relaxation with product lemmas decides every correct
+    2-D access at the root and never a buggy one."""
+    gens = w.config3(n=400)
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    for i, g in enumerate(gens):
+        assert cnf.view(i)["root_unsat"] == (g.label == "UNSAT"), g.query.name
+
+
 def _status(api, fn):
     from paper_2601_21552_amd import _lib
     with pytest.raises(_lib.ScubaError) as e:
@@ -151,6 +160,35 @@ def test_split_trees_complete_disjoint_and_canonical(ctx):
                     assert not ref["refuted"] and ref["f"] == cv["f"][c] <= k
                     total += ref["count"] << ref["m"]
             assert total == cnf_ref.count(f)
+
+
+def test_word_order_trees_count_integer_solutions(ctx):
+    """Word ordering on bit-blasted queries: complete, disjoint trees whose
+    leaf counts add up to the number of integer solutions."""
+    rng = np.random.Generator(np.random.PCG64(203))
+    qs = [random_query(rng, max_bits=10, name=f"wo{i}") for i in range(30)]
+    qs += [w.oob_2d(2, g, 1, 2, 1, False) for g in ("no_row", "col_le", "ld_free")]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs])
+    for k in (2, 6):
+        cubes = ctx.split(cnf, k=k, scorer="word")
+        static = ctx.split(cnf, k=k)
+        differ = False
+        for i, q in enumerate(qs):
+            cv = cubes.view(i)
+            assert cv["complete"]
+            _kraft_and_disjoint(cv["cubes"])
+            differ |= cv["cubes"] != static.view(i)["cubes"]
+            v = cnf.view(i)
+            f = CNF(v["n_vars"], v["clause_off"], v["lits"])
+            total = 0
+            for c, cube in enumerate(cv["cubes"]):
+                if cv["kind"][c] != 0:
+                    continue
+                ref = cnf_ref.leaf(f, cube)
+                assert not ref["refuted"] and ref["f"] == cv["f"][c] <= k
+                total += ref["count"] << ref["m"]
+            assert total == query_ref.int_bruteforce(q)[1], q.name
+        assert differ
 
 
 def test_split_budget_marks_incomplete(ctx):

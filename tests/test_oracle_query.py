@@ -7,7 +7,7 @@ import pytest
 
 from oracle import cnf_ref, query_ref
 from tests.querygen import random_query
-from workloads import Query, config1, config2, oob_1d, partition_query
+from workloads import oob_2d, config3, Query, config1, config2, oob_1d, partition_query
 
 
 # ---------------------------------------------------------------- worked examples
@@ -161,6 +161,57 @@ def test_config2_labels_by_construction():
         else:
             assert query_ref.int_eval_named(g.query, g.witness)
             assert query_ref.root_check(g.query) is None
+
+
+def test_config3_labels_by_construction():
+    """Correct 2-D guards are UNSAT by the chain row*ld + col <= (R-1)*ld +
+    (C-1) < R*ld (C <= ld); the root check must find it through the
+    product lemma ld*(R - 1 - row) >= 0.  Buggy ones carry witnesses."""
+    gens = config3(n=600)
+    assert sum(g.label == "UNSAT" for g in gens) == 300
+    kinds = set()
+    for g in gens:
+        kinds.add(g.kind)
+        if g.label == "UNSAT":
+            assert query_ref.root_check(g.query) == "UNSAT", g.query.name
+        else:
+            assert query_ref.int_eval_named(g.query, g.witness), g.query.name
+            assert query_ref.root_check(g.query) is None, g.query.name
+    assert len(kinds) == 6
+
+
+@pytest.mark.parametrize("w", [2, 3])
+def test_oob_2d_small_widths_match_brute_force(w):
+    """At widths the brute force covers, every 2-D variant's verdict and the
+    root check agree with exhaustive integer evaluation."""
+    for guard in ("ok", "no_row", "no_col", "row_le", "col_le", "ld_free"):
+        for mult, sep in ((1, False), (1, True), (2, False)):
+            if guard != "ok" and sep:
+                continue
+            q = oob_2d(w, guard, mult, 2, 1, sep)
+            if q.input_bits > 20:
+                continue
+            verdict = query_ref.int_bruteforce(q)[0]
+            assert verdict == ("UNSAT" if guard == "ok" else "SAT"), (guard, mult, sep)
+            rc = query_ref.root_check(q)
+            assert rc is None or verdict == "UNSAT"
+
+
+def test_fourier_motzkin_textbook_systems():
+    fm = query_ref.fm_infeasible
+    # x >= 1, y >= 1, x + y <= 1: infeasible
+    assert fm([({"x": 1}, -1), ({"y": 1}, -1), ({"x": -1, "y": -1}, 1)])
+    # 2x >= 1, 2x <= 1: x = 1/2 is a rational solution (integers aside)
+    assert fm([({"x": 2}, -1), ({"x": -2}, 1)]) is False
+    # x - y >= 0, y - z >= 0, z - x >= 1: a cycle that must grow
+    assert fm([({"x": 1, "y": -1}, 0), ({"y": 1, "z": -1}, 0), ({"z": 1, "x": -1}, -1)])
+    # the same cycle closed with 0: feasible (x = y = z)
+    assert fm([({"x": 1, "y": -1}, 0), ({"y": 1, "z": -1}, 0), ({"z": 1, "x": -1}, 0)]) is False
+    # 3x + 2y >= 7, x <= 1, y <= 2: max 3 + 4 = 7 -> feasible at (1, 2)
+    sys_ = [({"x": 3, "y": 2}, -7), ({"x": -1}, 1), ({"y": -1}, 2)]
+    assert fm(sys_) is False
+    sys_[0] = ({"x": 3, "y": 2}, -8)
+    assert fm(sys_)
 
 
 def test_config2_sat_decided_at_full_width():

@@ -192,3 +192,101 @@ def config5(seed: int = 5, n: int = 1024, width: int = 20):
             wit.update(t=idx, W=1, i=0)
         out.append(GenQuery(q, SAT, wit, kind=f"partition_{guard}"))
     return out
+
+
+def oob_2d(width: int, guard: str, mult: int, scale: int, header: int,
+           separate_ld: bool, name: str = "") -> Query:
+    """A row-major 2-D access ``buf[row*ld + col]`` into ``R`` rows of
+    ``ld`` elements of ``scale`` bytes after a ``header``-byte prefix.
+
+    mult (multipliers in the offset): 1: row and col are inputs; 2: row =
+    by*bdy + ty with ty < bdy; 3: also col = bx*bdx + tx with tx < bdx.
+    separate_ld: ld is its own input (with the assert C <= ld unless the
+    guard is "ld_free"); otherwise ld is C.
+    guard: "ok" (row < R and col < C), "no_row", "no_col", "row_le"
+    (row <= R), "col_le" (col <= C) or "ld_free" (ld independent of C, no
+    assert)."""
+    q = Query(name or f"oob2d_w{width}_{guard}_m{mult}_s{scale}_c{header}")
+    R = q.var("R", width)
+    C = q.var("C", width)
+    if separate_ld or guard == "ld_free":
+        ld = q.var("ld", width)
+        if guard != "ld_free":
+            q.require(C <= ld)
+    else:
+        ld = C
+    if mult >= 2:
+        by, bdy, ty = q.var("by", width), q.var("bdy", width), q.var("ty", width)
+        q.require(ty < bdy)
+        row = by * bdy + ty
+    else:
+        row = q.var("row", width)
+    if mult >= 3:
+        bx, bdx, tx = q.var("bx", width), q.var("bdx", width), q.var("tx", width)
+        q.require(tx < bdx)
+        col = bx * bdx + tx
+    else:
+        col = q.var("col", width)
+    if guard in ("ok", "no_col", "col_le", "ld_free"):
+        q.require(row < R)
+    elif guard == "row_le":
+        q.require(row <= R)
+    if guard in ("ok", "no_row", "row_le", "ld_free"):
+        q.require(col < C)
+    elif guard == "col_le":
+        q.require(col <= C)
+    offset = (row * ld + col) * scale + header
+    size = R * ld * scale + header
+    q.require(offset >= size)
+    return q
+
+
+def _witness_2d(guard: str, mult: int, has_ld: bool) -> dict:
+    """Inputs that make the buggy access of oob_2d go one element past the
+    end: R = 1 row, and either row = 1 (row guard missing or <=) or col =
+    1 with one column (col guard missing or <=), or ld = 1 < C = 2."""
+    if guard in ("no_row", "row_le"):
+        R, C, ld, row, col = 1, 1, 1, 1, 0
+    elif guard in ("no_col", "col_le"):
+        R, C, ld, row, col = 1, 1, 1, 0, 1
+    else:
+        R, C, ld, row, col = 1, 2, 1, 0, 1
+    wit = dict(R=R, C=C)
+    if has_ld:
+        wit["ld"] = ld
+    if mult >= 2:
+        wit.update(by=row, bdy=1, ty=0)
+    else:
+        wit["row"] = row
+    if mult >= 3:
+        wit.update(bx=col, bdx=1, tx=0)
+    else:
+        wit["col"] = col
+    return wit
+
+
+def config3(seed: int = 3, n: int = 4096, wmin: int = 8, wmax: int = 24):
+    """4096 row-major 2-D accesses of uneven size: widths w ~ U{wmin..wmax},
+    multipliers per offset mult ~ U{1,2,3}, element size s in {1,2,4,8},
+    header c ~ U{0..16}.  Half correct (row < R and col < C; ld is C, or a
+    separate ld with C <= ld in a quarter of them): UNSAT.  Half buggy,
+    evenly over no row guard, no col guard, row <= R, col <= C and an ld
+    independent of C: SAT."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    bugs = ["no_row", "no_col", "row_le", "col_le", "ld_free"]
+    kinds = ["ok"] * (n // 2) + [bugs[i % 5] for i in range(n - n // 2)]
+    kinds = [kinds[i] for i in rng.permutation(n)]
+    out = []
+    for i, g in enumerate(kinds):
+        w = int(rng.integers(wmin, wmax + 1))
+        mult = int(rng.integers(1, 4))
+        s = int(rng.choice([1, 2, 4, 8]))
+        c = int(rng.integers(0, 17))
+        sep = g == "ok" and rng.random() < 0.25
+        q = oob_2d(w, g, mult, s, c, sep, name=f"c3_{i}_w{w}_{g}_m{mult}_s{s}_c{c}")
+        if g == "ok":
+            out.append(GenQuery(q, UNSAT, kind="guarded_2d"))
+        else:
+            out.append(GenQuery(q, SAT, _witness_2d(g, mult, g == "ld_free"),
+                                kind=f"2d_{g}"))
+    return out
