@@ -45,6 +45,14 @@ class BigInt {
     return !t.bit(i);
   }
   bool fits_i64() const { return bit_length() <= 63; }
+  // value as a 128-bit integer when |x| < 2^bits (bits <= 126)
+  bool to_i128(__int128* out, uint32_t bits = 100) const {
+    if (bit_length() > bits) return false;
+    unsigned __int128 m = 0;
+    for (size_t i = mag_.size(); i-- > 0;) m = (m << 32) | mag_[i];
+    *out = neg_ ? -(__int128)m : (__int128)m;
+    return true;
+  }
   int64_t to_i64() const {
     uint64_t m = 0;
     if (mag_.size() > 0) m |= mag_[0];

@@ -16,6 +16,19 @@ struct Error : std::runtime_error {
 
 [[noreturn]] inline void fail(scuba_status c, const std::string& m) { throw Error(c, m); }
 
+// A root fact over atoms for word-level bounds at split nodes:
+// sum(coef * prod(atoms)) + c0 >= 0 (or == 0).  Atoms 0 .. inputs-1 are the
+// declared inputs; later atoms are quotients / remainders by constants.
+struct WordTerm {
+  std::vector<uint32_t> atoms;
+  __int128 coef;
+};
+struct WordFact {
+  std::vector<WordTerm> terms;
+  __int128 c0;
+  bool eq;
+};
+
 // One query's CNF plus what the result stage needs to decode witnesses.
 struct CnfQuery {
   uint32_t n_vars = 0;
@@ -23,7 +36,13 @@ struct CnfQuery {
   std::vector<int32_t> lits;
   std::vector<uint32_t> in_first;    // declared inputs: first CNF variable
   std::vector<uint32_t> in_width;    //                  width in bits
+  std::vector<uint8_t> in_defined;   // 1: a root equality defines the input
+                                     //    from the others (decided last)
   bool root_unsat = false;
+  // word-level root facts and the value range of every atom (empty when a
+  // magnitude would not fit 100 bits: then no word-level check)
+  std::vector<WordFact> word_facts;
+  std::vector<std::pair<__int128, __int128>> atom_range;
   // original query, kept for the exact integer witness check
   bool has_query = false;
   std::vector<scuba_node> nodes;

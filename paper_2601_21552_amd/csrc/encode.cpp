@@ -525,6 +525,7 @@ class Encoder {
       a.range = {BigInt(0), BigInt::pow2(nodes_[i].width) - BigInt(1)};
       out_.in_first.push_back(out_.n_vars + 1);
       out_.in_width.push_back(nodes_[i].width);
+      out_.in_defined.push_back(0);
       for (uint32_t b = 0; b < nodes_[i].width; b++) a.bits.push_back(g_.fresh());
       atoms_.push_back(a);
     }
@@ -585,6 +586,7 @@ class Encoder {
         if (&m != pivot) expr[m] = -(cc * c);
       for (auto& [a, e] : subs) e = substitute(e, atom, expr);
       subs.push_back({atom, expr});
+      if (atom < out_.in_defined.size()) out_.in_defined[atom] = 1;
     }
     if (!subs.empty())
       for (auto& [p, rel] : facts_) add_fact(check, substitute_all(p, subs), rel);
@@ -608,11 +610,53 @@ class Encoder {
       g_.clause(std::vector<int32_t>{});  // the empty clause
       return;
     }
+    export_word_facts(subs);
     for (auto& [key, b] : bounds_) assert_bound(key, b);
     for (auto& [node, pos] : complex_roots) {
       int32_t l = bool_lit(node);
       g_.clause({pos ? l : -l});
     }
+  }
+
+  // Root facts (as given and with the defining equalities substituted)
+  // for the splitter's word-level bounds; dropped as a whole when some
+  // magnitude could leave 100 bits.
+  void export_word_facts(const std::vector<std::pair<uint32_t, Poly>>& subs) {
+    std::vector<std::pair<Poly, Rel>> all = facts_;
+    if (!subs.empty())
+      for (auto& [p, rel] : facts_) all.push_back({substitute_all(p, subs), rel});
+    std::vector<std::pair<__int128, __int128>> ranges;
+    for (const Atom& a : atoms_) {
+      __int128 lo, hi;
+      if (!a.range.lo.to_i128(&lo, 64) || !a.range.hi.to_i128(&hi, 64) || lo < 0) return;
+      ranges.push_back({lo, hi});
+    }
+    std::vector<WordFact> out;
+    for (auto& [p, rel] : all) {
+      WordFact f;
+      f.eq = rel == Rel::EQ0;
+      f.c0 = 0;
+      BigInt mag;   // bound on |sum| over the atom ranges
+      for (auto& [m, c] : p) {
+        Range r = range_scale(mono_range(m), c);
+        mag = mag + (r.hi.abs() > r.lo.abs() ? r.hi.abs() : r.lo.abs());
+        if (m.empty()) {
+          if (!c.to_i128(&f.c0)) return;
+          continue;
+        }
+        WordTerm t;
+        t.atoms = m;
+        if (!c.to_i128(&t.coef)) return;
+        f.terms.push_back(std::move(t));
+      }
+      if (mag.bit_length() > 100 || f.terms.empty()) {
+        if (mag.bit_length() > 100) return;
+        continue;
+      }
+      out.push_back(std::move(f));
+    }
+    out_.word_facts = std::move(out);
+    out_.atom_range = std::move(ranges);
   }
 
   // Linear relaxation of the root facts: every fact, its product with each

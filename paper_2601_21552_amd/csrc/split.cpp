@@ -47,10 +47,19 @@ Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_
 void Splitter::set_word_order() {
   word_ = true;
   word_order_.clear();
+  // inputs that a root equality defines from the others come last: once
+  // the others are fixed, propagation through the equality fixes them
+  std::vector<uint8_t> defined(size_t(n_) + 1, 0);
+  for (size_t i = 0; i < q_.in_first.size(); i++) {
+    const bool d = i < q_.in_defined.size() && q_.in_defined[i];
+    for (uint32_t b = 0; b < q_.in_width[i]; b++) defined[q_.in_first[i] + b] = d;
+  }
   for (uint32_t v = 1; v <= n_; v++)
     if (bit_width_[v]) word_order_.push_back(int32_t(v));
-  std::stable_sort(word_order_.begin(), word_order_.end(),
-                   [&](int32_t a, int32_t b) { return bit_pos_[a] > bit_pos_[b]; });
+  std::stable_sort(word_order_.begin(), word_order_.end(), [&](int32_t a, int32_t b) {
+    if (defined[a] != defined[b]) return defined[a] < defined[b];
+    return bit_pos_[a] > bit_pos_[b];
+  });
 }
 
 void Splitter::set_learned(uint32_t candidates, uint32_t rescore) {
@@ -256,30 +265,144 @@ void Splitter::undo_to(size_t pos) {
 // Decision levels (1-based) that the last conflict depends on: walk the
 // implication graph back from the conflicting clause to decisions.
 std::vector<uint32_t> Splitter::analyze() {
-  std::vector<uint32_t> levels;
   if (conflict_clause_ < 0) {   // no clause to blame: depend on every decision
+    std::vector<uint32_t> levels;
     for (uint32_t l = 1; l <= stack_.size(); l++) levels.push_back(l);
     return levels;
   }
+  std::vector<int32_t> vars;
+  for (uint64_t i = q_.off[conflict_clause_]; i < q_.off[conflict_clause_ + 1]; i++)
+    vars.push_back(std::abs(q_.lits[i]));
+  return levels_of(vars);
+}
+
+// Decision levels behind the assignments of `vars` (through the implying
+// clauses).
+std::vector<uint32_t> Splitter::levels_of(const std::vector<int32_t>& vars) {
+  std::vector<uint32_t> levels;
   if (++seen_stamp_ == 0) { std::fill(seen_.begin(), seen_.end(), 0); seen_stamp_ = 1; }
   std::vector<int32_t> work;
-  auto push_clause = [&](uint64_t c) {
-    for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
-      int32_t u = std::abs(q_.lits[i]);
-      if (seen_[u] != seen_stamp_) { seen_[u] = seen_stamp_; work.push_back(u); }
-    }
+  auto push = [&](int32_t u) {
+    if (seen_[u] != seen_stamp_) { seen_[u] = seen_stamp_; work.push_back(u); }
   };
-  push_clause(uint64_t(conflict_clause_));
+  for (int32_t u : vars) push(u);
   while (!work.empty()) {
     int32_t u = work.back();
     work.pop_back();
     if (assign_[u] < 0 || level_[u] == 0) continue;   // root facts need no decision
-    if (reason_[u] < 0) levels.push_back(level_[u]);
-    else push_clause(uint64_t(reason_[u]));
+    if (reason_[u] < 0) {
+      levels.push_back(level_[u]);
+      continue;
+    }
+    const uint64_t c = uint64_t(reason_[u]);
+    for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) push(std::abs(q_.lits[i]));
   }
   std::sort(levels.begin(), levels.end());
   levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
   return levels;
+}
+
+namespace {
+__int128 floor_div128(__int128 a, __int128 b) {   // b > 0
+  __int128 q = a / b;
+  if (a % b != 0 && a < 0) q--;
+  return q;
+}
+__int128 ceil_div128(__int128 a, __int128 b) { return -floor_div128(-a, b); }
+}  // namespace
+
+// Interval propagation of the root facts over the atom ranges that the
+// current assignment of the input bits allows.  Returns false on an empty
+// range, with the decision levels it rests on.
+bool Splitter::word_check(std::vector<uint32_t>* levels) {
+  const size_t na = q_.atom_range.size();
+  const size_t ni = q_.in_first.size();
+  if (na == 0) return true;
+  wlo_.resize(na);
+  whi_.resize(na);
+  wsrc_.resize(na);
+  auto bit_of = [](size_t a) { return a < 63 ? uint64_t(1) << a : uint64_t(1) << 63; };
+  for (size_t a = 0; a < na; a++) {
+    wlo_[a] = q_.atom_range[a].first;
+    whi_[a] = q_.atom_range[a].second;
+    wsrc_[a] = 0;
+    if (a >= ni) continue;
+    __int128 lo = 0, hi = 0;
+    bool any = false;
+    for (uint32_t b = 0; b < q_.in_width[a]; b++) {
+      const int8_t v = assign_[q_.in_first[a] + b];
+      const __int128 w = (__int128)1 << b;
+      if (v == 1) { lo += w; hi += w; any = true; }
+      else if (v == 0) any = true;
+      else hi += w;
+    }
+    if (!any) continue;
+    if (lo > wlo_[a]) wlo_[a] = lo;
+    if (hi < whi_[a]) whi_[a] = hi;
+    wsrc_[a] = bit_of(a);
+  }
+  uint64_t blame = 0;
+  bool conflict = false;
+  for (int pass = 0; pass < 8 && !conflict; pass++) {
+    bool changed = false;
+    for (const WordFact& f : q_.word_facts) {
+      for (int sgn = 1; sgn >= -1 && !conflict; sgn -= 2) {
+        if (sgn < 0 && !f.eq) break;
+        // maximum of the fact's left side, and the atoms it rests on
+        __int128 total = sgn * f.c0;
+        uint64_t src = 0;
+        const size_t nt = f.terms.size();
+        __int128 tmax[64];
+        if (nt > 64) break;
+        for (size_t t = 0; t < nt; t++) {
+          const WordTerm& wt = f.terms[t];
+          __int128 plo = 1, phi = 1;
+          for (uint32_t a : wt.atoms) {
+            plo *= wlo_[a];
+            phi *= whi_[a];
+            src |= wsrc_[a];
+          }
+          const __int128 c = sgn * wt.coef;
+          tmax[t] = c > 0 ? c * phi : c * plo;
+          total += tmax[t];
+        }
+        if (total < 0) { conflict = true; blame = src; break; }
+        for (size_t t = 0; t < nt && !conflict; t++) {
+          const WordTerm& wt = f.terms[t];
+          const __int128 c = sgn * wt.coef;
+          const __int128 need = -(total - tmax[t]);   // c * prod >= need
+          for (size_t pos = 0; pos < wt.atoms.size(); pos++) {
+            const uint32_t a = wt.atoms[pos];
+            __int128 olo = 1, ohi = 1;
+            for (size_t o = 0; o < wt.atoms.size(); o++)
+              if (o != pos) { olo *= wlo_[wt.atoms[o]]; ohi *= whi_[wt.atoms[o]]; }
+            if (c > 0) {
+              if (need <= 0 || ohi <= 0) continue;   // nothing to learn (or 0 < need: total < 0 next pass)
+              const __int128 lo = ceil_div128(ceil_div128(need, c), ohi);
+              if (lo > wlo_[a]) { wlo_[a] = lo; wsrc_[a] |= src; changed = true; }
+            } else {
+              if (olo <= 0) continue;
+              const __int128 u = floor_div128(-need, -c);   // prod <= u
+              const __int128 hi = u < 0 ? -1 : floor_div128(u, olo);
+              if (hi < whi_[a]) { whi_[a] = hi; wsrc_[a] |= src; changed = true; }
+            }
+            if (wlo_[a] > whi_[a]) { conflict = true; blame = wsrc_[a] | src; break; }
+          }
+        }
+      }
+      if (conflict) break;
+    }
+    if (!changed) break;
+  }
+  if (!conflict) return true;
+  std::vector<int32_t> vars;
+  for (size_t a = 0; a < ni; a++) {
+    if (!(blame & bit_of(a))) continue;
+    for (uint32_t b = 0; b < q_.in_width[a]; b++)
+      if (assign_[q_.in_first[a] + b] >= 0) vars.push_back(int32_t(q_.in_first[a] + b));
+  }
+  *levels = levels_of(vars);
+  return false;
 }
 
 bool Splitter::root_propagate() {
@@ -385,6 +508,13 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
   }
   for (;;) {
     Failure r;
+    if (at_fresh_node_ && !stack_.empty() && !q_.word_facts.empty() && !word_checked_) {
+      word_checked_ = true;
+      if (!word_check(&r.levels)) {
+        emit(CubeKind::kPruned, path(), out, keep_refuted);
+        at_fresh_node_ = false;
+      }
+    }
     if (at_fresh_node_) {
       int32_t v = 0;
       if (f_ > k_ || n_unsat_ > max_res_) {
@@ -423,7 +553,7 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
       } else {
         const int32_t lit = first_literal(v);
         stack_.push_back({lit, 0, trail_.size(), Failure{}});
-        if (propagate(lit)) continue;
+        if (propagate(lit)) { word_checked_ = false; continue; }
         r.levels = analyze();
         emit(CubeKind::kRefuted, path(), out, keep_refuted);
       }
@@ -433,6 +563,7 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
     if (!moved) { state_ = kExhausted; return state_; }
     if (cubes_total() >= max_cubes_) { state_ = kBudget; return state_; }
     at_fresh_node_ = true;
+    word_checked_ = false;
     if (produced_ >= max_leaves) return kRunning;
   }
 }

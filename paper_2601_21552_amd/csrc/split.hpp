@@ -7,6 +7,12 @@
 // clauses is a leaf for the device; otherwise the scorer picks the branching
 // variable.  The walk is resumable, so leaves can be produced lazily.
 //
+// Word-level bounds: for bit-blasted queries the root facts over the inputs
+// are checked at every node against the value ranges the assigned input
+// bits leave (interval propagation to a fixpoint).  An empty range proves
+// the node has no model; it becomes a pruned cube, blamed on the decisions
+// behind the input bits the contradiction used.
+//
 // Backjumping: every propagation records the clause that implied each
 // variable, so a conflict names the decisions it depends on.  When every
 // failure below the 0-branch of a decision is a host conflict that does not
@@ -98,6 +104,8 @@ class Splitter {
   int32_t choose_word() const;
   int32_t first_literal(int32_t v) const;
   std::vector<uint32_t> analyze();
+  std::vector<uint32_t> levels_of(const std::vector<int32_t>& vars);
+  bool word_check(std::vector<uint32_t>* levels);
   void emit(CubeKind kind, std::vector<int32_t> lits, std::vector<Cube>& out, bool keep);
   std::vector<int32_t> path() const;
   bool finish_branch(Failure r, std::vector<Cube>& out, bool keep);
@@ -134,6 +142,10 @@ class Splitter {
   std::vector<uint32_t> static_rank_;   // position of each variable in order_
   std::vector<uint32_t> occurrences_;
   std::vector<uint32_t> bit_pos_, bit_width_;   // input bits: position and width
+  // word-level bounds (per atom: range and the atoms whose bits it rests on)
+  std::vector<__int128> wlo_, whi_;
+  std::vector<uint64_t> wsrc_;
+  bool word_checked_ = false;   // the current node passed the word check
   // learned ordering
   bool learned_ = false, have_scores_ = false, rank_valid_ = false;
   uint32_t n_cands_ = 32, rescore_ = 1;

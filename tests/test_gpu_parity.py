@@ -177,26 +177,63 @@ def test_decide_small_queries_brute_force(ctx):
                 assert query_ref.int_eval(q, res.witness(i, q.n_vars))
 
 
+def _witness_values(g):
+    """Generator witness as input values in declaration order."""
+    return [g.witness[name] for name in g.query.var_names]
+
+
 def test_decide_config5_partitions(ctx):
-    """1024 intra-allocation partition queries (20-bit sizes, 2..8 parts):
-    every guarded access UNSAT (decided at the root), every buggy one SAT
-    with a witness that goes past its partition under exact integers, or
-    UNKNOWN when the static-order walk runs out of cubes: never a wrong
-    verdict.  (Finding these witnesses by bit-level splitting is the known
-    weak spot of the static ordering.)"""
+    """1024 intra-allocation partition queries (20-bit sizes, 2..8 parts)
+    under the word ordering: every guarded access UNSAT at the root, every
+    buggy one SAT with a witness that goes past its partition under exact
+    integers; the oracle's verdict on a sample (DPLL, else the generator's
+    witness checked by the definition)."""
     gens = w.config5()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
-    res = ctx.decide(cnf, k=30, max_cubes=5000)
+    res = ctx.decide(cnf, k=30, max_cubes=20000, scorer="word")
+    for i, g in enumerate(gens):
+        r = res.result(i)
+        assert r["verdict"] == g.label, (g.query.name, r)
+        if g.label == "UNSAT":
+            assert query_ref.root_check(g.query) == "UNSAT"
+        else:
+            assert r["witness_checked"]
+            wit = res.witness(i, g.query.n_vars)
+            assert query_ref.int_eval(g.query, wit), g.query.name
+            if i % 16 == 0:
+                ov, _, how = query_ref.decide(g.query, max_nodes=300, candidate=_witness_values(g))
+                assert ov == "SAT", (g.query.name, how)
+
+
+def test_decide_config5_static_never_wrong(ctx):
+    """The static most-occurrences ordering on the same queries: UNKNOWN
+    when its walk runs out of cubes (the case the word ordering and the
+    learned scorer address), never a wrong verdict."""
+    gens = w.config5()[:256]
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    res = ctx.decide(cnf, k=30, max_cubes=3000)
     for i, g in enumerate(gens):
         r = res.result(i)
         if g.label == "SAT" and r["verdict"] == "UNKNOWN":
             continue
         assert r["verdict"] == g.label, (g.query.name, r)
-        if g.label == "UNSAT":
-            assert query_ref.root_check(g.query) == "UNSAT"
-        else:
-            wit = res.witness(i, g.query.n_vars)
-            assert query_ref.int_eval(g.query, wit), g.query.name
-            if i % 8 == 0:   # the oracle's own decision on a sample
-                ov, _, how = query_ref.decide(g.query, max_nodes=300, candidate=wit)
-                assert ov == "SAT", (g.query.name, how)
+        if g.label == "SAT":
+            assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
+
+
+def test_decide_config3_one_batch(ctx):
+    """All 4096 2-D accesses of uneven width (8..24 bits, 1..3 multipliers)
+    in one decide call: labels reproduced, correct ones UNSAT by the root
+    relaxation (the oracle's own root check agrees), every SAT witness
+    verified under exact integers."""
+    gens = w.config3()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    res = ctx.decide(cnf, k=30, max_cubes=20000, scorer="word")
+    for i, g in enumerate(gens):
+        r = res.result(i)
+        assert r["verdict"] == g.label, (g.query.name, r)
+        if g.label == "SAT":
+            assert r["witness_checked"]
+            assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars)), g.query.name
+        elif i % 8 == 0:
+            assert query_ref.root_check(g.query) == "UNSAT", g.query.name
