@@ -255,6 +255,13 @@ void scuba_trace_free(scuba_trace* t);
 /* ---------------------------------------------------------------- solve */
 #define SCUBA_MODE_DECIDE 0u   /* stop a query at its first satisfying leaf  */
 #define SCUBA_MODE_COUNT 1u    /* count every leaf's satisfying assignments   */
+/* Capture each device round (upload, propagation kernel, leaf kernel,
+ * download) as a HIP graph, once per round shape, and replay it on a
+ * library-owned stream ordered after the caller's stream; later rounds of
+ * the same shape (the same batch solved again) replay without capture.
+ * The graphs belong to the context (at most 64, least recently used
+ * dropped) and are released by scuba_ctx_destroy. */
+#define SCUBA_SOLVE_GRAPH 1u
 typedef struct {
   uint32_t mode;             /* SCUBA_MODE_*                                  */
   uint32_t k;                /* split bound for scuba_decide (<= 38)          */
@@ -265,7 +272,7 @@ typedef struct {
   uint32_t grid;             /* persistent workgroups (0 = 8 per CU)          */
   uint32_t max_rounds;       /* scuba_decide rounds (0 = unbounded)           */
   uint32_t scorer;           /* SCUBA_SCORER_*                                */
-  uint32_t reserved;
+  uint32_t flags;            /* SCUBA_SOLVE_*                                 */
   const scuba_learned_scorer* learned;   /* SCUBA_SCORER_LEARNED only; its
                                  buffers come from the end of the workspace */
 } scuba_solve_opts;
@@ -293,6 +300,41 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
  * is exhausted, or its budget is spent.                                    */
 scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
                           void* dev_ws, size_t ws_bytes, void* hip_stream, scuba_results** out);
+
+/* ---------------------------------------------------------------- autotune
+ * Picks k, chunk_log2, leaves_per_round and grid for scuba_decide on this
+ * batch.  A size-stratified sample of the queries is decided at every
+ * point of a coordinate sweep, one coordinate at a time, each keeping the
+ * best point before the next: k in {16, 20, 24, 28, 30}, chunk_log2 in
+ * {4, 6, 8, 10, 12}, leaves_per_round in {1, 2, 4, 8, 16}, grid in
+ * {2, 4, 8, 16} workgroups per CU; a point's time is the best wall time of
+ * `reps` runs.  Every point must give the same decided verdicts (UNKNOWN is
+ * compatible with SAT and UNSAT); a contradiction is SCUBA_E_INTERNAL.  The
+ * choice is cached in the context per bucket (log2 of the mean clause
+ * count, log2 of the batch size, scorer, flags): a cached bucket returns
+ * at once.  Points whose workspace exceeds ws_bytes are skipped;
+ * scuba_autotune_workspace gives the bytes for every point.             */
+typedef struct {
+  uint32_t sample;       /* queries decided per point (0 = 128)              */
+  uint32_t reps;         /* timed runs per point, best taken (0 = 2)         */
+  uint64_t max_cubes;    /* per query while tuning (0 = 20000)               */
+  uint32_t scorer;       /* SCUBA_SCORER_STATIC or SCUBA_SCORER_WORD          */
+  uint32_t flags;        /* SCUBA_SOLVE_* used while tuning and returned     */
+  uint32_t refresh;      /* 1: ignore the cache                              */
+  uint32_t reserved;
+} scuba_tune_opts;
+typedef struct {
+  uint32_t points;       /* points decided (0 when served from the cache)    */
+  uint32_t cached;       /* 1 when served from the cache                     */
+  double best_ms;        /* sample wall time at the chosen point             */
+  double default_ms;     /* sample wall time at the library defaults         */
+} scuba_tune_report;
+scuba_status scuba_autotune_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tune_opts* opts,
+                                      size_t* bytes);
+/* best: a complete scuba_solve_opts for scuba_decide on this batch. */
+scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tune_opts* opts, void* dev_ws,
+                            size_t ws_bytes, void* hip_stream, scuba_solve_opts* best,
+                            scuba_tune_report* report);
 
 /* ---------------------------------------------------------------- learned scorer
  * A perceptron scoring candidate branching variables: 16 features -> 128 ->
@@ -355,7 +397,9 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube,
 /* Stage times in ms: [0] host split, [1] upload, [2] device kernels (HIP
  * events on the caller's stream), [3] download, [4] verify, [5] total wall,
  * [6] propagation kernel, [7] leaf kernel; then launch counts: [8]
- * propagation kernel, [9] leaf kernel.  n <= 10.                            */
+ * propagation kernel, [9] leaf kernel; with SCUBA_SOLVE_GRAPH: [10] graph
+ * replays in ms (copies included; [1], [3], [6], [7] stay 0), [11] graph
+ * replays, [12] graph captures.  n <= 13.                                   */
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n);
 void scuba_results_free(scuba_results* r);
 

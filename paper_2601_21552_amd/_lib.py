@@ -19,6 +19,7 @@ VERDICT = {1: "SAT", 0: "UNSAT", 2: "UNKNOWN"}
 HOW = {0: "root", 1: "device", 2: "budget"}
 MODE_DECIDE, MODE_COUNT = 0, 1
 SCORER_STATIC, SCORER_LEARNED, SCORER_WORD = 0, 1, 2
+SOLVE_GRAPH = 1
 CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2
 BB_NO_REWRITE = 1
 
@@ -61,7 +62,18 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("k", C.c_uint32), ("max_cubes", C.c_uint64),
                 ("leaves_per_round", C.c_uint32), ("chunk_log2", C.c_uint32),
                 ("grid", C.c_uint32), ("max_rounds", C.c_uint32), ("scorer", C.c_uint32),
-                ("reserved", C.c_uint32), ("learned", C.POINTER(LearnedScorer))]
+                ("flags", C.c_uint32), ("learned", C.POINTER(LearnedScorer))]
+
+
+class TuneOpts(C.Structure):
+    _fields_ = [("sample", C.c_uint32), ("reps", C.c_uint32), ("max_cubes", C.c_uint64),
+                ("scorer", C.c_uint32), ("flags", C.c_uint32), ("refresh", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class TuneReport(C.Structure):
+    _fields_ = [("points", C.c_uint32), ("cached", C.c_uint32), ("best_ms", C.c_double),
+                ("default_ms", C.c_double)]
 
 
 class QueryResult(C.Structure):
@@ -111,6 +123,9 @@ SIGNATURES = {
     "scuba_leaf_get": (C.c_int32, [P, C.c_uint32, C.c_uint64, C.POINTER(LeafResult)]),
     "scuba_results_timing": (C.c_int32, [P, P, C.c_uint32]),
     "scuba_results_free": (None, [P]),
+    "scuba_autotune_workspace": (C.c_int32, [P, P, C.POINTER(TuneOpts), C.POINTER(C.c_size_t)]),
+    "scuba_autotune": (C.c_int32, [P, P, C.POINTER(TuneOpts), P, C.c_size_t, P, C.POINTER(SolveOpts),
+                                   C.POINTER(TuneReport)]),
     "scuba_mlp_param_count": (C.c_uint32, []),
     "scuba_mlp_sync": (C.c_int32, [P, P, P, P]),
     "scuba_mlp_forward": (C.c_int32, [P, P, P, P, C.c_uint32, P, P, P, P]),

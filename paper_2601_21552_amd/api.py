@@ -105,10 +105,10 @@ class Results(_Handle):
         return dict(refuted=bool(r.refuted), f=r.f, m=r.m, count=int(r.count), first=int(r.first))
 
     def timing(self) -> dict:
-        ms = np.zeros(10, np.float64)
-        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 10))
+        ms = np.zeros(13, np.float64)
+        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 13))
         keys = ["split", "h2d", "kernels", "d2h", "verify", "total", "up", "leaf",
-                "up_launches", "leaf_launches"]
+                "up_launches", "leaf_launches", "graph", "graph_launches", "graph_captures"]
         return dict(zip(keys, ms.tolist()))
 
 
@@ -120,7 +120,7 @@ def _scorer(scorer) -> int:
 
 
 def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_log2=0,
-                grid=0, max_rounds=0, learned=None, scorer="static"):
+                grid=0, max_rounds=0, learned=None, scorer="static", graph=False):
     """learned: an L.LearnedScorer (Mlp.scorer()) selects the learned
     ordering; otherwise scorer is "static" or "word"."""
     o = L.SolveOpts()
@@ -128,6 +128,7 @@ def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_
     o.leaves_per_round, o.chunk_log2, o.grid = leaves_per_round, chunk_log2, grid
     o.max_rounds = max_rounds
     o.scorer = _scorer(scorer)
+    o.flags = L.SOLVE_GRAPH if graph else 0
     if learned is not None:
         o.scorer = L.SCORER_LEARNED
         o.learned = C.pointer(learned)
@@ -281,6 +282,23 @@ class Context:
                                          ws.numel(), self._stream(stream), C.byref(h)))
         return Results(self, h, len(cnf))
 
+    def autotune(self, cnf: Cnf, workspace=None, stream=None, **tune):
+        """(decide options, report): k, chunk_log2, leaves_per_round and grid
+        for this batch (see scuba_autotune); the options go to decide()."""
+        t = _tune_opts(**tune)
+        n = C.c_size_t()
+        self._check(self.lib.scuba_autotune_workspace(self.h, cnf.h, C.byref(t), C.byref(n)))
+        ws = self._workspace(n.value, workspace)
+        best, rep = L.SolveOpts(), L.TuneReport()
+        self._check(self.lib.scuba_autotune(self.h, cnf.h, C.byref(t), _P(ws.data_ptr()), ws.numel(),
+                                            self._stream(stream), C.byref(best), C.byref(rep)))
+        names = {v: k for k, v in _SCORERS.items()}
+        opts = dict(k=best.k, leaves_per_round=best.leaves_per_round, chunk_log2=best.chunk_log2,
+                    grid=best.grid, scorer=names[best.scorer], graph=bool(best.flags & L.SOLVE_GRAPH))
+        report = dict(points=rep.points, cached=bool(rep.cached), best_ms=rep.best_ms,
+                      default_ms=rep.default_ms)
+        return opts, report
+
     def decide(self, cnf: Cnf, workspace=None, stream=None, **opts) -> Results:
         o = _solve_opts(**opts)
         ws = self._workspace(self.decide_workspace(cnf, **opts), workspace)
@@ -288,6 +306,11 @@ class Context:
         self._check(self.lib.scuba_decide(self.h, cnf.h, C.byref(o), _P(ws.data_ptr()), ws.numel(),
                                           self._stream(stream), C.byref(h)))
         return Results(self, h, len(cnf))
+
+
+def _tune_opts(sample=0, reps=0, max_cubes=0, scorer="static", graph=False, refresh=False):
+    return L.TuneOpts(sample, reps, max_cubes, _scorer(scorer), L.SOLVE_GRAPH if graph else 0,
+                      1 if refresh else 0, 0)
 
 
 class Mlp:

@@ -1,7 +1,10 @@
 // C ABI of the library: handles, the split/solve/decide drivers and results.
 #include <algorithm>
 #include <chrono>
+#include <limits>
+#include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 
@@ -21,6 +24,9 @@ struct scuba_ctx {
   std::string err;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  DevGraphs* graphs = nullptr;
+  // autotuner choices per size bucket (see scuba_autotune)
+  std::map<std::vector<uint64_t>, scuba_solve_opts> tuned;
 
   void ensure_device() {
     if (!dev_ready) {
@@ -39,7 +45,14 @@ struct scuba_ctx {
     }
     return pinned;
   }
-  ~scuba_ctx() { dev_pinned_free(pinned); }
+  DevGraphs* graph_cache() {
+    if (!graphs) graphs = dev_graphs_create(device);
+    return graphs;
+  }
+  ~scuba_ctx() {
+    dev_graphs_destroy(graphs);
+    dev_pinned_free(pinned);
+  }
 };
 
 struct scuba_cubes {
@@ -61,7 +74,7 @@ struct scuba_results {
     std::vector<scuba_leaf_result> leaves;
   };
   std::vector<Q> q;
-  double ms[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double ms[13] = {};
 };
 
 namespace {
@@ -101,10 +114,11 @@ struct Opts {
   uint32_t mode, k, lpr, chunk_log2, grid, max_rounds, scorer;
   uint64_t max_cubes;
   const scuba_learned_scorer* learned;
+  uint32_t flags;
 };
 Opts resolve(const scuba_solve_opts* o) {
   Opts r{SCUBA_MODE_DECIDE, kDefaultK, kDefaultLeavesPerRound, kDefaultChunkLog2, 0, 0, 0, kDefaultMaxCubes,
-         nullptr};
+         nullptr, 0};
   if (o) {
     r.mode = o->mode;
     if (o->k) r.k = o->k;
@@ -115,7 +129,9 @@ Opts resolve(const scuba_solve_opts* o) {
     r.scorer = o->scorer;
     if (o->max_cubes) r.max_cubes = o->max_cubes;
     r.learned = o->learned;
+    r.flags = o->flags;
   }
+  if (r.flags & ~SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "unknown solve flags");
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
   if (r.chunk_log2 > 26) fail(SCUBA_E_INVALID, "chunk_log2 above 26");
@@ -762,7 +778,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     std::vector<DevCubeOut> outs;
     std::vector<uint64_t> qkeys;
     dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, o.mode, o.grid, hip_stream, stg, ctx->pinned_bytes, &outs,
-              &qkeys, &rt);
+              &qkeys, &rt, (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr);
     auto tv = Clock::now();
     for (size_t i = 0; i < outs.size(); i++) {
       check_out(outs[i], sr.host[i]);
@@ -800,7 +816,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
       }
     });
     res->ms[1] = rt.h2d_ms;
-    res->ms[2] = rt.up_ms + rt.leaf_ms;
+    res->ms[2] = rt.up_ms + rt.leaf_ms + rt.graph_ms;
     res->ms[3] = rt.d2h_ms;
     res->ms[4] = ms_since(tv);
     res->ms[5] = ms_since(t0);
@@ -808,16 +824,18 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     res->ms[7] = rt.leaf_ms;
     res->ms[8] = rt.up_launches;
     res->ms[9] = rt.leaf_launches;
+    res->ms[10] = rt.graph_ms;
+    res->ms[11] = rt.graph_launches;
+    res->ms[12] = rt.graph_captures;
     *out = res.release();
   });
 }
 
-scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts, void* dev_ws,
-                          size_t ws_bytes, void* hip_stream, scuba_results** out) {
-  if (!ctx || !cnf || !out || !dev_ws) return SCUBA_E_INVALID;
-  return guard(ctx, [&] {
+// The lazy split / device round loop of scuba_decide (options resolved).
+std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf, const Opts& o, void* dev_ws,
+                                           size_t ws_bytes, void* hip_stream) {
+  {
     auto t0 = Clock::now();
-    Opts o = resolve(opts);
     if (o.mode != SCUBA_MODE_DECIDE) fail(SCUBA_E_INVALID, "scuba_decide runs in DECIDE mode");
     ctx->ensure_device();
     const size_t nq = cnf->q.size();
@@ -913,7 +931,8 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
       std::vector<DevCubeOut> outs;
       std::vector<uint64_t> qkeys;
       dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
-                ctx->pinned_bytes, &outs, &qkeys, &rt);
+                ctx->pinned_bytes, &outs, &qkeys, &rt,
+                (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr);
       auto tv = Clock::now();
       for (size_t i = 0; i < outs.size(); i++) {
         check_out(outs[i], sent[i].second);
@@ -955,7 +974,7 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
       }
     res->ms[0] = split_ms;
     res->ms[1] = rt.h2d_ms;
-    res->ms[2] = rt.up_ms + rt.leaf_ms;
+    res->ms[2] = rt.up_ms + rt.leaf_ms + rt.graph_ms;
     res->ms[3] = rt.d2h_ms;
     res->ms[4] = verify_ms;
     res->ms[5] = ms_since(t0);
@@ -963,7 +982,166 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
     res->ms[7] = rt.leaf_ms;
     res->ms[8] = rt.up_launches;
     res->ms[9] = rt.leaf_launches;
-    *out = res.release();
+    res->ms[10] = rt.graph_ms;
+    res->ms[11] = rt.graph_launches;
+    res->ms[12] = rt.graph_captures;
+    return res;
+  }
+}
+
+scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts, void* dev_ws,
+                          size_t ws_bytes, void* hip_stream, scuba_results** out) {
+  if (!ctx || !cnf || !out || !dev_ws) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    Opts o = resolve(opts);
+    *out = decide_impl(ctx, cnf, o, dev_ws, ws_bytes, hip_stream).release();
+  });
+}
+
+// ---------------------------------------------------------------- autotune
+
+namespace {
+
+constexpr uint32_t kTuneK[] = {16, 20, 24, 28, 30};
+constexpr uint32_t kTuneChunk[] = {4, 6, 8, 10, 12};
+constexpr uint32_t kTuneLpr[] = {1, 2, 4, 8, 16};
+constexpr uint32_t kTuneGridPerCu[] = {2, 4, 8, 16};
+
+struct TuneSetup {
+  uint32_t sample, reps, scorer, flags;
+  uint64_t max_cubes;
+};
+
+TuneSetup tune_setup(const scuba_tune_opts* t) {
+  TuneSetup r{128, 2, SCUBA_SCORER_STATIC, 0, 20000};
+  if (t) {
+    if (t->sample) r.sample = t->sample;
+    if (t->reps) r.reps = t->reps;
+    if (t->max_cubes) r.max_cubes = t->max_cubes;
+    r.scorer = t->scorer;
+    r.flags = t->flags;
+  }
+  if (r.scorer != SCUBA_SCORER_STATIC && r.scorer != SCUBA_SCORER_WORD)
+    fail(SCUBA_E_INVALID, "the autotuner tunes the static or the word ordering");
+  if (r.flags & ~SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "unknown solve flags");
+  return r;
+}
+
+// Queries spread over the size range: sorted by clause count, evenly spaced.
+scuba_cnf tune_sample(const scuba_cnf* cnf, uint32_t n) {
+  std::vector<size_t> idx(cnf->q.size());
+  for (size_t i = 0; i < idx.size(); i++) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](size_t a, size_t b) { return cnf->q[a].n_clauses() < cnf->q[b].n_clauses(); });
+  scuba_cnf out;
+  const size_t m = std::min<size_t>(n, idx.size());
+  for (size_t j = 0; j < m; j++) out.q.push_back(cnf->q[idx[j * idx.size() / m]]);
+  return out;
+}
+
+std::vector<uint64_t> tune_bucket(const scuba_cnf* cnf, const TuneSetup& ts) {
+  double mean = 0;
+  for (const CnfQuery& q : cnf->q) mean += double(q.n_clauses());
+  mean /= double(std::max<size_t>(cnf->q.size(), 1));
+  auto lg = [](double x) { return uint64_t(x < 1 ? 0 : std::log2(x)); };
+  return {lg(mean), lg(double(cnf->q.size())), ts.scorer, ts.flags};
+}
+
+Opts tune_point(const TuneSetup& ts, uint32_t k, uint32_t chunk, uint32_t lpr, uint32_t grid) {
+  Opts o{SCUBA_MODE_DECIDE, k, lpr, chunk, grid, 0, ts.scorer, ts.max_cubes, nullptr, ts.flags};
+  return o;
+}
+
+size_t tune_bytes(const scuba_cnf* sample, const Opts& o) {
+  CnfHost h = cnf_host(sample);
+  return dev_cnf_bytes(h) + round_bound(sample, sample->q.size() * o.lpr, o, kDefaultMaxResidual);
+}
+
+}  // namespace
+
+scuba_status scuba_autotune_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tune_opts* opts,
+                                      size_t* bytes) {
+  if (!ctx || !cnf || !bytes) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    TuneSetup ts = tune_setup(opts);
+    scuba_cnf sample = tune_sample(cnf, ts.sample);
+    size_t most = 0;
+    for (uint32_t k : kTuneK)
+      for (uint32_t c : kTuneChunk)
+        for (uint32_t l : kTuneLpr) most = std::max(most, tune_bytes(&sample, tune_point(ts, k, c, l, 0)));
+    *bytes = most;
+  });
+}
+
+scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tune_opts* opts, void* dev_ws,
+                            size_t ws_bytes, void* hip_stream, scuba_solve_opts* best,
+                            scuba_tune_report* report) {
+  if (!ctx || !cnf || !dev_ws || !best) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    TuneSetup ts = tune_setup(opts);
+    ctx->ensure_device();
+    scuba_tune_report rep{};
+    const std::vector<uint64_t> bucket = tune_bucket(cnf, ts);
+    auto hit = ctx->tuned.find(bucket);
+    if (hit != ctx->tuned.end() && !(opts && opts->refresh)) {
+      *best = hit->second;
+      rep.cached = 1;
+      if (report) *report = rep;
+      return;
+    }
+    scuba_cnf sample = tune_sample(cnf, ts.sample);
+    const uint32_t cus = uint32_t(ctx->dev.cus);
+    std::vector<int32_t> verdicts(sample.q.size(), SCUBA_UNKNOWN);
+    // wall time of the sample at a point (best of reps); +inf when skipped
+    auto measure = [&](const Opts& o) {
+      if (tune_bytes(&sample, o) > ws_bytes) return std::numeric_limits<double>::infinity();
+      double bestt = std::numeric_limits<double>::infinity();
+      for (uint32_t r = 0; r < ts.reps; r++) {
+        auto t0 = Clock::now();
+        std::unique_ptr<scuba_results> res = decide_impl(ctx, &sample, o, dev_ws, ws_bytes, hip_stream);
+        bestt = std::min(bestt, ms_since(t0));
+        for (size_t i = 0; i < verdicts.size(); i++) {
+          const int32_t v = res->q[i].r.verdict;
+          if (v == SCUBA_UNKNOWN) continue;
+          if (verdicts[i] != SCUBA_UNKNOWN && verdicts[i] != v)
+            fail(SCUBA_E_INTERNAL, "tuning points disagree on a verdict");
+          verdicts[i] = v;
+        }
+      }
+      rep.points++;
+      return bestt;
+    };
+    uint32_t k = kDefaultK, chunk = kDefaultChunkLog2, lpr = kDefaultLeavesPerRound, gpc = 8;
+    double cur = measure(tune_point(ts, k, chunk, lpr, gpc * cus));
+    rep.default_ms = cur;
+    auto sweep = [&](uint32_t* var, const uint32_t* vals, size_t n) {
+      for (size_t i = 0; i < n; i++) {
+        if (vals[i] == *var) continue;
+        const uint32_t keep = *var;
+        *var = vals[i];
+        double t = measure(tune_point(ts, k, chunk, lpr, gpc * cus));
+        if (t < cur) cur = t;
+        else *var = keep;
+      }
+    };
+    sweep(&k, kTuneK, std::size(kTuneK));
+    sweep(&chunk, kTuneChunk, std::size(kTuneChunk));
+    sweep(&lpr, kTuneLpr, std::size(kTuneLpr));
+    sweep(&gpc, kTuneGridPerCu, std::size(kTuneGridPerCu));
+    if (!std::isfinite(cur)) fail(SCUBA_E_CAPACITY, "no tuning point fits the workspace");
+    scuba_solve_opts b{};
+    b.mode = SCUBA_MODE_DECIDE;
+    b.k = k;
+    b.max_cubes = 0;
+    b.leaves_per_round = lpr;
+    b.chunk_log2 = chunk;
+    b.grid = gpc * cus;
+    b.scorer = ts.scorer;
+    b.flags = ts.flags;
+    ctx->tuned[bucket] = b;
+    *best = b;
+    rep.best_ms = cur;
+    if (report) *report = rep;
   });
 }
 
@@ -1043,7 +1221,7 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube, 
 }
 
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n) {
-  if (!r || !ms || n > 10) return SCUBA_E_INVALID;
+  if (!r || !ms || n > 13) return SCUBA_E_INVALID;
   std::copy(r->ms, r->ms + n, ms);
   return SCUBA_OK;
 }

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <list>
+#include <map>
 #include <string>
 
 #include "common.hpp"
@@ -495,9 +497,34 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
   HIP_OK(hipStreamSynchronize(st));
 }
 
+struct DevGraphs {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ready = nullptr;
+  std::map<std::vector<uint64_t>, hipGraphExec_t> execs;
+  std::list<std::vector<uint64_t>> lru;   // most recent first
+  static constexpr size_t kMax = 64;
+};
+
+DevGraphs* dev_graphs_create(int device) {
+  auto* g = new DevGraphs;
+  g->device = device;
+  return g;
+}
+
+void dev_graphs_destroy(DevGraphs* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  for (auto& [k, e] : g->execs) (void)hipGraphExecDestroy(e);
+  if (g->ready) (void)hipEventDestroy(g->ready);
+  if (g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+}
+
 void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
                uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
-               std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys, RoundTimes* times) {
+               std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys, RoundTimes* times,
+               DevGraphs* graphs) {
   HIP_OK(hipSetDevice(info.device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   CnfLayout cl = cnf_layout(cnf);
@@ -532,53 +559,104 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   for (size_t i = 0; i < nc; i++) std::memcpy(s + (rl.outs - b) + i * sizeof(DevCubeOut), &init, sizeof(init));
 
   char* w = static_cast<char*>(ws);
-  hipEvent_t ev[6];
-  for (auto& e : ev) HIP_OK(hipEventCreate(&e));
-  HIP_OK(hipEventRecord(ev[0], st));
-  HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, st));
-  HIP_OK(hipEventRecord(ev[1], st));
   const uint32_t g = grid ? grid : uint32_t(info.cus) * 8;
-  if (nc) {
-    uint32_t gu = std::min<uint32_t>(g, uint32_t(nc));
-    hipLaunchKernelGGL(up_kernel, dim3(gu), dim3(kBlock), up_lds, st,
-                       reinterpret_cast<const DevQueryDesc*>(w + cl.q),
-                       reinterpret_cast<const uint32_t*>(w + cl.coff),
-                       reinterpret_cast<const int32_t*>(w + cl.lits),
-                       reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
-                       reinterpret_cast<const int32_t*>(w + rl.lits), uint32_t(nc),
-                       reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
-                       reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
-    HIP_OK(hipGetLastError());
-    times->up_launches++;
+  const uint32_t gu = nc ? std::min<uint32_t>(g, uint32_t(nc)) : 0;
+  const uint32_t gl = ni ? std::min<uint32_t>(g, uint32_t(ni)) : 0;
+  // the whole round as one stream sequence: upload (the zeroed head and the
+  // initial outputs included, so no memset), kernels, download
+  auto enqueue = [&](hipStream_t q, hipEvent_t* ev) {
+    if (ev) HIP_OK(hipEventRecord(ev[0], q));
+    HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
+    if (ev) HIP_OK(hipEventRecord(ev[1], q));
+    if (gu) {
+      hipLaunchKernelGGL(up_kernel, dim3(gu), dim3(kBlock), up_lds, q,
+                         reinterpret_cast<const DevQueryDesc*>(w + cl.q),
+                         reinterpret_cast<const uint32_t*>(w + cl.coff),
+                         reinterpret_cast<const int32_t*>(w + cl.lits),
+                         reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
+                         reinterpret_cast<const int32_t*>(w + rl.lits), uint32_t(nc),
+                         reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
+                         reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
+      HIP_OK(hipGetLastError());
+    }
+    if (ev) HIP_OK(hipEventRecord(ev[2], q));
+    if (gl) {
+      hipLaunchKernelGGL(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, q,
+                         reinterpret_cast<const DevItem*>(w + rl.items), uint32_t(ni),
+                         reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
+                         reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
+                         reinterpret_cast<unsigned long long*>(w + cl.qkey),
+                         reinterpret_cast<uint32_t*>(w + rl.head), mode);
+      HIP_OK(hipGetLastError());
+    }
+    if (ev) HIP_OK(hipEventRecord(ev[3], q));
+    HIP_OK(hipMemcpyAsync(s, w + rl.outs, nc * sizeof(DevCubeOut), hipMemcpyDeviceToHost, q));
+    HIP_OK(hipMemcpyAsync(s + align256(nc * sizeof(DevCubeOut)), w + cl.qkey, cnf.q.size() * 8,
+                          hipMemcpyDeviceToHost, q));
+    if (ev) HIP_OK(hipEventRecord(ev[4], q));
+  };
+
+  hipEvent_t ev[5];
+  for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+  if (!graphs) {
+    enqueue(st, ev);
+    HIP_OK(hipStreamSynchronize(st));
+    float ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1])); times->h2d_ms += ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[1], ev[2])); times->up_ms += ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->leaf_ms += ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[3], ev[4])); times->d2h_ms += ms;
+    times->up_launches += gu != 0;
+    times->leaf_launches += gl != 0;
+  } else {
+    if (!graphs->stream) {
+      HIP_OK(hipStreamCreateWithFlags(&graphs->stream, hipStreamNonBlocking));
+      HIP_OK(hipEventCreateWithFlags(&graphs->ready, hipEventDisableTiming));
+    }
+    hipStream_t gs = graphs->stream;
+    std::vector<uint64_t> key = {uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(staging)), cl.end, nc,
+                                 rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), mode, gu, gl,
+                                 rh.nw_max, up_lds, leaf_lds, uint64_t(info.device)};
+    auto it = graphs->execs.find(key);
+    if (it == graphs->execs.end()) {
+      hipGraph_t graph;
+      HIP_OK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      enqueue(gs, nullptr);
+      HIP_OK(hipStreamEndCapture(gs, &graph));
+      hipGraphExec_t exec;
+      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIP_OK(e);
+      if (graphs->execs.size() >= DevGraphs::kMax) {
+        auto old = graphs->execs.find(graphs->lru.back());
+        (void)hipGraphExecDestroy(old->second);
+        graphs->execs.erase(old);
+        graphs->lru.pop_back();
+      }
+      it = graphs->execs.emplace(key, exec).first;
+      graphs->lru.push_front(key);
+      times->graph_captures++;
+    } else {
+      graphs->lru.remove(key);
+      graphs->lru.push_front(key);
+    }
+    // ordered after the caller's work on its stream
+    HIP_OK(hipEventRecord(graphs->ready, st));
+    HIP_OK(hipStreamWaitEvent(gs, graphs->ready, 0));
+    HIP_OK(hipEventRecord(ev[0], gs));
+    HIP_OK(hipGraphLaunch(it->second, gs));
+    HIP_OK(hipEventRecord(ev[1], gs));
+    HIP_OK(hipStreamSynchronize(gs));
+    float ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    times->graph_ms += ms;
+    times->graph_launches++;
   }
-  HIP_OK(hipEventRecord(ev[2], st));
-  if (ni) {
-    uint32_t gl = std::min<uint32_t>(g, uint32_t(ni));
-    hipLaunchKernelGGL(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, st,
-                       reinterpret_cast<const DevItem*>(w + rl.items), uint32_t(ni),
-                       reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
-                       reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
-                       reinterpret_cast<unsigned long long*>(w + cl.qkey),
-                       reinterpret_cast<uint32_t*>(w + rl.head), mode);
-    HIP_OK(hipGetLastError());
-    times->leaf_launches++;
-  }
-  HIP_OK(hipEventRecord(ev[3], st));
-  HIP_OK(hipMemcpyAsync(s, w + rl.outs, nc * sizeof(DevCubeOut), hipMemcpyDeviceToHost, st));
-  HIP_OK(hipMemcpyAsync(s + align256(nc * sizeof(DevCubeOut)), w + cl.qkey, cnf.q.size() * 8,
-                        hipMemcpyDeviceToHost, st));
-  HIP_OK(hipEventRecord(ev[4], st));
-  HIP_OK(hipStreamSynchronize(st));
+  for (auto& e : ev) (void)hipEventDestroy(e);
   outs->resize(nc);
   std::memcpy(outs->data(), s, nc * sizeof(DevCubeOut));
   qkeys->resize(cnf.q.size());
   std::memcpy(qkeys->data(), s + align256(nc * sizeof(DevCubeOut)), cnf.q.size() * 8);
-  float ms;
-  HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1])); times->h2d_ms += ms;
-  HIP_OK(hipEventElapsedTime(&ms, ev[1], ev[2])); times->up_ms += ms;
-  HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->leaf_ms += ms;
-  HIP_OK(hipEventElapsedTime(&ms, ev[3], ev[4])); times->d2h_ms += ms;
-  for (auto& e : ev) (void)hipEventDestroy(e);
 }
 
 }  // namespace scuba

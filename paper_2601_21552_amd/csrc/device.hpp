@@ -45,7 +45,16 @@ struct DevItem {
 struct RoundTimes {
   double up_ms = 0, leaf_ms = 0, h2d_ms = 0, d2h_ms = 0;
   uint32_t up_launches = 0, leaf_launches = 0;
+  double graph_ms = 0;            // replays of captured rounds (copies included)
+  uint32_t graph_launches = 0, graph_captures = 0;
 };
+
+// Captured rounds (HIP graphs) of one context, keyed by everything a
+// round's graph bakes in (pointers, sizes, launch shapes), with the stream
+// they are captured and replayed on.
+struct DevGraphs;
+DevGraphs* dev_graphs_create(int device);
+void dev_graphs_destroy(DevGraphs* g);
 
 // Device context: a device id, its CU count and events.
 struct DeviceInfo {
@@ -89,9 +98,11 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
 
 // Run one round: upload, unit propagation kernel, leaf kernel, download.
 // outs (n_cubes) and qkeys (nq) are filled; the stream is synchronised.
+// With graphs, the round is captured once per shape and replayed on the
+// cache's stream (ordered after the caller's stream).
 void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
                const RoundHost& round, uint32_t mode, uint32_t grid, void* stream, void* staging,
                size_t staging_bytes, std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys,
-               RoundTimes* times);
+               RoundTimes* times, DevGraphs* graphs = nullptr);
 
 }  // namespace scuba
