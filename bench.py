@@ -62,6 +62,86 @@ def _oracle_one(q):
     return query_ref.decide(q)[0]
 
 
+def train_scorer(ctx, batches, k, epochs, seed, candidates=32, depth=24):
+    """The learned scorer trained on the splitter's own traces of `batches`
+    (CNF handles), forward / backward / Adam in the library's kernels."""
+    from paper_2601_21552_amd import train
+    f, lab, nodes = train.collect(ctx, batches, k=k, candidates=candidates, depth=depth,
+                                  max_cubes=2000)
+    mlp, hist = train.train(ctx, f, train.node_targets(lab, nodes), epochs=epochs, seed=seed)
+    return mlp, {"rows": int(len(lab)), "epochs": epochs, "loss_first": round(hist[0], 4),
+                 "loss_last": round(hist[-1], 4)}
+
+
+def decide_stats(ctx, cnf, n, labels=None, **opts):
+    """One decide call: wall ms, verdict counts, leaves and cubes."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.decide(cnf, **opts)
+    ms = 1000.0 * (time.perf_counter() - t0)
+    out = {"ms": round(ms, 2), "SAT": 0, "UNSAT": 0, "UNKNOWN": 0, "leaves": 0, "cubes": 0}
+    verdicts = []
+    for i in range(n):
+        r = res.result(i)
+        verdicts.append(r["verdict"])
+        out[r["verdict"]] += 1
+        out["leaves"] += r["leaves_sent"]
+        out["cubes"] += r["cubes_total"]
+        if r["verdict"] == "SAT":
+            assert r["witness_checked"]
+    if labels is not None:
+        wrong = sum(v != "UNKNOWN" and v != l for v, l in zip(verdicts, labels))
+        assert wrong == 0, "a verdict contradicts the generator's label"
+        out["agree"] = sum(v == l for v, l in zip(verdicts, labels)) / n
+    return out, verdicts
+
+
+def gain_legs(ctx, mlp_q, log):
+    """Learned vs static on samples of the random 3-SAT workload (scorer
+    trained on disjoint-seed instances) and the partition queries (scorer
+    trained on 1-D / 2-D access traces): verdicts must agree; leaves, cubes
+    and wall time are reported."""
+    import workloads as w
+    from oracle import cnf_ref
+    out = {}
+    # random 3-SAT: n = 100 and 150, k = 16
+    tr = w.config4_train(per_n=48)
+    tr_batches = [ctx.cnf_from_arrays(*w.concat(tr[100])),
+                  ctx.cnf_from_arrays(*w.concat(tr[150][:16]))]
+    mlp_s, info = train_scorer(ctx, tr_batches, k=16, epochs=6, seed=4, candidates=16, depth=40)
+    log(f"3-SAT scorer trained: {info}")
+    ev = w.config4(per_n=32, ns=(100, 150))
+    for n, count in ((100, 32), (150, 16)):
+        cnfs = ev[n][:count]
+        raw = ctx.cnf_from_arrays(*w.concat(cnfs))
+        st, vs = decide_stats(ctx, raw, count, k=16, max_cubes=400000)
+        le, vl = decide_stats(ctx, raw, count, k=16, max_cubes=400000,
+                              learned=mlp_s.scorer(16, 1))
+        assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vs, vl))
+        leg = {"instances": count, "static": st, "learned": le,
+               "leaf_ratio": round(le["leaves"] / max(st["leaves"], 1), 3),
+               "time_ratio": round(le["ms"] / max(st["ms"], 1e-9), 3)}
+        if n == 100:
+            ov = [cnf_ref.solve(f)[0] for f in cnfs]
+            leg["oracle_agreement"] = sum(a == b for a, b in zip(ov, vs)) / count
+            assert leg["oracle_agreement"] == 1.0
+        out[f"random3sat_n{n}"] = leg
+        log(f"3-SAT n={n}: {leg}")
+    out["random3sat_scorer"] = info
+    # partition queries, all 1024
+    gens = w.config5()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    labels = [g.label for g in gens]
+    st, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000)
+    le, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000,
+                         learned=mlp_q.scorer(32, 1))
+    wo, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000, scorer="word")
+    out["partition_1024"] = {"static": st, "learned": le, "word": wo}
+    log(f"partition queries: {out['partition_1024']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +152,8 @@ def main():
     ap.add_argument("--leaves-per-round", type=int, default=4)
     ap.add_argument("--chunk-log2", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the word / learned forms")
+    ap.add_argument("--no-gain", action="store_true", help="skip the learned-vs-static legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -89,21 +171,30 @@ def main():
     stream = torch.cuda.current_stream()
     opts = dict(k=args.k, leaves_per_round=args.leaves_per_round, chunk_log2=args.chunk_log2)
 
-    def step():
-        cnf = ctx.bitblast(arrays)
-        res = ctx.decide(cnf, stream=stream, **opts)
-        return cnf, res
+    def run_steps(extra):
+        def step():
+            cnf = ctx.bitblast(arrays)
+            res = ctx.decide(cnf, stream=stream, **opts, **extra)
+            return cnf, res
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        results.append(step())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1000.0 * elapsed / args.steps
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for _ in range(args.steps):
+            out.append(step())
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        for cnf, res in out:
+            for i, g in enumerate(gens):
+                r = res.result(i)
+                assert r["verdict"] == labels[i], (g.query.name, r, extra)
+                if r["verdict"] == "SAT":
+                    assert r["witness_checked"]
+        return 1000.0 * elapsed / args.steps, out
+
+    ms_per_step, results = run_steps({})
 
     # agreement and accounting over the timed steps
     from oracle import query_ref
@@ -113,11 +204,6 @@ def main():
     leaf_launches = up_launches = 0
     split_ms = verify_ms = 0.0
     for cnf, res in results:
-        for i, g in enumerate(gens):
-            r = res.result(i)
-            assert r["verdict"] == labels[i], (g.query.name, r)
-            if r["verdict"] == "SAT":
-                assert r["witness_checked"]
         tm = res.timing()
         leaf_ms += tm["leaf"]
         up_ms += tm["up"]
@@ -136,18 +222,63 @@ def main():
             assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
 
     steps = args.steps
+    # algorithmic work of the last step (every step does the same work)
+    up_bytes = 0
+    for i in range(len(gens)):
+        r = res.result(i)
+        if r["leaves_sent"]:
+            v = cnf.view(i)
+            up_bytes += r["leaves_sent"] * 4 * (v["n_clauses"] + 1 + len(v["lits"]))
     leaf_avg_ms = leaf_ms / max(leaf_launches, 1)
-    ops_per_step = OPS_PER_CLAUSE_BLOCK * clause_blocks
-    leaf_launches_per_step = leaf_launches / steps
-    achieved = (ops_per_step / max(leaf_launches_per_step, 1)) / (leaf_avg_ms * 1e-3) / 1e12 \
-        if leaf_ms > 0 else 0.0
-    roofline = {"bound": "alu", "kernel": "leaf_kernel", "achieved": round(achieved, 4),
-                "peak": PEAK_INT32_TOPS, "unit": "TOP/s (int32 VALU lane-ops)",
-                "frac": round(achieved / PEAK_INT32_TOPS, 5), "traffic": None,
-                "avg_launch_ms": round(leaf_avg_ms, 4),
-                "launches_per_step": leaf_launches_per_step,
-                "clause_blocks_per_step": clause_blocks,
-                "up_kernel_avg_launch_ms": round(up_ms / max(up_launches, 1), 4)}
+    up_avg_ms = up_ms / max(up_launches, 1)
+    kernels = {
+        "leaf_kernel": dict(bound="alu", ms_step=leaf_ms / steps, avg=leaf_avg_ms,
+                            per_launch=OPS_PER_CLAUSE_BLOCK * clause_blocks / max(leaf_launches / steps, 1),
+                            peak=PEAK_INT32_TOPS, unit="TOP/s (int32 VALU lane-ops)", scale=1e12,
+                            launches=leaf_launches / steps),
+        "up_kernel": dict(bound="hbm", ms_step=up_ms / steps, avg=up_avg_ms,
+                          per_launch=up_bytes / max(up_launches / steps, 1),
+                          peak=PEAK_HBM_GBS, unit="GB/s (CNF bytes per cube)", scale=1e9,
+                          launches=up_launches / steps),
+    }
+    dom = max(kernels, key=lambda k: kernels[k]["ms_step"])
+    kd = kernels[dom]
+    achieved = kd["per_launch"] / (kd["avg"] * 1e-3) / kd["scale"] if kd["avg"] > 0 else 0.0
+    roofline = {"bound": kd["bound"], "kernel": dom, "achieved": round(achieved, 4),
+                "peak": kd["peak"], "unit": kd["unit"], "frac": round(achieved / kd["peak"], 5),
+                "traffic": None, "avg_launch_ms": round(kd["avg"], 4),
+                "launches_per_step": kd["launches"]}
+    other = "leaf_kernel" if dom == "up_kernel" else "up_kernel"
+    ko = kernels[other]
+    oach = ko["per_launch"] / (ko["avg"] * 1e-3) / ko["scale"] if ko["avg"] > 0 else 0.0
+    roofline["other"] = {"kernel": other, "bound": ko["bound"], "achieved": round(oach, 4),
+                         "peak": ko["peak"], "unit": ko["unit"], "frac": round(oach / ko["peak"], 5),
+                         "avg_launch_ms": round(ko["avg"], 4), "launches_per_step": ko["launches"]}
+    roofline["clause_blocks_per_step"] = clause_blocks
+    roofline["up_cnf_bytes_per_step"] = up_bytes
+
+    # the other orderings on the same batch and steps, and the learned
+    # scorer's gains on the random 3-SAT and partition workloads
+    def log(m):
+        print(m, file=sys.stderr, flush=True)
+
+    forms = {"static": round(len(gens) / (ms_per_step / 1000.0), 3)}
+    gain = None
+    scorer_info = None
+    if not (args.no_forms and args.no_gain):
+        import workloads as w
+        tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.config2(seed=102)]),
+              ctx.bitblast([g.query.arrays()[:2] for g in w.config3(seed=103, n=1024)])]
+        mlp_q, scorer_info = train_scorer(ctx, tr, k=30, epochs=4, seed=2)
+        log(f"access-query scorer trained: {scorer_info}")
+    if not args.no_forms:
+        for name, extra in (("word", dict(scorer="word")),
+                            ("learned", dict(learned=mlp_q.scorer(32, 1)))):
+            ms, _ = run_steps(extra)
+            forms[name] = round(len(gens) / (ms / 1000.0), 3)
+        log(f"forms (queries/s): {forms}")
+    if not args.no_gain:
+        gain = gain_legs(ctx, mlp_q, log)
 
     cpu = None
     agree = None
@@ -179,6 +310,9 @@ def main():
                    "chunk_log2": args.chunk_log2},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "forms": forms,
+        "learned_scorer": scorer_info,
+        "gain": gain,
         "detail": {"decided_at_root": n_root, "decided_on_device": n_dev,
                    "unknown": n_unknown, "oracle_agreement": agree,
                    "host_split_ms_per_step": round(split_ms / steps, 3),

@@ -9,6 +9,7 @@ import pytest
 
 from oracle import cnf_ref
 from workloads import CNF, pigeonhole, random_ksat
+import workloads as w
 
 
 def _rand_cnfs(seed, count, nmax=12):
@@ -177,3 +178,21 @@ def test_threshold_3sat_is_decided():
                 assert cnf_ref.check_model(cnf, model)
             if n == 20:
                 assert (v == "SAT") == (cnf_ref.brute_force(cnf)[0] > 0)
+
+
+def test_random_ksat_batch_model():
+    """Batch generator of the random k-SAT model: k distinct variables per
+    clause in range, signs and variables close to uniform."""
+    rng = np.random.Generator(np.random.PCG64(44))
+    fs = w.random_ksat_batch(50, 213, 3, 40, rng)
+    assert len(fs) == 40 and all(f.n_clauses == 213 and f.n_vars == 50 for f in fs)
+    lits = np.stack([f.lits.reshape(-1, 3) for f in fs])
+    v = np.abs(lits)
+    assert v.min() >= 1 and v.max() <= 50
+    s = np.sort(v, axis=2)
+    assert (s[:, :, 1:] != s[:, :, :-1]).all()
+    cnt = np.bincount(v.ravel(), minlength=51)[1:]
+    expect = v.size / 50
+    chi2 = float(((cnt - expect) ** 2 / expect).sum())
+    assert chi2 < 100, chi2          # 49 degrees of freedom
+    assert abs((lits > 0).mean() - 0.5) < 0.02

@@ -83,3 +83,24 @@ def concat(cnfs):
         base_lit += len(c.lits)
     return (n_vars, q_start, np.concatenate(offs),
             np.concatenate(lits) if lits else np.zeros(0, np.int32))
+
+
+def random_ksat_batch(n: int, m: int, k: int, count: int, rng: np.random.Generator,
+                      prefix: str = "") -> list:
+    """`count` independent uniform random k-SAT instances (the model of
+    random_ksat), drawn with whole-array operations: each clause's k
+    variables are uniform integers, rows with a repeated variable are drawn
+    again until every row is distinct (rejection keeps the distribution
+    uniform over distinct k-tuples)."""
+    vs = rng.integers(1, n + 1, size=(count, m, k))
+    while True:
+        s = np.sort(vs, axis=2)
+        bad = (s[:, :, 1:] == s[:, :, :-1]).any(axis=2)
+        nb = int(bad.sum())
+        if nb == 0:
+            break
+        vs[bad] = rng.integers(1, n + 1, size=(nb, k))
+    signs = rng.integers(0, 2, size=(count, m, k)) * 2 - 1
+    off = np.arange(0, m * k + 1, k, dtype=np.uint64)
+    return [CNF(n, off, (vs[i] * signs[i]).astype(np.int32).ravel(),
+                f"{prefix}r{k}sat_n{n}_m{m}_{i}") for i in range(count)]

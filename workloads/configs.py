@@ -19,6 +19,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .query import Query
+from .cnf import random_ksat_batch
 
 SAT, UNSAT = "SAT", "UNSAT"
 
@@ -290,3 +291,20 @@ def config3(seed: int = 3, n: int = 4096, wmin: int = 8, wmax: int = 24):
             out.append(GenQuery(q, SAT, _witness_2d(g, mult, g == "ld_free"),
                                 kind=f"2d_{g}"))
     return out
+
+
+def config4(seed: int = 4, per_n: int = 2500, ns=(100, 150, 200, 250), ratio: float = 4.26):
+    """Uniform random 3-SAT at the threshold: per_n instances for each n,
+    m = round(ratio * n) clauses.  Returns {n: [CNF, ...]} (no labels: the
+    oracle decides them)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return {n: random_ksat_batch(n, int(round(ratio * n)), 3, per_n, rng, prefix=f"c4_")
+            for n in ns}
+
+
+def config4_train(seed: int = 40, per_n: int = 1000, ns=(100, 150), ratio: float = 4.26):
+    """The scorer's training instances for the random 3-SAT workload: the
+    same model from a disjoint seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return {n: random_ksat_batch(n, int(round(ratio * n)), 3, per_n, rng, prefix=f"c4t_")
+            for n in ns}
