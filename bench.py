@@ -154,6 +154,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the word / learned forms")
     ap.add_argument("--no-gain", action="store_true", help="skip the learned-vs-static legs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device 3 times (a plain copy kernel of known "
+                         "size, to scale hardware byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -163,6 +166,15 @@ def main():
 
     import torch
     from paper_2601_21552_amd import api
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 18          # float32 elements
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     gens = make_batch(args.config)
     arrays = [g.query.arrays()[:2] for g in gens]

@@ -154,7 +154,7 @@ CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
   CnfHost h;
   uint32_t nw_all = 0;
   for (const CnfQuery& q : cnf->q) nw_all = std::max(nw_all, (q.n_vars >> 5) + 1);
-  const size_t bitmaps = size_t(nw_all) * 16 + 2048;   // + static LDS
+  const size_t bitmaps = size_t(nw_all) * 16 + 2048 + 2 * kUpQueue * 4;   // + static LDS, queues
   const size_t budget = lds_limit > bitmaps ? lds_limit - bitmaps : 0;
   for (const CnfQuery& q : cnf->q) {
     DevQueryDesc d{};
@@ -171,6 +171,21 @@ CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
     }
     for (uint64_t o : q.off) h.coff.push_back(uint32_t(o));
     h.lits.insert(h.lits.end(), q.lits.begin(), q.lits.end());
+    // occurrence lists: literal index 2*v + (l < 0) -> clauses, in clause order
+    d.occ_off_base = h.occ_off.size();
+    d.occ_base = h.occ.size();
+    const size_t nli = 2 * (size_t(q.n_vars) + 1);
+    std::vector<uint32_t> cnt(nli + 1, 0);
+    for (int32_t l : q.lits) cnt[2 * size_t(l > 0 ? l : -l) + (l < 0) + 1]++;
+    for (size_t i = 0; i < nli; i++) cnt[i + 1] += cnt[i];
+    h.occ_off.insert(h.occ_off.end(), cnt.begin(), cnt.end());
+    const size_t ob = h.occ.size();
+    h.occ.resize(ob + q.lits.size());
+    for (uint64_t c = 0; c < q.n_clauses(); c++)
+      for (uint64_t i = q.off[c]; i < q.off[c + 1]; i++) {
+        const int32_t l = q.lits[i];
+        h.occ[ob + cnt[2 * size_t(l > 0 ? l : -l) + (l < 0)]++] = uint32_t(c);
+      }
     h.q.push_back(d);
   }
   return h;

@@ -124,20 +124,55 @@ __device__ __forceinline__ bool clause_satisfied(const Cnf& cnf, uint32_t c, con
 }
 
 struct UpShared {
-  uint32_t conflict, flags[3], wave[kBlock / 64], error;
+  uint32_t conflict, wave[kBlock / 64], error;
+  // per round parity: frontier length, overflow, something newly set
+  uint32_t qn[2], ovf[2], chg[2];
 };
+
+// One clause against the current assignment: a conflict is flagged, a unit
+// literal is set and, when it is new, queued for the next round.
+template <class Cnf>
+__device__ __forceinline__ void visit_clause(const Cnf& cnf, uint32_t c, uint32_t* T, uint32_t* F,
+                                             uint32_t* next, uint32_t w, UpShared& sh) {
+  bool sat = false;
+  uint32_t open = 0, last_v = 0;
+  bool last_neg = false;
+  for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+    uint32_t v;
+    bool neg;
+    cnf.lit(i, &v, &neg);
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
+    if (neg ? f : t) { sat = true; break; }
+    if (!(t | f)) { open++; last_v = v; last_neg = neg; }
+  }
+  if (sat) return;
+  if (open == 0) {
+    sh.conflict = 1;
+  } else if (open == 1) {
+    const uint32_t bit = 1u << (last_v & 31);
+    const uint32_t old = atomicOr(last_neg ? &F[last_v >> 5] : &T[last_v >> 5], bit);
+    if (!(old & bit)) {
+      sh.chg[w] = 1;
+      const uint32_t slot = atomicAdd(&sh.qn[w], 1u);
+      if (slot < kUpQueue) next[slot] = (last_v << 1) | (last_neg ? 0u : 1u);   // value in bit 0
+      else sh.ovf[w] = 1;
+    }
+  }
+}
 
 // Unit propagation of one cube, then its active variables, slots and
 // residual records.  Called by the whole workgroup (uniform control flow).
 template <class Cnf>
-__device__ void propagate_cube(const Cnf& cnf, const DevCubeDesc& cd, uint32_t ci, uint32_t nv, uint32_t nc,
-                               const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
+__device__ void propagate_cube(const Cnf& cnf, const uint32_t* __restrict__ occ_off,
+                               const uint32_t* __restrict__ occ, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
+                               uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
                                uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
-                               UpShared& sh) {
+                               uint32_t* Q, UpShared& sh) {
   const uint32_t tid = threadIdx.x;
   const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
   for (uint32_t w = tid; w < nw; w += kBlock) { T[w] = 0; F[w] = 0; A[w] = 0; }
-  if (tid == 0) { sh.conflict = 0; sh.error = 0; sh.flags[0] = 0; sh.flags[1] = 0; sh.flags[2] = 0; }
+  if (tid == 0) { sh.conflict = 0; sh.error = 0; sh.qn[1] = 0; sh.ovf[1] = 0; sh.chg[1] = 0; }
   __syncthreads();
   for (uint32_t j = tid; j < cd.n_lits; j += kBlock) {
     int32_t l = cube_lits[cd.lit_off + j];
@@ -147,37 +182,37 @@ __device__ void propagate_cube(const Cnf& cnf, const DevCubeDesc& cd, uint32_t c
   }
   __syncthreads();
 
-  // ---- propagation rounds; at most 2*(nv+1) rounds change something
+  // ---- propagation rounds.  Round 0 scans every clause; later rounds visit
+  // only the clauses of the literals that the previous round made false
+  // (the frontier), unless that frontier overflowed its queue, in which
+  // case the round scans every clause again.  A round that sets nothing
+  // new ends at the fixpoint: every clause has been visited after its last
+  // false literal was assigned.  Each variable enters a queue at most once
+  // per value, so at most 2*(nv+1) rounds change something.
   const uint32_t max_rounds = 2 * nv + 4;
   for (uint32_t r = 0;; r++) {
-    if (tid == 0) sh.flags[(r + 1) % 3] = 0;
-    for (uint32_t w = tid; w < nw; w += kBlock)
-      if (T[w] & F[w]) sh.conflict = 1;
-    for (uint32_t c = tid; c < nc; c += kBlock) {
-      bool sat = false;
-      uint32_t open = 0, last_v = 0;
-      bool last_neg = false;
-      for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
-        uint32_t v;
-        bool neg;
-        cnf.lit(i, &v, &neg);
+    const uint32_t w = r & 1, pw = w ^ 1;
+    if (tid == 0) { sh.qn[w] = 0; sh.ovf[w] = 0; sh.chg[w] = 0; }
+    __syncthreads();
+    uint32_t* next = Q + w * kUpQueue;
+    if (r == 0 || sh.ovf[pw]) {
+      for (uint32_t c = tid; c < nc; c += kBlock) visit_clause(cnf, c, T, F, next, w, sh);
+    } else {
+      const uint32_t* cur = Q + pw * kUpQueue;
+      const uint32_t n = min(sh.qn[pw], kUpQueue);
+      for (uint32_t j = tid; j < n; j += kBlock) {
+        const uint32_t e = cur[j];
+        const uint32_t v = e >> 1, val = e & 1;
         const uint32_t bit = 1u << (v & 31);
-        const uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
-        if (neg ? f : t) { sat = true; break; }
-        if (!(t | f)) { open++; last_v = v; last_neg = neg; }
-      }
-      if (sat) continue;
-      if (open == 0) {
-        sh.conflict = 1;
-      } else if (open == 1) {
-        const uint32_t bit = 1u << (last_v & 31);
-        const uint32_t old = atomicOr(last_neg ? &F[last_v >> 5] : &T[last_v >> 5], bit);
-        if (!(old & bit)) sh.flags[r % 3] = 1;
+        if (T[v >> 5] & F[v >> 5] & bit) { sh.conflict = 1; continue; }
+        // the literal of v that is now false has sign "negative" iff v = 1
+        const uint32_t li = 2 * v + val;
+        for (uint32_t k = occ_off[li], ke = occ_off[li + 1]; k < ke; k++)
+          visit_clause(cnf, occ[k], T, F, next, w, sh);
       }
     }
     __syncthreads();
-    const uint32_t changed = sh.flags[r % 3], conflict = sh.conflict;
-    __syncthreads();   // every thread has read the flags of this round
+    const uint32_t changed = sh.chg[w], conflict = sh.conflict;
     if (conflict || !changed) break;
     if (r >= max_rounds) {   // cannot happen: every changing round sets a new bit
       if (tid == 0) sh.error = 1;
@@ -271,19 +306,22 @@ __device__ void propagate_cube(const Cnf& cnf, const DevCubeDesc& cd, uint32_t c
 __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restrict__ qd,
                                                    const uint32_t* __restrict__ coff,
                                                    const int32_t* __restrict__ lits,
+                                                   const uint32_t* __restrict__ occ_offs,
+                                                   const uint32_t* __restrict__ occs,
                                                    const DevCubeDesc* __restrict__ cubes,
                                                    const int32_t* __restrict__ cube_lits,
                                                    uint32_t n_cubes, DevCubeOut* __restrict__ out,
                                                    uint4* __restrict__ res, uint32_t* head,
                                                    uint32_t nw_max) {
-  // LDS: four bitmaps of nw_max words, then (for staged queries) the CNF
-  // as 16-bit offsets and 16-bit literals
+  // LDS: four bitmaps of nw_max words, the two frontier queues, then (for
+  // staged queries) the CNF as 16-bit offsets and 16-bit literals
   extern __shared__ uint32_t smem[];
   uint32_t* T = smem;
   uint32_t* F = T + nw_max;
   uint32_t* A = F + nw_max;
   uint32_t* P = A + nw_max;
-  uint16_t* stage = reinterpret_cast<uint16_t*>(P + nw_max);
+  uint32_t* Q = P + nw_max;
+  uint16_t* stage = reinterpret_cast<uint16_t*>(Q + 2 * kUpQueue);
   __shared__ UpShared sh;
   __shared__ uint32_t s_item;
   const uint32_t tid = threadIdx.x;
@@ -299,6 +337,8 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
     const DevQueryDesc q = qd[cd.qid];
     const uint32_t* co = coff + q.coff_base;
     const int32_t* L = lits + q.lit_base;
+    const uint32_t* oo = occ_offs + q.occ_off_base;
+    const uint32_t* oc = occs + q.occ_base;
     if (q.staged) {
       const uint32_t nl = co[q.n_clauses];
       uint16_t* sco = stage;
@@ -309,9 +349,11 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
         sl[i] = uint16_t((uint32_t(l > 0 ? l : -l) << 1) | (l < 0 ? 1u : 0u));
       }
       __syncthreads();
-      propagate_cube(LdsCnf{sco, sl}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P, sh);
+      propagate_cube(LdsCnf{sco, sl}, oo, oc, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P,
+                     Q, sh);
     } else {
-      propagate_cube(GlobalCnf{co, L}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P, sh);
+      propagate_cube(GlobalCnf{co, L}, oo, oc, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P,
+                     Q, sh);
     }
   }
 }
@@ -419,14 +461,16 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct CnfLayout {
-  size_t q, coff, lits, qkey, end;
+  size_t q, coff, lits, occ_off, occ, qkey, end;
 };
 CnfLayout cnf_layout(const CnfHost& c) {
   CnfLayout l;
   l.q = 0;
   l.coff = align256(l.q + c.q.size() * sizeof(DevQueryDesc));
   l.lits = align256(l.coff + c.coff.size() * 4);
-  l.qkey = align256(l.lits + c.lits.size() * 4);
+  l.occ_off = align256(l.lits + c.lits.size() * 4);
+  l.occ = align256(l.occ_off + c.occ_off.size() * 4);
+  l.qkey = align256(l.occ + c.occ.size() * 4);
   l.end = align256(l.qkey + c.q.size() * 8);
   return l;
 }
@@ -491,6 +535,8 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
   std::memcpy(s + l.q, cnf.q.data(), cnf.q.size() * sizeof(DevQueryDesc));
   std::memcpy(s + l.coff, cnf.coff.data(), cnf.coff.size() * 4);
   std::memcpy(s + l.lits, cnf.lits.data(), cnf.lits.size() * 4);
+  std::memcpy(s + l.occ_off, cnf.occ_off.data(), cnf.occ_off.size() * 4);
+  std::memcpy(s + l.occ, cnf.occ.data(), cnf.occ.size() * 4);
   std::memset(s + l.qkey, 0xFF, cnf.q.size() * 8);
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_OK(hipMemcpyAsync(ws, s, l.end, hipMemcpyHostToDevice, st));
@@ -535,7 +581,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   if (up_bytes > staging_bytes || align256(nc * sizeof(DevCubeOut)) + cnf.q.size() * 8 > staging_bytes)
     fail(SCUBA_E_INTERNAL, "staging too small");
   // host-side checks of what the kernels assume
-  const size_t up_lds = size_t(rh.nw_max) * 4 * 4 + cnf.stage_bytes;
+  const size_t up_lds = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * 4 + cnf.stage_bytes;
   const size_t leaf_lds = size_t(std::max<uint32_t>(rh.tile_max, 1)) * 16;
   if (up_lds + 1024 > info.max_lds) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
   if (leaf_lds + 64 > info.max_lds) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");
@@ -573,6 +619,8 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                          reinterpret_cast<const DevQueryDesc*>(w + cl.q),
                          reinterpret_cast<const uint32_t*>(w + cl.coff),
                          reinterpret_cast<const int32_t*>(w + cl.lits),
+                         reinterpret_cast<const uint32_t*>(w + cl.occ_off),
+                         reinterpret_cast<const uint32_t*>(w + cl.occ),
                          reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
                          reinterpret_cast<const int32_t*>(w + rl.lits), uint32_t(nc),
                          reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),

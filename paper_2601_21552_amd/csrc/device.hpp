@@ -10,6 +10,9 @@ namespace scuba {
 struct DevQueryDesc {
   uint64_t coff_base;   // index into the clause-offset array (u32, relative)
   uint64_t lit_base;    // index into the literal array
+  uint64_t occ_off_base;  // index into the occurrence offsets (u32, relative;
+                          // literal index 2*v + (negative))
+  uint64_t occ_base;    // index into the occurrence lists (clause numbers)
   uint32_t n_clauses;
   uint32_t n_vars;
   uint32_t staged;      // 1: the propagation kernel copies the CNF to LDS
@@ -78,6 +81,8 @@ struct CnfHost {
   std::vector<DevQueryDesc> q;
   std::vector<uint32_t> coff;
   std::vector<int32_t> lits;
+  std::vector<uint32_t> occ_off;   // per query: 2*(n_vars+1)+1 offsets
+  std::vector<uint32_t> occ;       // per query: the clauses of each literal
   size_t stage_bytes = 0;     // LDS for the largest staged CNF (16-bit form)
 };
 
@@ -87,6 +92,11 @@ void dev_copy_d2h(void* dst, const void* src, size_t bytes, void* stream);
 void dev_sync(void* stream);
 void* dev_pinned(size_t bytes);          // pinned host memory (or throws)
 void dev_pinned_free(void* p);
+
+// Frontier queue of the propagation kernel (entries per buffer; two buffers
+// in LDS).  A round whose new assignments overflow it is followed by a full
+// clause scan.
+constexpr uint32_t kUpQueue = 1024;
 
 // Workspace layout.  The CNF region persists across rounds of one call.
 size_t dev_cnf_bytes(const CnfHost& cnf);
