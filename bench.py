@@ -80,7 +80,12 @@ def decide_stats(ctx, cnf, n, labels=None, **opts):
     t0 = time.perf_counter()
     res = ctx.decide(cnf, **opts)
     ms = 1000.0 * (time.perf_counter() - t0)
-    out = {"ms": round(ms, 2), "SAT": 0, "UNSAT": 0, "UNKNOWN": 0, "leaves": 0, "cubes": 0}
+    tm = res.timing()
+    out = {"ms": round(ms, 2), "SAT": 0, "UNSAT": 0, "UNKNOWN": 0, "leaves": 0, "cubes": 0,
+           "split_ms": round(tm["split"], 2), "kernels_ms": round(tm["kernels"], 2)}
+    if tm["score_passes"]:
+        out.update(score_passes=int(tm["score_passes"]), score_rows=int(tm["score_rows"]),
+                   score_device_ms=round(tm["score_device"], 2))
     verdicts = []
     for i in range(n):
         r = res.result(i)
@@ -183,9 +188,13 @@ def main():
     stream = torch.cuda.current_stream()
     opts = dict(k=args.k, leaves_per_round=args.leaves_per_round, chunk_log2=args.chunk_log2)
 
+    bb_ms = []
+
     def run_steps(extra):
         def step():
+            t0 = time.perf_counter()
             cnf = ctx.bitblast(arrays)
+            bb_ms.append(1000.0 * (time.perf_counter() - t0))
             res = ctx.decide(cnf, stream=stream, **opts, **extra)
             return cnf, res
 
@@ -207,6 +216,7 @@ def main():
         return 1000.0 * elapsed / args.steps, out
 
     ms_per_step, results = run_steps({})
+    bitblast_ms = sorted(bb_ms[args.warmup:])[len(bb_ms[args.warmup:]) // 2]
 
     # agreement and accounting over the timed steps
     from oracle import query_ref
@@ -327,6 +337,7 @@ def main():
         "gain": gain,
         "detail": {"decided_at_root": n_root, "decided_on_device": n_dev,
                    "unknown": n_unknown, "oracle_agreement": agree,
+                   "bitblast_ms_per_step": round(bitblast_ms, 3),
                    "host_split_ms_per_step": round(split_ms / steps, 3),
                    "verify_ms_per_step": round(verify_ms / steps, 3),
                    "leaf_kernel_ms_per_step": round(leaf_ms / steps, 3),

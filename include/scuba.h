@@ -399,7 +399,10 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube,
  * [6] propagation kernel, [7] leaf kernel; then launch counts: [8]
  * propagation kernel, [9] leaf kernel; with SCUBA_SOLVE_GRAPH: [10] graph
  * replays in ms (copies included; [1], [3], [6], [7] stay 0), [11] graph
- * replays, [12] graph captures.  n <= 13.                                   */
+ * replays, [12] graph captures; with the learned scorer (scuba_decide):
+ * [13] ms in the scoring passes' copies, kernel and wait, [14] passes,
+ * [15] candidate rows scored; [16] cubes and [17] leaf work items sent to
+ * the kernels.  n <= 18.                                                    */
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n);
 void scuba_results_free(scuba_results* r);
 

@@ -74,7 +74,7 @@ struct scuba_results {
     std::vector<scuba_leaf_result> leaves;
   };
   std::vector<Q> q;
-  double ms[13] = {};
+  double ms[18] = {};
 };
 
 namespace {
@@ -152,40 +152,31 @@ Opts resolve(const scuba_solve_opts* o) {
 // marked for staging; lds_limit = 0 disables staging.
 CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
   CnfHost h;
+  h.src = cnf;
   uint32_t nw_all = 0;
   for (const CnfQuery& q : cnf->q) nw_all = std::max(nw_all, (q.n_vars >> 5) + 1);
   const size_t bitmaps = size_t(nw_all) * 16 + 2048 + 2 * kUpQueue * 4;   // + static LDS, queues
   const size_t budget = lds_limit > bitmaps ? lds_limit - bitmaps : 0;
   for (const CnfQuery& q : cnf->q) {
     DevQueryDesc d{};
-    d.coff_base = h.coff.size();
-    d.lit_base = h.lits.size();
+    d.coff_base = h.n_coff;
+    d.lit_base = h.n_lits;
+    d.occ_off_base = h.n_occ_off;
+    d.occ_base = h.n_occ;
     if (q.n_clauses() >= (uint64_t(1) << 32) || q.lits.size() >= (uint64_t(1) << 32))
       fail(SCUBA_E_CAPACITY, "query with 2^32 or more clauses or literals");
     d.n_clauses = uint32_t(q.n_clauses());
     d.n_vars = q.n_vars;
+    // staged in 16-bit form: clause offsets and literals
     const size_t bytes = ((q.n_clauses() + 1 + q.lits.size()) * 2 + 3) & ~size_t(3);
     if (q.n_vars < 32768 && q.lits.size() < 65536 && bytes <= budget) {
       d.staged = 1;
       h.stage_bytes = std::max(h.stage_bytes, bytes);
     }
-    for (uint64_t o : q.off) h.coff.push_back(uint32_t(o));
-    h.lits.insert(h.lits.end(), q.lits.begin(), q.lits.end());
-    // occurrence lists: literal index 2*v + (l < 0) -> clauses, in clause order
-    d.occ_off_base = h.occ_off.size();
-    d.occ_base = h.occ.size();
-    const size_t nli = 2 * (size_t(q.n_vars) + 1);
-    std::vector<uint32_t> cnt(nli + 1, 0);
-    for (int32_t l : q.lits) cnt[2 * size_t(l > 0 ? l : -l) + (l < 0) + 1]++;
-    for (size_t i = 0; i < nli; i++) cnt[i + 1] += cnt[i];
-    h.occ_off.insert(h.occ_off.end(), cnt.begin(), cnt.end());
-    const size_t ob = h.occ.size();
-    h.occ.resize(ob + q.lits.size());
-    for (uint64_t c = 0; c < q.n_clauses(); c++)
-      for (uint64_t i = q.off[c]; i < q.off[c + 1]; i++) {
-        const int32_t l = q.lits[i];
-        h.occ[ob + cnt[2 * size_t(l > 0 ? l : -l) + (l < 0)]++] = uint32_t(c);
-      }
+    h.n_coff += q.off.size();
+    h.n_lits += q.lits.size();
+    h.n_occ_off += 2 * (size_t(q.n_vars) + 1) + 1;
+    h.n_occ += q.lits.size();
     h.q.push_back(d);
   }
   return h;
@@ -349,6 +340,7 @@ struct ScorerRunner {
   size_t rows_cap;
   void* stream;
   uint64_t rows_scored = 0, passes = 0;
+  double device_ms = 0;   // staging, copies, kernel and wait of the passes
 
   void score(const std::vector<Splitter*>& waiting) {
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -372,10 +364,12 @@ struct ScorerRunner {
       uint16_t* a1 = reinterpret_cast<uint16_t*>(ws + al(rows_cap * kMlpF * 2));
       uint16_t* a2 = reinterpret_cast<uint16_t*>(ws + al(rows_cap * kMlpF * 2) + al(rows_cap * kMlpH * 2));
       float* y = reinterpret_cast<float*>(ws + al(rows_cap * kMlpF * 2) + 2 * al(rows_cap * kMlpH * 2));
+      auto td = Clock::now();
       dev_copy_h2d(x, xh, rows * kMlpF * 2, stream);
       mlp_forward(s->wbf16, s->master, x, uint32_t(rows), a1, a2, y, stream);
       dev_copy_d2h(stg, y, rows * 4, stream);
       dev_sync(stream);
+      device_ms += ms_since(td);
       const float* yh = static_cast<const float*>(stg);
       size_t off = 0;
       for (size_t q = i; q < j; q++) {
@@ -842,6 +836,8 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     res->ms[10] = rt.graph_ms;
     res->ms[11] = rt.graph_launches;
     res->ms[12] = rt.graph_captures;
+    res->ms[16] = double(rt.cubes);
+    res->ms[17] = double(rt.items);
     *out = res.release();
   });
 }
@@ -999,7 +995,14 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     res->ms[9] = rt.leaf_launches;
     res->ms[10] = rt.graph_ms;
     res->ms[11] = rt.graph_launches;
+    if (runner) {
+      res->ms[13] = runner->device_ms;
+      res->ms[14] = double(runner->passes);
+      res->ms[15] = double(runner->rows_scored);
+    }
     res->ms[12] = rt.graph_captures;
+    res->ms[16] = double(rt.cubes);
+    res->ms[17] = double(rt.items);
     return res;
   }
 }
@@ -1236,7 +1239,7 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube, 
 }
 
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n) {
-  if (!r || !ms || n > 13) return SCUBA_E_INVALID;
+  if (!r || !ms || n > 18) return SCUBA_E_INVALID;
   std::copy(r->ms, r->ms + n, ms);
   return SCUBA_OK;
 }

@@ -32,6 +32,7 @@
 
 #include "common.hpp"
 #include "device.hpp"
+#include "parallel.hpp"
 
 namespace scuba {
 
@@ -129,11 +130,23 @@ struct UpShared {
   uint32_t qn[2], ovf[2], chg[2];
 };
 
-// One clause against the current assignment: a conflict is flagged, a unit
-// literal is set and, when it is new, queued for the next round.
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Per-literal occurrence lists (literal index 2*v + negative -> clauses).
+struct GlobalOcc {
+  const uint32_t* off;
+  const uint32_t* occ;
+  __device__ __forceinline__ uint32_t beg(uint32_t li) const { return off[li]; }
+  __device__ __forceinline__ uint32_t end(uint32_t li) const { return off[li + 1]; }
+  __device__ __forceinline__ uint32_t at(uint32_t k) const { return occ[k]; }
+};
+
+// One clause against the current assignment: a conflict is flagged; a unit
+// literal is set, and when it is new its entry (variable << 1 | value) is
+// returned (kNone otherwise).
 template <class Cnf>
-__device__ __forceinline__ void visit_clause(const Cnf& cnf, uint32_t c, uint32_t* T, uint32_t* F,
-                                             uint32_t* next, uint32_t w, UpShared& sh) {
+__device__ __forceinline__ uint32_t visit_clause(const Cnf& cnf, uint32_t c, uint32_t* T, uint32_t* F,
+                                                 uint32_t w, UpShared& sh) {
   bool sat = false;
   uint32_t open = 0, last_v = 0;
   bool last_neg = false;
@@ -146,7 +159,7 @@ __device__ __forceinline__ void visit_clause(const Cnf& cnf, uint32_t c, uint32_
     if (neg ? f : t) { sat = true; break; }
     if (!(t | f)) { open++; last_v = v; last_neg = neg; }
   }
-  if (sat) return;
+  if (sat) return kNone;
   if (open == 0) {
     sh.conflict = 1;
   } else if (open == 1) {
@@ -154,18 +167,40 @@ __device__ __forceinline__ void visit_clause(const Cnf& cnf, uint32_t c, uint32_
     const uint32_t old = atomicOr(last_neg ? &F[last_v >> 5] : &T[last_v >> 5], bit);
     if (!(old & bit)) {
       sh.chg[w] = 1;
-      const uint32_t slot = atomicAdd(&sh.qn[w], 1u);
-      if (slot < kUpQueue) next[slot] = (last_v << 1) | (last_neg ? 0u : 1u);   // value in bit 0
-      else sh.ovf[w] = 1;
+      return (last_v << 1) | (last_neg ? 0u : 1u);
     }
   }
+  return kNone;
+}
+
+// Queue a new assignment for the next round (an overflow makes that round
+// scan every clause).
+__device__ __forceinline__ void push(uint32_t e, uint32_t* next, uint32_t w, UpShared& sh) {
+  if (e == kNone) return;
+  const uint32_t slot = atomicAdd(&sh.qn[w], 1u);
+  if (slot < kUpQueue) next[slot] = e;
+  else sh.ovf[w] = 1;
+}
+
+// The clauses in which the new assignment e (variable << 1 | value) made a
+// literal false are visited; the assignments this produces are queued for
+// the next round.
+template <class Cnf, class Occ>
+__device__ __forceinline__ void expand(const Cnf& cnf, const Occ& occ, uint32_t e, uint32_t* T, uint32_t* F,
+                                       uint32_t* next, uint32_t w, UpShared& sh) {
+  const uint32_t v = e >> 1, val = e & 1;
+  const uint32_t bit = 1u << (v & 31);
+  if (T[v >> 5] & F[v >> 5] & bit) { sh.conflict = 1; return; }
+  // the literal of v that is now false is the negative one iff v = 1
+  const uint32_t li = 2 * v + val;
+  for (uint32_t k = occ.beg(li), ke = occ.end(li); k < ke; k++)
+    push(visit_clause(cnf, occ.at(k), T, F, w, sh), next, w, sh);
 }
 
 // Unit propagation of one cube, then its active variables, slots and
 // residual records.  Called by the whole workgroup (uniform control flow).
-template <class Cnf>
-__device__ void propagate_cube(const Cnf& cnf, const uint32_t* __restrict__ occ_off,
-                               const uint32_t* __restrict__ occ, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
+template <class Cnf, class Occ>
+__device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
                                uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
                                uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
                                uint32_t* Q, UpShared& sh) {
@@ -187,8 +222,8 @@ __device__ void propagate_cube(const Cnf& cnf, const uint32_t* __restrict__ occ_
   // (the frontier), unless that frontier overflowed its queue, in which
   // case the round scans every clause again.  A round that sets nothing
   // new ends at the fixpoint: every clause has been visited after its last
-  // false literal was assigned.  Each variable enters a queue at most once
-  // per value, so at most 2*(nv+1) rounds change something.
+  // false literal was assigned.  Every changing round sets a new bit, so at
+  // most 2*(nv+1) rounds change something.
   const uint32_t max_rounds = 2 * nv + 4;
   for (uint32_t r = 0;; r++) {
     const uint32_t w = r & 1, pw = w ^ 1;
@@ -196,20 +231,11 @@ __device__ void propagate_cube(const Cnf& cnf, const uint32_t* __restrict__ occ_
     __syncthreads();
     uint32_t* next = Q + w * kUpQueue;
     if (r == 0 || sh.ovf[pw]) {
-      for (uint32_t c = tid; c < nc; c += kBlock) visit_clause(cnf, c, T, F, next, w, sh);
+      for (uint32_t c = tid; c < nc; c += kBlock) push(visit_clause(cnf, c, T, F, w, sh), next, w, sh);
     } else {
       const uint32_t* cur = Q + pw * kUpQueue;
       const uint32_t n = min(sh.qn[pw], kUpQueue);
-      for (uint32_t j = tid; j < n; j += kBlock) {
-        const uint32_t e = cur[j];
-        const uint32_t v = e >> 1, val = e & 1;
-        const uint32_t bit = 1u << (v & 31);
-        if (T[v >> 5] & F[v >> 5] & bit) { sh.conflict = 1; continue; }
-        // the literal of v that is now false has sign "negative" iff v = 1
-        const uint32_t li = 2 * v + val;
-        for (uint32_t k = occ_off[li], ke = occ_off[li + 1]; k < ke; k++)
-          visit_clause(cnf, occ[k], T, F, next, w, sh);
-      }
+      for (uint32_t j = tid; j < n; j += kBlock) expand(cnf, occ, cur[j], T, F, next, w, sh);
     }
     __syncthreads();
     const uint32_t changed = sh.chg[w], conflict = sh.conflict;
@@ -340,20 +366,21 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
     const uint32_t* oo = occ_offs + q.occ_off_base;
     const uint32_t* oc = occs + q.occ_base;
     if (q.staged) {
+      // 16-bit copies: clause offsets and literals (v << 1 | negative)
       const uint32_t nl = co[q.n_clauses];
       uint16_t* sco = stage;
-      uint16_t* sl = stage + q.n_clauses + 1;
+      uint16_t* sl = sco + q.n_clauses + 1;
       for (uint32_t c = tid; c <= q.n_clauses; c += kBlock) sco[c] = uint16_t(co[c]);
       for (uint32_t i = tid; i < nl; i += kBlock) {
         const int32_t l = L[i];
         sl[i] = uint16_t((uint32_t(l > 0 ? l : -l) << 1) | (l < 0 ? 1u : 0u));
       }
       __syncthreads();
-      propagate_cube(LdsCnf{sco, sl}, oo, oc, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P,
-                     Q, sh);
+      propagate_cube(LdsCnf{sco, sl}, GlobalOcc{oo, oc}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T,
+                     F, A, P, Q, sh);
     } else {
-      propagate_cube(GlobalCnf{co, L}, oo, oc, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T, F, A, P,
-                     Q, sh);
+      propagate_cube(GlobalCnf{co, L}, GlobalOcc{oo, oc}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res,
+                     T, F, A, P, Q, sh);
     }
   }
 }
@@ -366,95 +393,106 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
                                                      unsigned long long* __restrict__ qkey,
                                                      uint32_t* head, uint32_t mode) {
   extern __shared__ uint4 tile[];
-  __shared__ uint32_t s_item, s_skip;
+  __shared__ uint32_t s_base, s_skip;
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr uint32_t kWaves = kBlock / 64;
+  constexpr uint32_t kClaim = 8;   // items taken per claim
 
   for (;;) {
-    // thread 0 takes the next item and decides for the whole workgroup
-    // whether it is still useful (device-refuted leaf, or a witness of the
-    // query that precedes every assignment of the item)
-    if (tid == 0) {
-      const uint32_t i = atomicAdd(head + 1, 1u);
-      uint32_t skip = 0;
-      if (i < n_items) {
+    // the first wave claims kClaim consecutive items and decides, one lane
+    // per item, which are still useful (not a device-refuted leaf, and in
+    // DECIDE mode not preceded by a witness already found for the query)
+    if (wave == 0) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(head + 1, kClaim);
+      base = uniform_u32(__shfl(base, 0, 64));
+      bool skip = true;
+      const uint32_t i = base + lane;
+      if (lane < kClaim && i < n_items) {
         const DevItem it0 = items[i];
-        if (out[it0.cube].status != 0) skip = 1;
-        else if (mode == SCUBA_MODE_DECIDE) {
+        skip = out[it0.cube].status != 0;
+        if (!skip && mode == SCUBA_MODE_DECIDE) {
           const DevCubeDesc c0 = cubes[it0.cube];
           const uint64_t k = __hip_atomic_load(&qkey[c0.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (k <= (uint64_t(c0.seq) << 38) + (uint64_t(it0.it_lo) << 12)) skip = 1;
+          skip = k <= (uint64_t(c0.seq) << 38) + (uint64_t(it0.it_lo) << 12);
         }
       }
-      s_item = i;
-      s_skip = skip;
+      const uint64_t mask = __ballot(skip);
+      if (lane == 0) {
+        s_base = base;
+        s_skip = uint32_t(mask);
+      }
     }
     __syncthreads();
-    const uint32_t item = s_item, skip_item = s_skip;
+    const uint32_t base = s_base, skip_mask = s_skip;
     __syncthreads();
-    if (item >= n_items) break;
-    if (skip_item) continue;
+    if (base >= n_items) break;
+    for (uint32_t t = 0; t < kClaim; t++) {
+      const uint32_t item = base + t;
+      if (item >= n_items) break;
+      if ((skip_mask >> t) & 1) continue;
 
-    const DevItem it = items[item];
-    const DevCubeDesc cd = cubes[it.cube];
-    const uint32_t f = uint32_t(out[it.cube].f);
-    const uint32_t nres = uint32_t(out[it.cube].nres);
-    const uint64_t key_base = uint64_t(cd.seq) << 38;
+      const DevItem it = items[item];
+      const DevCubeDesc cd = cubes[it.cube];
+      const uint32_t f = uint32_t(out[it.cube].f);
+      const uint32_t nres = uint32_t(out[it.cube].nres);
+      const uint64_t key_base = uint64_t(cd.seq) << 38;
 
-    for (uint32_t j = tid; j < nres; j += kBlock) tile[j] = res[cd.res_base + j];
-    __syncthreads();
+      for (uint32_t j = tid; j < nres; j += kBlock) tile[j] = res[cd.res_base + j];
+      __syncthreads();
 
-    uint64_t valid;
-    if (f >= 12) valid = ~0ull;
-    else if (f >= 6) valid = lane < (1u << (f - 6)) ? ~0ull : 0ull;
-    else valid = lane == 0 ? ((2ull << ((1u << f) - 1)) - 1) : 0ull;
+      uint64_t valid;
+      if (f >= 12) valid = ~0ull;
+      else if (f >= 6) valid = lane < (1u << (f - 6)) ? ~0ull : 0ull;
+      else valid = lane == 0 ? ((2ull << ((1u << f) - 1)) - 1) : 0ull;
 
-    uint64_t count = 0, blocks = 0, evals = 0, first = ~0ull;
-    uint32_t steps = 0;
-    for (uint32_t blk = it.it_lo + wave; blk < it.it_hi; blk += kWaves) {
-      if (mode == SCUBA_MODE_DECIDE && (steps++ & 7) == 0) {
-        const uint64_t k = uniform_u64(
-            __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        if (k <= key_base + (uint64_t(blk) << 12)) break;
-      }
-      const uint32_t H = blk;
-      uint64_t acc = valid;
-      uint32_t done = 0;
-      for (uint32_t c = 0; c < nres; c++) {
-        const uint4 r = tile[c];
-        const uint32_t z = uniform_u32(r.z);
-        const uint32_t w = uniform_u32(r.w);
-        if (((H & z) | (~H & w)) & kHighMask) continue;
-        const uint32_t mn = w >> 26, mm = (z >> 26) | mn;
-        const uint64_t low = (uint64_t(uniform_u32(r.y)) << 32) | uniform_u32(r.x);
-        acc &= ((lane ^ mn) & mm) ? ~0ull : low;
-        done++;
-        if ((done & 3) == 0 && !__any(acc != 0)) break;
-      }
-      blocks++;
-      evals += done;
-      if (mode == SCUBA_MODE_COUNT) count += __popcll(acc);
-      const uint64_t hit = __ballot(acc != 0);
-      if (hit) {
-        const uint32_t fl = __builtin_ctzll(hit);
-        const uint64_t acc_fl = __shfl(acc, int(fl), 64);
-        const uint64_t a = (uint64_t(blk) << 12) | (uint64_t(fl) << 6) | uint64_t(__builtin_ctzll(acc_fl));
-        if (lane == 0) {
-          if (a < first) first = a;
-          if (mode == SCUBA_MODE_DECIDE) atomicMin(&qkey[cd.qid], (unsigned long long)(key_base | a));
+      uint64_t count = 0, blocks = 0, evals = 0, first = ~0ull;
+      uint32_t steps = 0;
+      for (uint32_t blk = it.it_lo + wave; blk < it.it_hi; blk += kWaves) {
+        if (mode == SCUBA_MODE_DECIDE && (steps++ & 7) == 0) {
+          const uint64_t k = uniform_u64(
+              __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (k <= key_base + (uint64_t(blk) << 12)) break;
         }
-        if (mode == SCUBA_MODE_DECIDE) break;
+        const uint32_t H = blk;
+        uint64_t acc = valid;
+        uint32_t done = 0;
+        for (uint32_t c = 0; c < nres; c++) {
+          const uint4 r = tile[c];
+          const uint32_t z = uniform_u32(r.z);
+          const uint32_t w = uniform_u32(r.w);
+          if (((H & z) | (~H & w)) & kHighMask) continue;
+          const uint32_t mn = w >> 26, mm = (z >> 26) | mn;
+          const uint64_t low = (uint64_t(uniform_u32(r.y)) << 32) | uniform_u32(r.x);
+          acc &= ((lane ^ mn) & mm) ? ~0ull : low;
+          done++;
+          if ((done & 3) == 0 && !__any(acc != 0)) break;
+        }
+        blocks++;
+        evals += done;
+        if (mode == SCUBA_MODE_COUNT) count += __popcll(acc);
+        const uint64_t hit = __ballot(acc != 0);
+        if (hit) {
+          const uint32_t fl = __builtin_ctzll(hit);
+          const uint64_t acc_fl = __shfl(acc, int(fl), 64);
+          const uint64_t a = (uint64_t(blk) << 12) | (uint64_t(fl) << 6) | uint64_t(__builtin_ctzll(acc_fl));
+          if (lane == 0) {
+            if (a < first) first = a;
+            if (mode == SCUBA_MODE_DECIDE) atomicMin(&qkey[cd.qid], (unsigned long long)(key_base | a));
+          }
+          if (mode == SCUBA_MODE_DECIDE) break;
+        }
       }
+      // wave totals
+      for (uint32_t d = 32; d >= 1; d >>= 1) count += __shfl_xor(count, int(d), 64);
+      if (lane == 0) {
+        if (mode == SCUBA_MODE_COUNT && count) atomicAdd((unsigned long long*)&out[it.cube].count, (unsigned long long)count);
+        if (first != ~0ull) atomicMin((unsigned long long*)&out[it.cube].first, (unsigned long long)first);
+        atomicAdd((unsigned long long*)&out[it.cube].blocks, (unsigned long long)blocks);
+        atomicAdd((unsigned long long*)&out[it.cube].clause_blocks, (unsigned long long)evals);
+      }
+      __syncthreads();
     }
-    // wave totals
-    for (uint32_t d = 32; d >= 1; d >>= 1) count += __shfl_xor(count, int(d), 64);
-    if (lane == 0) {
-      if (mode == SCUBA_MODE_COUNT && count) atomicAdd((unsigned long long*)&out[it.cube].count, (unsigned long long)count);
-      if (first != ~0ull) atomicMin((unsigned long long*)&out[it.cube].first, (unsigned long long)first);
-      atomicAdd((unsigned long long*)&out[it.cube].blocks, (unsigned long long)blocks);
-      atomicAdd((unsigned long long*)&out[it.cube].clause_blocks, (unsigned long long)evals);
-    }
-    __syncthreads();
   }
 }
 
@@ -467,10 +505,10 @@ CnfLayout cnf_layout(const CnfHost& c) {
   CnfLayout l;
   l.q = 0;
   l.coff = align256(l.q + c.q.size() * sizeof(DevQueryDesc));
-  l.lits = align256(l.coff + c.coff.size() * 4);
-  l.occ_off = align256(l.lits + c.lits.size() * 4);
-  l.occ = align256(l.occ_off + c.occ_off.size() * 4);
-  l.qkey = align256(l.occ + c.occ.size() * 4);
+  l.lits = align256(l.coff + c.n_coff * 4);
+  l.occ_off = align256(l.lits + c.n_lits * 4);
+  l.occ = align256(l.occ_off + c.n_occ_off * 4);
+  l.qkey = align256(l.occ + c.n_occ * 4);
   l.end = align256(l.qkey + c.q.size() * 8);
   return l;
 }
@@ -533,10 +571,31 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
   if (l.end > staging_bytes) fail(SCUBA_E_INTERNAL, "staging too small");
   char* s = static_cast<char*>(staging);
   std::memcpy(s + l.q, cnf.q.data(), cnf.q.size() * sizeof(DevQueryDesc));
-  std::memcpy(s + l.coff, cnf.coff.data(), cnf.coff.size() * 4);
-  std::memcpy(s + l.lits, cnf.lits.data(), cnf.lits.size() * 4);
-  std::memcpy(s + l.occ_off, cnf.occ_off.data(), cnf.occ_off.size() * 4);
-  std::memcpy(s + l.occ, cnf.occ.data(), cnf.occ.size() * 4);
+  uint32_t* coff = reinterpret_cast<uint32_t*>(s + l.coff);
+  int32_t* lits = reinterpret_cast<int32_t*>(s + l.lits);
+  uint32_t* occ_off = reinterpret_cast<uint32_t*>(s + l.occ_off);
+  uint32_t* occ = reinterpret_cast<uint32_t*>(s + l.occ);
+  // each query's arrays, written in place: clause offsets (query-relative),
+  // literals, and its occurrence lists (literal index 2*v + (l < 0), clauses
+  // in increasing order) by a counting sort
+  parallel_for(cnf.q.size(), [&](size_t qi) {
+    const CnfQuery& q = cnf.src->q[qi];
+    const DevQueryDesc& d = cnf.q[qi];
+    for (size_t c = 0; c < q.off.size(); c++) coff[d.coff_base + c] = uint32_t(q.off[c]);
+    std::memcpy(lits + d.lit_base, q.lits.data(), q.lits.size() * 4);
+    uint32_t* oo = occ_off + d.occ_off_base;
+    const size_t nli = 2 * (size_t(q.n_vars) + 1);
+    std::memset(oo, 0, (nli + 1) * 4);
+    for (int32_t x : q.lits) oo[2 * size_t(x > 0 ? x : -x) + (x < 0) + 1]++;
+    for (size_t i = 0; i < nli; i++) oo[i + 1] += oo[i];
+    std::vector<uint32_t> fill(oo, oo + nli);
+    uint32_t* oc = occ + d.occ_base;
+    for (uint64_t c = 0; c < q.n_clauses(); c++)
+      for (uint64_t i = q.off[c]; i < q.off[c + 1]; i++) {
+        const int32_t x = q.lits[i];
+        oc[fill[2 * size_t(x > 0 ? x : -x) + (x < 0)]++] = uint32_t(c);
+      }
+  });
   std::memset(s + l.qkey, 0xFF, cnf.q.size() * 8);
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_OK(hipMemcpyAsync(ws, s, l.end, hipMemcpyHostToDevice, st));
@@ -644,6 +703,8 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
     if (ev) HIP_OK(hipEventRecord(ev[4], q));
   };
 
+  times->cubes += nc;
+  times->items += ni;
   hipEvent_t ev[5];
   for (auto& e : ev) HIP_OK(hipEventCreate(&e));
   if (!graphs) {

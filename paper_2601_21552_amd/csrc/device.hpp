@@ -4,6 +4,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "common.hpp"
+
 namespace scuba {
 
 // One query's CNF on the device.
@@ -50,6 +52,7 @@ struct RoundTimes {
   uint32_t up_launches = 0, leaf_launches = 0;
   double graph_ms = 0;            // replays of captured rounds (copies included)
   uint32_t graph_launches = 0, graph_captures = 0;
+  uint64_t cubes = 0, items = 0;  // sent to the kernels
 };
 
 // Captured rounds (HIP graphs) of one context, keyed by everything a
@@ -77,12 +80,15 @@ struct RoundHost {
   uint32_t nw_max = 0;        // largest bitmap (32-bit words) of a query
 };
 
+// Device image of a CNF batch: descriptors and array sizes.  The arrays
+// (query-relative clause offsets, literals, per-literal occurrence offsets
+// and lists) are written straight into the staging buffer at upload.
 struct CnfHost {
+  const scuba_cnf* src = nullptr;
   std::vector<DevQueryDesc> q;
-  std::vector<uint32_t> coff;
-  std::vector<int32_t> lits;
-  std::vector<uint32_t> occ_off;   // per query: 2*(n_vars+1)+1 offsets
-  std::vector<uint32_t> occ;       // per query: the clauses of each literal
+  size_t n_coff = 0, n_lits = 0;
+  size_t n_occ_off = 0;       // per query: 2*(n_vars+1)+1 offsets
+  size_t n_occ = 0;           // per query: the clauses of each literal
   size_t stage_bytes = 0;     // LDS for the largest staged CNF (16-bit form)
 };
 

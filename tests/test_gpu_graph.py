@@ -21,12 +21,16 @@ def ctx():
 
 
 def _summary(res, n, nvars):
+    """What DECIDE fixes: verdicts, witnesses (the smallest key), cubes and
+    leaves per query and rounds.  Blocks evaluated are left out: in DECIDE
+    mode other waves stop when they see the witness key, so the count
+    depends on scheduling."""
     out = []
     for i in range(n):
         r = res.result(i)
         wit = res.witness(i, nvars[i]) if r["verdict"] == "SAT" else None
         out.append((r["verdict"], r["cubes_total"], r["leaves_sent"], r["leaves_refuted"],
-                    r["blocks_evaluated"], r["rounds"], tuple(wit) if wit else None))
+                    r["rounds"], tuple(wit) if wit else None))
     return out
 
 
