@@ -41,6 +41,11 @@ MEASURED_TRAFFIC = {
     "leaf_kernel": 11_219_046,
 }
 
+# learned ordering: candidates scored per decision node, and the levels
+# below a scored node that reuse its ranking (fewer device scoring passes)
+LEARNED_CANDIDATES = 16
+LEARNED_RESCORE = 4
+
 WORKLOADS = {
     2: ("config2: 256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, "
         "c in 0..16, 128 guarded (UNSAT) / 64 unguarded + 64 off-by-one (SAT); "
@@ -140,13 +145,13 @@ def gain_legs(ctx, mlp_q, log):
                   ctx.cnf_from_arrays(*w.concat(tr[150][:16]))]
     mlp_s, info = train_scorer(ctx, tr_batches, k=16, epochs=6, seed=4, candidates=16, depth=40)
     log(f"3-SAT scorer trained: {info}")
-    ev = w.config4(per_n=32, ns=(100, 150))
-    for n, count in ((100, 32), (150, 16)):
+    ev = w.config4(per_n=128, ns=(100, 150))
+    for n, count in ((100, 128), (150, 32)):
         cnfs = ev[n][:count]
         raw = ctx.cnf_from_arrays(*w.concat(cnfs))
         st, vs = decide_stats(ctx, raw, count, k=16, max_cubes=400000)
         le, vl = decide_stats(ctx, raw, count, k=16, max_cubes=400000,
-                              learned=mlp_s.scorer(16, 1))
+                              learned=mlp_s.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE))
         assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vs, vl))
         leg = {"instances": count, "static": st, "learned": le,
                "leaf_ratio": round(le["leaves"] / max(st["leaves"], 1), 3),
@@ -164,7 +169,7 @@ def gain_legs(ctx, mlp_q, log):
     labels = [g.label for g in gens]
     st, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000)
     le, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000,
-                         learned=mlp_q.scorer(32, 1))
+                         learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE))
     wo, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000, scorer="word")
     out["partition_1024"] = {"static": st, "learned": le, "word": wo}
     log(f"partition queries: {out['partition_1024']}")
@@ -323,7 +328,7 @@ def main():
         log(f"access-query scorer trained: {scorer_info}")
     if not args.no_forms:
         for name, extra in (("word", dict(scorer="word")),
-                            ("learned", dict(learned=mlp_q.scorer(32, 1)))):
+                            ("learned", dict(learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE)))):
             ms, _ = run_steps(extra)
             forms[name] = round(len(gens) / (ms / 1000.0), 3)
         log(f"forms (queries/s): {forms}")

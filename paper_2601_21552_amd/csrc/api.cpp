@@ -155,7 +155,8 @@ CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
   h.src = cnf;
   uint32_t nw_all = 0;
   for (const CnfQuery& q : cnf->q) nw_all = std::max(nw_all, (q.n_vars >> 5) + 1);
-  const size_t bitmaps = size_t(nw_all) * 16 + 2048 + 2 * kUpQueue * 4;   // + static LDS, queues
+  // per wave: four bitmaps, two frontier queues and 128 words of scan space
+  const size_t bitmaps = kUpWaves * (size_t(nw_all) * 16 + 2 * kUpQueue * 4 + 128 * 4);
   const size_t budget = lds_limit > bitmaps ? lds_limit - bitmaps : 0;
   for (const CnfQuery& q : cnf->q) {
     DevQueryDesc d{};
@@ -167,8 +168,11 @@ CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
       fail(SCUBA_E_CAPACITY, "query with 2^32 or more clauses or literals");
     d.n_clauses = uint32_t(q.n_clauses());
     d.n_vars = q.n_vars;
-    // staged in 16-bit form: clause offsets and literals
-    const size_t bytes = ((q.n_clauses() + 1 + q.lits.size()) * 2 + 3) & ~size_t(3);
+    // staged in 16-bit form: clause offsets, literals, occurrence offsets
+    // and occurrence lists
+    const size_t bytes =
+        ((q.n_clauses() + 1 + q.lits.size() + 2 * (size_t(q.n_vars) + 1) + 1 + q.lits.size()) * 2 + 3) &
+        ~size_t(3);
     if (q.n_vars < 32768 && q.lits.size() < 65536 && bytes <= budget) {
       d.staged = 1;
       h.stage_bytes = std::max(h.stage_bytes, bytes);
@@ -181,8 +185,9 @@ CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
   }
   return h;
 }
-// LDS the propagation kernel may use (64 KB: no launch attribute needed)
-size_t up_lds_limit(const scuba_ctx* ctx) { return std::min<size_t>(ctx->dev.max_lds, 65536); }
+// LDS the propagation kernel may use (the device's opt-in size when the
+// kernel attribute could be set)
+size_t up_lds_limit(const scuba_ctx* ctx) { return ctx->dev.up_lds_max; }
 
 uint64_t blocks_of(int32_t f) { return f >= 12 ? (uint64_t(1) << (f - 12)) : 1; }
 

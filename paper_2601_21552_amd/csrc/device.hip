@@ -67,26 +67,6 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
   return (uint64_t(uniform_u32(uint32_t(x >> 32))) << 32) | uniform_u32(uint32_t(x));
 }
 
-// exclusive scan of one value per thread over the workgroup
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave, uint32_t* total) {
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-  for (uint32_t d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) s_wave[wave] = x;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-  for (uint32_t w = 0; w < kBlock / 64; w++) {
-    if (w < wave) base += s_wave[w];
-    tot += s_wave[w];
-  }
-  __syncthreads();
-  *total = tot;
-  return base + x - v;
-}
-
 // Clause access for the propagation kernel: the query's CNF either read
 // from global memory (DIMACS literals, 32-bit offsets) or staged in LDS as
 // 16-bit literals (variable << 1 | negated) with 16-bit offsets.
@@ -124,18 +104,87 @@ __device__ __forceinline__ bool clause_satisfied(const Cnf& cnf, uint32_t c, con
   return false;
 }
 
+// Per-team state of the propagation kernel (one cube per team).
 struct UpShared {
-  uint32_t conflict, wave[kBlock / 64], error;
+  uint32_t conflict, error;
   // per round parity: frontier length, overflow, something newly set
   uint32_t qn[2], ovf[2], chg[2];
+  uint32_t scan[2][kBlock / 64];   // alternating, so one barrier per scan
 };
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+static_assert(kUpWaves == kBlock / 64, "a workgroup holds kUpWaves waves");
 
-// Per-literal occurrence lists (literal index 2*v + negative -> clauses).
+// Makes LDS writes of the wave visible to all its lanes, and keeps the
+// compiler from moving LDS accesses across it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// exclusive scan of one value per lane over the wave
+__device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t x = v;
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  *total = uniform_u32(__shfl(x, 63, 64));
+  return x - v;
+}
+
+// The threads that propagate one cube: one wave (TW = 1, four cubes per
+// workgroup) or the whole workgroup (TW = 4, for rounds with few cubes).
+template <int TW>
+struct Team {
+  static constexpr uint32_t kSize = 64 * TW;
+  static constexpr uint32_t kQueue = kUpQueue * TW;   // frontier entries per buffer
+  UpShared& sh;
+  uint32_t par = 0;   // scan buffer of the next scan (every thread keeps its own copy)
+  __device__ __forceinline__ uint32_t lane() const { return TW == 1 ? (threadIdx.x & 63) : threadIdx.x; }
+  __device__ __forceinline__ void sync() const {
+    if (TW == 1) wave_sync();
+    else __syncthreads();
+  }
+  // exclusive scan of one value per thread over the team
+  __device__ __forceinline__ uint32_t scan(uint32_t v, uint32_t* total) {
+    if (TW == 1) return wave_exclusive_scan(v, total);
+    const uint32_t l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t x = v;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(x, d, 64);
+      if (l >= d) x += y;
+    }
+    // consecutive scans alternate buffers: a thread writing scan i+1 has
+    // passed scan i's barrier, and every thread reads scan i-1's buffer
+    // before it reaches that barrier, so one barrier per scan suffices
+    if (l == 63) sh.scan[par][wv] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (uint32_t w = 0; w < uint32_t(TW); w++) {
+      if (w < wv) base += sh.scan[par][w];
+      tot += sh.scan[par][w];
+    }
+    par ^= 1;
+    *total = tot;
+    return base + x - v;
+  }
+};
+
+// Per-literal occurrence lists (literal index 2*v + negative -> clauses),
+// in HBM (32-bit) or staged in LDS (16-bit).
 struct GlobalOcc {
   const uint32_t* off;
   const uint32_t* occ;
+  __device__ __forceinline__ uint32_t beg(uint32_t li) const { return off[li]; }
+  __device__ __forceinline__ uint32_t end(uint32_t li) const { return off[li + 1]; }
+  __device__ __forceinline__ uint32_t at(uint32_t k) const { return occ[k]; }
+};
+struct LdsOcc {
+  const uint16_t* off;
+  const uint16_t* occ;
   __device__ __forceinline__ uint32_t beg(uint32_t li) const { return off[li]; }
   __device__ __forceinline__ uint32_t end(uint32_t li) const { return off[li + 1]; }
   __device__ __forceinline__ uint32_t at(uint32_t k) const { return occ[k]; }
@@ -175,47 +224,35 @@ __device__ __forceinline__ uint32_t visit_clause(const Cnf& cnf, uint32_t c, uin
 
 // Queue a new assignment for the next round (an overflow makes that round
 // scan every clause).
-__device__ __forceinline__ void push(uint32_t e, uint32_t* next, uint32_t w, UpShared& sh) {
+__device__ __forceinline__ void push(uint32_t e, uint32_t* next, uint32_t cap, uint32_t w, UpShared& sh) {
   if (e == kNone) return;
   const uint32_t slot = atomicAdd(&sh.qn[w], 1u);
-  if (slot < kUpQueue) next[slot] = e;
+  if (slot < cap) next[slot] = e;
   else sh.ovf[w] = 1;
 }
 
-// The clauses in which the new assignment e (variable << 1 | value) made a
-// literal false are visited; the assignments this produces are queued for
-// the next round.
-template <class Cnf, class Occ>
-__device__ __forceinline__ void expand(const Cnf& cnf, const Occ& occ, uint32_t e, uint32_t* T, uint32_t* F,
-                                       uint32_t* next, uint32_t w, UpShared& sh) {
-  const uint32_t v = e >> 1, val = e & 1;
-  const uint32_t bit = 1u << (v & 31);
-  if (T[v >> 5] & F[v >> 5] & bit) { sh.conflict = 1; return; }
-  // the literal of v that is now false is the negative one iff v = 1
-  const uint32_t li = 2 * v + val;
-  for (uint32_t k = occ.beg(li), ke = occ.end(li); k < ke; k++)
-    push(visit_clause(cnf, occ.at(k), T, F, w, sh), next, w, sh);
-}
-
-// Unit propagation of one cube, then its active variables, slots and
-// residual records.  Called by the whole workgroup (uniform control flow).
-template <class Cnf, class Occ>
+// Unit propagation of one cube by one team, then its active variables,
+// slots and residual records.  Every thread of the team calls it (uniform
+// control flow within the team).
+template <int TW, class Cnf, class Occ>
 __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
                                uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
                                uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
-                               uint32_t* Q, UpShared& sh) {
-  const uint32_t tid = threadIdx.x;
+                               uint32_t* Q, uint32_t* X, UpShared& sh) {
+  Team<TW> tm{sh};
+  constexpr uint32_t S = Team<TW>::kSize, QC = Team<TW>::kQueue;
+  const uint32_t lane = tm.lane();
   const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
-  for (uint32_t w = tid; w < nw; w += kBlock) { T[w] = 0; F[w] = 0; A[w] = 0; }
-  if (tid == 0) { sh.conflict = 0; sh.error = 0; sh.qn[1] = 0; sh.ovf[1] = 0; sh.chg[1] = 0; }
-  __syncthreads();
-  for (uint32_t j = tid; j < cd.n_lits; j += kBlock) {
+  for (uint32_t w = lane; w < nw; w += S) { T[w] = 0; F[w] = 0; A[w] = 0; }
+  if (lane == 0) { sh.conflict = 0; sh.error = 0; sh.qn[1] = 0; sh.ovf[1] = 0; sh.chg[1] = 0; }
+  tm.sync();
+  for (uint32_t j = lane; j < cd.n_lits; j += S) {
     int32_t l = cube_lits[cd.lit_off + j];
     uint32_t v = uint32_t(l > 0 ? l : -l);
     if (v == 0 || v > nv) { sh.error = 1; continue; }
     atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], 1u << (v & 31));
   }
-  __syncthreads();
+  tm.sync();
 
   // ---- propagation rounds.  Round 0 scans every clause; later rounds visit
   // only the clauses of the literals that the previous round made false
@@ -227,39 +264,76 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   const uint32_t max_rounds = 2 * nv + 4;
   for (uint32_t r = 0;; r++) {
     const uint32_t w = r & 1, pw = w ^ 1;
-    if (tid == 0) { sh.qn[w] = 0; sh.ovf[w] = 0; sh.chg[w] = 0; }
-    __syncthreads();
-    uint32_t* next = Q + w * kUpQueue;
+    if (lane == 0) { sh.qn[w] = 0; sh.ovf[w] = 0; sh.chg[w] = 0; }
+    tm.sync();
+    uint32_t* next = Q + w * QC;
     if (r == 0 || sh.ovf[pw]) {
-      for (uint32_t c = tid; c < nc; c += kBlock) push(visit_clause(cnf, c, T, F, w, sh), next, w, sh);
+      for (uint32_t c = lane; c < nc; c += S) push(visit_clause(cnf, c, T, F, w, sh), next, QC, w, sh);
     } else {
-      const uint32_t* cur = Q + pw * kUpQueue;
-      const uint32_t n = min(sh.qn[pw], kUpQueue);
-      for (uint32_t j = tid; j < n; j += kBlock) expand(cnf, occ, cur[j], T, F, next, w, sh);
+      // the (entry, occurrence) pairs of up to S frontier entries at a
+      // time are spread over the team: a scan of the occurrence counts
+      // gives each entry's first pair; a thread finds the entry of its pair
+      // by binary search over those offsets (X[0..S-1] in LDS) and the
+      // occurrence list start (X[S..2S-1])
+      const uint32_t* cur = Q + pw * QC;
+      const uint32_t n = min(uniform_u32(sh.qn[pw]), QC);
+      for (uint32_t base = 0; base < n; base += S) {
+        const uint32_t j = base + lane;
+        uint32_t cnt = 0, start = 0;
+        if (j < n) {
+          const uint32_t e = cur[j];
+          const uint32_t v = e >> 1, val = e & 1;
+          const uint32_t bit = 1u << (v & 31);
+          if (T[v >> 5] & F[v >> 5] & bit) {
+            sh.conflict = 1;
+          } else {
+            // the literal of v that is now false is the negative one iff v = 1
+            const uint32_t li = 2 * v + val;
+            start = occ.beg(li);
+            cnt = occ.end(li) - start;
+          }
+        }
+        uint32_t total;
+        const uint32_t off = tm.scan(cnt, &total);
+        X[lane] = off;
+        X[S + lane] = start;
+        tm.sync();
+        const uint32_t m = min(S, n - base);
+        for (uint32_t k = lane; k < total; k += S) {
+          uint32_t lo = 0, hi = m;   // X[lo] <= k < X[hi] (X[m] = total)
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (X[mid] <= k) lo = mid;
+            else hi = mid;
+          }
+          push(visit_clause(cnf, occ.at(X[S + lo] + (k - X[lo])), T, F, w, sh), next, QC, w, sh);
+        }
+        tm.sync();   // X is rewritten by the next entries
+      }
     }
-    __syncthreads();
-    const uint32_t changed = sh.chg[w], conflict = sh.conflict;
+    tm.sync();
+    const uint32_t changed = uniform_u32(sh.chg[w]), conflict = uniform_u32(sh.conflict);
     if (conflict || !changed) break;
     if (r >= max_rounds) {   // cannot happen: every changing round sets a new bit
-      if (tid == 0) sh.error = 1;
+      if (lane == 0) sh.error = 1;
       break;
     }
   }
-  __syncthreads();
-  for (uint32_t w = tid; w < nw; w += kBlock)
+  tm.sync();
+  for (uint32_t w = lane; w < nw; w += S)
     if (T[w] & F[w]) sh.conflict = 1;
-  __syncthreads();
-  if (sh.conflict || sh.error) {
-    if (tid == 0) {
+  tm.sync();
+  if (uniform_u32(sh.conflict) || uniform_u32(sh.error)) {
+    if (lane == 0) {
       out[ci].status = sh.error ? 2 : 1;
       out[ci].f = out[ci].m = out[ci].nres = 0;
     }
-    __syncthreads();
+    tm.sync();
     return;
   }
 
   // ---- active variables
-  for (uint32_t c = tid; c < nc; c += kBlock) {
+  for (uint32_t c = lane; c < nc; c += S) {
     if (clause_satisfied(cnf, c, T, F)) continue;
     for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
       uint32_t v;
@@ -269,11 +343,11 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
       if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
     }
   }
-  __syncthreads();
+  tm.sync();
 
-  // ---- slot prefix per bitmap word (contiguous words per thread)
-  const uint32_t wpt = (nw + kBlock - 1) / kBlock;
-  const uint32_t w0 = tid * wpt, w1 = min(nw, w0 + wpt);
+  // ---- slot prefix per bitmap word (contiguous words per lane)
+  const uint32_t wpl = (nw + S - 1) / S;
+  const uint32_t w0 = min(nw, lane * wpl), w1 = min(nw, w0 + wpl);
   uint32_t my_act = 0, my_free = 0;
   for (uint32_t w = w0; w < w1; w++) {
     uint32_t valid = 0xFFFFFFFFu;
@@ -283,21 +357,21 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
     my_free += __popc(~(T[w] | F[w]) & valid);
   }
   uint32_t f_total, free_total;
-  uint32_t base = block_exclusive_scan(my_act, sh.wave, &f_total);
-  block_exclusive_scan(my_free, sh.wave, &free_total);
+  uint32_t base = tm.scan(my_act, &f_total);
+  tm.scan(my_free, &free_total);
   for (uint32_t w = w0; w < w1; w++) { P[w] = base; base += __popc(A[w]); }
-  __syncthreads();
+  tm.sync();
 
   const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
 
-  // ---- residual records, in clause order (contiguous clauses per thread)
-  const uint32_t cpt = (nc + kBlock - 1) / kBlock;
-  const uint32_t c0 = tid * cpt, c1 = min(nc, c0 + cpt);
+  // ---- residual records, in clause order (contiguous clauses per lane)
+  const uint32_t cpl = (nc + S - 1) / S;
+  const uint32_t c0 = min(nc, lane * cpl), c1 = min(nc, c0 + cpl);
   uint32_t my_unsat = 0;
   for (uint32_t c = c0; c < c1; c++)
     if (!clause_satisfied(cnf, c, T, F)) my_unsat++;
   uint32_t n_unsat;
-  uint32_t pos = block_exclusive_scan(my_unsat, sh.wave, &n_unsat);
+  uint32_t pos = tm.scan(my_unsat, &n_unsat);
   const bool cap_ok = n_unsat <= cd.nres_cap;
   if (f_ok && cap_ok) {
     for (uint32_t c = c0; c < c1; c++) {
@@ -320,15 +394,21 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
       pos++;
     }
   }
-  if (tid == 0) {
+  if (lane == 0) {
     out[ci].status = !f_ok ? 2 : (!cap_ok ? 3 : 0);
     out[ci].f = int32_t(f_total);
     out[ci].m = int32_t(free_total - f_total);
     out[ci].nres = int32_t(n_unsat);
   }
-  __syncthreads();
+  tm.sync();
 }
 
+// Persistent propagation kernel.  A workgroup takes a group of up to
+// kUpWaves / TW consecutive cubes of one query; a query whose CNF fits the
+// LDS budget is staged once (16-bit clause offsets, literals, occurrence
+// offsets and occurrence lists) and shared by the group's teams; each team
+// then propagates one cube on its own bitmaps and frontier queues.
+template <int TW>
 __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restrict__ qd,
                                                    const uint32_t* __restrict__ coff,
                                                    const int32_t* __restrict__ lits,
@@ -336,52 +416,64 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
                                                    const uint32_t* __restrict__ occs,
                                                    const DevCubeDesc* __restrict__ cubes,
                                                    const int32_t* __restrict__ cube_lits,
-                                                   uint32_t n_cubes, DevCubeOut* __restrict__ out,
-                                                   uint4* __restrict__ res, uint32_t* head,
-                                                   uint32_t nw_max) {
-  // LDS: four bitmaps of nw_max words, the two frontier queues, then (for
-  // staged queries) the CNF as 16-bit offsets and 16-bit literals
+                                                   const uint2* __restrict__ groups, uint32_t n_groups,
+                                                   DevCubeOut* __restrict__ out, uint4* __restrict__ res,
+                                                   uint32_t* head, uint32_t nw_max) {
+  // LDS: per team four bitmaps of nw_max words, two frontier queues and
+  // the scan space, then the staged CNF
+  constexpr uint32_t kTeams = kUpWaves / TW;
   extern __shared__ uint32_t smem[];
-  uint32_t* T = smem;
+  __shared__ UpShared sh[kTeams];
+  __shared__ uint32_t s_group;
+  const uint32_t tid = threadIdx.x, team = (tid >> 6) / TW;
+  const size_t per_team = size_t(nw_max) * 4 + 2 * Team<TW>::kQueue + 2 * Team<TW>::kSize;
+  uint32_t* T = smem + team * per_team;
   uint32_t* F = T + nw_max;
   uint32_t* A = F + nw_max;
   uint32_t* P = A + nw_max;
   uint32_t* Q = P + nw_max;
-  uint16_t* stage = reinterpret_cast<uint16_t*>(Q + 2 * kUpQueue);
-  __shared__ UpShared sh;
-  __shared__ uint32_t s_item;
-  const uint32_t tid = threadIdx.x;
+  uint32_t* X = Q + 2 * Team<TW>::kQueue;
+  uint16_t* stage = reinterpret_cast<uint16_t*>(smem + kTeams * per_team);
 
   for (;;) {
-    if (tid == 0) s_item = atomicAdd(head, 1u);
+    if (tid == 0) s_group = atomicAdd(head, 1u);
     __syncthreads();
-    const uint32_t ci = s_item;
+    const uint32_t gi = s_group;
     __syncthreads();
-    if (ci >= n_cubes) break;
+    if (gi >= n_groups) break;
 
-    const DevCubeDesc cd = cubes[ci];
-    const DevQueryDesc q = qd[cd.qid];
+    const uint2 g = groups[gi];                  // (first cube, count)
+    const DevQueryDesc q = qd[cubes[g.x].qid];
     const uint32_t* co = coff + q.coff_base;
     const int32_t* L = lits + q.lit_base;
     const uint32_t* oo = occ_offs + q.occ_off_base;
     const uint32_t* oc = occs + q.occ_base;
     if (q.staged) {
-      // 16-bit copies: clause offsets and literals (v << 1 | negative)
       const uint32_t nl = co[q.n_clauses];
+      const uint32_t nli = 2 * (q.n_vars + 1);
       uint16_t* sco = stage;
       uint16_t* sl = sco + q.n_clauses + 1;
+      uint16_t* soo = sl + nl;
+      uint16_t* soc = soo + nli + 1;
       for (uint32_t c = tid; c <= q.n_clauses; c += kBlock) sco[c] = uint16_t(co[c]);
       for (uint32_t i = tid; i < nl; i += kBlock) {
         const int32_t l = L[i];
         sl[i] = uint16_t((uint32_t(l > 0 ? l : -l) << 1) | (l < 0 ? 1u : 0u));
+        soc[i] = uint16_t(oc[i]);
       }
+      for (uint32_t i = tid; i <= nli; i += kBlock) soo[i] = uint16_t(oo[i]);
       __syncthreads();
-      propagate_cube(LdsCnf{sco, sl}, GlobalOcc{oo, oc}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res, T,
-                     F, A, P, Q, sh);
-    } else {
-      propagate_cube(GlobalCnf{co, L}, GlobalOcc{oo, oc}, cd, ci, q.n_vars, q.n_clauses, cube_lits, out, res,
-                     T, F, A, P, Q, sh);
+      if (team < g.y) {
+        const uint32_t ci = g.x + team;
+        propagate_cube<TW>(LdsCnf{sco, sl}, LdsOcc{soo, soc}, cubes[ci], ci, q.n_vars, q.n_clauses, cube_lits,
+                           out, res, T, F, A, P, Q, X, sh[team]);
+      }
+    } else if (team < g.y) {
+      const uint32_t ci = g.x + team;
+      propagate_cube<TW>(GlobalCnf{co, L}, GlobalOcc{oo, oc}, cubes[ci], ci, q.n_vars, q.n_clauses, cube_lits,
+                         out, res, T, F, A, P, Q, X, sh[team]);
     }
+    __syncthreads();   // the staged CNF is replaced by the next group
   }
 }
 
@@ -513,13 +605,14 @@ CnfLayout cnf_layout(const CnfHost& c) {
   return l;
 }
 struct RoundLayout {
-  size_t head, cubes, lits, items, outs, res, end;
+  size_t head, cubes, groups, lits, items, outs, res, end;
 };
 RoundLayout round_layout(size_t base, size_t n_cubes, size_t n_lits, size_t n_items, uint64_t nres) {
   RoundLayout l;
   l.head = base;
   l.cubes = align256(l.head + 256);
-  l.lits = align256(l.cubes + n_cubes * sizeof(DevCubeDesc));
+  l.groups = align256(l.cubes + n_cubes * sizeof(DevCubeDesc));   // at most one group per cube
+  l.lits = align256(l.groups + n_cubes * sizeof(uint2));
   l.items = align256(l.lits + n_lits * 4);
   l.outs = align256(l.items + n_items * sizeof(DevItem));
   l.res = align256(l.outs + n_cubes * sizeof(DevCubeOut));
@@ -539,6 +632,23 @@ void dev_init(DeviceInfo* info, int device) {
   info->device = device;
   info->cus = p.multiProcessorCount;
   info->max_lds = p.sharedMemPerBlock;
+  info->up_lds_max = info->max_lds;
+  // the propagation kernel stages whole CNFs: let it use the opt-in LDS
+  // size of the device when that is larger (160 KB per CU on gfx950)
+  int optin = 0;
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
+      size_t(optin) > info->max_lds) {
+    const size_t want = size_t(optin) - 1024;   // static LDS of the kernel
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&up_kernel<1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&up_kernel<4>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
+      info->up_lds_max = want;
+    else
+      (void)hipGetLastError();
+  } else {
+    (void)hipGetLastError();
+  }
 }
 
 void dev_copy_h2d(void* dst, const void* src, size_t bytes, void* stream) {
@@ -640,9 +750,13 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   if (up_bytes > staging_bytes || align256(nc * sizeof(DevCubeOut)) + cnf.q.size() * 8 > staging_bytes)
     fail(SCUBA_E_INTERNAL, "staging too small");
   // host-side checks of what the kernels assume
-  const size_t up_lds = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * 4 + cnf.stage_bytes;
+  // a round with at most one cube per CU gives each cube a whole workgroup
+  // (team of four waves); larger rounds give each cube one wave
+  const uint32_t tw = nc <= uint32_t(info.cus) ? 4 : 1;
+  const size_t team_bytes = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 + 2 * 64 * size_t(tw) * 4;
+  const size_t up_lds = (kUpWaves / tw) * team_bytes + cnf.stage_bytes;
   const size_t leaf_lds = size_t(std::max<uint32_t>(rh.tile_max, 1)) * 16;
-  if (up_lds + 1024 > info.max_lds) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
+  if (up_lds > info.up_lds_max) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
   if (leaf_lds + 64 > info.max_lds) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");
   for (const DevCubeDesc& c : rh.cubes) {
     if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + c.n_lits > rh.cube_lits.size() ||
@@ -657,6 +771,17 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   const size_t b = rl.head;
   std::memset(s + (rl.head - b), 0, 256);
   std::memcpy(s + (rl.cubes - b), rh.cubes.data(), nc * sizeof(DevCubeDesc));
+  // groups of up to kUpWaves consecutive cubes of one query
+  uint32_t n_groups = 0;
+  {
+    uint2* gp = reinterpret_cast<uint2*>(s + (rl.groups - b));
+    for (uint32_t i = 0; i < nc;) {
+      uint32_t j = i + 1;
+      while (j < nc && j - i < kUpWaves / tw && rh.cubes[j].qid == rh.cubes[i].qid) j++;
+      gp[n_groups++] = make_uint2(i, j - i);
+      i = j;
+    }
+  }
   std::memcpy(s + (rl.lits - b), rh.cube_lits.data(), rh.cube_lits.size() * 4);
   std::memcpy(s + (rl.items - b), rh.items.data(), ni * sizeof(DevItem));
   DevCubeOut init{};
@@ -665,7 +790,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
 
   char* w = static_cast<char*>(ws);
   const uint32_t g = grid ? grid : uint32_t(info.cus) * 8;
-  const uint32_t gu = nc ? std::min<uint32_t>(g, uint32_t(nc)) : 0;
+  const uint32_t gu = n_groups ? std::min<uint32_t>(g, n_groups) : 0;
   const uint32_t gl = ni ? std::min<uint32_t>(g, uint32_t(ni)) : 0;
   // the whole round as one stream sequence: upload (the zeroed head and the
   // initial outputs included, so no memset), kernels, download
@@ -674,14 +799,15 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
     HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
     if (ev) HIP_OK(hipEventRecord(ev[1], q));
     if (gu) {
-      hipLaunchKernelGGL(up_kernel, dim3(gu), dim3(kBlock), up_lds, q,
+      hipLaunchKernelGGL(tw == 4 ? up_kernel<4> : up_kernel<1>, dim3(gu), dim3(kBlock), up_lds, q,
                          reinterpret_cast<const DevQueryDesc*>(w + cl.q),
                          reinterpret_cast<const uint32_t*>(w + cl.coff),
                          reinterpret_cast<const int32_t*>(w + cl.lits),
                          reinterpret_cast<const uint32_t*>(w + cl.occ_off),
                          reinterpret_cast<const uint32_t*>(w + cl.occ),
                          reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
-                         reinterpret_cast<const int32_t*>(w + rl.lits), uint32_t(nc),
+                         reinterpret_cast<const int32_t*>(w + rl.lits),
+                         reinterpret_cast<const uint2*>(w + rl.groups), n_groups,
                          reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
                          reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
       HIP_OK(hipGetLastError());
@@ -725,7 +851,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
     hipStream_t gs = graphs->stream;
     std::vector<uint64_t> key = {uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(staging)), cl.end, nc,
                                  rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), mode, gu, gl,
-                                 rh.nw_max, up_lds, leaf_lds, uint64_t(info.device)};
+                                 rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw};
     auto it = graphs->execs.find(key);
     if (it == graphs->execs.end()) {
       hipGraph_t graph;

@@ -66,7 +66,8 @@ void dev_graphs_destroy(DevGraphs* g);
 struct DeviceInfo {
   int device = 0;
   int cus = 256;
-  size_t max_lds = 65536;
+  size_t max_lds = 65536;      // dynamic LDS a kernel may use by default
+  size_t up_lds_max = 65536;   // dynamic LDS the propagation kernel may use
 };
 
 // Host staging for one launch pair; the layout inside the workspace is
@@ -102,7 +103,10 @@ void dev_pinned_free(void* p);
 // Frontier queue of the propagation kernel (entries per buffer; two buffers
 // in LDS).  A round whose new assignments overflow it is followed by a full
 // clause scan.
-constexpr uint32_t kUpQueue = 1024;
+constexpr uint32_t kUpQueue = 512;
+// Cubes per workgroup of the propagation kernel (one per wave); they share
+// the staged CNF of their query.
+constexpr uint32_t kUpWaves = 4;
 
 // Workspace layout.  The CNF region persists across rounds of one call.
 size_t dev_cnf_bytes(const CnfHost& cnf);
