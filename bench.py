@@ -163,6 +163,20 @@ def gain_legs(ctx, mlp_q, log):
         out[f"random3sat_n{n}"] = leg
         log(f"3-SAT n={n}: {leg}")
     out["random3sat_scorer"] = info
+    # 4096 2-D accesses of uneven width in one decide call, autotuned and
+    # captured as HIP graphs (word ordering)
+    gens3 = w.config3()
+    t0 = time.perf_counter()
+    cnf3 = ctx.bitblast([g.query.arrays()[:2] for g in gens3])
+    bb3 = 1000.0 * (time.perf_counter() - t0)
+    tuned, rep = ctx.autotune(cnf3, sample=128, reps=1, scorer="word", graph=True)
+    labels3 = [g.label for g in gens3]
+    dec = [decide_stats(ctx, cnf3, len(gens3), labels3, max_cubes=20000, **tuned)[0] for _ in range(2)]
+    best = min(dec, key=lambda d: d["ms"])
+    out["batch_4096_2d"] = {"bitblast_ms": round(bb3, 1), "tuned": tuned,
+                            "tune_points": rep["points"], "decide": best,
+                            "queries_per_s": round(len(gens3) / ((bb3 + best["ms"]) / 1000.0), 1)}
+    log(f"4096 2-D accesses: {out['batch_4096_2d']}")
     # partition queries, all 1024
     gens = w.config5()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])

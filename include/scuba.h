@@ -275,6 +275,10 @@ typedef struct {
   uint32_t flags;            /* SCUBA_SOLVE_*                                 */
   const scuba_learned_scorer* learned;   /* SCUBA_SCORER_LEARNED only; its
                                  buffers come from the end of the workspace */
+  uint32_t max_residual;     /* scuba_decide: a leaf's residual clauses must
+                                fit this tile (16 B each, in LDS; 0 = 2048,
+                                at most 8192)                                 */
+  uint32_t reserved;
 } scuba_solve_opts;
 
 /* Device bytes scuba_solve / scuba_decide need for this batch. */
@@ -307,7 +311,8 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
  * point of a coordinate sweep, one coordinate at a time, each keeping the
  * best point before the next: k in {16, 20, 24, 28, 30}, chunk_log2 in
  * {4, 6, 8, 10, 12}, leaves_per_round in {1, 2, 4, 8, 16}, grid in
- * {2, 4, 8, 16} workgroups per CU; a point's time is the best wall time of
+ * {2, 4, 8, 16} workgroups per CU, leaf tile (max_residual) in {1024,
+ * 2048, 4096, 8192} clauses; a point's time is the best wall time of
  * `reps` runs.  Every point must give the same decided verdicts (UNKNOWN is
  * compatible with SAT and UNSAT); a contradiction is SCUBA_E_INTERNAL.  The
  * choice is cached in the context per bucket (log2 of the mean clause

@@ -62,7 +62,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("k", C.c_uint32), ("max_cubes", C.c_uint64),
                 ("leaves_per_round", C.c_uint32), ("chunk_log2", C.c_uint32),
                 ("grid", C.c_uint32), ("max_rounds", C.c_uint32), ("scorer", C.c_uint32),
-                ("flags", C.c_uint32), ("learned", C.POINTER(LearnedScorer))]
+                ("flags", C.c_uint32), ("learned", C.POINTER(LearnedScorer)),
+                ("max_residual", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class TuneOpts(C.Structure):

@@ -121,7 +121,7 @@ def _scorer(scorer) -> int:
 
 
 def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_log2=0,
-                grid=0, max_rounds=0, learned=None, scorer="static", graph=False):
+                grid=0, max_rounds=0, learned=None, scorer="static", graph=False, max_residual=0):
     """learned: an L.LearnedScorer (Mlp.scorer()) selects the learned
     ordering; otherwise scorer is "static" or "word"."""
     o = L.SolveOpts()
@@ -130,6 +130,7 @@ def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_
     o.max_rounds = max_rounds
     o.scorer = _scorer(scorer)
     o.flags = L.SOLVE_GRAPH if graph else 0
+    o.max_residual = max_residual
     if learned is not None:
         o.scorer = L.SCORER_LEARNED
         o.learned = C.pointer(learned)
@@ -295,7 +296,8 @@ class Context:
                                             self._stream(stream), C.byref(best), C.byref(rep)))
         names = {v: k for k, v in _SCORERS.items()}
         opts = dict(k=best.k, leaves_per_round=best.leaves_per_round, chunk_log2=best.chunk_log2,
-                    grid=best.grid, scorer=names[best.scorer], graph=bool(best.flags & L.SOLVE_GRAPH))
+                    grid=best.grid, scorer=names[best.scorer], graph=bool(best.flags & L.SOLVE_GRAPH),
+                    max_residual=best.max_residual)
         report = dict(points=rep.points, cached=bool(rep.cached), best_ms=rep.best_ms,
                       default_ms=rep.default_ms)
         return opts, report

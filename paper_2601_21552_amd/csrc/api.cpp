@@ -115,10 +115,11 @@ struct Opts {
   uint64_t max_cubes;
   const scuba_learned_scorer* learned;
   uint32_t flags;
+  uint32_t max_res;
 };
 Opts resolve(const scuba_solve_opts* o) {
   Opts r{SCUBA_MODE_DECIDE, kDefaultK, kDefaultLeavesPerRound, kDefaultChunkLog2, 0, 0, 0, kDefaultMaxCubes,
-         nullptr, 0};
+         nullptr, 0, kDefaultMaxResidual};
   if (o) {
     r.mode = o->mode;
     if (o->k) r.k = o->k;
@@ -130,7 +131,9 @@ Opts resolve(const scuba_solve_opts* o) {
     if (o->max_cubes) r.max_cubes = o->max_cubes;
     r.learned = o->learned;
     r.flags = o->flags;
+    if (o->max_residual) r.max_res = o->max_residual;
   }
+  if (r.max_res > 8192) fail(SCUBA_E_INVALID, "max_residual above 8192");
   if (r.flags & ~SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "unknown solve flags");
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
@@ -752,7 +755,7 @@ scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const 
   return guard(ctx, [&] {
     Opts o = resolve(opts);
     CnfHost h = cnf_host(cnf);
-    *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, kDefaultMaxResidual);
+    *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, o.max_res);
     if (o.scorer == SCUBA_SCORER_LEARNED)
       *bytes += scorer_bytes(size_t(cnf->q.size()) * o.learned->candidates) + 256;
   });
@@ -875,7 +878,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     const bool learned = o.scorer == SCUBA_SCORER_LEARNED;
     parallel_for(nq, [&](size_t qi) {
       if (!open[qi]) return;
-      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, kDefaultMaxResidual, o.max_cubes);
+      sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, o.max_res, o.max_cubes);
       if (learned) sp[qi]->set_learned(o.learned->candidates, o.learned->rescore);
       if (o.scorer == SCUBA_SCORER_WORD) sp[qi]->set_word_order();
     });
@@ -1029,6 +1032,7 @@ constexpr uint32_t kTuneK[] = {16, 20, 24, 28, 30};
 constexpr uint32_t kTuneChunk[] = {4, 6, 8, 10, 12};
 constexpr uint32_t kTuneLpr[] = {1, 2, 4, 8, 16};
 constexpr uint32_t kTuneGridPerCu[] = {2, 4, 8, 16};
+constexpr uint32_t kTuneTile[] = {1024, 2048, 4096, 8192};
 
 struct TuneSetup {
   uint32_t sample, reps, scorer, flags;
@@ -1070,14 +1074,15 @@ std::vector<uint64_t> tune_bucket(const scuba_cnf* cnf, const TuneSetup& ts) {
   return {lg(mean), lg(double(cnf->q.size())), ts.scorer, ts.flags};
 }
 
-Opts tune_point(const TuneSetup& ts, uint32_t k, uint32_t chunk, uint32_t lpr, uint32_t grid) {
-  Opts o{SCUBA_MODE_DECIDE, k, lpr, chunk, grid, 0, ts.scorer, ts.max_cubes, nullptr, ts.flags};
+Opts tune_point(const TuneSetup& ts, uint32_t k, uint32_t chunk, uint32_t lpr, uint32_t grid,
+                uint32_t tile = kDefaultMaxResidual) {
+  Opts o{SCUBA_MODE_DECIDE, k, lpr, chunk, grid, 0, ts.scorer, ts.max_cubes, nullptr, ts.flags, tile};
   return o;
 }
 
 size_t tune_bytes(const scuba_cnf* sample, const Opts& o) {
   CnfHost h = cnf_host(sample);
-  return dev_cnf_bytes(h) + round_bound(sample, sample->q.size() * o.lpr, o, kDefaultMaxResidual);
+  return dev_cnf_bytes(h) + round_bound(sample, sample->q.size() * o.lpr, o, o.max_res);
 }
 
 }  // namespace
@@ -1091,7 +1096,8 @@ scuba_status scuba_autotune_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, cons
     size_t most = 0;
     for (uint32_t k : kTuneK)
       for (uint32_t c : kTuneChunk)
-        for (uint32_t l : kTuneLpr) most = std::max(most, tune_bytes(&sample, tune_point(ts, k, c, l, 0)));
+        for (uint32_t l : kTuneLpr)
+          for (uint32_t t : kTuneTile) most = std::max(most, tune_bytes(&sample, tune_point(ts, k, c, l, 0, t)));
     *bytes = most;
   });
 }
@@ -1135,14 +1141,15 @@ scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tu
       return bestt;
     };
     uint32_t k = kDefaultK, chunk = kDefaultChunkLog2, lpr = kDefaultLeavesPerRound, gpc = 8;
-    double cur = measure(tune_point(ts, k, chunk, lpr, gpc * cus));
+    uint32_t tile = kDefaultMaxResidual;
+    double cur = measure(tune_point(ts, k, chunk, lpr, gpc * cus, tile));
     rep.default_ms = cur;
     auto sweep = [&](uint32_t* var, const uint32_t* vals, size_t n) {
       for (size_t i = 0; i < n; i++) {
         if (vals[i] == *var) continue;
         const uint32_t keep = *var;
         *var = vals[i];
-        double t = measure(tune_point(ts, k, chunk, lpr, gpc * cus));
+        double t = measure(tune_point(ts, k, chunk, lpr, gpc * cus, tile));
         if (t < cur) cur = t;
         else *var = keep;
       }
@@ -1151,6 +1158,7 @@ scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tu
     sweep(&chunk, kTuneChunk, std::size(kTuneChunk));
     sweep(&lpr, kTuneLpr, std::size(kTuneLpr));
     sweep(&gpc, kTuneGridPerCu, std::size(kTuneGridPerCu));
+    sweep(&tile, kTuneTile, std::size(kTuneTile));
     if (!std::isfinite(cur)) fail(SCUBA_E_CAPACITY, "no tuning point fits the workspace");
     scuba_solve_opts b{};
     b.mode = SCUBA_MODE_DECIDE;
@@ -1161,6 +1169,7 @@ scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tu
     b.grid = gpc * cus;
     b.scorer = ts.scorer;
     b.flags = ts.flags;
+    b.max_residual = tile;
     ctx->tuned[bucket] = b;
     *best = b;
     rep.best_ms = cur;

@@ -633,6 +633,7 @@ void dev_init(DeviceInfo* info, int device) {
   info->cus = p.multiProcessorCount;
   info->max_lds = p.sharedMemPerBlock;
   info->up_lds_max = info->max_lds;
+  info->leaf_lds_max = info->max_lds;
   // the propagation kernel stages whole CNFs: let it use the opt-in LDS
   // size of the device when that is larger (160 KB per CU on gfx950)
   int optin = 0;
@@ -644,6 +645,12 @@ void dev_init(DeviceInfo* info, int device) {
         hipFuncSetAttribute(reinterpret_cast<const void*>(&up_kernel<4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
       info->up_lds_max = want;
+    else
+      (void)hipGetLastError();
+    // the leaf kernel's residual tile (16 B per clause) likewise
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
+      info->leaf_lds_max = want;
     else
       (void)hipGetLastError();
   } else {
@@ -757,7 +764,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   const size_t up_lds = (kUpWaves / tw) * team_bytes + cnf.stage_bytes;
   const size_t leaf_lds = size_t(std::max<uint32_t>(rh.tile_max, 1)) * 16;
   if (up_lds > info.up_lds_max) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
-  if (leaf_lds + 64 > info.max_lds) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");
+  if (leaf_lds > info.leaf_lds_max) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");
   for (const DevCubeDesc& c : rh.cubes) {
     if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + c.n_lits > rh.cube_lits.size() ||
         c.res_base + c.nres_cap > rh.res_records || c.nres_cap > rh.tile_max ||

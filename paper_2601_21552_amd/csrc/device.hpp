@@ -68,6 +68,7 @@ struct DeviceInfo {
   int cus = 256;
   size_t max_lds = 65536;      // dynamic LDS a kernel may use by default
   size_t up_lds_max = 65536;   // dynamic LDS the propagation kernel may use
+  size_t leaf_lds_max = 65536; // dynamic LDS the leaf kernel may use
 };
 
 // Host staging for one launch pair; the layout inside the workspace is

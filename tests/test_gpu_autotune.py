@@ -31,6 +31,7 @@ def test_autotune_choice_and_cache(ctx, batch):
     assert opts["k"] in (16, 20, 24, 28, 30)
     assert opts["chunk_log2"] in (4, 6, 8, 10, 12)
     assert opts["leaves_per_round"] in (1, 2, 4, 8, 16)
+    assert opts["max_residual"] in (1024, 2048, 4096, 8192)
     assert opts["scorer"] == "word"
     again, rep2 = ctx.autotune(cnf, sample=48, reps=1, scorer="word")
     assert rep2["cached"] and again == opts
@@ -43,6 +44,7 @@ def test_autotune_choice_and_cache(ctx, batch):
     dict(chunk_log2=4), dict(chunk_log2=12),
     dict(leaves_per_round=1), dict(leaves_per_round=16),
     dict(grid=512), dict(grid=4096),
+    dict(max_residual=1024), dict(max_residual=8192),
     dict(k=20, chunk_log2=6, leaves_per_round=2, graph=True),
 ])
 def test_verdicts_do_not_depend_on_the_point(ctx, batch, point):
