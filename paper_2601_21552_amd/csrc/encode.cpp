@@ -51,10 +51,52 @@ struct GateKeyHash {
   }
 };
 
+// Structural-hashing table of the gate library: open addressing with linear
+// probing (keys never leave it); type 0 marks an empty slot.
+class GateMap {
+ public:
+  GateMap() : slots_(1024) {}
+  const int32_t* find(const GateKey& k) const {
+    for (size_t i = GateKeyHash()(k) & (slots_.size() - 1);; i = (i + 1) & (slots_.size() - 1)) {
+      const Slot& s = slots_[i];
+      if (s.key.type == 0) return nullptr;
+      if (s.key == k) return &s.value;
+    }
+  }
+  void insert(const GateKey& k, int32_t v) {
+    if (2 * (used_ + 1) > slots_.size()) grow();
+    put(k, v);
+    used_++;
+  }
+
+ private:
+  struct Slot {
+    GateKey key{0, 0, 0, 0};
+    int32_t value = 0;
+  };
+  void put(const GateKey& k, int32_t v) {
+    size_t i = GateKeyHash()(k) & (slots_.size() - 1);
+    while (slots_[i].key.type != 0) i = (i + 1) & (slots_.size() - 1);
+    slots_[i].key = k;
+    slots_[i].value = v;
+  }
+  void grow() {
+    std::vector<Slot> old(slots_.size() * 2);
+    old.swap(slots_);
+    for (const Slot& s : old)
+      if (s.key.type != 0) put(s.key, s.value);
+  }
+  std::vector<Slot> slots_;
+  size_t used_ = 0;
+};
+
 // Clause sink + gate library with constant folding and structural hashing.
 class Gates {
  public:
-  explicit Gates(CnfQuery& out) : q_(out) {}
+  explicit Gates(CnfQuery& out) : q_(out) {
+    q_.lits.reserve(1 << 14);
+    q_.off.reserve(1 << 12);
+  }
 
   int32_t fresh() { return int32_t(++q_.n_vars); }
 
@@ -89,13 +131,12 @@ class Gates {
     if (b == kTrue) return a;
     if (std::abs(a) > std::abs(b)) std::swap(a, b);
     GateKey k{1, a, b, 0};
-    auto it = cache_.find(k);
-    if (it != cache_.end()) return it->second;
+    if (const int32_t* hit = cache_.find(k)) return *hit;
     int32_t o = fresh();
     clause({-o, a});
     clause({-o, b});
     clause({o, -a, -b});
-    cache_.emplace(k, o);
+    cache_.insert(k, o);
     return o;
   }
   int32_t OR(int32_t a, int32_t b) { return -AND(-a, -b); }
@@ -115,15 +156,14 @@ class Gates {
     else {
       if (a > b) std::swap(a, b);
       GateKey k{2, a, b, 0};
-      auto it = cache_.find(k);
-      if (it != cache_.end()) r = it->second;
+      if (const int32_t* hit = cache_.find(k)) r = *hit;
       else {
         int32_t o = fresh();
         clause({-o, a, b});
         clause({-o, -a, -b});
         clause({o, -a, b});
         clause({o, a, -b});
-        cache_.emplace(k, o);
+        cache_.insert(k, o);
         r = o;
       }
     }
@@ -154,8 +194,7 @@ class Gates {
     else if (ny == 2) r = XOR(ys[0], ys[1]);
     else {
       GateKey k{3, ys[0], ys[1], ys[2]};
-      auto it = cache_.find(k);
-      if (it != cache_.end()) r = it->second;
+      if (const int32_t* hit = cache_.find(k)) r = *hit;
       else {
         int32_t o = fresh();
         for (int m = 0; m < 8; m++) {
@@ -163,7 +202,7 @@ class Gates {
           int p = va ^ vb ^ vc;
           clause({va ? -ys[0] : ys[0], vb ? -ys[1] : ys[1], vc ? -ys[2] : ys[2], p ? o : -o});
         }
-        cache_.emplace(k, o);
+        cache_.insert(k, o);
         r = o;
       }
     }
@@ -192,8 +231,7 @@ class Gates {
     by_var(s[0], s[1]);
     GateKey k{4, s[0], s[1], s[2]};
     int32_t r;
-    auto it = cache_.find(k);
-    if (it != cache_.end()) r = it->second;
+    if (const int32_t* hit = cache_.find(k)) r = *hit;
     else {
       int32_t o = fresh();
       clause({-s[0], -s[1], o});
@@ -202,7 +240,7 @@ class Gates {
       clause({s[0], s[1], -o});
       clause({s[0], s[2], -o});
       clause({s[1], s[2], -o});
-      cache_.emplace(k, o);
+      cache_.insert(k, o);
       r = o;
     }
     return flip ? -r : r;
@@ -305,7 +343,7 @@ class Gates {
 
  private:
   CnfQuery& q_;
-  std::unordered_map<GateKey, int32_t, GateKeyHash> cache_;
+  GateMap cache_;
 };
 
 // ---------------------------------------------------------------- validation

@@ -21,20 +21,26 @@ Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_
       occ_[fill[2 * size_t(std::abs(l)) + (l < 0)]++] = uint32_t(c);
     }
   // static order: literal occurrences in the original CNF, most first,
-  // ties to the lowest variable
-  auto occurrences = [&](int32_t v) {
-    return (occ_off_[2 * v + 1] - occ_off_[2 * v]) + (occ_off_[2 * v + 2] - occ_off_[2 * v + 1]);
-  };
-  order_.resize(n_);
-  for (uint32_t v = 1; v <= n_; v++) order_[v - 1] = int32_t(v);
-  std::stable_sort(order_.begin(), order_.end(), [&](int32_t a, int32_t b) {
-    uint32_t oa = occurrences(a), ob = occurrences(b);
-    return oa != ob ? oa > ob : a < b;
-  });
-  static_rank_.assign(size_t(n_) + 1, 0);
+  // ties to the lowest variable (a counting sort by occurrences; variables
+  // enter their bucket in increasing order)
   occurrences_.assign(size_t(n_) + 1, 0);
+  uint32_t most = 0;
+  for (uint32_t v = 1; v <= n_; v++) {
+    occurrences_[v] = occ_off_[2 * v + 2] - occ_off_[2 * v];
+    most = std::max(most, occurrences_[v]);
+  }
+  std::vector<uint32_t> start(size_t(most) + 2, 0);
+  for (uint32_t v = 1; v <= n_; v++) start[most - occurrences_[v] + 1]++;
+  for (size_t i = 1; i < start.size(); i++) start[i] += start[i - 1];
+  order_.resize(n_);
+  for (uint32_t v = 1; v <= n_; v++) order_[start[most - occurrences_[v]]++] = int32_t(v);
+  static_rank_.assign(size_t(n_) + 1, 0);
   for (uint32_t i = 0; i < n_; i++) static_rank_[order_[i]] = i;
-  for (uint32_t v = 1; v <= n_; v++) occurrences_[v] = occurrences(int32_t(v));
+  // clause counts per variable at the root (copied by every reset)
+  act_init_.assign(size_t(n_) + 1, 0);
+  for (int32_t l : q_.lits) act_init_[std::abs(l)]++;
+  f_init_ = 0;
+  for (uint32_t v = 1; v <= n_; v++) f_init_ += act_init_[v] > 0;
   bit_pos_.assign(size_t(n_) + 1, 0);
   bit_width_.assign(size_t(n_) + 1, 0);
   for (size_t i = 0; i < q_.in_first.size(); i++)
@@ -177,10 +183,8 @@ void Splitter::reset_state() {
   seen_stamp_ = 0;
   ntrue_.assign(q_.n_clauses(), 0);
   nfalse_.assign(q_.n_clauses(), 0);
-  act_cnt_.assign(size_t(n_) + 1, 0);
-  for (int32_t l : q_.lits) act_cnt_[std::abs(l)]++;
-  f_ = 0;
-  for (uint32_t v = 1; v <= n_; v++) f_ += act_cnt_[v] > 0;
+  act_cnt_ = act_init_;
+  f_ = f_init_;
   n_unsat_ = q_.n_clauses();
   trail_.clear();
   stack_.clear();

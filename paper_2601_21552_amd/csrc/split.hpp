@@ -130,8 +130,8 @@ class Splitter {
   std::vector<int32_t> reason_;     // implying clause, -1 for decisions
   std::vector<uint32_t> level_;     // decision level of the assignment
   std::vector<uint32_t> ntrue_, nfalse_;
-  std::vector<uint32_t> act_cnt_;
-  uint32_t f_ = 0;
+  std::vector<uint32_t> act_cnt_, act_init_;
+  uint32_t f_ = 0, f_init_ = 0;
   uint64_t n_unsat_ = 0;
   std::vector<int32_t> trail_;
   std::vector<std::pair<int32_t, int32_t>> queue_;   // (literal, reason)
