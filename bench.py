@@ -183,7 +183,7 @@ def gain_legs(ctx, mlp_q, log):
     labels = [g.label for g in gens]
     st, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000)
     le, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000,
-                         learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE))
+                         learned=mlp_q.scorer(LEARNED_CANDIDATES, 1))
     wo, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000, scorer="word")
     out["partition_1024"] = {"static": st, "learned": le, "word": wo}
     log(f"partition queries: {out['partition_1024']}")

@@ -179,7 +179,8 @@ void scuba_cnf_free(scuba_cnf* cnf);
  * static order for auxiliary variables and raw CNFs. */
 #define SCUBA_SCORER_WORD 2u
 /* Learned ordering: at a decision node the top `candidates` active variables
- * of the static order are scored by the perceptron below (scuba_mlp_*),
+ * of the static order, and the most significant active bit of each input
+ * word, are scored by the perceptron below (scuba_mlp_*),
  * batched over all queries on the device; the ranking orders the decisions
  * of that node and of `rescore` levels below it.  Non-finite scores fall
  * back to the static order.  master / wbf16: device parameter block and its
@@ -206,7 +207,8 @@ typedef struct {
   void* hip_stream;
 } scuba_split_opts;
 /* Device bytes the learned scorer needs for a batch (one row per candidate
- * of every query). */
+ * of every query: `candidates` from the static order plus one per input
+ * word). */
 size_t scuba_scorer_workspace(const scuba_cnf* cnf, uint32_t candidates);
 
 #define SCUBA_CUBE_LEAF 0
@@ -235,10 +237,14 @@ scuba_status scuba_cubes_view_get(const scuba_cubes* cubes, uint32_t qi, scuba_c
 void scuba_cubes_free(scuba_cubes* cubes);
 
 /* Traces for training the scorer: the static walk of every query, and at
- * every `every`-th decision node above depth `depth` the features of the top
- * `candidates` variables with a one-step lookahead label: log2(1 + f - f0)
- * + log2(1 + f - f1), f the node's active count and f0 / f1 those after
- * propagating the variable to 0 / 1 (0 for a conflict).  Rows of a node are
+ * every `every`-th decision node above depth `depth` the features of the
+ * candidates (the top `candidates` variables of the static order and the
+ * most significant active bit of each input word) with a one-step lookahead
+ * label: log2(1 + f - f0) + log2(1 + f - f1) + (r - r0) + (r - r1), with f
+ * the node's active count and f0 / f1 those after propagating the variable
+ * to 0 / 1 (0 for a conflict), and r, r0, r1 the same for the inputs' range
+ * width in bits (sum over input words of log2(hi - lo + 1), ranges narrowed
+ * by the root facts; 0 for raw CNFs and conflicts).  Rows of a node are
  * contiguous; node = query index << 32 | decision number. */
 typedef struct scuba_trace scuba_trace;
 typedef struct {

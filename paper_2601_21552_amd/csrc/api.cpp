@@ -329,6 +329,13 @@ void check_out(const DevCubeOut& o, const Cube& host) {
 // Batched device scoring for learned orderings: the candidates of every
 // waiting walk go through the perceptron in one pass.  Workspace layout:
 // x bf16 [cap x 16] | a1 bf16 [cap x 128] | a2 bf16 [cap x 128] | y f32 [cap].
+// Candidate rows of one scoring pass over every query: the static
+// candidates plus one per input word.
+size_t scorer_rows(const scuba_cnf* cnf, uint32_t candidates) {
+  size_t rows = 0;
+  for (const CnfQuery& q : cnf->q) rows += std::max<uint32_t>(candidates, 1) + q.in_first.size();
+  return std::max<size_t>(rows, 1);
+}
 size_t scorer_bytes(size_t rows) {
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   return al(rows * kMlpF * 2) + 2 * al(rows * kMlpH * 2) + al(rows * 4);
@@ -550,7 +557,7 @@ void scuba_cnf_free(scuba_cnf* cnf) { delete cnf; }
 // ---------------------------------------------------------------- cubes
 
 size_t scuba_scorer_workspace(const scuba_cnf* cnf, uint32_t candidates) {
-  return cnf ? scorer_bytes(size_t(cnf->q.size()) * std::max<uint32_t>(candidates, 1)) : 0;
+  return cnf ? scorer_bytes(scorer_rows(cnf, candidates)) : 0;
 }
 
 scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split_opts* opts, scuba_cubes** out) {
@@ -565,11 +572,12 @@ scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split
     std::unique_ptr<ScorerRunner> runner;
     if (learned) {
       check_learned(opts->learned);
-      if (!opts->dev_ws || opts->ws_bytes < scorer_bytes(nq * opts->learned->candidates))
+      const size_t rows = scorer_rows(cnf, opts->learned->candidates);
+      if (!opts->dev_ws || opts->ws_bytes < scorer_bytes(rows))
         fail(SCUBA_E_CAPACITY, "scorer workspace smaller than scuba_scorer_workspace");
       ctx->ensure_device();
       runner.reset(new ScorerRunner{ctx, opts->learned, static_cast<char*>(opts->dev_ws),
-                                    nq * opts->learned->candidates, opts->hip_stream});
+                                    rows, opts->hip_stream});
     }
     std::vector<std::unique_ptr<Splitter>> sp(nq);
     std::vector<Splitter*> walks(nq);
@@ -757,7 +765,7 @@ scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const 
     CnfHost h = cnf_host(cnf);
     *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, o.max_res);
     if (o.scorer == SCUBA_SCORER_LEARNED)
-      *bytes += scorer_bytes(size_t(cnf->q.size()) * o.learned->candidates) + 256;
+      *bytes += scorer_bytes(scorer_rows(cnf, o.learned->candidates)) + 256;
   });
 }
 
@@ -887,11 +895,12 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     // the scorer's buffers sit at the end of the workspace
     std::unique_ptr<ScorerRunner> runner;
     if (learned) {
-      const size_t sb = scorer_bytes(nq * o.learned->candidates);
+      const size_t rows = scorer_rows(cnf, o.learned->candidates);
+      const size_t sb = scorer_bytes(rows);
       if (sb + 256 + cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the scorer");
       uintptr_t base = (reinterpret_cast<uintptr_t>(dev_ws) + ws_bytes - sb) & ~uintptr_t(255);
       ws_bytes = base - reinterpret_cast<uintptr_t>(dev_ws);
-      runner.reset(new ScorerRunner{ctx, o.learned, reinterpret_cast<char*>(base), nq * o.learned->candidates,
+      runner.reset(new ScorerRunner{ctx, o.learned, reinterpret_cast<char*>(base), rows,
                                     hip_stream});
     }
     if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");

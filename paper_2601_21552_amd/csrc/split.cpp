@@ -88,6 +88,15 @@ std::vector<int32_t> Splitter::candidates(uint32_t m) const {
     if (c.size() >= m) break;
     if (assign_[v] < 0 && act_cnt_[v] > 0) c.push_back(v);
   }
+  // and the most significant active bit of each input word
+  const size_t n_static = c.size();
+  for (size_t i = 0; i < q_.in_first.size(); i++)
+    for (uint32_t b = q_.in_width[i]; b-- > 0;) {
+      const int32_t v = int32_t(q_.in_first[i] + b);
+      if (assign_[v] >= 0 || act_cnt_[v] == 0) continue;
+      if (std::find(c.begin(), c.begin() + n_static, v) == c.begin() + n_static) c.push_back(v);
+      break;
+    }
   return c;
 }
 
@@ -137,20 +146,55 @@ void Splitter::features(const std::vector<int32_t>& cands, std::vector<float>* o
   }
 }
 
-// One-step lookahead: active counts after propagating v = 0 and v = 1 (a
-// conflicting branch counts as 0); label log2(1 + reduction) summed over
-// the two branches, so that balanced large reductions score highest.
+// Width in bits of the value ranges left to the inputs: sum over input
+// words of log2(hi - lo + 1), the ranges narrowed by the word-level facts
+// when the query has them (0 when they conflict).
+float Splitter::input_range_bits() {
+  const size_t ni = q_.in_first.size();
+  if (ni == 0) return 0.f;
+  if (!q_.word_facts.empty()) {
+    std::vector<uint32_t> lv;
+    if (!word_check(&lv)) return 0.f;
+  }
+  float bits = 0.f;
+  for (size_t a = 0; a < ni; a++) {
+    __int128 lo, hi;
+    if (!q_.word_facts.empty()) {
+      lo = wlo_[a];
+      hi = whi_[a];
+    } else {
+      lo = hi = 0;
+      for (uint32_t b = 0; b < q_.in_width[a]; b++) {
+        const int8_t x = assign_[q_.in_first[a] + b];
+        const __int128 w = (__int128)1 << b;
+        if (x == 1) { lo += w; hi += w; }
+        else if (x < 0) hi += w;
+      }
+    }
+    bits += std::log2(float(double(hi - lo) + 1.0));
+  }
+  return bits;
+}
+
+// One-step lookahead after propagating v = 0 and v = 1: the reduction of
+// the active variable count (a conflicting branch counts as reducing it
+// to 0), log2(1 + reduction) summed over the two branches, plus the
+// reduction of the inputs' range width in bits (a word-level view of the
+// same progress: deciding a high input bit halves that input's range).
 float Splitter::lookahead_label(int32_t v) {
   const size_t pos = trail_.size();
   const uint32_t f = f_;
+  const float r = input_range_bits();
+  float dr = 0.f;
   auto branch = [&](int32_t lit) {
     const bool ok = propagate(lit);
     const uint32_t fb = ok ? f_ : 0;
+    dr += r - (ok ? input_range_bits() : 0.f);
     undo_to(pos);
     return fb;
   };
   const uint32_t f0 = branch(-v), f1 = branch(v);
-  return std::log2(1.f + float(f - f0)) + std::log2(1.f + float(f - f1));
+  return std::log2(1.f + float(f - f0)) + std::log2(1.f + float(f - f1)) + dr;
 }
 
 void Splitter::provide_scores(const float* scores) {

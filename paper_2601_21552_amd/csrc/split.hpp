@@ -48,9 +48,10 @@ class Splitter {
 
   // Learned ordering: at a decision node the walk stops with kNeedScore and
   // asks for scores of the top `candidates` active variables of the static
-  // order; the ranking by score then orders the decisions of that node and
-  // of its descendants up to `rescore` levels below.  Non-finite scores fall
-  // back to the static order.
+  // order and of the most significant active bit of each input word; the
+  // ranking by score then orders the decisions of that node and of its
+  // descendants up to `rescore` levels below.  Non-finite scores fall back
+  // to the static order.
   void set_learned(uint32_t candidates, uint32_t rescore);
   // Word ordering: among active input bits the most significant first (ties
   // to the lowest variable), which halves an input's value range per
@@ -114,6 +115,7 @@ class Splitter {
   std::vector<int32_t> candidates(uint32_t m) const;
   void features(const std::vector<int32_t>& cands, std::vector<float>* out) const;
   float lookahead_label(int32_t v);
+  float input_range_bits();
   int32_t choose_learned();
 
   const CnfQuery& q_;

@@ -270,3 +270,66 @@ def test_learned_options_are_validated(api, ctx):
     with pytest.raises(_lib.ScubaError):
         ctx.decide_workspace(batch, learned=ok_ptrs)
     assert ctx.lib.scuba_scorer_workspace(batch.h, 16) >= 16 * (16 + 2 * 128) * 2
+
+
+def test_trace_word_candidates_and_range_label(api, ctx):
+    """On a bit-blasted query (encoded as given, so input ranges come from
+    the input bits alone) the root's candidates are the first active
+    variables of the static order plus the most significant active bit of
+    each input word, and each label adds the reduction of the inputs'
+    range width in bits, sum of log2(hi - lo + 1), over the two branches."""
+    from paper_2601_21552_amd import _lib
+    q = w.oob_1d(4, "none", scale=2, header=1)
+    batch = ctx.bitblast([q.arrays()[:2]], flags=_lib.BB_NO_REWRITE)
+    v = batch.view(0)
+    c = CNF(v["n_vars"], v["clause_off"], v["lits"])
+    first, width = batch.input_map(0)
+    first = [int(x) for x in first]
+    width = [int(x) for x in width]
+    m = 5
+    feats, labels, nodes = ctx.trace(batch, k=2, candidates=m, every=1, depth=64)
+    sel = nodes == 1
+    conflict, a = cnf_ref.up(c)
+    assert not conflict
+
+    def active(assign):
+        return {abs(int(l)) for j in range(c.n_clauses)
+                for l in c.lits[c.clause_off[j]:c.clause_off[j + 1]]
+                if assign[abs(l)] < 0
+                and not any((x > 0 and assign[x] == 1) or (x < 0 and assign[-x] == 0)
+                            for x in c.lits[c.clause_off[j]:c.clause_off[j + 1]])}
+
+    def range_bits(assign):
+        bits = 0.0
+        for f0, wd in zip(first, width):
+            lo = sum(1 << b for b in range(wd) if assign[f0 + b] == 1)
+            hi = lo + sum(1 << b for b in range(wd) if assign[f0 + b] < 0)
+            bits += np.log2(hi - lo + 1)
+        return bits
+
+    act = active(a)
+    occ = np.zeros(c.n_vars + 1, np.int64)
+    np.add.at(occ, np.abs(c.lits), 1)
+    order = sorted(range(1, c.n_vars + 1), key=lambda x: (-occ[x], x))
+    cands = [x for x in order if x in act][:m]
+    for f0, wd in zip(first, width):
+        for b in reversed(range(wd)):
+            x = f0 + b
+            if a[x] < 0 and x in act:
+                if x not in cands:
+                    cands.append(x)
+                break
+    assert sel.sum() == len(cands) > m
+    f, r = len(act), range_bits(a)
+    want = []
+    for x in cands:
+        lab = 0.0
+        for lit in (-x, x):
+            cf, ab = cnf_ref.up(c, [lit])
+            lab += np.log2(1 + f - (0 if cf else len(active(ab))))
+            lab += r - (0.0 if cf else range_bits(ab))
+        want.append(lab)
+    np.testing.assert_allclose(labels[sel], want, rtol=1e-4, atol=1e-4)
+    # the word candidates are input bits at the top of their words
+    tail = feats[sel][m:]
+    assert np.all(tail[:, 7] == 1.0)
