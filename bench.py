@@ -36,9 +36,9 @@ OPS_PER_CLAUSE_BLOCK = 128
 # read for a device copy of known size), valid only for the kernel source
 # they were taken on
 MEASURED_TRAFFIC = {
-    "device_hip_sha256_16": "c2e58a9696af2eb2",
-    "up_kernel": 21_070_131,
-    "leaf_kernel": 11_219_046,
+    "device_hip_sha256_16": "0ef177e263fd1fef",
+    "up_kernel": 14_575_352,
+    "leaf_kernel": 11_259_814,
 }
 
 # learned ordering: candidates scored per decision node, and the levels
