@@ -9,18 +9,21 @@
 // nothing changes.  The fixpoint is unique, so the order does not matter.
 // Then the active variables (unassigned and in an unsatisfied clause) get
 // slots 0..f-1 in increasing variable order and every unsatisfied clause is
-// compiled, in clause order, into a 16-byte record:
-//   x,y : 64-bit word, OR of the literal patterns of slots 0..5
-//   z   : bits 0..25 positive literals of slots 12..37, bits 26..31 of 6..11
-//   w   : the same for negative literals
+// compiled, in clause order, into a 32-byte record (two uint4):
+//   [0].x,y : 64-bit word, OR of the literal patterns of slots 0..5
+//   [0].z,w : 64-bit lane mask, the lanes where a literal of slots 6..11
+//             is true (the same patterns over the lane id)
+//   [1].x   : positive literals of slots 12..37 (26 bits)
+//   [1].y   : negative literals of slots 12..37
 //
 // Leaf kernel: assignment index a = 4096*block + 64*lane + bit.  Slot j < 6
 // is bit j of `bit` (a constant 64-bit pattern), slot 6..11 is bit j-6 of
 // the lane id, slot >= 12 is bit j-12 of the block (the same for the whole
-// wave).  A wave evaluates one block (64 lanes x 64 bits) per step: a clause
-// satisfied by a block-level literal is skipped with a scalar test; else a
-// lane whose lane-level literals satisfy it keeps its word, other lanes AND
-// the clause's pattern word in.  A block dies when every lane's word is 0.
+// wave).  A wave evaluates one block (64 lanes x 64 bits) per step, reading
+// the records with wave-uniform loads: a clause satisfied by a block-level
+// literal is skipped with a scalar test; else a lane in the clause's lane
+// mask keeps its word and the other lanes AND the clause's pattern word
+// in.  A block dies when every lane's word is 0.
 // DECIDE takes the smallest (cube, index) witness per query with atomicMin
 // and lets later work of that query stop early; COUNT sums popcounts.
 #include <hip/hip_runtime.h>
@@ -376,8 +379,8 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   if (f_ok && cap_ok) {
     for (uint32_t c = c0; c < c1; c++) {
       if (clause_satisfied(cnf, c, T, F)) continue;
-      uint64_t low = 0;
-      uint32_t hp = 0, hn = 0, mp = 0, mn = 0;
+      uint64_t low = 0, lm = 0;
+      uint32_t hp = 0, hn = 0;
       for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
         uint32_t v;
         bool neg;
@@ -386,11 +389,12 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
         if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
         const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
         if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
-        else if (slot < 12) (neg ? mn : mp) |= 1u << (slot - 6);
+        else if (slot < 12) lm |= neg ? ~slot_pattern(slot - 6) : slot_pattern(slot - 6);
         else (neg ? hn : hp) |= 1u << (slot - 12);
       }
-      res[cd.res_base + pos] = make_uint4(uint32_t(low), uint32_t(low >> 32), hp | (mp << 26),
-                                          hn | (mn << 26));
+      const size_t rec = 2 * (cd.res_base + pos);
+      res[rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
+      res[rec + 1] = make_uint4(hp, hn, 0u, 0u);
       pos++;
     }
   }
@@ -477,6 +481,20 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
   }
 }
 
+// acc AND a clause's satisfaction word: lanes in the clause's lane mask (a
+// literal of slots 6..11 holds there) keep acc, the others AND in the OR of
+// the slot-0..5 literal patterns.  The uniform lane mask serves directly as
+// the per-lane condition of the select (its only scalar operand).
+__device__ __forceinline__ uint64_t clause_and(uint64_t acc, const uint4& r) {
+  const uint64_t lanes = (uint64_t(r.w) << 32) | r.z;
+  const uint32_t alo = uint32_t(acc), ahi = uint32_t(acc >> 32);
+  const uint32_t tlo = alo & r.x, thi = ahi & r.y;
+  uint32_t nlo, nhi;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(nlo) : "v"(tlo), "v"(alo), "s"(lanes));
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(nhi) : "v"(thi), "v"(ahi), "s"(lanes));
+  return (uint64_t(nhi) << 32) | nlo;
+}
+
 __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict__ items,
                                                      uint32_t n_items,
                                                      const DevCubeDesc* __restrict__ cubes,
@@ -484,9 +502,10 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
                                                      const uint4* __restrict__ res,
                                                      unsigned long long* __restrict__ qkey,
                                                      uint32_t* head, uint32_t mode) {
-  extern __shared__ uint4 tile[];
   __shared__ uint32_t s_base, s_skip;
-  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is the same for all lanes of a wave: make that explicit so
+  // that block indices, the skip tests and the clause loop stay scalar
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = uniform_u32(tid >> 6);
   constexpr uint32_t kWaves = kBlock / 64;
   constexpr uint32_t kClaim = 8;   // items taken per claim
 
@@ -526,12 +545,11 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
 
       const DevItem it = items[item];
       const DevCubeDesc cd = cubes[it.cube];
-      const uint32_t f = uint32_t(out[it.cube].f);
-      const uint32_t nres = uint32_t(out[it.cube].nres);
+      const uint32_t f = uniform_u32(uint32_t(out[it.cube].f));
+      const uint32_t nres = uniform_u32(uint32_t(out[it.cube].nres));
       const uint64_t key_base = uint64_t(cd.seq) << 38;
-
-      for (uint32_t j = tid; j < nres; j += kBlock) tile[j] = res[cd.res_base + j];
-      __syncthreads();
+      // the leaf's records, read with wave-uniform (scalar) loads
+      const uint4* __restrict__ rec = res + 2 * uniform_u64(cd.res_base);
 
       uint64_t valid;
       if (f >= 12) valid = ~0ull;
@@ -546,19 +564,21 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
               __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
           if (k <= key_base + (uint64_t(blk) << 12)) break;
         }
-        const uint32_t H = blk;
+        const uint32_t H = blk & kHighMask;
         uint64_t acc = valid;
         uint32_t done = 0;
-        for (uint32_t c = 0; c < nres; c++) {
-          const uint4 r = tile[c];
-          const uint32_t z = uniform_u32(r.z);
-          const uint32_t w = uniform_u32(r.w);
-          if (((H & z) | (~H & w)) & kHighMask) continue;
-          const uint32_t mn = w >> 26, mm = (z >> 26) | mn;
-          const uint64_t low = (uint64_t(uniform_u32(r.y)) << 32) | uniform_u32(r.x);
-          acc &= ((lane ^ mn) & mm) ? ~0ull : low;
-          done++;
-          if ((done & 3) == 0 && !__any(acc != 0)) break;
+        // four clauses per step: their records are loaded together (the
+        // record region is padded so that reading past nres stays inside
+        // it), clauses past nres are masked out
+        for (uint32_t c = 0; c < nres; c += 4) {
+          const uint4 r0 = rec[2 * c], r1 = rec[2 * c + 1], r2 = rec[2 * c + 2], r3 = rec[2 * c + 3];
+          const uint4 r4 = rec[2 * c + 4], r5 = rec[2 * c + 5], r6 = rec[2 * c + 6], r7 = rec[2 * c + 7];
+          const uint32_t left = nres - c;
+          if (!((H & r1.x) | (~H & r1.y))) { acc = clause_and(acc, r0); done++; }
+          if (left > 1 && !((H & r3.x) | (~H & r3.y))) { acc = clause_and(acc, r2); done++; }
+          if (left > 2 && !((H & r5.x) | (~H & r5.y))) { acc = clause_and(acc, r4); done++; }
+          if (left > 3 && !((H & r7.x) | (~H & r7.y))) { acc = clause_and(acc, r6); done++; }
+          if (!__any(acc != 0)) break;
         }
         blocks++;
         evals += done;
@@ -583,7 +603,6 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
         atomicAdd((unsigned long long*)&out[it.cube].blocks, (unsigned long long)blocks);
         atomicAdd((unsigned long long*)&out[it.cube].clause_blocks, (unsigned long long)evals);
       }
-      __syncthreads();
     }
   }
 }
@@ -616,7 +635,7 @@ RoundLayout round_layout(size_t base, size_t n_cubes, size_t n_lits, size_t n_it
   l.items = align256(l.lits + n_lits * 4);
   l.outs = align256(l.items + n_items * sizeof(DevItem));
   l.res = align256(l.outs + n_cubes * sizeof(DevCubeOut));
-  l.end = align256(l.res + size_t(nres) * 16);
+  l.end = align256(l.res + (size_t(nres) + 4) * 32);   // + look-ahead of the leaf kernel
   return l;
 }
 
@@ -647,7 +666,7 @@ void dev_init(DeviceInfo* info, int device) {
       info->up_lds_max = want;
     else
       (void)hipGetLastError();
-    // the leaf kernel's residual tile (16 B per clause) likewise
+    // and the leaf kernel (no dynamic LDS at present; kept for larger tiles)
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
       info->leaf_lds_max = want;
@@ -762,9 +781,9 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   const uint32_t tw = nc <= uint32_t(info.cus) ? 4 : 1;
   const size_t team_bytes = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 + 2 * 64 * size_t(tw) * 4;
   const size_t up_lds = (kUpWaves / tw) * team_bytes + cnf.stage_bytes;
-  const size_t leaf_lds = size_t(std::max<uint32_t>(rh.tile_max, 1)) * 16;
+  const size_t leaf_lds = 0;   // the leaf kernel reads its records from memory
   if (up_lds > info.up_lds_max) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
-  if (leaf_lds > info.leaf_lds_max) fail(SCUBA_E_CAPACITY, "residual tile too large for LDS");
+
   for (const DevCubeDesc& c : rh.cubes) {
     if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + c.n_lits > rh.cube_lits.size() ||
         c.res_base + c.nres_cap > rh.res_records || c.nres_cap > rh.tile_max ||
