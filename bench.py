@@ -42,9 +42,12 @@ MEASURED_TRAFFIC = {
 }
 
 # learned ordering: candidates scored per decision node, and the levels
-# below a scored node that reuse its ranking (fewer device scoring passes)
+# below a scored node that reuse its ranking (fewer device scoring passes).
+# The access queries are shallow trees: one ranking per 16 levels serves
+# them; the random 3-SAT trees are deeper and are rescored every 4 levels.
 LEARNED_CANDIDATES = 16
 LEARNED_RESCORE = 4
+LEARNED_RESCORE_ACCESS = 16
 
 WORKLOADS = {
     2: ("config2: 256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, "
@@ -84,8 +87,8 @@ def measured_traffic(args):
     src = os.path.join(ROOT, "paper_2601_21552_amd", "csrc", "device.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    default = (args.config == 2 and args.k == 30 and args.leaves_per_round == 4
-               and args.chunk_log2 == 8)
+    default = (args.config == 2 and args.k == 30 and args.leaves_per_round == 1
+               and args.chunk_log2 == 12)
     if sha != MEASURED_TRAFFIC["device_hip_sha256_16"] or not default:
         return None
     return MEASURED_TRAFFIC
@@ -197,8 +200,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=30)
-    ap.add_argument("--leaves-per-round", type=int, default=4)
-    ap.add_argument("--chunk-log2", type=int, default=8)
+    ap.add_argument("--leaves-per-round", type=int, default=1)
+    ap.add_argument("--chunk-log2", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the word / learned forms")
     ap.add_argument("--no-gain", action="store_true", help="skip the learned-vs-static legs")
@@ -342,7 +345,7 @@ def main():
         log(f"access-query scorer trained: {scorer_info}")
     if not args.no_forms:
         for name, extra in (("word", dict(scorer="word")),
-                            ("learned", dict(learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE)))):
+                            ("learned", dict(learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)))):
             ms, _ = run_steps(extra)
             forms[name] = round(len(gens) / (ms / 1000.0), 3)
         log(f"forms (queries/s): {forms}")

@@ -1,12 +1,14 @@
 // Host thread pool for the per-query stages (bit-blasting, splitting and
 // witness checks are independent across queries).  The workers live for
-// the whole process and sleep between jobs, so a call costs a wake-up, not
-// a thread start.
+// the whole process.  After a job they spin briefly on the job counter
+// before they sleep, so the back-to-back parallel stages of one call (split,
+// walk, witness checks) start without a wake-up each.
 #pragma once
 #include <sched.h>
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <condition_variable>
 #include <cstdlib>
 #include <exception>
@@ -31,6 +33,8 @@ inline unsigned host_threads() {
   return std::max(1u, std::min(n ? n : 1u, 64u));
 }
 
+inline void cpu_relax() { __builtin_ia32_pause(); }
+
 class HostPool {
  public:
   static HostPool& get() {
@@ -46,29 +50,38 @@ class HostPool {
       return;
     }
     std::unique_lock<std::mutex> call(call_mu_);   // one job at a time
+    // the job's fields are published by the release store of gen_, which
+    // also carries the number of workers that take part
+    job_ = &fn;
+    n_ = n;
+    next_.store(0, std::memory_order_relaxed);
+    err_ = nullptr;
+    const uint64_t parts = std::min<size_t>(workers_.size(), n - 1);   // < 2^16 workers
+    remaining_.store(unsigned(parts), std::memory_order_relaxed);
+    seq_++;
+    gen_.store((seq_ << 16) | parts, std::memory_order_release);
     {
+      // a worker that checked gen_ before the increment is either still
+      // spinning (and sees it) or waits on cv_ (and gets the notify)
       std::lock_guard<std::mutex> g(mu_);
-      job_ = &fn;
-      n_ = n;
-      next_.store(0);
-      err_ = nullptr;
-      participants_ = unsigned(std::min<size_t>(workers_.size(), n - 1));
-      remaining_ = participants_;
-      gen_++;
     }
     cv_.notify_all();
     work();
-    std::unique_lock<std::mutex> g(mu_);
-    done_cv_.wait(g, [&] { return remaining_ == 0; });
+    // the caller's share is done: the workers hold at most one item each
+    for (uint32_t spins = 0; remaining_.load(std::memory_order_acquire) != 0; spins++) {
+      if (spins < 4096) cpu_relax();
+      else std::this_thread::yield();
+    }
     job_ = nullptr;
     if (err_) std::rethrow_exception(err_);
   }
 
   ~HostPool() {
+    stop_.store(true);
+    seq_++;
+    gen_.store(seq_ << 16, std::memory_order_release);
     {
       std::lock_guard<std::mutex> g(mu_);
-      stop_ = true;
-      gen_++;
     }
     cv_.notify_all();
     for (auto& t : workers_) t.join();
@@ -82,7 +95,7 @@ class HostPool {
   void work() {
     in_job_ = true;
     for (;;) {
-      size_t i = next_.fetch_add(1);
+      size_t i = next_.fetch_add(1, std::memory_order_relaxed);
       if (i >= n_) break;
       try {
         (*job_)(i);
@@ -95,33 +108,48 @@ class HostPool {
     in_job_ = false;
   }
 
+  // Waits for a generation other than `seen`: spins for about kSpinUs
+  // microseconds, then sleeps on cv_.
+  uint64_t wait_job(uint64_t seen) {
+    using Clock = std::chrono::steady_clock;
+    const auto until = Clock::now() + std::chrono::microseconds(kSpinUs);
+    for (uint32_t spins = 0;; spins++) {
+      uint64_t g = gen_.load(std::memory_order_acquire);
+      if (g != seen) return g;
+      cpu_relax();
+      if ((spins & 255) == 255 && Clock::now() > until) break;
+    }
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+    return gen_.load(std::memory_order_acquire);
+  }
+
   void loop(unsigned id) {
     uint64_t seen = 0;
     for (;;) {
-      {
-        std::unique_lock<std::mutex> g(mu_);
-        cv_.wait(g, [&] { return stop_ || gen_ != seen; });
-        if (stop_) return;
-        seen = gen_;
-        // only the first `participants_` workers of a job take part
-        if (id > participants_) continue;
-      }
+      seen = wait_job(seen);
+      if (stop_.load()) return;
+      // only the first workers of a job take part (the count is read from
+      // the same word as the job's generation, so a worker never joins a
+      // job it was not counted in)
+      if (id > (seen & 0xffff)) continue;
       work();
-      std::lock_guard<std::mutex> g(mu_);
-      if (--remaining_ == 0) done_cv_.notify_all();
+      remaining_.fetch_sub(1, std::memory_order_acq_rel);
     }
   }
 
+  static constexpr int kSpinUs = 300;
   std::vector<std::thread> workers_;
   std::mutex mu_, call_mu_;
-  std::condition_variable cv_, done_cv_;
+  std::condition_variable cv_;
   const std::function<void(size_t)>* job_ = nullptr;
   size_t n_ = 0;
   std::atomic<size_t> next_{0};
   std::exception_ptr err_;
-  unsigned participants_ = 0, remaining_ = 0;
-  uint64_t gen_ = 0;
-  bool stop_ = false;
+  uint64_t seq_ = 0;   // written under call_mu_ (and by the destructor)
+  std::atomic<unsigned> remaining_{0};
+  std::atomic<uint64_t> gen_{0};
+  std::atomic<bool> stop_{false};
   static thread_local bool in_job_;
 };
 
