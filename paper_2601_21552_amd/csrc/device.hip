@@ -110,12 +110,15 @@ __device__ __forceinline__ bool clause_satisfied(const Cnf& cnf, uint32_t c, con
 // Per-team state of the propagation kernel (one cube per team).
 struct UpShared {
   uint32_t conflict, error;
-  // per round parity: frontier length, overflow, something newly set
-  uint32_t qn[2], ovf[2], chg[2];
+  // frontier length, overflow and "something newly set" of round r in set
+  // r % 3: a set is read in the round after it is written and cleared in
+  // the round after that, so one barrier per round separates all three
+  uint32_t qn[3], ovf[3], chg[3];
   uint32_t scan[2][kBlock / 64];   // alternating, so one barrier per scan
 };
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kStageUnroll = 8;   // CNF staging: loads in flight per thread
 static_assert(kUpWaves == kBlock / 64, "a workgroup holds kUpWaves waves");
 
 // Makes LDS writes of the wave visible to all its lanes, and keeps the
@@ -126,16 +129,25 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// exclusive scan of one value per lane over the wave
+// exclusive scan of one value per lane over the wave: inclusive scans of
+// the four 16-lane rows by DPP row shifts, then the row totals (read into
+// scalar registers) added to the rows above them
 __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t* total) {
   const uint32_t lane = threadIdx.x & 63;
-  uint32_t x = v;
-  for (uint32_t d = 1; d < 64; d <<= 1) {
-    const uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  *total = uniform_u32(__shfl(x, 63, 64));
-  return x - v;
+  int x = int(v);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+  const uint32_t r0 = uint32_t(__builtin_amdgcn_readlane(x, 15)), r1 = uint32_t(__builtin_amdgcn_readlane(x, 31)),
+                 r2 = uint32_t(__builtin_amdgcn_readlane(x, 47)), r3 = uint32_t(__builtin_amdgcn_readlane(x, 63));
+  const uint32_t row = lane >> 4;
+  uint32_t y = uint32_t(x);
+  if (row >= 1) y += r0;
+  if (row >= 2) y += r1;
+  if (row >= 3) y += r2;
+  *total = r0 + r1 + r2 + r3;
+  return y - v;
 }
 
 // The threads that propagate one cube: one wave (TW = 1, four cubes per
@@ -155,15 +167,12 @@ struct Team {
   __device__ __forceinline__ uint32_t scan(uint32_t v, uint32_t* total) {
     if (TW == 1) return wave_exclusive_scan(v, total);
     const uint32_t l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t x = v;
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-      const uint32_t y = __shfl_up(x, d, 64);
-      if (l >= d) x += y;
-    }
+    uint32_t wtot;
+    const uint32_t x = wave_exclusive_scan(v, &wtot) + v;   // inclusive within the wave
     // consecutive scans alternate buffers: a thread writing scan i+1 has
     // passed scan i's barrier, and every thread reads scan i-1's buffer
     // before it reaches that barrier, so one barrier per scan suffices
-    if (l == 63) sh.scan[par][wv] = x;
+    if (l == 63) sh.scan[par][wv] = wtot;
     __syncthreads();
     uint32_t base = 0, tot = 0;
     for (uint32_t w = 0; w < uint32_t(TW); w++) {
@@ -202,14 +211,41 @@ __device__ __forceinline__ uint32_t visit_clause(const Cnf& cnf, uint32_t c, uin
   bool sat = false;
   uint32_t open = 0, last_v = 0;
   bool last_neg = false;
-  for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
-    uint32_t v;
-    bool neg;
-    cnf.lit(i, &v, &neg);
-    const uint32_t bit = 1u << (v & 31);
-    const uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
-    if (neg ? f : t) { sat = true; break; }
-    if (!(t | f)) { open++; last_v = v; last_neg = neg; }
+  const uint32_t b = cnf.beg(c), e = cnf.end(c);
+  if (e - b <= 4) {
+    // short clauses (the gate clauses): the literals, then their
+    // assignment words, are loaded independently of each other
+    uint32_t v[4], t[4], f[4];
+    bool neg[4];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; u++) {
+      v[u] = 0;
+      neg[u] = false;
+      if (b + u < e) cnf.lit(b + u, &v[u], &neg[u]);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 4; u++) {
+      t[u] = b + u < e ? T[v[u] >> 5] : 0u;
+      f[u] = b + u < e ? F[v[u] >> 5] : 0u;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 4; u++) {
+      if (b + u >= e) break;
+      const uint32_t bit = 1u << (v[u] & 31);
+      const uint32_t tu = t[u] & bit, fu = f[u] & bit;
+      if (neg[u] ? fu : tu) sat = true;
+      if (!(tu | fu)) { open++; last_v = v[u]; last_neg = neg[u]; }
+    }
+  } else {
+    for (uint32_t i = b; i < e; i++) {
+      uint32_t v;
+      bool neg;
+      cnf.lit(i, &v, &neg);
+      const uint32_t bit = 1u << (v & 31);
+      const uint32_t t = T[v >> 5] & bit, f = F[v >> 5] & bit;
+      if (neg ? f : t) { sat = true; break; }
+      if (!(t | f)) { open++; last_v = v; last_neg = neg; }
+    }
   }
   if (sat) return kNone;
   if (open == 0) {
@@ -227,9 +263,18 @@ __device__ __forceinline__ uint32_t visit_clause(const Cnf& cnf, uint32_t c, uin
 
 // Queue a new assignment for the next round (an overflow makes that round
 // scan every clause).
+// The active lanes of a wave that have an entry take consecutive slots with
+// one atomic per wave (ranked by the ballot of the lanes that push).
 __device__ __forceinline__ void push(uint32_t e, uint32_t* next, uint32_t cap, uint32_t w, UpShared& sh) {
+  const uint64_t m = __ballot(e != kNone);
+  if (!m) return;
+  const uint32_t leader = uint32_t(__builtin_ctzll(m));
+  uint32_t base = 0;
+  if ((threadIdx.x & 63) == leader) base = atomicAdd(&sh.qn[w], uint32_t(__popcll(m)));
+  base = uint32_t(__builtin_amdgcn_readlane(int(base), int(leader)));
   if (e == kNone) return;
-  const uint32_t slot = atomicAdd(&sh.qn[w], 1u);
+  const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+  const uint32_t slot = base + rank;
   if (slot < cap) next[slot] = e;
   else sh.ovf[w] = 1;
 }
@@ -247,41 +292,66 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   const uint32_t lane = tm.lane();
   const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
   for (uint32_t w = lane; w < nw; w += S) { T[w] = 0; F[w] = 0; A[w] = 0; }
-  if (lane == 0) { sh.conflict = 0; sh.error = 0; sh.qn[1] = 0; sh.ovf[1] = 0; sh.chg[1] = 0; }
-  tm.sync();
-  for (uint32_t j = lane; j < cd.n_lits; j += S) {
-    int32_t l = cube_lits[cd.lit_off + j];
-    uint32_t v = uint32_t(l > 0 ? l : -l);
-    if (v == 0 || v > nv) { sh.error = 1; continue; }
-    atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], 1u << (v & 31));
+  if (lane == 0) {
+    sh.conflict = 0;
+    sh.error = 0;
+    for (uint32_t k = 0; k < 3; k++) { sh.qn[k] = 0; sh.ovf[k] = 0; sh.chg[k] = 0; }
   }
   tm.sync();
 
-  // ---- propagation rounds.  Round 0 scans every clause; later rounds visit
-  // only the clauses of the literals that the previous round made false
-  // (the frontier), unless that frontier overflowed its queue, in which
-  // case the round scans every clause again.  A round that sets nothing
-  // new ends at the fixpoint: every clause has been visited after its last
-  // false literal was assigned.  Every changing round sets a new bit, so at
-  // most 2*(nv+1) rounds change something.
+  // ---- the first frontier: every literal that holds before propagation
+  // (the cube's literals and the unit clauses), as if a round -1 had set
+  // them (queue 1, counter set 2).  An empty clause is a conflict.
+  {
+    uint32_t* seed = Q + QC;
+    for (uint32_t j = lane; j < cd.n_lits; j += S) {
+      const int32_t l = cube_lits[cd.lit_off + j];
+      const uint32_t v = uint32_t(l > 0 ? l : -l);
+      if (v == 0 || v > nv) { sh.error = 1; continue; }
+      const uint32_t bit = 1u << (v & 31);
+      const uint32_t old = atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], bit);
+      if (!(old & bit)) push((v << 1) | (l > 0 ? 1u : 0u), seed, QC, 2, sh);
+    }
+    for (uint32_t c = lane; c < nc; c += S) {
+      const uint32_t b = cnf.beg(c), e = cnf.end(c);
+      if (e == b) { sh.conflict = 1; continue; }
+      if (e - b != 1) continue;
+      uint32_t v;
+      bool neg;
+      cnf.lit(b, &v, &neg);
+      const uint32_t bit = 1u << (v & 31);
+      const uint32_t old = atomicOr(neg ? &F[v >> 5] : &T[v >> 5], bit);
+      if (!(old & bit)) push((v << 1) | (neg ? 0u : 1u), seed, QC, 2, sh);
+    }
+  }
+  tm.sync();
+
+  // ---- propagation rounds.  Round r visits the clauses of the literals
+  // that round r-1 made false (its frontier); when that frontier overflowed
+  // its queue, round r scans every clause instead.  A round that sets
+  // nothing new ends at the fixpoint: every clause has been visited after
+  // its last false literal was assigned.  Every changing round sets a new
+  // bit, so at most 2*(nv+1) rounds change something.  Each wave takes
+  // every TW-th frontier entry and spreads the (entry, occurrence) pairs of
+  // up to 64 entries at a time over its lanes: a wave scan of the
+  // occurrence counts gives each entry's first pair, and a lane finds the
+  // entry of its pair by binary search over those offsets (Xw[0..63] in
+  // LDS) and the occurrence list starts (Xw[64..127]).  The only team-wide
+  // barrier of a round is at its end.
+  const uint32_t wl = threadIdx.x & 63, wv = TW == 1 ? 0u : uniform_u32(lane >> 6);
+  uint32_t* Xw = X + wv * 128;
   const uint32_t max_rounds = 2 * nv + 4;
   for (uint32_t r = 0;; r++) {
-    const uint32_t w = r & 1, pw = w ^ 1;
-    if (lane == 0) { sh.qn[w] = 0; sh.ovf[w] = 0; sh.chg[w] = 0; }
-    tm.sync();
-    uint32_t* next = Q + w * QC;
-    if (r == 0 || sh.ovf[pw]) {
-      for (uint32_t c = lane; c < nc; c += S) push(visit_clause(cnf, c, T, F, w, sh), next, QC, w, sh);
+    const uint32_t k = r % 3, kp = (r + 2) % 3, kn = (r + 1) % 3;
+    const uint32_t* cur = Q + ((r + 1) & 1) * QC;
+    uint32_t* next = Q + (r & 1) * QC;
+    if (lane == 0) { sh.qn[kn] = 0; sh.ovf[kn] = 0; sh.chg[kn] = 0; }
+    if (uniform_u32(sh.ovf[kp])) {
+      for (uint32_t c = lane; c < nc; c += S) push(visit_clause(cnf, c, T, F, k, sh), next, QC, k, sh);
     } else {
-      // the (entry, occurrence) pairs of up to S frontier entries at a
-      // time are spread over the team: a scan of the occurrence counts
-      // gives each entry's first pair; a thread finds the entry of its pair
-      // by binary search over those offsets (X[0..S-1] in LDS) and the
-      // occurrence list start (X[S..2S-1])
-      const uint32_t* cur = Q + pw * QC;
-      const uint32_t n = min(uniform_u32(sh.qn[pw]), QC);
-      for (uint32_t base = 0; base < n; base += S) {
-        const uint32_t j = base + lane;
+      const uint32_t n = min(uniform_u32(sh.qn[kp]), QC);
+      for (uint32_t base = 0; wv + TW * base < n; base += 64) {
+        const uint32_t j = wv + TW * (base + wl);
         uint32_t cnt = 0, start = 0;
         if (j < n) {
           const uint32_t e = cur[j];
@@ -297,25 +367,26 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
           }
         }
         uint32_t total;
-        const uint32_t off = tm.scan(cnt, &total);
-        X[lane] = off;
-        X[S + lane] = start;
-        tm.sync();
-        const uint32_t m = min(S, n - base);
-        for (uint32_t k = lane; k < total; k += S) {
-          uint32_t lo = 0, hi = m;   // X[lo] <= k < X[hi] (X[m] = total)
+        const uint32_t off = wave_exclusive_scan(cnt, &total);
+        Xw[wl] = off;
+        Xw[64 + wl] = start;
+        wave_sync();
+        const uint32_t rem = n - (wv + TW * base);
+        const uint32_t m = min(64u, (rem + TW - 1) / TW);
+        for (uint32_t q = wl; q < total; q += 64) {
+          uint32_t lo = 0, hi = m;   // Xw[lo] <= q < Xw[hi] (Xw[m] = total)
           while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (X[mid] <= k) lo = mid;
+            if (Xw[mid] <= q) lo = mid;
             else hi = mid;
           }
-          push(visit_clause(cnf, occ.at(X[S + lo] + (k - X[lo])), T, F, w, sh), next, QC, w, sh);
+          push(visit_clause(cnf, occ.at(Xw[64 + lo] + (q - Xw[lo])), T, F, k, sh), next, QC, k, sh);
         }
-        tm.sync();   // X is rewritten by the next entries
+        wave_sync();   // Xw is rewritten by the next entries
       }
     }
     tm.sync();
-    const uint32_t changed = uniform_u32(sh.chg[w]), conflict = uniform_u32(sh.conflict);
+    const uint32_t changed = uniform_u32(sh.chg[k]), conflict = uniform_u32(sh.conflict);
     if (conflict || !changed) break;
     if (r >= max_rounds) {   // cannot happen: every changing round sets a new bit
       if (lane == 0) sh.error = 1;
@@ -459,13 +530,51 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
       uint16_t* sl = sco + q.n_clauses + 1;
       uint16_t* soo = sl + nl;
       uint16_t* soc = soo + nli + 1;
-      for (uint32_t c = tid; c <= q.n_clauses; c += kBlock) sco[c] = uint16_t(co[c]);
-      for (uint32_t i = tid; i < nl; i += kBlock) {
-        const int32_t l = L[i];
-        sl[i] = uint16_t((uint32_t(l > 0 ? l : -l) << 1) | (l < 0 ? 1u : 0u));
-        soc[i] = uint16_t(oc[i]);
+      // kStageUnroll loads in flight per thread and array
+      for (uint32_t b = tid; b <= q.n_clauses; b += kStageUnroll * kBlock) {
+        uint32_t x[kStageUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kStageUnroll; u++) {
+          const uint32_t c = b + u * kBlock;
+          x[u] = c <= q.n_clauses ? co[c] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kStageUnroll; u++) {
+          const uint32_t c = b + u * kBlock;
+          if (c <= q.n_clauses) sco[c] = uint16_t(x[u]);
+        }
       }
-      for (uint32_t i = tid; i <= nli; i += kBlock) soo[i] = uint16_t(oo[i]);
+      for (uint32_t b = tid; b < nl; b += kStageUnroll * kBlock) {
+        int32_t x[kStageUnroll];
+        uint32_t y[kStageUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kStageUnroll; u++) {
+          const uint32_t i = b + u * kBlock;
+          x[u] = i < nl ? L[i] : 0;
+          y[u] = i < nl ? oc[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kStageUnroll; u++) {
+          const uint32_t i = b + u * kBlock;
+          if (i < nl) {
+            sl[i] = uint16_t((uint32_t(x[u] > 0 ? x[u] : -x[u]) << 1) | (x[u] < 0 ? 1u : 0u));
+            soc[i] = uint16_t(y[u]);
+          }
+        }
+      }
+      for (uint32_t b = tid; b <= nli; b += kStageUnroll * kBlock) {
+        uint32_t x[kStageUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kStageUnroll; u++) {
+          const uint32_t i = b + u * kBlock;
+          x[u] = i <= nli ? oo[i] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kStageUnroll; u++) {
+          const uint32_t i = b + u * kBlock;
+          if (i <= nli) soo[i] = uint16_t(x[u]);
+        }
+      }
       __syncthreads();
       if (team < g.y) {
         const uint32_t ci = g.x + team;
