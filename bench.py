@@ -36,9 +36,9 @@ OPS_PER_CLAUSE_BLOCK = 128
 # read for a device copy of known size), valid only for the kernel source
 # they were taken on
 MEASURED_TRAFFIC = {
-    "device_hip_sha256_16": "0ef177e263fd1fef",
-    "up_kernel": 14_575_352,
-    "leaf_kernel": 11_259_814,
+    "device_hip_sha256_16": "4ce10ac2fe4f47cb",
+    "up_kernel": 14_454_067,
+    "leaf_kernel": 2_928_640,
 }
 
 # learned ordering: candidates scored per decision node, and the levels

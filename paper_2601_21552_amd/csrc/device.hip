@@ -26,11 +26,13 @@
 // in.  A block dies when every lane's word is 0.
 // DECIDE takes the smallest (cube, index) witness per query with atomicMin
 // and lets later work of that query stop early; COUNT sums popcounts.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstring>
 #include <list>
 #include <map>
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -871,6 +873,30 @@ void dev_graphs_destroy(DevGraphs* g) {
   delete g;
 }
 
+// One copy stream per device for the eager rounds' uploads (created on
+// first use, kept for the process; default priority).
+hipStream_t copy_stream(int device) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = streams.find(device);
+  if (it != streams.end()) return it->second;
+  hipStream_t cs;
+  HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  streams.emplace(device, cs);
+  return cs;
+}
+
+// A kernel launch; with events, the events bracket the dispatch itself (so
+// their interval is the kernel's execution), else a plain launch (the form
+// that stream capture records).
+template <typename K, typename... Args>
+void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t q, hipEvent_t start, hipEvent_t stop,
+            Args... args) {
+  if (start) hipExtLaunchKernelGGL(kernel, grid, block, uint32_t(lds), q, start, stop, 0u, args...);
+  else hipLaunchKernelGGL(kernel, grid, block, lds, q, args...);
+}
+
 void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
                uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
                std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys, RoundTimes* times,
@@ -929,53 +955,68 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   const uint32_t gl = ni ? std::min<uint32_t>(g, uint32_t(ni)) : 0;
   // the whole round as one stream sequence: upload (the zeroed head and the
   // initial outputs included, so no memset), kernels, download
+  // eager rounds time the two kernels with events that bracket their
+  // dispatches (ev[2..3] and ev[4..5]); ev[0..1] and ev[6..7] bracket the
+  // copies
+  // The eager form uploads on the device's copy stream (ordered after the
+  // caller's work by ev[8]) and makes q wait for it, so that the upload's
+  // completion is not inside the first kernel's events.
   auto enqueue = [&](hipStream_t q, hipEvent_t* ev) {
-    if (ev) HIP_OK(hipEventRecord(ev[0], q));
-    HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
-    if (ev) HIP_OK(hipEventRecord(ev[1], q));
+    if (ev) {
+      hipStream_t cs = copy_stream(info.device);
+      HIP_OK(hipEventRecord(ev[8], q));
+      HIP_OK(hipStreamWaitEvent(cs, ev[8], 0));
+      HIP_OK(hipEventRecord(ev[0], cs));
+      HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, cs));
+      HIP_OK(hipEventRecord(ev[1], cs));
+      HIP_OK(hipStreamWaitEvent(q, ev[1], 0));
+    } else {
+      HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
+    }
     if (gu) {
-      hipLaunchKernelGGL(tw == 4 ? up_kernel<4> : up_kernel<1>, dim3(gu), dim3(kBlock), up_lds, q,
-                         reinterpret_cast<const DevQueryDesc*>(w + cl.q),
-                         reinterpret_cast<const uint32_t*>(w + cl.coff),
-                         reinterpret_cast<const int32_t*>(w + cl.lits),
-                         reinterpret_cast<const uint32_t*>(w + cl.occ_off),
-                         reinterpret_cast<const uint32_t*>(w + cl.occ),
-                         reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
-                         reinterpret_cast<const int32_t*>(w + rl.lits),
-                         reinterpret_cast<const uint2*>(w + rl.groups), n_groups,
-                         reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
-                         reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
+      launch(tw == 4 ? up_kernel<4> : up_kernel<1>, dim3(gu), dim3(kBlock), up_lds, q,
+                            ev ? ev[2] : nullptr, ev ? ev[3] : nullptr,
+                            reinterpret_cast<const DevQueryDesc*>(w + cl.q),
+                            reinterpret_cast<const uint32_t*>(w + cl.coff),
+                            reinterpret_cast<const int32_t*>(w + cl.lits),
+                            reinterpret_cast<const uint32_t*>(w + cl.occ_off),
+                            reinterpret_cast<const uint32_t*>(w + cl.occ),
+                            reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
+                            reinterpret_cast<const int32_t*>(w + rl.lits),
+                            reinterpret_cast<const uint2*>(w + rl.groups), n_groups,
+                            reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
+                            reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
       HIP_OK(hipGetLastError());
     }
-    if (ev) HIP_OK(hipEventRecord(ev[2], q));
     if (gl) {
-      hipLaunchKernelGGL(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, q,
-                         reinterpret_cast<const DevItem*>(w + rl.items), uint32_t(ni),
-                         reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
-                         reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
-                         reinterpret_cast<unsigned long long*>(w + cl.qkey),
-                         reinterpret_cast<uint32_t*>(w + rl.head), mode);
+      launch(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, q, ev ? ev[4] : nullptr,
+                            ev ? ev[5] : nullptr,
+                            reinterpret_cast<const DevItem*>(w + rl.items), uint32_t(ni),
+                            reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
+                            reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
+                            reinterpret_cast<unsigned long long*>(w + cl.qkey),
+                            reinterpret_cast<uint32_t*>(w + rl.head), mode);
       HIP_OK(hipGetLastError());
     }
-    if (ev) HIP_OK(hipEventRecord(ev[3], q));
+    if (ev) HIP_OK(hipEventRecord(ev[6], q));
     HIP_OK(hipMemcpyAsync(s, w + rl.outs, nc * sizeof(DevCubeOut), hipMemcpyDeviceToHost, q));
     HIP_OK(hipMemcpyAsync(s + align256(nc * sizeof(DevCubeOut)), w + cl.qkey, cnf.q.size() * 8,
                           hipMemcpyDeviceToHost, q));
-    if (ev) HIP_OK(hipEventRecord(ev[4], q));
+    if (ev) HIP_OK(hipEventRecord(ev[7], q));
   };
 
   times->cubes += nc;
   times->items += ni;
-  hipEvent_t ev[5];
+  hipEvent_t ev[9];
   for (auto& e : ev) HIP_OK(hipEventCreate(&e));
   if (!graphs) {
     enqueue(st, ev);
     HIP_OK(hipStreamSynchronize(st));
     float ms;
     HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1])); times->h2d_ms += ms;
-    HIP_OK(hipEventElapsedTime(&ms, ev[1], ev[2])); times->up_ms += ms;
-    HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->leaf_ms += ms;
-    HIP_OK(hipEventElapsedTime(&ms, ev[3], ev[4])); times->d2h_ms += ms;
+    if (gu) { HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->up_ms += ms; }
+    if (gl) { HIP_OK(hipEventElapsedTime(&ms, ev[4], ev[5])); times->leaf_ms += ms; }
+    HIP_OK(hipEventElapsedTime(&ms, ev[6], ev[7])); times->d2h_ms += ms;
     times->up_launches += gu != 0;
     times->leaf_launches += gl != 0;
   } else {
