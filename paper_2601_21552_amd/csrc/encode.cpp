@@ -124,6 +124,13 @@ class Gates {
     }
     q_.off.push_back(q_.lits.size());
   }
+  // Appends a clause that is known to hold no constant, no repeated variable
+  // and no complementary pair (the gate definitions below, after their
+  // special cases).
+  void gate_clause(std::initializer_list<int32_t> ls) {
+    for (int32_t l : ls) q_.lits.push_back(l);
+    q_.off.push_back(q_.lits.size());
+  }
 
   int32_t AND(int32_t a, int32_t b) {
     if (a == kFalse || b == kFalse || a == -b) return kFalse;
@@ -133,9 +140,9 @@ class Gates {
     GateKey k{1, a, b, 0};
     if (const int32_t* hit = cache_.find(k)) return *hit;
     int32_t o = fresh();
-    clause({-o, a});
-    clause({-o, b});
-    clause({o, -a, -b});
+    gate_clause({-o, a});
+    gate_clause({-o, b});
+    gate_clause({o, -a, -b});
     cache_.insert(k, o);
     return o;
   }
@@ -159,10 +166,10 @@ class Gates {
       if (const int32_t* hit = cache_.find(k)) r = *hit;
       else {
         int32_t o = fresh();
-        clause({-o, a, b});
-        clause({-o, -a, -b});
-        clause({o, -a, b});
-        clause({o, a, -b});
+        gate_clause({-o, a, b});
+        gate_clause({-o, -a, -b});
+        gate_clause({o, -a, b});
+        gate_clause({o, a, -b});
         cache_.insert(k, o);
         r = o;
       }
@@ -200,7 +207,7 @@ class Gates {
         for (int m = 0; m < 8; m++) {
           int va = m & 1, vb = (m >> 1) & 1, vc = (m >> 2) & 1;
           int p = va ^ vb ^ vc;
-          clause({va ? -ys[0] : ys[0], vb ? -ys[1] : ys[1], vc ? -ys[2] : ys[2], p ? o : -o});
+          gate_clause({va ? -ys[0] : ys[0], vb ? -ys[1] : ys[1], vc ? -ys[2] : ys[2], p ? o : -o});
         }
         cache_.insert(k, o);
         r = o;
@@ -234,12 +241,12 @@ class Gates {
     if (const int32_t* hit = cache_.find(k)) r = *hit;
     else {
       int32_t o = fresh();
-      clause({-s[0], -s[1], o});
-      clause({-s[0], -s[2], o});
-      clause({-s[1], -s[2], o});
-      clause({s[0], s[1], -o});
-      clause({s[0], s[2], -o});
-      clause({s[1], s[2], -o});
+      gate_clause({-s[0], -s[1], o});
+      gate_clause({-s[0], -s[2], o});
+      gate_clause({-s[1], -s[2], o});
+      gate_clause({s[0], s[1], -o});
+      gate_clause({s[0], s[2], -o});
+      gate_clause({s[1], s[2], -o});
       cache_.insert(k, o);
       r = o;
     }
