@@ -153,9 +153,13 @@ Opts resolve(const scuba_solve_opts* o) {
 // Device image of the CNF batch.  A query whose CNF fits the LDS left over
 // by the propagation kernel's bitmaps (16-bit literals and offsets) is
 // marked for staging; lds_limit = 0 disables staging.
-CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
+// Device descriptors of a CNF batch.  With skip_root_unsat, the queries
+// decided at the root get empty descriptors and are not uploaded (DECIDE
+// sends them no cube).
+CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0, bool skip_root_unsat = false) {
   CnfHost h;
   h.src = cnf;
+  h.skip_root_unsat = skip_root_unsat;
   uint32_t nw_all = 0;
   for (const CnfQuery& q : cnf->q) nw_all = std::max(nw_all, (q.n_vars >> 5) + 1);
   // per wave: four bitmaps, two frontier queues and 128 words of scan space
@@ -167,6 +171,10 @@ CnfHost cnf_host(const scuba_cnf* cnf, size_t lds_limit = 0) {
     d.lit_base = h.n_lits;
     d.occ_off_base = h.n_occ_off;
     d.occ_base = h.n_occ;
+    if (skip_root_unsat && q.root_unsat) {
+      h.q.push_back(d);
+      continue;
+    }
     if (q.n_clauses() >= (uint64_t(1) << 32) || q.lits.size() >= (uint64_t(1) << 32))
       fail(SCUBA_E_CAPACITY, "query with 2^32 or more clauses or literals");
     d.n_clauses = uint32_t(q.n_clauses());
@@ -281,14 +289,22 @@ size_t round_bound(const scuba_cnf* cnf, size_t n_cubes, const Opts& o, uint32_t
   return dev_round_bytes(n_cubes, lits, n_cubes * per, uint64_t(n_cubes) * max_res);
 }
 
-// Model of a SAT leaf: propagation of the cube, slot j = bit j of `a`,
-// remaining unassigned variables 0.  Then the checks of the result stage.
-void assemble_witness(const CnfQuery& q, Splitter& sp, const std::vector<int32_t>& cube, uint64_t a,
-                      scuba_results::Q& out) {
+// Model of a SAT leaf: the leaf's fixpoint (kept by the splitter, else the
+// propagation of the cube again), slot j = bit j of `a`, remaining
+// unassigned variables 0.  Then the checks of the result stage: every clause
+// and the exact integer query.
+void assemble_witness(const CnfQuery& q, Splitter& sp, const Cube& cube, uint64_t a, scuba_results::Q& out) {
   std::vector<int8_t> assign;
   std::vector<int32_t> active;
-  uint32_t nres = 0;
-  if (!sp.leaf_of(cube, &assign, &active, &nres)) fail(SCUBA_E_INTERNAL, "witness cube conflicts on the host");
+  if (!cube.assign.empty()) {   // the leaf's fixpoint, kept by the splitter
+    assign = cube.assign;
+    active = cube.active;
+  } else {
+    uint32_t nres = 0;
+    if (!sp.leaf_of(cube.lits, &assign, &active, &nres)) fail(SCUBA_E_INTERNAL, "witness cube conflicts on the host");
+  }
+  if (active.size() > 64 || assign.size() != size_t(q.n_vars) + 1)
+    fail(SCUBA_E_INTERNAL, "leaf state does not match the query");
   for (size_t j = 0; j < active.size(); j++) assign[active[j]] = int8_t((a >> j) & 1);
   out.model.assign(size_t(q.n_vars) + 1, 0);
   for (uint32_t v = 1; v <= q.n_vars; v++) out.model[v] = assign[v] > 0 ? 1 : 0;
@@ -519,6 +535,7 @@ scuba_status scuba_cnf_from_arrays(scuba_ctx* ctx, uint32_t nq, const uint32_t* 
         }
         q.off.push_back(q.lits.size());
       }
+      q.build_occurrences();
       cnf->q.push_back(std::move(q));
     }
     *out = cnf.release();
@@ -762,7 +779,7 @@ scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const 
   if (!ctx || !cnf || !bytes) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     Opts o = resolve(opts);
-    CnfHost h = cnf_host(cnf);
+    CnfHost h = cnf_host(cnf, 0, true);
     *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, o.max_res);
     if (o.scorer == SCUBA_SCORER_LEARNED)
       *bytes += scorer_bytes(scorer_rows(cnf, o.learned->candidates)) + 256;
@@ -834,7 +851,9 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
         const auto& cq = cubes->q[qi];
         std::vector<int32_t> lits(cq.lits.begin() + cq.off[sat_cube], cq.lits.begin() + cq.off[sat_cube + 1]);
         Splitter sp(cnf->q[qi], 0, 0, 1);
-        assemble_witness(cnf->q[qi], sp, lits, uint64_t(rq.leaves[sat_cube].first), rq);
+        Cube cb;
+        cb.lits = std::move(lits);
+        assemble_witness(cnf->q[qi], sp, cb, uint64_t(rq.leaves[sat_cube].first), rq);
       } else {
         rq.r.verdict = cubes->q[qi].complete ? SCUBA_UNSAT : SCUBA_UNKNOWN;
         if (cnf->q[qi].root_unsat) { rq.r.verdict = SCUBA_UNSAT; rq.r.how = SCUBA_HOW_ROOT; }
@@ -866,7 +885,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     if (o.mode != SCUBA_MODE_DECIDE) fail(SCUBA_E_INVALID, "scuba_decide runs in DECIDE mode");
     ctx->ensure_device();
     const size_t nq = cnf->q.size();
-    CnfHost h = cnf_host(cnf, up_lds_limit(ctx));
+    CnfHost h = cnf_host(cnf, up_lds_limit(ctx), true);
     auto res = std::make_unique<scuba_results>();
     res->q.resize(nq);
     std::vector<std::unique_ptr<Splitter>> sp(nq);
@@ -887,6 +906,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     parallel_for(nq, [&](size_t qi) {
       if (!open[qi]) return;
       sp[qi] = std::make_unique<Splitter>(cnf->q[qi], o.k, o.max_res, o.max_cubes);
+      sp[qi]->set_keep_leaf_state();   // witnesses are built from the leaf's fixpoint
       if (learned) sp[qi]->set_learned(o.learned->candidates, o.learned->rescore);
       if (o.scorer == SCUBA_SCORER_WORD) sp[qi]->set_word_order();
     });
@@ -990,7 +1010,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
         auto& rq = res->q[qi];
         rq.r.verdict = SCUBA_SAT;
         rq.r.how = SCUBA_HOW_DEVICE;
-        assemble_witness(cnf->q[qi], *sp[qi], cube->lits, a, rq);   // ends this query's walk
+        assemble_witness(cnf->q[qi], *sp[qi], *cube, a, rq);
       });
       for (uint32_t qi : sat_q) open[qi] = 0;
       verify_ms += ms_since(tv);

@@ -48,7 +48,17 @@ struct CnfQuery {
   std::vector<scuba_node> nodes;
   std::vector<uint32_t> roots;
 
+  // Occurrence lists: literal index 2*v + (1 if negative) -> the clauses
+  // that hold the literal, in increasing order (occ_off has 2*(n_vars+1)+1
+  // entries).  Built with the CNF for every query not decided at the root,
+  // and shared by the splitter and the device upload.
+  std::vector<uint32_t> occ_off, occ;
+
   uint64_t n_clauses() const { return off.size() - 1; }
+  bool has_occurrences() const {
+    return occ_off.size() == 2 * (size_t(n_vars) + 1) + 1 && occ.size() == lits.size();
+  }
+  void build_occurrences();
 };
 
 // Limits shared by host and device code paths.

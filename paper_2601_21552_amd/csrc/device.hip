@@ -828,15 +828,21 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
   parallel_for(cnf.q.size(), [&](size_t qi) {
     const CnfQuery& q = cnf.src->q[qi];
     const DevQueryDesc& d = cnf.q[qi];
+    if (cnf.skip_root_unsat && q.root_unsat) return;   // an empty descriptor
     for (size_t c = 0; c < q.off.size(); c++) coff[d.coff_base + c] = uint32_t(q.off[c]);
     std::memcpy(lits + d.lit_base, q.lits.data(), q.lits.size() * 4);
     uint32_t* oo = occ_off + d.occ_off_base;
     const size_t nli = 2 * (size_t(q.n_vars) + 1);
+    uint32_t* oc = occ + d.occ_base;
+    if (q.has_occurrences()) {   // built with the CNF
+      std::memcpy(oo, q.occ_off.data(), (nli + 1) * 4);
+      std::memcpy(oc, q.occ.data(), q.occ.size() * 4);
+      return;
+    }
     std::memset(oo, 0, (nli + 1) * 4);
     for (int32_t x : q.lits) oo[2 * size_t(x > 0 ? x : -x) + (x < 0) + 1]++;
     for (size_t i = 0; i < nli; i++) oo[i + 1] += oo[i];
     std::vector<uint32_t> fill(oo, oo + nli);
-    uint32_t* oc = occ + d.occ_base;
     for (uint64_t c = 0; c < q.n_clauses(); c++)
       for (uint64_t i = q.off[c]; i < q.off[c + 1]; i++) {
         const int32_t x = q.lits[i];
@@ -922,7 +928,8 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   for (const DevCubeDesc& c : rh.cubes) {
     if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + c.n_lits > rh.cube_lits.size() ||
         c.res_base + c.nres_cap > rh.res_records || c.nres_cap > rh.tile_max ||
-        (cnf.q[c.qid].n_vars >> 5) + 1 > rh.nw_max)
+        (cnf.q[c.qid].n_vars >> 5) + 1 > rh.nw_max ||
+        (cnf.skip_root_unsat && cnf.src->q[c.qid].root_unsat))
       fail(SCUBA_E_INTERNAL, "cube descriptor out of range");
   }
   for (const DevItem& it : rh.items)

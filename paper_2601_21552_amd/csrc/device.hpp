@@ -92,6 +92,7 @@ struct CnfHost {
   size_t n_occ_off = 0;       // per query: 2*(n_vars+1)+1 offsets
   size_t n_occ = 0;           // per query: the clauses of each literal
   size_t stage_bytes = 0;     // LDS for the largest staged CNF (16-bit form)
+  bool skip_root_unsat = false;   // queries decided at the root are not uploaded
 };
 
 void dev_init(DeviceInfo* info, int device);

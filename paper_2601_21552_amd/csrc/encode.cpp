@@ -1157,7 +1157,24 @@ CnfQuery bitblast_query(const scuba_node* nodes, uint64_t n_nodes, const uint32_
   q.has_query = true;
   q.nodes.assign(nodes, nodes + n_nodes);
   q.roots.assign(roots, roots + n_roots);
+  if (!q.root_unsat) q.build_occurrences();   // a query decided at the root is not split
   return q;
+}
+
+// A counting sort of the literal occurrences by literal index.
+void CnfQuery::build_occurrences() {
+  const size_t nli = 2 * (size_t(n_vars) + 1);
+  occ_off.assign(nli + 1, 0);
+  for (int32_t x : lits) occ_off[2 * size_t(x > 0 ? x : -x) + (x < 0) + 1]++;
+  for (size_t i = 0; i < nli; i++) occ_off[i + 1] += occ_off[i];
+  occ.resize(lits.size());
+  std::vector<uint32_t> fill(occ_off.begin(), occ_off.end() - 1);
+  const uint64_t nc = n_clauses();
+  for (uint64_t c = 0; c < nc; c++)
+    for (uint64_t i = off[c]; i < off[c + 1]; i++) {
+      const int32_t x = lits[i];
+      occ[fill[2 * size_t(x > 0 ? x : -x) + (x < 0)]++] = uint32_t(c);
+    }
 }
 
 }  // namespace scuba

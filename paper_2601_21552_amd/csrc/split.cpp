@@ -9,17 +9,20 @@ namespace scuba {
 
 Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_t max_cubes)
     : q_(q), k_(k), max_res_(max_residual), max_cubes_(max_cubes), n_(q.n_vars) {
-  std::vector<uint32_t> cnt(2 * (size_t(n_) + 1) + 1, 0);
-  for (int32_t l : q_.lits) cnt[2 * size_t(std::abs(l)) + (l < 0)]++;
-  occ_off_.assign(cnt.size() + 1, 0);
-  for (size_t i = 0; i < cnt.size(); i++) occ_off_[i + 1] = occ_off_[i] + cnt[i];
-  occ_.assign(occ_off_.back(), 0);
-  std::vector<uint32_t> fill(occ_off_.begin(), occ_off_.end() - 1);
-  for (uint64_t c = 0; c < q_.n_clauses(); c++)
-    for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
-      int32_t l = q_.lits[i];
-      occ_[fill[2 * size_t(std::abs(l)) + (l < 0)]++] = uint32_t(c);
-    }
+  if (q_.has_occurrences()) {
+    occ_off_ = q_.occ_off.data();
+    occ_ = q_.occ.data();
+  } else {   // built here for a query that has none
+    CnfQuery tmp;
+    tmp.n_vars = q_.n_vars;
+    tmp.off = q_.off;
+    tmp.lits = q_.lits;
+    tmp.build_occurrences();
+    own_occ_off_ = std::move(tmp.occ_off);
+    own_occ_ = std::move(tmp.occ);
+    occ_off_ = own_occ_off_.data();
+    occ_ = own_occ_.data();
+  }
   // static order: literal occurrences in the original CNF, most first,
   // ties to the lowest variable (a counting sort by occurrences; variables
   // enter their bucket in increasing order)
@@ -36,9 +39,9 @@ Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_
   for (uint32_t v = 1; v <= n_; v++) order_[start[most - occurrences_[v]]++] = int32_t(v);
   static_rank_.assign(size_t(n_) + 1, 0);
   for (uint32_t i = 0; i < n_; i++) static_rank_[order_[i]] = i;
-  // clause counts per variable at the root (copied by every reset)
-  act_init_.assign(size_t(n_) + 1, 0);
-  for (int32_t l : q_.lits) act_init_[std::abs(l)]++;
+  // clause counts per variable at the root (copied by every reset); a clause
+  // holds a variable at most once, so this is the occurrence count
+  act_init_ = occurrences_;
   f_init_ = 0;
   for (uint32_t v = 1; v <= n_; v++) f_init_ += act_init_[v] > 0;
   bit_pos_.assign(size_t(n_) + 1, 0);
@@ -495,6 +498,12 @@ void Splitter::emit(CubeKind kind, std::vector<int32_t> lits, std::vector<Cube>&
   } else {
     c.f = int32_t(f_);
     c.nres = uint32_t(n_unsat_);
+    if (keep_leaf_state_) {
+      c.assign = assign_;
+      c.active.reserve(f_);
+      for (uint32_t v = 1; v <= n_; v++)
+        if (assign_[v] < 0 && act_cnt_[v] > 0) c.active.push_back(int32_t(v));
+    }
     n_leaves_++;
     out.push_back(std::move(c));
   }

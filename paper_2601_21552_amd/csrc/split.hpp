@@ -34,6 +34,10 @@ struct Cube {
   int32_t f = -1;             // active variables (leaves)
   uint32_t nres = 0;          // unsatisfied clauses at the fixpoint (leaves)
   CubeKind kind = CubeKind::kLeaf;
+  // the leaf's fixpoint, kept when the splitter is asked to: the assignment
+  // (-1 unassigned, 0, 1 per variable) and the active variables, ascending
+  std::vector<int8_t> assign;
+  std::vector<int32_t> active;
   bool refuted() const { return kind != CubeKind::kLeaf; }
 };
 
@@ -57,6 +61,8 @@ class Splitter {
   // to the lowest variable), which halves an input's value range per
   // decision; then the static order for the remaining (auxiliary) variables.
   void set_word_order();
+  // Leaves carry their fixpoint (Cube::assign, Cube::active).
+  void set_keep_leaf_state() { keep_leaf_state_ = true; }
   // Trace mode (static ordering): at every `every`-th decision node above
   // depth `depth`, record features and one-step lookahead labels of the top
   // `candidates` variables.
@@ -122,11 +128,15 @@ class Splitter {
   uint32_t k_, max_res_;
   uint64_t max_cubes_;
   uint32_t n_;
-  std::vector<uint32_t> occ_off_;   // literal index 2v+neg -> clause list
-  std::vector<uint32_t> occ_;
+  // occurrence lists (literal index 2v+neg -> clause list): the query's own,
+  // or built here when the query has none
+  std::vector<uint32_t> own_occ_off_, own_occ_;
+  const uint32_t* occ_off_ = nullptr;
+  const uint32_t* occ_ = nullptr;
   std::vector<int32_t> order_;      // static branching order
   std::vector<int32_t> word_order_; // input bits by significance (word ordering)
   bool word_ = false;
+  bool keep_leaf_state_ = false;
   // search state
   std::vector<int8_t> assign_;
   std::vector<int32_t> reason_;     // implying clause, -1 for decisions
