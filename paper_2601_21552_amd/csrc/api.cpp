@@ -24,6 +24,10 @@ struct scuba_ctx {
   std::string err;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
+  // pinned staging of the CNF upload, apart from the rounds' staging so that
+  // the upload can run while the host splits
+  void* cnf_pinned = nullptr;
+  size_t cnf_pinned_bytes = 0;
   DevGraphs* graphs = nullptr;
   // autotuner choices per size bucket (see scuba_autotune)
   std::map<std::vector<uint64_t>, scuba_solve_opts> tuned;
@@ -45,6 +49,17 @@ struct scuba_ctx {
     }
     return pinned;
   }
+  void* cnf_staging(size_t bytes) {
+    if (bytes > cnf_pinned_bytes) {
+      dev_pinned_free(cnf_pinned);
+      cnf_pinned = nullptr;
+      cnf_pinned_bytes = 0;
+      size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+      cnf_pinned = dev_pinned(want);
+      cnf_pinned_bytes = want;
+    }
+    return cnf_pinned;
+  }
   DevGraphs* graph_cache() {
     if (!graphs) graphs = dev_graphs_create(device);
     return graphs;
@@ -52,6 +67,7 @@ struct scuba_ctx {
   ~scuba_ctx() {
     dev_graphs_destroy(graphs);
     dev_pinned_free(pinned);
+    dev_pinned_free(cnf_pinned);
   }
 };
 
@@ -816,7 +832,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than scuba_solve_workspace");
     void* stg = ctx->staging(std::max(cnf_b, round_b) + 4096 + rh.cubes.size() * sizeof(DevCubeOut) + h.q.size() * 8);
     RoundTimes rt;
-    dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->pinned_bytes);
+    dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->pinned_bytes, true);
     std::vector<DevCubeOut> outs;
     std::vector<uint64_t> qkeys;
     dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, o.mode, o.grid, hip_stream, stg, ctx->pinned_bytes, &outs,
@@ -924,7 +940,13 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
                                     hip_stream});
     }
     if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
+    // the CNF upload does not depend on the split: it runs while the walks do
     bool uploaded = false;
+    if (std::find(open.begin(), open.end(), 1) != open.end()) {
+      void* cstg = ctx->cnf_staging(cnf_b);
+      dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, cstg, ctx->cnf_pinned_bytes, false);
+      uploaded = true;
+    }
     RoundTimes rt;
     const uint32_t grid = grid_of(ctx, o);
     for (uint32_t round = 0; o.max_rounds == 0 || round < o.max_rounds; round++) {
@@ -972,10 +994,6 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);
       if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than this round needs");
       void* stg = ctx->staging(std::max(cnf_b, round_b) + 4096 + rh.cubes.size() * sizeof(DevCubeOut) + nq * 8);
-      if (!uploaded) {
-        dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->pinned_bytes);
-        uploaded = true;
-      }
       std::vector<DevCubeOut> outs;
       std::vector<uint64_t> qkeys;
       dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
@@ -1020,6 +1038,8 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
         res->q[qi].r.verdict = SCUBA_UNKNOWN;
         res->q[qi].r.how = SCUBA_HOW_BUDGET;
       }
+    // the upload's pinned staging is free again only once the copy is done
+    if (uploaded) dev_sync(hip_stream);
     res->ms[0] = split_ms;
     res->ms[1] = rt.h2d_ms;
     res->ms[2] = rt.up_ms + rt.leaf_ms + rt.graph_ms;

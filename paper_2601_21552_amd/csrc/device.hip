@@ -811,7 +811,7 @@ size_t dev_round_bytes(size_t n_cubes, size_t n_cube_lits, size_t n_items, uint6
 }
 
 void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, void* stream,
-                    void* staging, size_t staging_bytes) {
+                    void* staging, size_t staging_bytes, bool wait) {
   HIP_OK(hipSetDevice(info.device));
   CnfLayout l = cnf_layout(cnf);
   if (l.end > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
@@ -852,7 +852,7 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
   std::memset(s + l.qkey, 0xFF, cnf.q.size() * 8);
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_OK(hipMemcpyAsync(ws, s, l.end, hipMemcpyHostToDevice, st));
-  HIP_OK(hipStreamSynchronize(st));
+  if (wait) HIP_OK(hipStreamSynchronize(st));
 }
 
 struct DevGraphs {

@@ -115,8 +115,10 @@ size_t dev_cnf_bytes(const CnfHost& cnf);
 size_t dev_round_bytes(size_t n_cubes, size_t n_cube_lits, size_t n_items, uint64_t res_records);
 
 // Upload the CNF and reset the per-query witness keys (stream-ordered).
+// With wait false the copy may still run on return: the staging buffer must
+// stay untouched until the stream has passed it.
 void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
-                    void* stream, void* staging, size_t staging_bytes);
+                    void* stream, void* staging, size_t staging_bytes, bool wait);
 
 // Run one round: upload, unit propagation kernel, leaf kernel, download.
 // outs (n_cubes) and qkeys (nq) are filled; the stream is synchronised.
