@@ -162,20 +162,25 @@ class Context:
     # ------------------------------------------------------------ CNF
     def bitblast(self, queries, flags: int = 0) -> Cnf:
         """queries: iterable of (nodes: NODE_DTYPE array, roots: uint32 array)."""
-        nodes, roots, ns, rs = [], [], [0], [0]
+        queries = list(queries)
+        nq = len(queries)
+        isz = L.NODE_DTYPE.itemsize
+        nb, rb = [], []
         for n, r in queries:
-            n = np.asarray(n)
-            assert n.dtype.itemsize == L.NODE_DTYPE.itemsize
-            nodes.append(n.view(L.NODE_DTYPE) if n.dtype != L.NODE_DTYPE else n)
-            roots.append(np.asarray(r, dtype=np.uint32))
-            ns.append(ns[-1] + len(n))
-            rs.append(rs[-1] + len(r))
-        nq = len(ns) - 1
-        an = np.ascontiguousarray(np.concatenate(nodes)) if nodes else np.zeros(0, L.NODE_DTYPE)
-        ar = np.ascontiguousarray(np.concatenate(roots)) if roots else np.zeros(0, np.uint32)
-        ans, ars = np.array(ns, np.uint64), np.array(rs, np.uint64)
+            n = np.ascontiguousarray(n)
+            if n.dtype.itemsize != isz:
+                raise ValueError("node records must have the NODE_DTYPE layout")
+            nb.append(n.view(np.uint8).reshape(-1))   # records as raw bytes
+            rb.append(np.asarray(r))
+        ns = np.zeros(nq + 1, np.uint64)
+        rs = np.zeros(nq + 1, np.uint64)
+        if nq:
+            ns[1:] = np.cumsum([len(b) // isz for b in nb])
+            rs[1:] = np.cumsum([len(r) for r in rb])
+        an = np.concatenate(nb).view(L.NODE_DTYPE) if nq else np.zeros(0, L.NODE_DTYPE)
+        ar = np.ascontiguousarray(np.concatenate(rb).astype(np.uint32, copy=False)) if nq else np.zeros(0, np.uint32)
         h = _P()
-        self._check(self.lib.scuba_bitblast(self.h, nq, _ptr(an), _ptr(ans), _ptr(ar), _ptr(ars),
+        self._check(self.lib.scuba_bitblast(self.h, nq, _ptr(an), _ptr(ns), _ptr(ar), _ptr(rs),
                                             flags, C.byref(h)))
         return Cnf(self, h)
 

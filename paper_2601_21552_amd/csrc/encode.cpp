@@ -200,18 +200,15 @@ class Gates {
     else if (ny == 1) r = ys[0];
     else if (ny == 2) r = XOR(ys[0], ys[1]);
     else {
-      GateKey k{3, ys[0], ys[1], ys[2]};
-      if (const int32_t* hit = cache_.find(k)) r = *hit;
-      else {
-        int32_t o = fresh();
-        for (int m = 0; m < 8; m++) {
-          int va = m & 1, vb = (m >> 1) & 1, vc = (m >> 2) & 1;
-          int p = va ^ vb ^ vc;
-          gate_clause({va ? -ys[0] : ys[0], vb ? -ys[1] : ys[1], vc ? -ys[2] : ys[2], p ? o : -o});
-        }
-        cache_.insert(k, o);
-        r = o;
+      // three-input gates (the full adders' sum and carry) are not looked up
+      // in the structural hash: the adders never share them
+      int32_t o = fresh();
+      for (int m = 0; m < 8; m++) {
+        int va = m & 1, vb = (m >> 1) & 1, vc = (m >> 2) & 1;
+        int p = va ^ vb ^ vc;
+        gate_clause({va ? -ys[0] : ys[0], vb ? -ys[1] : ys[1], vc ? -ys[2] : ys[2], p ? o : -o});
       }
+      r = o;
     }
     return flip ? -r : r;
   }
@@ -236,21 +233,14 @@ class Gates {
     by_var(s[0], s[1]);
     by_var(s[1], s[2]);
     by_var(s[0], s[1]);
-    GateKey k{4, s[0], s[1], s[2]};
-    int32_t r;
-    if (const int32_t* hit = cache_.find(k)) r = *hit;
-    else {
-      int32_t o = fresh();
-      gate_clause({-s[0], -s[1], o});
-      gate_clause({-s[0], -s[2], o});
-      gate_clause({-s[1], -s[2], o});
-      gate_clause({s[0], s[1], -o});
-      gate_clause({s[0], s[2], -o});
-      gate_clause({s[1], s[2], -o});
-      cache_.insert(k, o);
-      r = o;
-    }
-    return flip ? -r : r;
+    const int32_t o = fresh();
+    gate_clause({-s[0], -s[1], o});
+    gate_clause({-s[0], -s[2], o});
+    gate_clause({-s[1], -s[2], o});
+    gate_clause({s[0], s[1], -o});
+    gate_clause({s[0], s[2], -o});
+    gate_clause({s[1], s[2], -o});
+    return flip ? -o : o;
   }
 
   // ---- words (two's complement, modulo 2^W) ----
@@ -271,6 +261,12 @@ class Gates {
     BitVec r(w);
     int32_t carry = kFalse;
     for (uint32_t i = 0; i < w; i++) {
+      // a false operand bit with no carry passes the other bit through and
+      // carries nothing (what XOR3 and MAJ return there, without the calls)
+      if (carry == kFalse && (x[i] == kFalse || y[i] == kFalse)) {
+        r[i] = x[i] == kFalse ? y[i] : x[i];
+        continue;
+      }
       r[i] = XOR3(x[i], y[i], carry);
       if (i + 1 < w) carry = MAJ(x[i], y[i], carry);
     }
