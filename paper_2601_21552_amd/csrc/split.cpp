@@ -9,6 +9,8 @@ namespace scuba {
 
 Splitter::Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_t max_cubes)
     : q_(q), k_(k), max_res_(max_residual), max_cubes_(max_cubes), n_(q.n_vars) {
+  if (q_.lits.size() >= (uint64_t(1) << 32)) throw Error(SCUBA_E_CAPACITY, "query with 2^32 or more literals");
+  coff_.assign(q_.off.begin(), q_.off.end());   // 32-bit clause offsets for the propagation loops
   if (q_.has_occurrences()) {
     occ_off_ = q_.occ_off.data();
     occ_ = q_.occ.data();
@@ -120,7 +122,7 @@ void Splitter::features(const std::vector<int32_t>& cands, std::vector<float>* o
       for (uint32_t j = occ_off_[li]; j < occ_off_[li + 1]; j++) {
         const uint32_t c = occ_[j];
         if (ntrue_[c]) continue;
-        const uint32_t open = uint32_t(q_.off[c + 1] - q_.off[c]) - nfalse_[c];
+        const uint32_t open = uint32_t(coff_[c + 1] - coff_[c]) - nfalse_[c];
         (side ? neg : pos) += 1;
         if (open == 2) bin += 1;
         else if (open == 3) ter += 1;
@@ -267,7 +269,7 @@ bool Splitter::propagate(int32_t lit) {
       uint32_t c = occ_[j];
       if (ntrue_[c]++ == 0) {
         n_unsat_--;
-        for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
+        for (uint64_t i = coff_[c]; i < coff_[c + 1]; i++) {
           int32_t u = std::abs(q_.lits[i]);
           if (--act_cnt_[u] == 0 && assign_[u] < 0) f_--;
         }
@@ -277,12 +279,12 @@ bool Splitter::propagate(int32_t lit) {
       uint32_t c = occ_[j];
       nfalse_[c]++;
       if (ntrue_[c] != 0) continue;
-      uint64_t size = q_.off[c + 1] - q_.off[c];
+      uint64_t size = coff_[c + 1] - coff_[c];
       if (nfalse_[c] == size) {
         if (!conflict) conflict_clause_ = int64_t(c);
         conflict = true;
       } else if (nfalse_[c] + 1 == size) {
-        for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++)
+        for (uint64_t i = coff_[c]; i < coff_[c + 1]; i++)
           if (assign_[std::abs(q_.lits[i])] < 0) { queue_.push_back({q_.lits[i], int32_t(c)}); break; }
       }
     }
@@ -301,7 +303,7 @@ void Splitter::undo_to(size_t pos) {
       uint32_t c = occ_[j];
       if (--ntrue_[c] == 0) {
         n_unsat_++;
-        for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
+        for (uint64_t i = coff_[c]; i < coff_[c + 1]; i++) {
           int32_t u = std::abs(q_.lits[i]);
           if (act_cnt_[u]++ == 0 && assign_[u] < 0) f_++;
         }
@@ -322,7 +324,7 @@ std::vector<uint32_t> Splitter::analyze() {
     return levels;
   }
   std::vector<int32_t> vars;
-  for (uint64_t i = q_.off[conflict_clause_]; i < q_.off[conflict_clause_ + 1]; i++)
+  for (uint64_t i = coff_[conflict_clause_]; i < coff_[conflict_clause_ + 1]; i++)
     vars.push_back(std::abs(q_.lits[i]));
   return levels_of(vars);
 }
@@ -346,7 +348,7 @@ std::vector<uint32_t> Splitter::levels_of(const std::vector<int32_t>& vars) {
       continue;
     }
     const uint64_t c = uint64_t(reason_[u]);
-    for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) push(std::abs(q_.lits[i]));
+    for (uint64_t i = coff_[c]; i < coff_[c + 1]; i++) push(std::abs(q_.lits[i]));
   }
   std::sort(levels.begin(), levels.end());
   levels.erase(std::unique(levels.begin(), levels.end()), levels.end());
@@ -458,9 +460,9 @@ bool Splitter::word_check(std::vector<uint32_t>* levels) {
 
 bool Splitter::root_propagate() {
   for (uint64_t c = 0; c < q_.n_clauses(); c++) {
-    uint64_t size = q_.off[c + 1] - q_.off[c];
+    uint64_t size = coff_[c + 1] - coff_[c];
     if (size == 0) return false;
-    if (size == 1 && !propagate(q_.lits[q_.off[c]])) return false;
+    if (size == 1 && !propagate(q_.lits[coff_[c]])) return false;
   }
   return true;
 }
@@ -640,7 +642,7 @@ bool Splitter::leaf_of(const std::vector<int32_t>& cube, std::vector<int8_t>* as
   for (uint64_t c = 0; c < q_.n_clauses(); c++) {
     if (ntrue_[c]) continue;
     unsat++;
-    for (uint64_t i = q_.off[c]; i < q_.off[c + 1]; i++) {
+    for (uint64_t i = coff_[c]; i < coff_[c + 1]; i++) {
       int32_t v = std::abs(q_.lits[i]);
       if (assign_[v] < 0) act[v] = 1;
     }

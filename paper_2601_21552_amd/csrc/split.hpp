@@ -131,6 +131,7 @@ class Splitter {
   // occurrence lists (literal index 2v+neg -> clause list): the query's own,
   // or built here when the query has none
   std::vector<uint32_t> own_occ_off_, own_occ_;
+  std::vector<uint32_t> coff_;   // the query's clause offsets, 32-bit
   const uint32_t* occ_off_ = nullptr;
   const uint32_t* occ_ = nullptr;
   std::vector<int32_t> order_;      // static branching order
