@@ -249,19 +249,25 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = []
+        last_cnf = None
         for _ in range(args.steps):
-            out.append(step())
+            cnf, res = step()
+            out.append(res)
+            # a step's CNF is released when the next step replaces it, as in a
+            # pipeline that frees each batch after deciding it; the results stay
+            last_cnf = cnf
+            del cnf
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        for cnf, res in out:
+        for res in out:
             for i, g in enumerate(gens):
                 r = res.result(i)
                 assert r["verdict"] == labels[i], (g.query.name, r, extra)
                 if r["verdict"] == "SAT":
                     assert r["witness_checked"]
-        return 1000.0 * elapsed / args.steps, out
+        return 1000.0 * elapsed / args.steps, out, last_cnf
 
-    ms_per_step, results = run_steps({})
+    ms_per_step, results, last_cnf = run_steps({})
     bitblast_ms = sorted(bb_ms[args.warmup:])[len(bb_ms[args.warmup:]) // 2]
 
     # agreement and accounting over the timed steps
@@ -271,7 +277,7 @@ def main():
     leaf_ms = up_ms = 0.0
     leaf_launches = up_launches = 0
     split_ms = verify_ms = 0.0
-    for cnf, res in results:
+    for res in results:
         tm = res.timing()
         leaf_ms += tm["leaf"]
         up_ms += tm["up"]
@@ -279,7 +285,7 @@ def main():
         up_launches += int(tm["up_launches"])
         split_ms += tm["split"]
         verify_ms += tm["verify"]
-    cnf, res = results[-1]
+    cnf, res = last_cnf, results[-1]
     for i, g in enumerate(gens):
         r = res.result(i)
         n_root += r["how"] == "root"
@@ -346,7 +352,7 @@ def main():
     if not args.no_forms:
         for name, extra in (("word", dict(scorer="word")),
                             ("learned", dict(learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)))):
-            ms, _ = run_steps(extra)
+            ms, _, _ = run_steps(extra)
             forms[name] = round(len(gens) / (ms / 1000.0), 3)
         log(f"forms (queries/s): {forms}")
     if not args.no_gain:

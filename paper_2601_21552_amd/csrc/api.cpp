@@ -585,7 +585,17 @@ scuba_status scuba_cnf_input_map(const scuba_cnf* cnf, uint32_t qi, uint32_t* fi
   return SCUBA_OK;
 }
 
-void scuba_cnf_free(scuba_cnf* cnf) { delete cnf; }
+// The queries' memory is released on the host pool: each query was built on
+// a pool thread, so its blocks go back to the allocator arena that the next
+// bit-blast reuses.
+void scuba_cnf_free(scuba_cnf* cnf) {
+  if (!cnf) return;
+  try {
+    parallel_for(cnf->q.size(), [&](size_t i) { cnf->q[i] = CnfQuery(); });
+  } catch (...) {
+  }
+  delete cnf;
+}
 
 // ---------------------------------------------------------------- cubes
 
