@@ -402,11 +402,14 @@ struct ScorerRunner {
       if (j == i) fail(SCUBA_E_CAPACITY, "scorer workspace smaller than one request");
       void* stg = ctx->staging(std::max(rows * kMlpF * 2, rows * 4) + 256);
       uint16_t* xh = static_cast<uint16_t*>(stg);
-      size_t r = 0;
-      for (size_t q = i; q < j; q++) {
-        const std::vector<float>& fe = waiting[q]->request_features();
-        for (float v : fe) xh[r++] = to_bf16(v);
-      }
+      // each request's rows at their offset, converted on the host pool
+      std::vector<size_t> at(j - i + 1, 0);
+      for (size_t q = i; q < j; q++) at[q - i + 1] = at[q - i] + waiting[q]->request_features().size();
+      parallel_for(j - i, [&](size_t t) {
+        const std::vector<float>& fe = waiting[i + t]->request_features();
+        uint16_t* dst = xh + at[t];
+        for (size_t e = 0; e < fe.size(); e++) dst[e] = to_bf16(fe[e]);
+      });
       uint16_t* x = reinterpret_cast<uint16_t*>(ws);
       uint16_t* a1 = reinterpret_cast<uint16_t*>(ws + al(rows_cap * kMlpF * 2));
       uint16_t* a2 = reinterpret_cast<uint16_t*>(ws + al(rows_cap * kMlpF * 2) + al(rows_cap * kMlpH * 2));
