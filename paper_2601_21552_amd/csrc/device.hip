@@ -14,14 +14,15 @@
 //   [0].z,w : 64-bit lane mask, the lanes where a literal of slots 6..11
 //             is true (the same patterns over the lane id)
 //   [1].x   : positive literals of slots 12..37 (26 bits)
-//   [1].y   : negative literals of slots 12..37
+//   [1].y   : all literals of slots 12..37 (positive or negative)
 //
 // Leaf kernel: assignment index a = 4096*block + 64*lane + bit.  Slot j < 6
 // is bit j of `bit` (a constant 64-bit pattern), slot 6..11 is bit j-6 of
 // the lane id, slot >= 12 is bit j-12 of the block (the same for the whole
 // wave).  A wave evaluates one block (64 lanes x 64 bits) per step, reading
 // the records with wave-uniform loads: a clause satisfied by a block-level
-// literal is skipped with a scalar test; else a lane in the clause's lane
+// literal is skipped with a scalar test (such a literal holds where the block
+// bits equal the positive mask: ~(H ^ [1].x) & [1].y != 0); else a lane in the clause's lane
 // mask keeps its word and the other lanes AND the clause's pattern word
 // in.  A block dies when every lane's word is 0.
 // DECIDE takes the smallest (cube, index) witness per query with atomicMin
@@ -467,7 +468,7 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
       }
       const size_t rec = 2 * (cd.res_base + pos);
       res[rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
-      res[rec + 1] = make_uint4(hp, hn, 0u, 0u);
+      res[rec + 1] = make_uint4(hp, hp | hn, 0u, 0u);
       pos++;
     }
   }
@@ -685,10 +686,13 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
           const uint4 r0 = rec[2 * c], r1 = rec[2 * c + 1], r2 = rec[2 * c + 2], r3 = rec[2 * c + 3];
           const uint4 r4 = rec[2 * c + 4], r5 = rec[2 * c + 5], r6 = rec[2 * c + 6], r7 = rec[2 * c + 7];
           const uint32_t left = nres - c;
-          if (!((H & r1.x) | (~H & r1.y))) { acc = clause_and(acc, r0); done++; }
-          if (left > 1 && !((H & r3.x) | (~H & r3.y))) { acc = clause_and(acc, r2); done++; }
-          if (left > 2 && !((H & r5.x) | (~H & r5.y))) { acc = clause_and(acc, r4); done++; }
-          if (left > 3 && !((H & r7.x) | (~H & r7.y))) { acc = clause_and(acc, r6); done++; }
+          // the four skip masks are needed first: keep their loads together
+          // (else each test waits for its own load)
+          asm volatile("" :: "s"(r1.x), "s"(r1.y), "s"(r3.x), "s"(r3.y), "s"(r5.x), "s"(r5.y), "s"(r7.x), "s"(r7.y));
+          if (!(~(H ^ r1.x) & r1.y)) { acc = clause_and(acc, r0); done++; }
+          if (left > 1 && !(~(H ^ r3.x) & r3.y)) { acc = clause_and(acc, r2); done++; }
+          if (left > 2 && !(~(H ^ r5.x) & r5.y)) { acc = clause_and(acc, r4); done++; }
+          if (left > 3 && !(~(H ^ r7.x) & r7.y)) { acc = clause_and(acc, r6); done++; }
           if (!__any(acc != 0)) break;
         }
         blocks++;
