@@ -190,6 +190,17 @@ def gain_legs(ctx, mlp_q, log):
     wo, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000, scorer="word")
     out["partition_1024"] = {"static": st, "learned": le, "word": wo}
     log(f"partition queries: {out['partition_1024']}")
+    # lower-bound stencil reads (offset < 0), 256 of them, static cubing
+    gens = w.config_lower()
+    t0 = time.perf_counter()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    bbl = 1000.0 * (time.perf_counter() - t0)
+    dec = [decide_stats(ctx, cnf, len(gens), [g.label for g in gens], k=30, leaves_per_round=1,
+                        chunk_log2=12)[0] for _ in range(3)]
+    best = min(dec, key=lambda d: d["ms"])
+    out["lower_bound_256"] = {"bitblast_ms": round(bbl, 2), "decide": best,
+                              "queries_per_s": round(len(gens) / ((bbl + best["ms"]) / 1000.0), 1)}
+    log(f"lower-bound reads: {out['lower_bound_256']}")
     return out
 
 

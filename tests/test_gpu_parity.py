@@ -177,6 +177,22 @@ def test_decide_small_queries_brute_force(ctx):
                 assert query_ref.int_eval(q, res.witness(i, q.n_vars))
 
 
+def test_decide_lower_bound_batch(ctx):
+    """256 lower-bound stencil reads (offset < 0 with signed exact
+    arithmetic): verdicts equal the labels and the oracle's, and every
+    witness reads below the buffer under exact integers."""
+    gens = w.config_lower()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    res = ctx.decide(cnf, k=30, leaves_per_round=1, chunk_log2=12)
+    for i, g in enumerate(gens):
+        r = res.result(i)
+        assert r["verdict"] == g.label, (g.query.name, r)
+        assert query_ref.decide(g.query)[0] == r["verdict"], g.query.name
+        if g.label == "SAT":
+            assert r["witness_checked"]
+            assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
+
+
 def _witness_values(g):
     """Generator witness as input values in declaration order."""
     return [g.witness[name] for name in g.query.var_names]

@@ -81,6 +81,15 @@ def test_root_unsat_on_guarded_queries(ctx):
     assert one["root_unsat"] and one["n_clauses"] == 1
 
 
+def test_root_unsat_on_lower_bound_queries(ctx):
+    """Guarded lower-bound reads (idx >= h, offset (idx - h)*s < 0) are
+    decided at the root; the off-by-one and unguarded ones are not."""
+    gens = w.config_lower()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    for i, g in enumerate(gens):
+        assert cnf.view(i)["root_unsat"] == (g.label == "UNSAT"), g.query.name
+
+
 def test_root_unsat_on_2d_queries(ctx):
     """The library's relaxation with product lemmas decides every correct
     2-D access at the root and never a buggy one."""

@@ -163,6 +163,51 @@ def test_config2_labels_by_construction():
             assert query_ref.root_check(g.query) is None
 
 
+@pytest.mark.parametrize("w", [2, 3, 4])
+def test_lower_bound_small_widths(w):
+    """Lower-bound stencil reads buf[idx - h] against exhaustive integer
+    search: the guard idx >= h leaves no input below the buffer, the guard
+    off by one and no guard do; the oracle's encoding agrees at w <= 3."""
+    from workloads import oob_lower_1d
+    for h in (1, 2, 3):
+        if h >= (1 << w):
+            continue
+        for s in (1, 4):
+            for g, want in (("ge", "UNSAT"), ("ge_off", "SAT"), ("none", "SAT")):
+                q = oob_lower_1d(w, g, h, scale=s)
+                assert query_ref.int_bruteforce(q)[0] == want, (w, h, s, g)
+                assert query_ref.decide(q)[0] == want, (w, h, s, g)
+                if w <= 3:
+                    cnf, _ = query_ref.encode(q)
+                    assert cnf_ref.solve(cnf)[0] == want
+
+
+def test_lower_bound_unguarded_count_closed_form():
+    """#{(bdim, bid, tid) : tid < bdim, bid*bdim + tid < h} over 3-bit
+    inputs, counted directly, equals the brute-force count of the unguarded
+    lower-bound query (every admissible idx below h reads below the buffer)."""
+    from workloads import oob_lower_1d
+    top, h = 8, 3
+    b = np.arange(top)[:, None, None]
+    i = np.arange(top)[None, :, None]
+    t = np.arange(top)[None, None, :]
+    want = int(((t < b) & (i * b + t < h)).sum())
+    q = oob_lower_1d(3, "none", h, scale=4)
+    assert query_ref.int_bruteforce(q)[1] == want
+
+
+def test_lower_bound_labels_by_construction():
+    from workloads import config_lower
+    gens = config_lower(n=96)
+    assert sum(g.label == "UNSAT" for g in gens) == 48
+    for g in gens:
+        if g.label == "UNSAT":
+            assert query_ref.root_check(g.query) == "UNSAT", g.query.name
+        else:
+            assert query_ref.int_eval_named(g.query, g.witness), g.query.name
+            assert query_ref.root_check(g.query) is None
+
+
 def test_config3_labels_by_construction():
     """Correct 2-D guards are UNSAT by the chain row*ld + col <= (R-1)*ld +
     (C-1) < R*ld (C <= ld); the root check must find it through the

@@ -65,6 +65,58 @@ def oob_1d(width: int, guard: str, scale: int = 4, header: int = 0,
     return q
 
 
+def oob_lower_1d(width: int, guard: str, halo: int, scale: int = 4, name: str = "") -> Query:
+    """A stencil read ``buf[idx - halo]`` below the start of its buffer:
+    ``idx = blockIdx*blockDim + threadIdx``, byte offset
+    ``(idx - halo) * scale`` from the allocation's start, and the lower-bound
+    test ``offset < 0`` (the other side of the access range, with exact,
+    signed arithmetic).
+
+    guard: ``"ge"`` (idx >= halo), ``"ge_off"`` (idx >= halo - 1, off by
+    one) or ``"none"``.
+    """
+    assert 1 <= halo < 2 ** width
+    q = Query(name or f"oobl_w{width}_{guard}_h{halo}_s{scale}")
+    bdim = q.var("blockDim", width)
+    bid = q.var("blockIdx", width)
+    tid = q.var("threadIdx", width)
+    q.require(tid < bdim)
+    idx = bid * bdim + tid
+    if guard == "ge":
+        q.require(idx >= halo)
+    elif guard == "ge_off":
+        q.require(idx + 1 >= halo)
+    else:
+        assert guard == "none"
+    offset = (idx - halo) * scale
+    q.require(offset < 0)
+    return q
+
+
+def config_lower(seed: int = 6, n: int = 256, wmin: int = 8, wmax: int = 16):
+    """Batch of lower-bound stencil queries: widths w ~ U{wmin..wmax}, halo
+    ~ U{1..8}, element size s in {1,2,4,8}; half guarded (UNSAT), a quarter
+    unguarded and a quarter off by one (SAT); shuffled."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kinds = ["ge"] * (n // 2) + ["none"] * (n // 4)
+    kinds += ["ge_off"] * (n - len(kinds))
+    kinds = [kinds[i] for i in rng.permutation(n)]
+    out = []
+    for i, g in enumerate(kinds):
+        w = int(rng.integers(wmin, wmax + 1))
+        h = int(rng.integers(1, 9))
+        s = int(rng.choice([1, 2, 4, 8]))
+        q = oob_lower_1d(w, g, h, scale=s, name=f"lo_{i}_w{w}_{g}_h{h}_s{s}")
+        if g == "ge":
+            out.append(GenQuery(q, UNSAT, kind="lower_guarded"))
+        elif g == "none":
+            out.append(GenQuery(q, SAT, dict(blockDim=1, blockIdx=0, threadIdx=0), kind="lower_unguarded"))
+        else:
+            out.append(GenQuery(q, SAT, dict(blockDim=h, blockIdx=0, threadIdx=h - 1),
+                                kind="lower_off_by_one"))
+    return out
+
+
 def config1(variant: str = "lt") -> GenQuery:
     """The single query: 12-bit N, blockDim, blockIdx, threadIdx; guard
     idx < N; size 4*N bytes; offset 4*idx; OOB test offset >= size."""
