@@ -201,6 +201,19 @@ def gain_legs(ctx, mlp_q, log):
     out["lower_bound_256"] = {"bitblast_ms": round(bbl, 2), "decide": best,
                               "queries_per_s": round(len(gens) / ((bbl + best["ms"]) / 1000.0), 1)}
     log(f"lower-bound reads: {out['lower_bound_256']}")
+    # the same guarded 1-D accesses with 32-bit machine integers: byte sizes
+    # that wrap are found SAT; the wrap-safe UNSAT ones may stay UNKNOWN
+    from paper_2601_21552_amd import _lib
+    gens = w.config_wrap(m=32)
+    t0 = time.perf_counter()
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens], flags=_lib.BB_WRAP(32))
+    bbw = 1000.0 * (time.perf_counter() - t0)
+    st, verd = decide_stats(ctx, cnf, len(gens), [g.label for g in gens], k=30, leaves_per_round=1,
+                            chunk_log2=12, max_cubes=300)
+    out["wrap32_256"] = {"bitblast_ms": round(bbw, 2), "decide": st,
+                         "sat_found": sum(v == "SAT" for v, g in zip(verd, gens) if g.label == "SAT"),
+                         "sat_labels": sum(g.label == "SAT" for g in gens)}
+    log(f"32-bit wrap-around: {out['wrap32_256']}")
     return out
 
 

@@ -128,9 +128,18 @@ uint32_t scuba_abi_version(void);
  * variable first_var[i] + j.
  * nodes/roots: concatenated per query; node_start/root_start: nq+1 offsets.
  * flags: SCUBA_BB_NO_REWRITE encodes the DAG as given (no normalisation).
+ *   SCUBA_BB_WRAP(m), 1 <= m <= 64: machine integers of m bits instead of
+ *   exact ones (m = 32: CUDA's 32-bit unsigned arithmetic, where an index
+ *   computation can overflow).  Every integer node is an unsigned m-bit
+ *   word; ADD, SUB, MUL and SHL are taken modulo 2^m; UDIV / UREM are the
+ *   unsigned quotient and remainder; comparisons are unsigned; constants
+ *   are reduced modulo 2^m; inputs may be at most m bits wide (else
+ *   SCUBA_E_WIDTH).  No normalisation (it assumes exact integers), and the
+ *   witness check uses the same arithmetic.
  * Errors: SCUBA_E_INVALID (bad op, order, type, negative division operand),
  * SCUBA_E_WIDTH (width outside 1..64).                                      */
 #define SCUBA_BB_NO_REWRITE 1u
+#define SCUBA_BB_WRAP(m) ((uint32_t)(m) << 8)
 scuba_status scuba_bitblast(scuba_ctx* ctx, uint32_t nq, const scuba_node* nodes,
                             const uint64_t* node_start, const uint32_t* roots,
                             const uint64_t* root_start, uint32_t flags, scuba_cnf** out);

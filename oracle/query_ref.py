@@ -21,6 +21,8 @@ Contents
   every monomial form a linear system over the monomials; if it has no
   rational solution (Fourier-Motzkin elimination) the query is UNSAT.
 * ``decide``          - root check, else encode + DPLL.
+* ``wrap_eval`` / ``wrap_bruteforce`` - the same definition with m-bit
+  machine integers (every integer node modulo 2**m, unsigned comparisons).
 """
 from __future__ import annotations
 
@@ -99,6 +101,128 @@ def int_eval(q, values) -> bool:
 
 def int_eval_named(q, named: dict) -> bool:
     return int_eval(q, [named[n] for n in q.var_names])
+
+
+# ---------------------------------------------------------------- machine integers
+# The variant with m-bit machine integers (the semantics a 32-bit CUDA index
+# computation has, where it can overflow): every integer node is reduced
+# modulo 2**m, division and remainder are unsigned, comparisons compare the
+# reduced values.  Written out from that definition, apart from the exact
+# evaluator above.
+
+def wrap_eval_nodes(q, values, m: int):
+    """Value of every node with m-bit machine integers."""
+    mod = 1 << m
+    nodes, _, widths = _nodes(q)
+    val = []
+    for (op, a, b, w, imm) in nodes:
+        if op == OP_VAR:
+            x = int(values[imm])
+            assert 0 <= x < (1 << widths[imm]), "input out of its domain"
+            val.append(x % mod)
+        elif op == OP_CONST:
+            val.append(int(imm) % mod)
+        elif op == OP_ADD:
+            val.append((val[a] + val[b]) % mod)
+        elif op == OP_SUB:
+            val.append((val[a] - val[b]) % mod)
+        elif op == OP_MUL:
+            val.append((val[a] * val[b]) % mod)
+        elif op == OP_SHL:
+            val.append((val[a] << imm) % mod)
+        elif op == OP_UDIV:
+            val.append(val[a] // imm)
+        elif op == OP_UREM:
+            val.append(val[a] % imm)
+        elif op == OP_LT:
+            val.append(val[a] < val[b])
+        elif op == OP_LE:
+            val.append(val[a] <= val[b])
+        elif op == OP_GT:
+            val.append(val[a] > val[b])
+        elif op == OP_GE:
+            val.append(val[a] >= val[b])
+        elif op == OP_EQ:
+            val.append(val[a] == val[b])
+        elif op == OP_NE:
+            val.append(val[a] != val[b])
+        elif op == OP_AND:
+            val.append(bool(val[a]) and bool(val[b]))
+        elif op == OP_OR:
+            val.append(bool(val[a]) or bool(val[b]))
+        elif op == OP_NOT:
+            val.append(not bool(val[a]))
+        else:
+            raise ValueError(op)
+    return val
+
+
+def wrap_eval(q, values, m: int) -> bool:
+    """True iff every root holds for the inputs with m-bit machine integers."""
+    val = wrap_eval_nodes(q, values, m)
+    return all(bool(val[r]) for r in q.roots)
+
+
+def wrap_bruteforce(q, m: int, max_bits: int = 22):
+    """Every input tuple (product order, first declared slowest) with m-bit
+    machine integers; (verdict, number of satisfying tuples, first one)."""
+    assert 1 <= m <= 63
+    bits = sum(q.var_widths)
+    assert bits <= max_bits, f"{bits} input bits is too many for brute force"
+    grids = np.meshgrid(*[np.arange(1 << w, dtype=np.int64) for w in q.var_widths], indexing="ij")
+    cols = [g.ravel() for g in grids]
+    n = cols[0].size if cols else 1
+    mod = 1 << m
+
+    def red(x):   # Python-object arithmetic, then reduced: no int64 overflow
+        return np.array([int(v) % mod for v in x], dtype=object) if x.dtype == object else x % mod
+
+    val = []
+    for (op, a, b, w, imm) in q.nodes:
+        if op == OP_VAR:
+            val.append(cols[imm].astype(object) % mod)
+        elif op == OP_CONST:
+            val.append(np.full(n, int(imm) % mod, dtype=object))
+        elif op == OP_ADD:
+            val.append(red(val[a] + val[b]))
+        elif op == OP_SUB:
+            val.append(red(val[a] - val[b]))
+        elif op == OP_MUL:
+            val.append(red(val[a] * val[b]))
+        elif op == OP_SHL:
+            val.append(red(val[a] * (1 << int(imm))))
+        elif op == OP_UDIV:
+            val.append(val[a] // int(imm))
+        elif op == OP_UREM:
+            val.append(val[a] % int(imm))
+        elif op == OP_LT:
+            val.append(val[a] < val[b])
+        elif op == OP_LE:
+            val.append(val[a] <= val[b])
+        elif op == OP_GT:
+            val.append(val[a] > val[b])
+        elif op == OP_GE:
+            val.append(val[a] >= val[b])
+        elif op == OP_EQ:
+            val.append(val[a] == val[b])
+        elif op == OP_NE:
+            val.append(val[a] != val[b])
+        elif op == OP_AND:
+            val.append(np.asarray(val[a], dtype=bool) & np.asarray(val[b], dtype=bool))
+        elif op == OP_OR:
+            val.append(np.asarray(val[a], dtype=bool) | np.asarray(val[b], dtype=bool))
+        elif op == OP_NOT:
+            val.append(~np.asarray(val[a], dtype=bool))
+        else:
+            raise ValueError(op)
+    ok = np.ones(n, dtype=bool)
+    for r in q.roots:
+        ok &= np.asarray(val[r], dtype=bool)
+    cnt = int(ok.sum())
+    if cnt == 0:
+        return UNSAT, 0, None
+    i = int(np.argmax(ok))
+    return SAT, cnt, [int(c[i]) for c in cols]
 
 
 def int_bruteforce(q, max_bits: int = 22):

@@ -18,6 +18,13 @@ SAT, UNSAT, UNKNOWN = 1, 0, 2
 VERDICT = {1: "SAT", 0: "UNSAT", 2: "UNKNOWN"}
 HOW = {0: "root", 1: "device", 2: "budget"}
 MODE_DECIDE, MODE_COUNT = 0, 1
+
+
+def BB_WRAP(m: int) -> int:
+    """Bit-blast flag: machine integers of m bits (1..64)."""
+    return int(m) << 8
+
+
 SCORER_STATIC, SCORER_LEARNED, SCORER_WORD = 0, 1, 2
 SOLVE_GRAPH = 1
 CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2

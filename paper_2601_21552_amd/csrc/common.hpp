@@ -39,6 +39,7 @@ struct CnfQuery {
   std::vector<uint8_t> in_defined;   // 1: a root equality defines the input
                                      //    from the others (decided last)
   bool root_unsat = false;
+  uint32_t wrap_bits = 0;             // > 0: machine integers of this width
   // word-level root facts and the value range of every atom (empty when a
   // magnitude would not fit 100 bits: then no word-level check)
   std::vector<WordFact> word_facts;

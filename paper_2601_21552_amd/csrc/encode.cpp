@@ -570,8 +570,19 @@ class Encoder {
       for (uint32_t b = 0; b < nodes_[i].width; b++) a.bits.push_back(g_.fresh());
       atoms_.push_back(a);
     }
-    if (flags_ & SCUBA_BB_NO_REWRITE) run_structural();
-    else run_normalised();
+    const uint32_t wrap = (flags_ >> 8) & 0xFF;
+    if (wrap) {
+      if (wrap > 64) fail(SCUBA_E_WIDTH, "wrap-around width outside 1..64");
+      for (uint64_t i = 0; i < n_; i++)
+        if (nodes_[i].op == SCUBA_OP_VAR && nodes_[i].width > wrap)
+          fail(SCUBA_E_WIDTH, "node " + std::to_string(i) + ": input wider than the wrap-around width");
+      out_.wrap_bits = wrap;
+      run_wrap(wrap);
+    } else if (flags_ & SCUBA_BB_NO_REWRITE) {
+      run_structural();
+    } else {
+      run_normalised();
+    }
   }
 
  private:
@@ -1025,6 +1036,87 @@ class Encoder {
   // ---------------------------------------------------------- structural
   // Each node is a circuit of its own (no normalisation): widths from value
   // ranges, comparisons through the sign or zero test of a - b.
+  // ---------------------------------------------------------- modular
+  // Every integer node is an unsigned m-bit word: ADD, SUB, MUL and SHL are
+  // taken modulo 2^m, UDIV / UREM by a constant are the unsigned quotient
+  // and remainder, comparisons are unsigned (machine integers of m bits).
+  void run_wrap(uint32_t m) {
+    std::vector<BitVec> bv(n_);
+    std::vector<int32_t> bl(n_, kFalse);
+    std::map<std::pair<BitVec, BitVec>, std::pair<int32_t, int32_t>> cmp_cache;
+    const BigInt mod = BigInt::pow2(m);
+    for (uint64_t i = 0; i < n_; i++) {
+      const scuba_node& x = nodes_[i];
+      switch (x.op) {
+        case SCUBA_OP_VAR: bv[i] = Gates::resize(atoms_[x.imm].bits, m, false); break;
+        case SCUBA_OP_CONST: {
+          BigInt r;
+          BigInt::floor_divmod(BigInt::from_u64(x.imm), mod, nullptr, &r);
+          bv[i] = Gates::constant(r, m);
+          break;
+        }
+        case SCUBA_OP_ADD: bv[i] = g_.add(bv[x.a], bv[x.b], m); break;
+        case SCUBA_OP_SUB: bv[i] = g_.add(bv[x.a], g_.neg(bv[x.b], m), m); break;
+        case SCUBA_OP_MUL: bv[i] = g_.mul_u(bv[x.a], bv[x.b], m); break;
+        case SCUBA_OP_SHL: {
+          BitVec b(std::min<uint64_t>(x.imm, m), kFalse);
+          for (uint32_t j = 0; b.size() < m; j++) b.push_back(bv[x.a][j]);
+          bv[i] = b;
+          break;
+        }
+        case SCUBA_OP_UDIV: case SCUBA_OP_UREM: {
+          const BigInt k = BigInt::from_u64(x.imm);
+          if (k >= mod) {   // every m-bit value is below k
+            bv[i] = x.op == SCUBA_OP_UDIV ? Gates::constant(BigInt(0), m) : bv[x.a];
+            break;
+          }
+          // fresh q (m bits) and r (< k): a == q*k + r exactly, r < k
+          BitVec qb, rb;
+          for (uint32_t b = 0; b < m; b++) qb.push_back(g_.fresh());
+          const uint32_t rw = std::max<uint32_t>(1, (k - BigInt(1)).bit_length());
+          for (uint32_t b = 0; b < rw; b++) rb.push_back(g_.fresh());
+          const uint32_t w = m + k.bit_length() + 1;
+          BitVec sum = g_.add(g_.mul_const(Gates::resize(qb, w, false), k, w), Gates::resize(rb, w, false), w);
+          BitVec xa = Gates::resize(bv[x.a], w, false);
+          for (uint32_t b = 0; b < w; b++) g_.clause({-g_.XOR(xa[b], sum[b])});
+          g_.clause({-g_.ge_const_gate(rb, k)});
+          bv[i] = x.op == SCUBA_OP_UDIV ? qb : Gates::resize(rb, m, false);
+          break;
+        }
+        case SCUBA_OP_LT: case SCUBA_OP_LE: case SCUBA_OP_GT: case SCUBA_OP_GE:
+        case SCUBA_OP_EQ: case SCUBA_OP_NE: {
+          uint32_t a = x.a, b = x.b;
+          if (x.op == SCUBA_OP_GT || x.op == SCUBA_OP_LE) std::swap(a, b);
+          // unsigned: the borrow of a - b over m + 1 bits, and equality; one
+          // comparator per pair of words (nodes with the same bits share it,
+          // so comparing a word with itself twice is one gate)
+          auto key = std::make_pair(bv[a], bv[b]);
+          auto hit = cmp_cache.find(key);
+          if (hit == cmp_cache.end()) {
+            BitVec d = g_.add(Gates::resize(bv[a], m + 1, false),
+                              g_.neg(Gates::resize(bv[b], m + 1, false), m + 1), m + 1);
+            int32_t e = kTrue;
+            for (uint32_t j = 0; j < m; j++) e = g_.AND(e, -g_.XOR(bv[a][j], bv[b][j]));
+            hit = cmp_cache.emplace(key, std::make_pair(d.back(), e)).first;
+          }
+          const int32_t lt = hit->second.first, eq = hit->second.second;
+          switch (x.op) {
+            case SCUBA_OP_LT: case SCUBA_OP_GT: bl[i] = lt; break;
+            case SCUBA_OP_LE: case SCUBA_OP_GE: bl[i] = -lt; break;
+            case SCUBA_OP_EQ: bl[i] = eq; break;
+            default: bl[i] = -eq; break;
+          }
+          break;
+        }
+        case SCUBA_OP_AND: bl[i] = g_.AND(bl[x.a], bl[x.b]); break;
+        case SCUBA_OP_OR: bl[i] = g_.OR(bl[x.a], bl[x.b]); break;
+        case SCUBA_OP_NOT: bl[i] = -bl[x.a]; break;
+        default: break;
+      }
+    }
+    for (uint64_t r = 0; r < nr_; r++) g_.clause({bl[roots_[r]]});
+  }
+
   void run_structural() {
     std::vector<Range> rg(n_);
     std::vector<BitVec> bv(n_);

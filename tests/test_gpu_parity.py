@@ -193,6 +193,47 @@ def test_decide_lower_bound_batch(ctx):
             assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
 
 
+def test_decide_wrap32_batch(ctx):
+    """256 guarded accesses with 32-bit machine integers (SCUBA_BB_WRAP(32)).
+    Those whose byte size N*s can wrap are found SAT, with a witness that
+    goes out of bounds under 32-bit arithmetic.  With s = 1 the offset and
+    the size are the guard's own words, and propagation refutes the query at
+    the root.  The rest are UNSAT by construction but need a proof through
+    the multipliers that cubing alone cannot give: within the cube budget
+    they may stay UNKNOWN, never SAT."""
+    from paper_2601_21552_amd import _lib
+    gens = w.config_wrap(m=32)
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens], flags=_lib.BB_WRAP(32))
+    res = ctx.decide(cnf, k=30, leaves_per_round=1, chunk_log2=12, max_cubes=300)
+    for i, g in enumerate(gens):
+        r = res.result(i)
+        assert r["verdict"] in (g.label, "UNKNOWN"), (g.query.name, r)
+        if g.label == "SAT":
+            assert r["verdict"] == "SAT", g.query.name
+            assert r["witness_checked"]
+            assert query_ref.wrap_eval(g.query, res.witness(i, g.query.n_vars), 32)
+        elif g.query.name.endswith("_s1"):
+            assert r["verdict"] == "UNSAT" and r["how"] == "root", g.query.name
+
+
+@pytest.mark.parametrize("m", [4, 6])
+def test_decide_wrap_small_brute_force(ctx, m):
+    from paper_2601_21552_amd import _lib
+    from tests.querygen import random_query
+    rng = np.random.Generator(np.random.PCG64(501 + m))
+    qs = [random_query(rng, max_bits=10, name=f"wd{m}_{i}") for i in range(60)]
+    qs = [q for q in qs if max(q.var_widths) <= m]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs], flags=_lib.BB_WRAP(m))
+    for k in (4, 12):
+        res = ctx.decide(cnf, k=k, leaves_per_round=2)
+        for i, q in enumerate(qs):
+            want = query_ref.wrap_bruteforce(q, m)[0]
+            r = res.result(i)
+            assert r["verdict"] == want, (q.name, k, r)
+            if want == "SAT":
+                assert query_ref.wrap_eval(q, res.witness(i, q.n_vars), m)
+
+
 def _witness_values(g):
     """Generator witness as input values in declaration order."""
     return [g.witness[name] for name in g.query.var_names]

@@ -59,6 +59,31 @@ def test_cnf_counts_equal_integer_solutions(ctx, flags):
         assert cnf_ref.count(_cnf(v)) == query_ref.int_bruteforce(q)[1], q.nodes
 
 
+@pytest.mark.parametrize("m", [3, 4, 6])
+def test_wrap_cnf_counts_equal_machine_solutions(ctx, m):
+    """With m-bit machine integers (SCUBA_BB_WRAP(m)) the library's CNF has
+    one model per input tuple that satisfies the query under m-bit
+    arithmetic: the oracle's model count of that CNF equals exhaustive
+    search with the same arithmetic."""
+    from paper_2601_21552_amd import _lib
+    rng = np.random.Generator(np.random.PCG64(301 + m))
+    qs = [random_query(rng, max_bits=8, name=f"m{m}_{i}") for i in range(60)]
+    qs = [q for q in qs if max(q.var_widths) <= m]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs], flags=_lib.BB_WRAP(m))
+    for i, q in enumerate(qs):
+        v = cnf.view(i)
+        assert not v["root_unsat"]
+        assert cnf_ref.count(_cnf(v)) == query_ref.wrap_bruteforce(q, m)[1], q.nodes
+
+
+def test_wrap_rejects_inputs_wider_than_the_machine_word(api, ctx):
+    from paper_2601_21552_amd import _lib
+    q = Query("wide")
+    x = q.var("x", 40)
+    q.require(x > 3)
+    assert _status(api, lambda: ctx.bitblast([q.arrays()[:2]], flags=_lib.BB_WRAP(32))) == -2   # SCUBA_E_WIDTH
+
+
 def test_input_map_and_witness_decoding(ctx):
     g = w.config1("none")
     cnf = ctx.bitblast([g.query.arrays()[:2]])

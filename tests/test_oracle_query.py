@@ -5,6 +5,7 @@ encoding and brute force over every input tuple.  CPU only."""
 import numpy as np
 import pytest
 
+import workloads as w
 from oracle import cnf_ref, query_ref
 from tests.querygen import random_query
 from workloads import oob_2d, config3, Query, config1, config2, oob_1d, partition_query
@@ -206,6 +207,46 @@ def test_lower_bound_labels_by_construction():
         else:
             assert query_ref.int_eval_named(g.query, g.witness), g.query.name
             assert query_ref.root_check(g.query) is None
+
+
+# ---------------------------------------------------------------- machine integers
+
+@pytest.mark.parametrize("m", [2, 3, 4, 5])
+def test_wrap_unsigned_overflow_closed_form(m):
+    """a + b < a (unsigned) holds exactly when a + b >= 2^m, i.e. for
+    sum_a a = 2^m (2^m - 1) / 2 pairs; never with exact integers."""
+    q = Query("ovf")
+    a, b = q.var("a", m), q.var("b", m)
+    q.require(a + b < a)
+    assert query_ref.wrap_bruteforce(q, m)[1] == (1 << m) * ((1 << m) - 1) // 2
+    assert query_ref.int_bruteforce(q)[0] == "UNSAT"
+
+
+def test_wrap_matches_exact_when_nothing_overflows():
+    """With no subtraction and m far above every magnitude the machine
+    integers are the integers: both brute forces count the same tuples."""
+    rng = np.random.Generator(np.random.PCG64(401))
+    checked = 0
+    for i in range(80):
+        q = random_query(rng, max_bits=9, ops=("add", "mul", "shl", "udiv", "urem", "const"), name=f"n{i}")
+        if max(query_ref._magnitude_bounds(q) + [0]) >= (1 << 59):
+            continue
+        assert query_ref.wrap_bruteforce(q, 60)[1] == query_ref.int_bruteforce(q)[1], q.nodes
+        checked += 1
+    assert checked >= 40
+
+
+def test_wrap_labels_by_construction_small():
+    """The wrap-around workload at m = 5 (inputs of 3..5 bits): every label
+    equals exhaustive search with 5-bit machine integers, and each SAT
+    witness satisfies that evaluation; with exact integers all are UNSAT."""
+    gens = w.config_wrap(n=48, m=5, wspan=2)
+    assert {g.label for g in gens} == {"SAT", "UNSAT"}
+    for g in gens:
+        assert query_ref.wrap_bruteforce(g.query, 5)[0] == g.label, g.query.name
+        assert query_ref.int_bruteforce(g.query)[0] == "UNSAT"
+        if g.label == "SAT":
+            assert query_ref.wrap_eval(g.query, [g.witness[n] for n in g.query.var_names], 5)
 
 
 def test_config3_labels_by_construction():

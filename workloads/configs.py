@@ -117,6 +117,27 @@ def config_lower(seed: int = 6, n: int = 256, wmin: int = 8, wmax: int = 16):
     return out
 
 
+def config_wrap(seed: int = 7, n: int = 256, m: int = 32, wspan: int = 3):
+    """Guarded 1-D accesses (guard idx < N, test idx*s >= N*s) evaluated with
+    m-bit machine integers: widths w ~ U{m-wspan..m}, element size s in
+    {1,2,4,8}.  The byte size N*s wraps once N >= 2^m / s, which a w-bit N
+    reaches iff s * 2^w > 2^m: then N = 2^m / s makes the size 0 and the
+    first element is already past it (SAT).  Otherwise no product wraps,
+    idx < N gives idx*s < N*s, and the guard holds (UNSAT)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n):
+        w = int(rng.integers(max(1, m - wspan), m + 1))
+        s = int(rng.choice([1, 2, 4, 8]))
+        q = oob_1d(w, "lt", scale=s, header=0, name=f"wr{m}_{i}_w{w}_s{s}")
+        if s * (1 << w) > (1 << m):
+            out.append(GenQuery(q, SAT, dict(N=(1 << m) // s, blockDim=1, blockIdx=0, threadIdx=0),
+                                kind="size_wraps"))
+        else:
+            out.append(GenQuery(q, UNSAT, kind="no_wrap"))
+    return out
+
+
 def config1(variant: str = "lt") -> GenQuery:
     """The single query: 12-bit N, blockDim, blockIdx, threadIdx; guard
     idx < N; size 4*N bytes; offset 4*idx; OOB test offset >= size."""
