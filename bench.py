@@ -50,18 +50,18 @@ LEARNED_RESCORE = 4
 LEARNED_RESCORE_ACCESS = 16
 
 WORKLOADS = {
-    2: ("config2: 256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, "
-        "c in 0..16, 128 guarded (UNSAT) / 64 unguarded + 64 off-by-one (SAT); "
-        "static cubing k=30"),
-    1: "config1: one 12-bit guarded idx<N query (UNSAT), static cubing k=30",
+    "batch_1d": ("256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, "
+                 "c in 0..16, 128 guarded (UNSAT) / 64 unguarded + 64 off-by-one (SAT); "
+                 "static cubing k=30"),
+    "single": "one 12-bit guarded idx<N query (UNSAT), static cubing k=30",
 }
 
 
-def make_batch(config: int):
+def make_batch(workload: str):
     import workloads as w
-    if config == 1:
-        return [w.config1("lt")]
-    return w.config2()
+    if workload == "single":
+        return [w.single_access("lt")]
+    return w.batch_1d()
 
 
 def oracle_leg(gens, cores: int):
@@ -87,7 +87,7 @@ def measured_traffic(args):
     src = os.path.join(ROOT, "paper_2601_21552_amd", "csrc", "device.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    default = (args.config == 2 and args.k == 30 and args.leaves_per_round == 1
+    default = (args.workload == "batch_1d" and args.k == 30 and args.leaves_per_round == 1
                and args.chunk_log2 == 12)
     if sha != MEASURED_TRAFFIC["device_hip_sha256_16"] or not default:
         return None
@@ -143,12 +143,12 @@ def gain_legs(ctx, mlp_q, log):
     from oracle import cnf_ref
     out = {}
     # random 3-SAT: n = 100 and 150, k = 16
-    tr = w.config4_train(per_n=48)
+    tr = w.random_3sat_train(per_n=48)
     tr_batches = [ctx.cnf_from_arrays(*w.concat(tr[100])),
                   ctx.cnf_from_arrays(*w.concat(tr[150][:16]))]
     mlp_s, info = train_scorer(ctx, tr_batches, k=16, epochs=6, seed=4, candidates=16, depth=40)
     log(f"3-SAT scorer trained: {info}")
-    ev = w.config4(per_n=128, ns=(100, 150))
+    ev = w.random_3sat_sets(per_n=128, ns=(100, 150))
     for n, count in ((100, 128), (150, 32)):
         cnfs = ev[n][:count]
         raw = ctx.cnf_from_arrays(*w.concat(cnfs))
@@ -168,7 +168,7 @@ def gain_legs(ctx, mlp_q, log):
     out["random3sat_scorer"] = info
     # 4096 2-D accesses of uneven width in one decide call, autotuned and
     # captured as HIP graphs (word ordering)
-    gens3 = w.config3()
+    gens3 = w.batch_2d()
     t0 = time.perf_counter()
     cnf3 = ctx.bitblast([g.query.arrays()[:2] for g in gens3])
     bb3 = 1000.0 * (time.perf_counter() - t0)
@@ -181,7 +181,7 @@ def gain_legs(ctx, mlp_q, log):
                             "queries_per_s": round(len(gens3) / ((bb3 + best["ms"]) / 1000.0), 1)}
     log(f"4096 2-D accesses: {out['batch_4096_2d']}")
     # partition queries, all 1024
-    gens = w.config5()
+    gens = w.partition_batch()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     labels = [g.label for g in gens]
     st, _ = decide_stats(ctx, cnf, len(gens), labels, k=30, max_cubes=3000)
@@ -191,7 +191,7 @@ def gain_legs(ctx, mlp_q, log):
     out["partition_1024"] = {"static": st, "learned": le, "word": wo}
     log(f"partition queries: {out['partition_1024']}")
     # lower-bound stencil reads (offset < 0), 256 of them, static cubing
-    gens = w.config_lower()
+    gens = w.batch_lower()
     t0 = time.perf_counter()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     bbl = 1000.0 * (time.perf_counter() - t0)
@@ -204,7 +204,7 @@ def gain_legs(ctx, mlp_q, log):
     # the same guarded 1-D accesses with 32-bit machine integers: byte sizes
     # that wrap are found SAT; the wrap-safe UNSAT ones may stay UNKNOWN
     from paper_2601_21552_amd import _lib
-    gens = w.config_wrap(m=32)
+    gens = w.batch_wrap(m=32)
     t0 = time.perf_counter()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens], flags=_lib.BB_WRAP(32))
     bbw = 1000.0 * (time.perf_counter() - t0)
@@ -222,7 +222,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch_1d", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=30)
     ap.add_argument("--leaves-per-round", type=int, default=1)
     ap.add_argument("--chunk-log2", type=int, default=12)
@@ -251,7 +251,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    gens = make_batch(args.config)
+    gens = make_batch(args.workload)
     arrays = [g.query.arrays()[:2] for g in gens]
     labels = [g.label for g in gens]
     ctx = api.Context(0)
@@ -369,8 +369,8 @@ def main():
     scorer_info = None
     if not (args.no_forms and args.no_gain):
         import workloads as w
-        tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.config2(seed=102)]),
-              ctx.bitblast([g.query.arrays()[:2] for g in w.config3(seed=103, n=1024)])]
+        tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.batch_1d(seed=102)]),
+              ctx.bitblast([g.query.arrays()[:2] for g in w.batch_2d(seed=103, n=1024)])]
         mlp_q, scorer_info = train_scorer(ctx, tr, k=30, epochs=4, seed=2)
         log(f"access-query scorer trained: {scorer_info}")
     if not args.no_forms:
@@ -407,7 +407,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic (seeded generators)",
-        "config": {"workload": WORKLOADS[args.config], "queries": len(gens), "k": args.k,
+        "config": {"workload": WORKLOADS[args.workload], "queries": len(gens), "k": args.k,
                    "scorer": "static", "leaves_per_round": args.leaves_per_round,
                    "chunk_log2": args.chunk_log2},
         "roofline": roofline,

@@ -19,7 +19,7 @@ def ctx():
 
 @pytest.fixture(scope="module")
 def batch(ctx):
-    gens = w.config3(n=512) + w.config2()[:128]
+    gens = w.batch_2d(n=512) + w.batch_1d()[:128]
     return gens, ctx.bitblast([g.query.arrays()[:2] for g in gens])
 
 

@@ -37,7 +37,7 @@ def test_empty_batch(ctx):
 
 
 def test_batch_decided_at_the_root(ctx):
-    gens = [g for g in w.config2() if g.kind.startswith("guarded")]
+    gens = [g for g in w.batch_1d() if g.kind.startswith("guarded")]
     assert gens
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30)
@@ -52,7 +52,7 @@ def test_batch_decided_at_the_root(ctx):
 def test_mixed_batch_and_repeat(ctx):
     # root-decided queries interleaved with device ones, decided twice on one
     # CNF handle: the second call must give the first call's results
-    gens = w.config2()[::3] + [w.config1("lt"), w.config1("none")]
+    gens = w.batch_1d()[::3] + [w.single_access("lt"), w.single_access("none")]
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     first = ctx.decide(cnf, k=30, leaves_per_round=1, chunk_log2=12)
     again = ctx.decide(cnf, k=30, leaves_per_round=1, chunk_log2=12)
@@ -67,6 +67,6 @@ def test_mixed_batch_and_repeat(ctx):
 
 def test_options_beyond_the_limits_are_rejected(ctx):
     from paper_2601_21552_amd._lib import ScubaError
-    cnf = ctx.bitblast([w.config1("none").query.arrays()[:2]])
+    cnf = ctx.bitblast([w.single_access("none").query.arrays()[:2]])
     with pytest.raises(ScubaError):
         ctx.decide(cnf, k=39)

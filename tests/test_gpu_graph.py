@@ -36,7 +36,7 @@ def _summary(res, n, nvars):
 
 def test_decide_graph_replays_match_eager(ctx):
     import torch
-    gens = w.config2()
+    gens = w.batch_1d()
     nvars = [g.query.n_vars for g in gens]
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     eager = _summary(ctx.decide(cnf, k=30), len(gens), nvars)

@@ -76,7 +76,7 @@ def test_learned_decide_verdicts(ctx, untrained):
         assert r["verdict"] == want, qi
         if want == "SAT":
             assert cnf_ref.check_model(f, res.model(qi, f.n_vars))
-    gens = w.config2()[:96]
+    gens = w.batch_1d()[:96]
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30, learned=sc)
     for i, g in enumerate(gens):

@@ -137,8 +137,8 @@ def test_product_cnf_counts_small_widths(ctx):
         assert total == query_ref.int_bruteforce(q)[1], q.name
 
 
-def test_decide_config1(ctx):
-    gens = [w.config1("lt"), w.config1("none"), w.config1("le")]
+def test_decide_single_access(ctx):
+    gens = [w.single_access("lt"), w.single_access("none"), w.single_access("le")]
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30)
     for i, g in enumerate(gens):
@@ -149,8 +149,8 @@ def test_decide_config1(ctx):
             assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
 
 
-def test_decide_config2_full(ctx):
-    gens = w.config2()
+def test_decide_batch_1d_full(ctx):
+    gens = w.batch_1d()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30)
     for i, g in enumerate(gens):
@@ -181,7 +181,7 @@ def test_decide_lower_bound_batch(ctx):
     """256 lower-bound stencil reads (offset < 0 with signed exact
     arithmetic): verdicts equal the labels and the oracle's, and every
     witness reads below the buffer under exact integers."""
-    gens = w.config_lower()
+    gens = w.batch_lower()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30, leaves_per_round=1, chunk_log2=12)
     for i, g in enumerate(gens):
@@ -202,7 +202,7 @@ def test_decide_wrap32_batch(ctx):
     the multipliers that cubing alone cannot give: within the cube budget
     they may stay UNKNOWN, never SAT."""
     from paper_2601_21552_amd import _lib
-    gens = w.config_wrap(m=32)
+    gens = w.batch_wrap(m=32)
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens], flags=_lib.BB_WRAP(32))
     res = ctx.decide(cnf, k=30, leaves_per_round=1, chunk_log2=12, max_cubes=300)
     for i, g in enumerate(gens):
@@ -239,13 +239,13 @@ def _witness_values(g):
     return [g.witness[name] for name in g.query.var_names]
 
 
-def test_decide_config5_partitions(ctx):
+def test_decide_partition_batch(ctx):
     """1024 intra-allocation partition queries (20-bit sizes, 2..8 parts)
     under the word ordering: every guarded access UNSAT at the root, every
     buggy one SAT with a witness that goes past its partition under exact
     integers; the oracle's verdict on a sample (DPLL, else the generator's
     witness checked by the definition)."""
-    gens = w.config5()
+    gens = w.partition_batch()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30, max_cubes=20000, scorer="word")
     for i, g in enumerate(gens):
@@ -262,11 +262,11 @@ def test_decide_config5_partitions(ctx):
                 assert ov == "SAT", (g.query.name, how)
 
 
-def test_decide_config5_static_never_wrong(ctx):
+def test_decide_partition_batch_static_never_wrong(ctx):
     """The static most-occurrences ordering on the same queries: UNKNOWN
     when its walk runs out of cubes (the case the word ordering and the
     learned scorer address), never a wrong verdict."""
-    gens = w.config5()[:256]
+    gens = w.partition_batch()[:256]
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30, max_cubes=3000)
     for i, g in enumerate(gens):
@@ -278,12 +278,12 @@ def test_decide_config5_static_never_wrong(ctx):
             assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
 
 
-def test_decide_config3_one_batch(ctx):
+def test_decide_batch_2d_one_call(ctx):
     """All 4096 2-D accesses of uneven width (8..24 bits, 1..3 multipliers)
     in one decide call: labels reproduced, correct ones UNSAT by the root
     relaxation (the oracle's own root check agrees), every SAT witness
     verified under exact integers."""
-    gens = w.config3()
+    gens = w.batch_2d()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     res = ctx.decide(cnf, k=30, max_cubes=20000, scorer="word")
     for i, g in enumerate(gens):

@@ -85,7 +85,7 @@ def test_wrap_rejects_inputs_wider_than_the_machine_word(api, ctx):
 
 
 def test_input_map_and_witness_decoding(ctx):
-    g = w.config1("none")
+    g = w.single_access("none")
     cnf = ctx.bitblast([g.query.arrays()[:2]])
     first, width = cnf.input_map(0)
     assert list(width) == [12, 12, 12, 12]
@@ -98,18 +98,18 @@ def test_input_map_and_witness_decoding(ctx):
 
 
 def test_root_unsat_on_guarded_queries(ctx):
-    gens = w.config2()
+    gens = w.batch_1d()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     for i, g in enumerate(gens):
         assert cnf.view(i)["root_unsat"] == (g.label == "UNSAT"), g.query.name
-    one = ctx.bitblast([w.config1("lt").query.arrays()[:2]]).view(0)
+    one = ctx.bitblast([w.single_access("lt").query.arrays()[:2]]).view(0)
     assert one["root_unsat"] and one["n_clauses"] == 1
 
 
 def test_root_unsat_on_lower_bound_queries(ctx):
     """Guarded lower-bound reads (idx >= h, offset (idx - h)*s < 0) are
     decided at the root; the off-by-one and unguarded ones are not."""
-    gens = w.config_lower()
+    gens = w.batch_lower()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     for i, g in enumerate(gens):
         assert cnf.view(i)["root_unsat"] == (g.label == "UNSAT"), g.query.name
@@ -118,7 +118,7 @@ def test_root_unsat_on_lower_bound_queries(ctx):
 def test_root_unsat_on_2d_queries(ctx):
     """The library's relaxation with product lemmas decides every correct
     2-D access at the root and never a buggy one."""
-    gens = w.config3(n=400)
+    gens = w.batch_2d(n=400)
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
     for i, g in enumerate(gens):
         assert cnf.view(i)["root_unsat"] == (g.label == "UNSAT"), g.query.name
@@ -226,7 +226,7 @@ def test_word_order_trees_count_integer_solutions(ctx):
 
 
 def test_split_budget_marks_incomplete(ctx):
-    g = w.config1("none")
+    g = w.single_access("none")
     cnf = ctx.bitblast([g.query.arrays()[:2]])
     cv = ctx.split(cnf, k=20, max_cubes=10).view(0)
     assert not cv["complete"] and len(cv["cubes"]) == 10
@@ -237,7 +237,7 @@ def test_decide_needs_a_device(api, ctx):
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
-    cnf = ctx.bitblast([w.config1("none").query.arrays()[:2]])
+    cnf = ctx.bitblast([w.single_access("none").query.arrays()[:2]])
     from paper_2601_21552_amd import _lib
     with pytest.raises(Exception):
         ctx.decide(cnf, k=30)

@@ -8,7 +8,7 @@ import pytest
 import workloads as w
 from oracle import cnf_ref, query_ref
 from tests.querygen import random_query
-from workloads import oob_2d, config3, Query, config1, config2, oob_1d, partition_query
+from workloads import oob_2d, batch_2d, Query, single_access, batch_1d, oob_1d, partition_query
 
 
 # ---------------------------------------------------------------- worked examples
@@ -119,9 +119,9 @@ def test_t6_lu_decomposition_multiple_of_16():
 # ---------------------------------------------------------------- fixed facts
 
 def test_guarded_access_is_unsat_and_unguarded_sat():
-    assert query_ref.root_check(config1("lt").query) == "UNSAT"
+    assert query_ref.root_check(single_access("lt").query) == "UNSAT"
     for variant in ("none", "le"):
-        g = config1(variant)
+        g = single_access(variant)
         assert query_ref.int_eval_named(g.query, g.witness)
         v, wit, _ = query_ref.decide(g.query)
         assert v == "SAT" and query_ref.int_eval(g.query, wit)
@@ -153,8 +153,8 @@ def test_guarded_small_widths_unsat(w):
         assert cnf_ref.solve(cnf)[0] == "UNSAT"
 
 
-def test_config2_labels_by_construction():
-    gens = config2()
+def test_batch_1d_labels_by_construction():
+    gens = batch_1d()
     assert sum(g.label == "UNSAT" for g in gens) == 128
     for g in gens:
         if g.label == "UNSAT":
@@ -198,8 +198,8 @@ def test_lower_bound_unguarded_count_closed_form():
 
 
 def test_lower_bound_labels_by_construction():
-    from workloads import config_lower
-    gens = config_lower(n=96)
+    from workloads import batch_lower
+    gens = batch_lower(n=96)
     assert sum(g.label == "UNSAT" for g in gens) == 48
     for g in gens:
         if g.label == "UNSAT":
@@ -240,7 +240,7 @@ def test_wrap_labels_by_construction_small():
     """The wrap-around workload at m = 5 (inputs of 3..5 bits): every label
     equals exhaustive search with 5-bit machine integers, and each SAT
     witness satisfies that evaluation; with exact integers all are UNSAT."""
-    gens = w.config_wrap(n=48, m=5, wspan=2)
+    gens = w.batch_wrap(n=48, m=5, wspan=2)
     assert {g.label for g in gens} == {"SAT", "UNSAT"}
     for g in gens:
         assert query_ref.wrap_bruteforce(g.query, 5)[0] == g.label, g.query.name
@@ -249,11 +249,11 @@ def test_wrap_labels_by_construction_small():
             assert query_ref.wrap_eval(g.query, [g.witness[n] for n in g.query.var_names], 5)
 
 
-def test_config3_labels_by_construction():
+def test_batch_2d_labels_by_construction():
     """Correct 2-D guards are UNSAT by the chain row*ld + col <= (R-1)*ld +
     (C-1) < R*ld (C <= ld); the root check must find it through the
     product lemma ld*(R - 1 - row) >= 0.  Buggy ones carry witnesses."""
-    gens = config3(n=600)
+    gens = batch_2d(n=600)
     assert sum(g.label == "UNSAT" for g in gens) == 300
     kinds = set()
     for g in gens:
@@ -300,8 +300,8 @@ def test_fourier_motzkin_textbook_systems():
     assert fm(sys_)
 
 
-def test_config2_sat_decided_at_full_width():
-    gens = [g for g in config2() if g.label == "SAT"][:12]
+def test_batch_1d_sat_decided_at_full_width():
+    gens = [g for g in batch_1d() if g.label == "SAT"][:12]
     for g in gens:
         v, wit, _ = query_ref.decide(g.query)
         assert v == "SAT" and query_ref.int_eval(g.query, wit), g.query.name

@@ -93,7 +93,7 @@ def oob_lower_1d(width: int, guard: str, halo: int, scale: int = 4, name: str = 
     return q
 
 
-def config_lower(seed: int = 6, n: int = 256, wmin: int = 8, wmax: int = 16):
+def batch_lower(seed: int = 6, n: int = 256, wmin: int = 8, wmax: int = 16):
     """Batch of lower-bound stencil queries: widths w ~ U{wmin..wmax}, halo
     ~ U{1..8}, element size s in {1,2,4,8}; half guarded (UNSAT), a quarter
     unguarded and a quarter off by one (SAT); shuffled."""
@@ -117,7 +117,7 @@ def config_lower(seed: int = 6, n: int = 256, wmin: int = 8, wmax: int = 16):
     return out
 
 
-def config_wrap(seed: int = 7, n: int = 256, m: int = 32, wspan: int = 3):
+def batch_wrap(seed: int = 7, n: int = 256, m: int = 32, wspan: int = 3):
     """Guarded 1-D accesses (guard idx < N, test idx*s >= N*s) evaluated with
     m-bit machine integers: widths w ~ U{m-wspan..m}, element size s in
     {1,2,4,8}.  The byte size N*s wraps once N >= 2^m / s, which a w-bit N
@@ -138,10 +138,10 @@ def config_wrap(seed: int = 7, n: int = 256, m: int = 32, wspan: int = 3):
     return out
 
 
-def config1(variant: str = "lt") -> GenQuery:
+def single_access(variant: str = "lt") -> GenQuery:
     """The single query: 12-bit N, blockDim, blockIdx, threadIdx; guard
     idx < N; size 4*N bytes; offset 4*idx; OOB test offset >= size."""
-    q = oob_1d(12, variant, scale=4, header=0, name=f"config1_{variant}")
+    q = oob_1d(12, variant, scale=4, header=0, name=f"single_{variant}")
     if variant == "lt":
         return GenQuery(q, UNSAT, kind="guarded")
     if variant == "none":
@@ -151,7 +151,7 @@ def config1(variant: str = "lt") -> GenQuery:
                     kind="off_by_one")
 
 
-def config2(seed: int = 2, n: int = 256, wmin: int = 8, wmax: int = 16):
+def batch_1d(seed: int = 2, n: int = 256, wmin: int = 8, wmax: int = 16):
     """Batch of 1-D queries: widths w ~ U{wmin..wmax}; element size s in
     {1,2,4,8}; header c ~ U{0..16}; half with the correct guard (UNSAT),
     a quarter unguarded and a quarter off by one (SAT); shuffled."""
@@ -164,7 +164,7 @@ def config2(seed: int = 2, n: int = 256, wmin: int = 8, wmax: int = 16):
         w = int(rng.integers(wmin, wmax + 1))
         s = int(rng.choice([1, 2, 4, 8]))
         c = int(rng.integers(0, 17))
-        q = oob_1d(w, g, scale=s, header=c, name=f"c2_{i}_w{w}_{g}_s{s}_c{c}")
+        q = oob_1d(w, g, scale=s, header=c, name=f"b1d_{i}_w{w}_{g}_s{s}_c{c}")
         if g == "lt":
             out.append(GenQuery(q, UNSAT, kind="guarded"))
         elif g == "none":
@@ -227,7 +227,7 @@ def partition_query(width: int, lens_w: int, k_sub: int, target: int,
     return q
 
 
-def config5(seed: int = 5, n: int = 1024, width: int = 20):
+def partition_batch(seed: int = 5, n: int = 1024, width: int = 20):
     """Intra-allocation partition queries: one allocation of `width`-bit
     size split into k_sub ~ U{2..8} parts at prefix-sum offsets, partition
     sizes by subtraction, a guarded access into part j ~ U{0..k_sub-1}.
@@ -247,7 +247,7 @@ def config5(seed: int = 5, n: int = 1024, width: int = 20):
         else:
             guard = ["le", "next", "prev"][int(rng.integers(3))]
         q = partition_query(width, width, k_sub, j, index, guard, level="partition",
-                            name=f"c5_{qi}_k{k_sub}_j{j}_{index}_{guard}")
+                            name=f"part_{qi}_k{k_sub}_j{j}_{index}_{guard}")
         if guard == "lt":
             out.append(GenQuery(q, UNSAT, kind="partition_guarded"))
             continue
@@ -339,7 +339,7 @@ def _witness_2d(guard: str, mult: int, has_ld: bool) -> dict:
     return wit
 
 
-def config3(seed: int = 3, n: int = 4096, wmin: int = 8, wmax: int = 24):
+def batch_2d(seed: int = 3, n: int = 4096, wmin: int = 8, wmax: int = 24):
     """4096 row-major 2-D accesses of uneven size: widths w ~ U{wmin..wmax},
     multipliers per offset mult ~ U{1,2,3}, element size s in {1,2,4,8},
     header c ~ U{0..16}.  Half correct (row < R and col < C; ld is C, or a
@@ -357,7 +357,7 @@ def config3(seed: int = 3, n: int = 4096, wmin: int = 8, wmax: int = 24):
         s = int(rng.choice([1, 2, 4, 8]))
         c = int(rng.integers(0, 17))
         sep = g == "ok" and rng.random() < 0.25
-        q = oob_2d(w, g, mult, s, c, sep, name=f"c3_{i}_w{w}_{g}_m{mult}_s{s}_c{c}")
+        q = oob_2d(w, g, mult, s, c, sep, name=f"b2d_{i}_w{w}_{g}_m{mult}_s{s}_c{c}")
         if g == "ok":
             out.append(GenQuery(q, UNSAT, kind="guarded_2d"))
         else:
@@ -366,16 +366,16 @@ def config3(seed: int = 3, n: int = 4096, wmin: int = 8, wmax: int = 24):
     return out
 
 
-def config4(seed: int = 4, per_n: int = 2500, ns=(100, 150, 200, 250), ratio: float = 4.26):
+def random_3sat_sets(seed: int = 4, per_n: int = 2500, ns=(100, 150, 200, 250), ratio: float = 4.26):
     """Uniform random 3-SAT at the threshold: per_n instances for each n,
     m = round(ratio * n) clauses.  Returns {n: [CNF, ...]} (no labels: the
     oracle decides them)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return {n: random_ksat_batch(n, int(round(ratio * n)), 3, per_n, rng, prefix=f"c4_")
+    return {n: random_ksat_batch(n, int(round(ratio * n)), 3, per_n, rng, prefix=f"r3sat_")
             for n in ns}
 
 
-def config4_train(seed: int = 40, per_n: int = 1000, ns=(100, 150), ratio: float = 4.26):
+def random_3sat_train(seed: int = 40, per_n: int = 1000, ns=(100, 150), ratio: float = 4.26):
     """The scorer's training instances for the random 3-SAT workload: the
     same model from a disjoint seed."""
     rng = np.random.Generator(np.random.PCG64(seed))
