@@ -153,6 +153,24 @@ __device__ __forceinline__ uint32_t wave_exclusive_scan(uint32_t v, uint32_t* to
   return y - v;
 }
 
+// inclusive maximum over the lanes 0..lane (values below 2^31), by the same
+// DPP row shifts and row totals as the scan above
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
+  const uint32_t lane = threadIdx.x & 63;
+  int x = int(v);
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));   // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));   // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));   // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));   // row_shr:8
+  const int r0 = __builtin_amdgcn_readlane(x, 15), r1 = __builtin_amdgcn_readlane(x, 31),
+            r2 = __builtin_amdgcn_readlane(x, 47);
+  const uint32_t row = lane >> 4;
+  if (row >= 1) x = max(x, r0);
+  if (row >= 2) x = max(x, r1);
+  if (row >= 3) x = max(x, r2);
+  return uint32_t(x);
+}
+
 // The threads that propagate one cube: one wave (TW = 1, four cubes per
 // workgroup) or the whole workgroup (TW = 4, for rounds with few cubes).
 template <int TW>
@@ -295,6 +313,7 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   const uint32_t lane = tm.lane();
   const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
   for (uint32_t w = lane; w < nw; w += S) { T[w] = 0; F[w] = 0; A[w] = 0; }
+  for (uint32_t t = lane; t < S; t += S) X[2 * (t & ~63u) + 64 + (t & 63)] = 0;   // the owner marks
   if (lane == 0) {
     sh.conflict = 0;
     sh.error = 0;
@@ -338,11 +357,15 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   // every TW-th frontier entry and spreads the (entry, occurrence) pairs of
   // up to 64 entries at a time over its lanes: a wave scan of the
   // occurrence counts gives each entry's first pair, and a lane finds the
-  // entry of its pair by binary search over those offsets (Xw[0..63] in
-  // LDS) and the occurrence list starts (Xw[64..127]).  The only team-wide
-  // barrier of a round is at its end.
+  // entry of its pair: among up to four entries by comparisons with their
+  // offsets held in scalar registers, else from marks that each entry
+  // writes at its first pair of a 64-pair chunk (Xw[64..127] in LDS) and a
+  // wave max-scan over them.  The only team-wide barrier of a round is at
+  // its end.
   const uint32_t wl = threadIdx.x & 63, wv = TW == 1 ? 0u : uniform_u32(lane >> 6);
   uint32_t* Xw = X + wv * 128;
+  uint32_t mark_tag = 0;   // tags of the owner marks; 0 (the cleared marks) never matches
+  const uint32_t occ_total = occ.end(2 * nv + 1);
   const uint32_t max_rounds = 2 * nv + 4;
   for (uint32_t r = 0;; r++) {
     const uint32_t k = r % 3, kp = (r + 2) % 3, kn = (r + 1) % 3;
@@ -371,19 +394,47 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
         }
         uint32_t total;
         const uint32_t off = wave_exclusive_scan(cnt, &total);
-        Xw[wl] = off;
-        Xw[64 + wl] = start;
-        wave_sync();
-        const uint32_t rem = n - (wv + TW * base);
-        const uint32_t m = min(64u, (rem + TW - 1) / TW);
-        for (uint32_t q = wl; q < total; q += 64) {
-          uint32_t lo = 0, hi = m;   // Xw[lo] <= q < Xw[hi] (Xw[m] = total)
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (Xw[mid] <= q) lo = mid;
-            else hi = mid;
+        // pair q of an entry reads occurrence q + (start - off) of its list
+        const uint32_t d = start - off;
+        const uint32_t m = min(64u, (n - (wv + TW * base) + TW - 1) / TW);   // lanes with an entry
+        if (m <= 4) {
+          // few entries: a pair's entry is the last one whose offset is at
+          // or below it, among the offsets of lanes 0..3 read into scalar
+          // registers (no LDS round trip; a lane without an entry has
+          // offset = total, above every pair)
+          const uint32_t d0 = uint32_t(__builtin_amdgcn_readlane(int(d), 0)),
+                         d1 = uint32_t(__builtin_amdgcn_readlane(int(d), 1)),
+                         d2 = uint32_t(__builtin_amdgcn_readlane(int(d), 2)),
+                         d3 = uint32_t(__builtin_amdgcn_readlane(int(d), 3)),
+                         o1 = uint32_t(__builtin_amdgcn_readlane(int(off), 1)),
+                         o2 = uint32_t(__builtin_amdgcn_readlane(int(off), 2)),
+                         o3 = uint32_t(__builtin_amdgcn_readlane(int(off), 3));
+          for (uint32_t q = wl; q < total; q += 64) {
+            const uint32_t p = q + (q >= o3 ? d3 : q >= o2 ? d2 : q >= o1 ? d1 : d0);
+            push(visit_clause(cnf, occ.at(p), T, F, k, sh), next, QC, k, sh);
           }
-          push(visit_clause(cnf, occ.at(Xw[64 + lo] + (q - Xw[lo])), T, F, k, sh), next, QC, k, sh);
+          continue;
+        }
+        Xw[wl] = d;
+        uint32_t carry = 0;   // owner (lane + 1) of the previous chunk's last pair
+        for (uint32_t q0 = 0; q0 < total; q0 += 64) {
+          // each entry marks the position of its first pair in this chunk;
+          // a lane's owner is the last mark at or before it (a max-scan of
+          // the tagged marks), else the previous chunk's last owner
+          const uint32_t tag = ++mark_tag % 0xFFFFFFu + 1;   // 1 .. 2^24 - 1
+          if (cnt && off >= q0 && off - q0 < 64) Xw[64 + (off - q0)] = (tag << 8) | (wl + 1);
+          wave_sync();
+          const uint32_t mk = Xw[64 + wl];
+          const uint32_t own = max(wave_inclusive_max((mk >> 8) == tag ? (mk & 0xFFu) : 0u), carry);
+          carry = uint32_t(__builtin_amdgcn_readlane(int(own), 63));
+          const uint32_t q = q0 + wl;
+          uint32_t e = kNone;
+          if (q < total && own != 0) {
+            const uint32_t oi = q + Xw[own - 1];
+            if (oi < occ_total) e = visit_clause(cnf, occ.at(oi), T, F, k, sh);
+          }
+          push(e, next, QC, k, sh);
+          wave_sync();   // the marks are rewritten by the next chunk
         }
         wave_sync();   // Xw is rewritten by the next entries
       }
