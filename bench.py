@@ -214,6 +214,24 @@ def gain_legs(ctx, mlp_q, log):
                          "sat_found": sum(v == "SAT" for v, g in zip(verd, gens) if g.label == "SAT"),
                          "sat_labels": sum(g.label == "SAT" for g in gens)}
     log(f"32-bit wrap-around: {out['wrap32_256']}")
+    # queries that the front-end emits from 128 small generated programs
+    # (host and kernel analysis, upper and lower bound of every access)
+    from paper_2601_21552_amd import frontend
+    import workloads.program as wp
+    progs = wp.random_programs(seed=14, n=128)
+    t0 = time.perf_counter()
+    aqs = [a for p in progs for a in frontend.analyse(p, lower=True)]
+    t1 = time.perf_counter()
+    cnf = ctx.bitblast([a.query.arrays()[:2] for a in aqs])
+    t2 = time.perf_counter()
+    dec = [decide_stats(ctx, cnf, len(aqs), k=30, leaves_per_round=1, chunk_log2=12)[0]
+           for _ in range(3)]
+    best = min(dec, key=lambda d: d["ms"])
+    fe_ms, bbp = 1000.0 * (t1 - t0), 1000.0 * (t2 - t1)
+    out["programs_128"] = {"queries": len(aqs), "frontend_ms": round(fe_ms, 2),
+                           "bitblast_ms": round(bbp, 2), "decide": best,
+                           "queries_per_s": round(len(aqs) / ((fe_ms + bbp + best["ms"]) / 1000.0), 1)}
+    log(f"programs: {out['programs_128']}")
     return out
 
 
