@@ -36,9 +36,9 @@ OPS_PER_CLAUSE_BLOCK = 128
 # read for a device copy of known size), valid only for the kernel source
 # they were taken on
 MEASURED_TRAFFIC = {
-    "device_hip_sha256_16": "a914d44b74b51b37",
-    "up_kernel": 14_431_744,
-    "leaf_kernel": 2_955_878,
+    "device_hip_sha256_16": "3ed960de60b4d0e0",
+    "up_kernel": 14_496_870,
+    "leaf_kernel": 2_953_626,
 }
 
 # learned ordering: candidates scored per decision node, and the levels
@@ -232,6 +232,14 @@ def gain_legs(ctx, mlp_q, log):
                            "bitblast_ms": round(bbp, 2), "decide": best,
                            "queries_per_s": round(len(aqs) / ((fe_ms + bbp + best["ms"]) / 1000.0), 1)}
     log(f"programs: {out['programs_128']}")
+    # use-after-free live-set analysis (host only) on 64 generated programs
+    from paper_2601_21552_amd import uaf
+    uprogs = wp.random_uaf_programs(seed=23, n=64)
+    t0 = time.perf_counter()
+    reports = sum(len(uaf.analyse(p)) for p in uprogs)
+    out["uaf_64"] = {"programs": len(uprogs), "reports": reports,
+                     "analysis_ms": round(1000.0 * (time.perf_counter() - t0), 2)}
+    log(f"use after free: {out['uaf_64']}")
     return out
 
 

@@ -16,6 +16,15 @@ partition offsets in program order, each part ending where the next begins
 and the last one at the dynamic shared size of the launch (the layout that
 Sec. 4.2 and Fig. 9b describe).
 
+Use after free (paper Sec. 4.3 and Sec. 5.3): the run also tracks which
+buffers are live.  On the host a ``malloc`` makes a buffer live and a
+``free`` ends it; a launch that passes a buffer that is not live is a use
+after free, reported as ``("uaf", "launch", launch index, kernel, argument
+position)``.  In a kernel every parameter and every array is live when the
+thread starts, a device ``free`` ends the parameter for the rest of that
+thread, and an access to a data structure that is not live is reported as
+``("uaf", "access", kernel, access index)``.
+
 ``brute_force`` enumerates every input assignment, which is the plain
 definition of "some legal input makes the access go out of bounds"; it is
 meant for programs of a few input bits and a few hundred threads.
@@ -80,13 +89,14 @@ def _number_accesses(body, out):
 
 
 class _Thread:
-    def __init__(self, kname, li, numbering, sizes, shm, record):
+    def __init__(self, kname, li, numbering, sizes, shm, record, params):
         self.kname, self.li, self.num = kname, li, numbering
         self.sizes = dict(sizes)          # buffer name -> size (globals filled in)
         self.shm = shm
         self.parts = []                   # [(name, offset)] of the dynamic shared buffer
         self.record = record
         self.loops = {}
+        self.live = set(params)           # data structures this thread may still use
 
     def part_size(self, name):
         names = [p[0] for p in self.parts]
@@ -101,15 +111,22 @@ class _Thread:
                 env[s[1]] = _value(s[2], env)
             elif k == "static":
                 self.sizes[s[1]] = _value(s[2], env)
+                self.live.add(s[1])
             elif k == "dynshared":
                 self.parts.append((s[1], 0))
+                self.live.add(s[1])
             elif k == "partition":
                 self.parts.append((s[1], _value(s[3], env)))
+                self.live.add(s[1])
+            elif k == "free":
+                self.live.discard(s[1])
             elif k == "access":
                 ds = s[2]
                 offset = _value(s[3], env)
                 size = self.sizes[ds] if ds in self.sizes else self.part_size(ds)
                 ai = self.num[id(s)]
+                if ds not in self.live:
+                    self.record(("uaf", "access", self.kname, ai), env, dict(self.loops))
                 if offset >= size:
                     self.record((self.li, self.kname, ai, "upper"), env, dict(self.loops))
                 if offset < 0:
@@ -128,14 +145,39 @@ class _Thread:
                 env.pop(s[1], None)
 
 
+def _number_launches(stmts, out):
+    """Program-order index of every launch statement, then-branches of host
+    ``if`` blocks before their else-branches."""
+    for s in stmts:
+        if s[0] == "launch":
+            out[id(s)] = len(out)
+        elif s[0] == "hif":
+            _number_launches(s[2], out)
+            _number_launches(s[3], out)
+    return out
+
+
+class _Abort(Exception):
+    pass
+
+
 def run(prog, inputs: dict, record, only=None):
     """Run the program for one input assignment; ``record(key, env, loops)``
     is called for every out-of-bounds access.  ``only`` = (launch index,
-    block (x, y, z), thread (x, y, z)) runs just that thread of that launch."""
+    block (x, y, z), thread (x, y, z)) runs just that thread of that launch.
+    Returns False when an assert stopped the run."""
     env = {}
     sizes = {}
-    li = -1
-    for s in prog.host:
+    numbering = _number_launches(prog.host, {})
+    try:
+        _host(prog, prog.host, inputs, env, sizes, numbering, record, only, set())
+    except _Abort:
+        return False
+    return True
+
+
+def _host(prog, stmts, inputs, env, sizes, launch_no, record, only, live):
+    for s in stmts:
         k = s[0]
         if k == "input":
             env[s[1]] = inputs[s[1]]
@@ -144,11 +186,17 @@ def run(prog, inputs: dict, record, only=None):
         elif k == "malloc":
             sizes[s[1]] = _value(s[2], env)
             env[s[1]] = ("ptr", s[1])
+            live.add(s[1])
+        elif k == "free":
+            live.discard(s[1])
         elif k == "assert":
             if not _value(s[1], env):
-                return False
-        else:
-            li += 1
+                raise _Abort()
+        elif k == "hif":
+            _host(prog, s[2] if _value(s[1], env) else s[3], inputs, env, sizes, launch_no, record,
+                  only, live)
+        elif k == "launch":
+            li = launch_no[id(s)]
             _, kname, grid, blk, shm, args = s
             if only is not None and only[0] != li:
                 continue
@@ -157,9 +205,11 @@ def run(prog, inputs: dict, record, only=None):
             shm_v = _value(shm, env) if shm is not None else 0
             params, body = prog.kernels[kname]
             kenv0, ksizes = {}, {}
-            for name, a in zip(params, args):
+            for pos, (name, a) in enumerate(zip(params, args)):
                 if a[0] == "ref" and isinstance(env[a[1]], tuple):
                     ksizes[name] = sizes[a[1]]
+                    if a[1] not in live and only is None:
+                        record(("uaf", "launch", li, kname, pos), env, {})
                 else:
                     kenv0[name] = _value(a, env)
             numbering = _number_accesses(body, {})
@@ -180,18 +230,24 @@ def run(prog, inputs: dict, record, only=None):
                         kenv[f"blockIdx.{a}"] = bid[i]
                         kenv[f"blockDim.{a}"] = b[i]
                         kenv[f"gridDim.{a}"] = g[i]
-                    _Thread(kname, li, numbering, ksizes, shm_v, record).block(body, kenv)
+                    _Thread(kname, li, numbering, ksizes, shm_v, record, params).block(body, kenv)
     return True
 
 
 def keys(prog, lower=True):
     """Every (launch index, kernel, access index, bound) of the program."""
     out = []
-    li = -1
-    for s in prog.host:
-        if s[0] != "launch":
-            continue
-        li += 1
+    launches = []
+
+    def walk(stmts):
+        for s in stmts:
+            if s[0] == "launch":
+                launches.append(s)
+            elif s[0] == "hif":
+                walk(s[2])
+                walk(s[3])
+    walk(prog.host)
+    for li, s in enumerate(launches):
         n = len(_number_accesses(prog.kernels[s[1]][1], {}))
         for ai in range(n):
             out.append((li, s[1], ai, "upper"))
@@ -239,3 +295,17 @@ def witness_goes_out(prog, key, values: dict) -> bool:
             hits.append(loops)
     run(prog, inputs, record, only=(key[0], bid, tid))
     return bool(hits)
+
+
+def uaf_brute_force(prog):
+    """Every use after free that some input assignment makes happen: the
+    set of ``("uaf", ...)`` keys met over all runs."""
+    found = set()
+    names = [s[1] for s in prog.host if s[0] == "input"]
+    widths = [s[2] for s in prog.host if s[0] == "input"]
+    for vals in itertools.product(*[range(2 ** w) for w in widths]):
+        def record(key, env, loops):
+            if key[0] == "uaf":
+                found.add(key)
+        run(prog, dict(zip(names, vals)), record)
+    return found

@@ -18,7 +18,8 @@ One query per (launch, memory instruction):
   every axis whose dimension is not the literal 1;
 * kind 3: offset, size and grid dimensions are their trees, shared in one
   DAG so that a program variable is one node wherever it is used (the
-  paper's IR-value identity), plus the asserts that precede the launch;
+  paper's IR-value identity), plus the asserts that precede the launch and
+  the conditions of the host branches that hold it;
 * the guards and loop bounds on the access's path;
 * kind 2: ``offset >= size`` (upper), or ``offset < 0`` (lower bound).
 
@@ -60,11 +61,10 @@ def _lit1(e):
 class _Launch:
     """Symbolic context of one launch: expression trees built into one query."""
 
-    def __init__(self, prog: Program, launch, asserts, q: Query):
+    def __init__(self, prog: Program, launch, q: Query):
         self.p, self.q = prog, q
         _, self.kname, self.grid, self.block, shm, args = launch
         self.shm = shm if shm is not None else ("num", 0)
-        self.asserts = asserts
         params, self.body = prog.kernels[self.kname]
         self.host_defs = {}
         for s in prog.host:
@@ -247,25 +247,31 @@ def _kernel_accesses(body):
     return out, lets, statics, parts
 
 
+def _host_launches(stmts, asserts, conds, out):
+    """(launch, asserts before it, host branch conditions on its path) in
+    program order, then-branches first."""
+    for s in stmts:
+        if s[0] == "assert":
+            asserts.append(s[1])
+        elif s[0] == "launch":
+            out.append((s, list(asserts), list(conds)))
+        elif s[0] == "hif":
+            _host_launches(s[2], asserts, conds + [(s[1], True)], out)
+            _host_launches(s[3], asserts, conds + [(s[1], False)], out)
+    return out
+
+
 def analyse(prog: Program, lower: bool = False) -> list[AccessQuery]:
     """One query per (launch, memory instruction), in launch then program
     order; with ``lower`` each access also gets its lower-bound query."""
     out = []
-    asserts = []
-    li = -1
-    for s in prog.host:
-        if s[0] == "assert":
-            asserts.append(s[1])
-            continue
-        if s[0] != "launch":
-            continue
-        li += 1
+    for li, (s, asserts, conds) in enumerate(_host_launches(prog.host, [], [], [])):
         accesses, lets, statics, parts = _kernel_accesses(prog.kernels[s[1]][1])
         for ai, (acc, path) in enumerate(accesses):
             for bound in (("upper", "lower") if lower else ("upper",)):
                 key = (li, s[1], ai, bound)
                 q = Query(f"{prog.name}:L{li}:{s[1]}:{ai}:{bound}")
-                L = _Launch(prog, s, list(asserts), q)
+                L = _Launch(prog, s, q)
                 L.klets = dict(lets)
                 # kind 1 on every axis whose dimension is not the literal 1
                 for ax in range(3):
@@ -274,6 +280,9 @@ def analyse(prog: Program, lower: bool = False) -> list[AccessQuery]:
                             q.require(L.id_var(b, ax) < L.sym(dims[ax], "host"))
                 for a in asserts:
                     q.require(L.sym(a, "host"))
+                for c, taken in conds:
+                    hc = L.sym(c, "host")
+                    q.require(hc if taken else ~hc)
                 for step in path:
                     if step[0] == "if":
                         c = L.sym(step[1], "kernel")

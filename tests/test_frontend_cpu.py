@@ -71,6 +71,20 @@ def test_asserts_after_a_launch_do_not_constrain_it():
     assert truth[(0, "k", 0, "upper")][0]
 
 
+def test_launches_under_host_branches():
+    # the launch of the small-n branch can run past A; the other cannot
+    prog = P.parse("""
+        input n : 4
+        malloc A = n
+        if (n < 4) { launch k grid(1) block(4) args(A) }
+        else { launch k grid(1) block(4) args(A) }
+        kernel k(a) { load a[threadIdx.x] }
+    """, "host_branches")
+    aqs, truth = _check(prog)
+    assert truth[(0, "k", 0, "upper")][0]
+    assert not truth[(1, "k", 0, "upper")][0]
+
+
 @pytest.mark.parametrize("text,match", [
     ("input n : 4\nlet m = k + 1", "before its definition"),
     ("input n : 4\nlet n = 3", "defined twice"),
@@ -85,6 +99,9 @@ def test_asserts_after_a_launch_do_not_constrain_it():
     ("input n : 4\nlaunch k grid(1) block(1) args(n, n)\nkernel k(a) { }", "takes 1 arguments"),
     ("input n : 4\nlaunch q grid(1) block(1) args()", "unknown kernel"),
     ("kernel k(a) { let t = threadIdx.w }", "unknown builtin"),
+    ("input n : 4\nfree n", "not a malloc'd buffer"),
+    ("input n : 4\nif (n < 2) { let m = 3 }", "inside a host branch"),
+    ("kernel k(a) { shared s[2] free s }", "not a parameter"),
 ])
 def test_parse_errors(text, match):
     with pytest.raises(P.ParseError, match=match):

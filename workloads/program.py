@@ -17,8 +17,13 @@ starts a comment)::
               | 'let' NAME '=' expr
               | 'malloc' NAME '=' expr              global buffer of expr elements
               | 'assert' expr
-              | 'launch' NAME 'grid' dims 'block' dims ['shm' '(' expr ')']
+              | 'free' NAME                          release a global buffer
+              | launch
+              | 'if' '(' expr ')' hblock ['else' hblock]
+    launch   := 'launch' NAME 'grid' dims 'block' dims ['shm' '(' expr ')']
                        'args' '(' [expr {',' expr}] ')'
+    hblock   := '{' { 'free' NAME | launch | 'if' ... } '}'   (no inputs, lets,
+                                                    mallocs or asserts in branches)
     dims     := '(' expr [',' expr [',' expr]] ')'   missing axes are 1
     kernel   := 'kernel' NAME '(' [NAME {',' NAME}] ')' block
     block    := '{' { kstmt } '}'
@@ -27,6 +32,7 @@ starts a comment)::
               | 'dynshared' NAME                           base of the dynamic shared buffer
               | 'partition' NAME '=' NAME '+' expr         a part starting at that offset
               | ('load' | 'store' | 'atomic') NAME '[' expr ']'
+              | 'free' NAME                                release a pointer parameter
               | 'if' '(' expr ')' block ['else' block]
               | 'guard' expr        the rest of the block runs only where expr holds
               | 'for' NAME '<' expr block                  NAME = 0, 1, ..., expr - 1
@@ -35,7 +41,8 @@ Expressions use C's operators and precedence (``|| && == != < <= > >= <<
 + - * / % !``), integer literals, names, and ``threadIdx``, ``blockIdx``,
 ``blockDim``, ``gridDim`` with ``.x``/``.y``/``.z``.  Arithmetic is over the
 unbounded integers; ``/``, ``%`` and ``<<`` take a constant right operand.
-All sizes and offsets count elements.
+All sizes and offsets count elements.  Launches are numbered in program
+order, the then-branch of a host ``if`` before its else-branch.
 
 Parsed form: expressions are tuples ``("num", v)``, ``("ref", name)`` (a
 builtin is the name ``"threadIdx.x"`` etc.), ``("bin", op, a, b)``,
@@ -56,7 +63,7 @@ _TOKEN = re.compile(r"\s*(?:(//[^\n]*)|(\d+)|([A-Za-z_][A-Za-z_0-9]*(?:\.[A-Za-z
                     r"(\|\||&&|==|!=|<=|>=|<<|[-+*/%<>!=(){}\[\],:]))")
 _KEYWORDS = {"input", "let", "malloc", "assert", "launch", "grid", "block", "shm", "args",
              "kernel", "shared", "local", "dynshared", "partition", "load", "store",
-             "atomic", "if", "else", "guard", "for"}
+             "atomic", "if", "else", "guard", "for", "free"}
 # C precedence, loosest first
 _LEVELS = [("||",), ("&&",), ("==", "!="), ("<", "<=", ">", ">="), ("<<",), ("+", "-"),
            ("*", "/", "%")]
@@ -161,6 +168,15 @@ class _Parser:
             return (kw, name, self.expr())
         if kw == "assert":
             return ("assert", self.expr())
+        if kw == "free":
+            return ("free", self.take("name"))
+        if kw == "if":
+            self.take("op", "(")
+            c = self.expr()
+            self.take("op", ")")
+            then = self.hblock()
+            other = self.hblock() if self.accept("else") else ()
+            return ("hif", c, then, other)
         if kw == "launch":
             kname = self.take("name")
             self.take("kw", "grid")
@@ -182,6 +198,16 @@ class _Parser:
                 self.take("op", ")")
             return ("launch", kname, grid, block, shm, tuple(args))
         raise ParseError(f"unexpected {kw!r} in host code")
+
+    def hblock(self):
+        self.take("op", "{")
+        body = []
+        while not self.accept("}"):
+            st = self.host()
+            if st[0] not in ("free", "launch", "hif"):
+                raise ParseError(f"{st[0]} inside a host branch")
+            body.append(st)
+        return tuple(body)
 
     def block(self):
         self.take("op", "{")
@@ -210,6 +236,8 @@ class _Parser:
             base = self.take("name")
             self.take("op", "+")
             return ("partition", name, base, self.expr())
+        if kw == "free":
+            return ("free", self.take("name"))
         if kw in ("load", "store", "atomic"):
             ds = self.take("name")
             self.take("op", "[")
@@ -284,7 +312,18 @@ class Program:
         return out
 
     def launches(self):
-        return [s for s in self.host if s[0] == "launch"]
+        """Launch statements in program order (then-branches first)."""
+        out = []
+
+        def walk(stmts):
+            for s in stmts:
+                if s[0] == "launch":
+                    out.append(s)
+                elif s[0] == "hif":
+                    walk(s[2])
+                    walk(s[3])
+        walk(self.host)
+        return out
 
 
 def _names_in(e, out):
@@ -334,7 +373,23 @@ def parse(text: str, name: str = "") -> Program:
         for n in _names_in(e, set()):
             if n not in scope and n not in BUILTINS:
                 raise ParseError(f"{name}: {n} used before its definition")
-    for s in host:
+    def host_stmts(stmts):
+        for s in stmts:
+            if s[0] == "hif":
+                use(s[1], defined)
+                _check_types(s[1], "bool", name)
+                yield s
+                yield from host_stmts(s[2])
+                yield from host_stmts(s[3])
+            else:
+                yield s
+    for s in host_stmts(host):
+        if s[0] == "hif":
+            continue
+        if s[0] == "free":
+            if s[1] not in ptrs:
+                raise ParseError(f"{name}: free of {s[1]}, not a malloc'd buffer")
+            continue
         if s[0] in ("input", "let", "malloc"):
             if s[1] in defined:
                 raise ParseError(f"{name}: {s[1]} defined twice")
@@ -381,7 +436,10 @@ def parse(text: str, name: str = "") -> Program:
                     raise ParseError(f"{name}: {k} {s[1]} must precede the accesses of {kname}")
                 if k == "access":
                     seen_access.append(s)
-                if k == "let":
+                if k == "free":
+                    if s[1] not in params:
+                        raise ParseError(f"{name}: free of {s[1]}, not a parameter of {kname}")
+                elif k == "let":
                     use(s[2], scope)
                     _check_types(s[2], "int", name)
                 elif k == "static":
@@ -596,3 +654,86 @@ def random_program(rng: np.random.Generator, name: str = "") -> Program:
 def random_programs(seed: int = 11, n: int = 24):
     rng = np.random.Generator(np.random.PCG64(seed))
     return [random_program(rng, f"rprog{seed}_{i}") for i in range(n)]
+
+
+# --------------------------------------------------- use-after-free programs
+UAF_EXAMPLES = {
+    # a buffer freed on one path, then passed to a launch; then freed for good
+    "free_then_launch": """
+        input c : 1
+        malloc A = 8
+        malloc B = 8
+        launch k grid(1) block(4) args(A, B)
+        if (c == 1) { free A }
+        launch k grid(1) block(4) args(A, B)
+        free B
+        launch k grid(1) block(4) args(A, B)
+        kernel k(p, q) { load p[threadIdx.x] store q[threadIdx.x] }
+    """,
+    # device-side frees: one under a branch before a later read, one at the
+    # end of a loop body before the next iteration's read
+    "device_free": """
+        input n : 2
+        input f : 1
+        malloc A = 4
+        malloc B = 4
+        launch k grid(1) block(2) args(A, B, n, f)
+        kernel k(p, q, cnt, flag) {
+          shared s[2]
+          load p[0]
+          if (flag == 1) { free p }
+          store s[threadIdx.x]
+          for j < cnt {
+            load q[j]
+            if (flag == 0) { free q }
+          }
+          load p[1]
+        }
+    """,
+    # two branches on the same condition: the buffer is never used after its
+    # free in any run, but a path-insensitive analysis pairs the free of one
+    # branch with the launch of the other
+    "correlated_branches": """
+        input c : 1
+        malloc A = 4
+        if (c == 1) { free A }
+        if (c == 0) { launch k grid(1) block(1) args(A) }
+        kernel k(p) { load p[0] }
+    """,
+}
+
+
+def uaf_examples():
+    return [parse(t, name) for name, t in UAF_EXAMPLES.items()]
+
+
+def random_uaf_program(rng: np.random.Generator, name: str = "") -> Program:
+    """Host code with two buffers, frees and launches under branches that
+    each test an input of their own (so every path is feasible), and a
+    kernel whose device frees sit under branches on a flag argument before
+    unconditional accesses and a loop."""
+    r = lambda n: int(rng.integers(n))
+    n_if = 2 + r(3)
+    lines = [f"input c{i} : 1" for i in range(n_if)]
+    lines += ["input n : 2", "input f : 1", "malloc A = 4", "malloc B = 4"]
+    launch = "launch k grid(1) block(2) args(A, B, n, f)"
+    lines.append(launch)
+    for i in range(n_if):
+        lines.append([f"if (c{i} == 1) {{ free A }}", f"if (c{i} == 1) {{ free B }}",
+                      f"if (c{i} == 1) {{ free A }} else {{ free B }}",
+                      f"if (c{i} == 1) {{ {launch} }}",
+                      f"if (c{i} == 1) {{ {launch} }} else {{ free A }}"][r(5)])
+        if r(2):
+            lines.append(launch)
+    body = ["load p[0]"]
+    for t in range(1 + r(3)):
+        body.append(["if (flag == 1) { free p }", "if (flag == 0) { free q }", "load p[1]",
+                     "store q[0]", f"for j{t} < cnt {{ load q[j{t}] if (flag == 1) {{ free q }} }}",
+                     f"for j{t} < cnt {{ store p[j{t}] }}"][r(6)])
+    kern = "kernel k(p, q, cnt, flag) {\n  " + "\n  ".join(body) + "\n}"
+    return parse("\n".join(lines) + "\n" + kern, name)
+
+
+def random_uaf_programs(seed: int = 21, n: int = 64):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [random_uaf_program(rng, f"ruaf{seed}_{i}") for i in range(n)]
