@@ -42,6 +42,16 @@ def test_random_programs():
     assert 0 < n_sat < n
 
 
+def test_programs_with_host_branches():
+    # launches under host branches: their conditions join the queries
+    n_sat = n = 0
+    for prog in P.uaf_examples() + P.random_uaf_programs(seed=24, n=24):
+        aqs, truth = _check(prog)
+        n += len(aqs)
+        n_sat += sum(truth[a.key][0] for a in aqs)
+    assert 0 < n_sat < n
+
+
 def test_query_shape():
     prog = P.parse(P.EXAMPLES["guarded_grid"], "guarded_grid")
     aqs = fe.analyse(prog)

@@ -58,3 +58,9 @@ def test_random_programs_small_leaves(ctx):
     # a small leaf bound sends the splitter below the root on most queries
     n, n_sat = _decide(ctx, P.random_programs(seed=13, n=48), k=4)
     assert 0 < n_sat < n
+
+
+def test_programs_with_host_branches(ctx):
+    progs = P.uaf_examples() + P.random_uaf_programs(seed=25, n=48)
+    n, n_sat = _decide(ctx, progs, k=30)
+    assert 0 < n_sat < n

@@ -708,14 +708,15 @@ def uaf_examples():
 
 
 def random_uaf_program(rng: np.random.Generator, name: str = "") -> Program:
-    """Host code with two buffers, frees and launches under branches that
-    each test an input of their own (so every path is feasible), and a
-    kernel whose device frees sit under branches on a flag argument before
-    unconditional accesses and a loop."""
+    """Host code with two buffers (A of n + 1 elements, B of 4), frees and
+    launches under branches that each test an input of their own (so every
+    path is feasible), and a kernel whose device frees sit under branches on
+    a flag argument before unconditional accesses and loops of up to n
+    iterations."""
     r = lambda n: int(rng.integers(n))
     n_if = 2 + r(3)
     lines = [f"input c{i} : 1" for i in range(n_if)]
-    lines += ["input n : 2", "input f : 1", "malloc A = 4", "malloc B = 4"]
+    lines += ["input n : 2", "input f : 1", "malloc A = n + 1", "malloc B = 4"]
     launch = "launch k grid(1) block(2) args(A, B, n, f)"
     lines.append(launch)
     for i in range(n_if):
