@@ -227,10 +227,17 @@ def gain_legs(ctx, mlp_q, log):
     dec = [decide_stats(ctx, cnf, len(aqs), k=30, leaves_per_round=1, chunk_log2=12)[0]
            for _ in range(3)]
     best = min(dec, key=lambda d: d["ms"])
+    # the UNSAT queries that the root stage leaves open end in exhaustive
+    # leaves of up to 2^30 assignments at k = 30; the tuner trades leaf size
+    # for splitting
+    tuned, rep = ctx.autotune(cnf, sample=len(aqs), reps=1)
+    dec_t = [decide_stats(ctx, cnf, len(aqs), **tuned)[0] for _ in range(3)]
+    best_t = min(dec_t, key=lambda d: d["ms"])
     fe_ms, bbp = 1000.0 * (t1 - t0), 1000.0 * (t2 - t1)
     out["programs_128"] = {"queries": len(aqs), "frontend_ms": round(fe_ms, 2),
-                           "bitblast_ms": round(bbp, 2), "decide": best,
-                           "queries_per_s": round(len(aqs) / ((fe_ms + bbp + best["ms"]) / 1000.0), 1)}
+                           "bitblast_ms": round(bbp, 2), "decide_k30": best,
+                           "tuned": tuned, "decide_tuned": best_t,
+                           "queries_per_s": round(len(aqs) / ((fe_ms + bbp + best_t["ms"]) / 1000.0), 1)}
     log(f"programs: {out['programs_128']}")
     # use-after-free live-set analysis (host only) on 64 generated programs
     from paper_2601_21552_amd import uaf
