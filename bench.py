@@ -43,11 +43,14 @@ MEASURED_TRAFFIC = {
 
 # learned ordering: candidates scored per decision node, and the levels
 # below a scored node that reuse its ranking (fewer device scoring passes).
-# The access queries are shallow trees: one ranking per 16 levels serves
-# them; the random 3-SAT trees are deeper and are rescored every 4 levels.
+# The access queries are shallow trees (about 27 decisions to a k = 30
+# leaf): one ranking per 32 levels serves them.  With the scorer trained here
+# (seeded), 16 and 64 levels pick leaves whose first model lies deep in the
+# enumeration (3 ms of leaf kernel per step against 0.4 ms).  The random
+# 3-SAT trees are deeper and are rescored every 4 levels.
 LEARNED_CANDIDATES = 16
 LEARNED_RESCORE = 4
-LEARNED_RESCORE_ACCESS = 16
+LEARNED_RESCORE_ACCESS = 32
 
 WORKLOADS = {
     "batch_1d": ("256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, "
