@@ -149,10 +149,15 @@ def test_decide_single_access(ctx):
             assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
 
 
-def test_decide_batch_1d_full(ctx):
+@pytest.mark.parametrize("opts", [
+    dict(k=30),                                             # the library's defaults
+    dict(k=30, leaves_per_round=1, chunk_log2=12),          # the launch point bench.py times
+    dict(k=30, leaves_per_round=1, chunk_log2=12, scorer="word"),
+], ids=["defaults", "bench_point", "word"])
+def test_decide_batch_1d_full(ctx, opts):
     gens = w.batch_1d()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
-    res = ctx.decide(cnf, k=30)
+    res = ctx.decide(cnf, **opts)
     for i, g in enumerate(gens):
         r = res.result(i)
         assert r["verdict"] == g.label, (g.query.name, r)
