@@ -1053,6 +1053,9 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       }
     // the upload's pinned staging is free again only once the copy is done
     if (uploaded) dev_sync(hip_stream);
+    // the walks' state (per-query counters, trails, orders) is released on
+    // the pool rather than one query after another at scope exit
+    parallel_for(nq, [&](size_t qi) { sp[qi].reset(); });
     res->ms[0] = split_ms;
     res->ms[1] = rt.h2d_ms;
     res->ms[2] = rt.up_ms + rt.leaf_ms + rt.graph_ms;
