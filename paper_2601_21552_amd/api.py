@@ -113,6 +113,30 @@ class Results(_Handle):
         return dict(zip(keys, ms.tolist()))
 
 
+def pack_queries(queries):
+    """A batch of query DAGs, each (nodes: NODE_DTYPE array, roots: uint32
+    array), in the layout that scuba_bitblast takes: (all node records, node
+    offsets per query (nq + 1), all roots, root offsets per query (nq + 1))."""
+    queries = list(queries)
+    nq = len(queries)
+    isz = L.NODE_DTYPE.itemsize
+    nb, rb = [], []
+    for n, r in queries:
+        n = np.ascontiguousarray(n)
+        if n.dtype.itemsize != isz:
+            raise ValueError("node records must have the NODE_DTYPE layout")
+        nb.append(n.view(np.uint8).reshape(-1))   # records as raw bytes
+        rb.append(np.asarray(r))
+    ns = np.zeros(nq + 1, np.uint64)
+    rs = np.zeros(nq + 1, np.uint64)
+    if nq:
+        ns[1:] = np.cumsum([len(b) // isz for b in nb])
+        rs[1:] = np.cumsum([len(r) for r in rb])
+    an = np.concatenate(nb).view(L.NODE_DTYPE) if nq else np.zeros(0, L.NODE_DTYPE)
+    ar = np.ascontiguousarray(np.concatenate(rb).astype(np.uint32, copy=False)) if nq else np.zeros(0, np.uint32)
+    return an, ns, ar, rs
+
+
 _SCORERS = {"static": L.SCORER_STATIC, "learned": L.SCORER_LEARNED, "word": L.SCORER_WORD}
 
 
@@ -162,25 +186,18 @@ class Context:
     # ------------------------------------------------------------ CNF
     def bitblast(self, queries, flags: int = 0) -> Cnf:
         """queries: iterable of (nodes: NODE_DTYPE array, roots: uint32 array)."""
-        queries = list(queries)
-        nq = len(queries)
-        isz = L.NODE_DTYPE.itemsize
-        nb, rb = [], []
-        for n, r in queries:
-            n = np.ascontiguousarray(n)
-            if n.dtype.itemsize != isz:
-                raise ValueError("node records must have the NODE_DTYPE layout")
-            nb.append(n.view(np.uint8).reshape(-1))   # records as raw bytes
-            rb.append(np.asarray(r))
-        ns = np.zeros(nq + 1, np.uint64)
-        rs = np.zeros(nq + 1, np.uint64)
-        if nq:
-            ns[1:] = np.cumsum([len(b) // isz for b in nb])
-            rs[1:] = np.cumsum([len(r) for r in rb])
-        an = np.concatenate(nb).view(L.NODE_DTYPE) if nq else np.zeros(0, L.NODE_DTYPE)
-        ar = np.ascontiguousarray(np.concatenate(rb).astype(np.uint32, copy=False)) if nq else np.zeros(0, np.uint32)
+        return self.bitblast_packed(*pack_queries(queries), flags=flags)
+
+    def bitblast_packed(self, nodes, node_start, roots, root_start, flags: int = 0) -> Cnf:
+        """A batch already in scuba_bitblast's layout (see ``pack_queries``)."""
+        an = np.ascontiguousarray(nodes)
+        if an.dtype != L.NODE_DTYPE:
+            raise ValueError("node records must have the NODE_DTYPE layout")
+        ns = np.ascontiguousarray(node_start, dtype=np.uint64)
+        ar = np.ascontiguousarray(roots, dtype=np.uint32)
+        rs = np.ascontiguousarray(root_start, dtype=np.uint64)
         h = _P()
-        self._check(self.lib.scuba_bitblast(self.h, nq, _ptr(an), _ptr(ns), _ptr(ar), _ptr(rs),
+        self._check(self.lib.scuba_bitblast(self.h, len(ns) - 1, _ptr(an), _ptr(ns), _ptr(ar), _ptr(rs),
                                             flags, C.byref(h)))
         return Cnf(self, h)
 
