@@ -84,6 +84,20 @@ def test_wrap_rejects_inputs_wider_than_the_machine_word(api, ctx):
     assert _status(api, lambda: ctx.bitblast([q.arrays()[:2]], flags=_lib.BB_WRAP(32))) == -2   # SCUBA_E_WIDTH
 
 
+def test_packed_batch_gives_the_same_cnf(api, ctx):
+    gens = w.batch_1d(n=32) + [w.single_access("none")]
+    arrays = [g.query.arrays()[:2] for g in gens]
+    a = ctx.bitblast(arrays)
+    b = ctx.bitblast_packed(*api.pack_queries(arrays))
+    assert len(a) == len(b) == len(gens)
+    for i in range(len(gens)):
+        va, vb = a.view(i), b.view(i)
+        assert va["n_vars"] == vb["n_vars"] and va["root_unsat"] == vb["root_unsat"]
+        assert np.array_equal(va["clause_off"], vb["clause_off"])
+        assert np.array_equal(va["lits"], vb["lits"])
+    assert len(ctx.bitblast_packed(*api.pack_queries([]))) == 0
+
+
 def test_input_map_and_witness_decoding(ctx):
     g = w.single_access("none")
     cnf = ctx.bitblast([g.query.arrays()[:2]])
