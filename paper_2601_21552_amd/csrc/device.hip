@@ -460,9 +460,18 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
     return;
   }
 
-  // ---- active variables
-  for (uint32_t c = lane; c < nc; c += S) {
+  // ---- active variables, over contiguous clauses per lane; a lane with at
+  // most 64 clauses keeps which of them are unsatisfied for the residual
+  // records below (others test them again there)
+  const uint32_t cpl = (nc + S - 1) / S;
+  const uint32_t c0 = min(nc, lane * cpl), c1 = min(nc, c0 + cpl);
+  const bool keep = cpl <= 64;
+  uint64_t unsat = 0;
+  uint32_t my_unsat = 0;
+  for (uint32_t c = c0; c < c1; c++) {
     if (clause_satisfied(cnf, c, T, F)) continue;
+    my_unsat++;
+    if (keep) unsat |= uint64_t(1) << (c - c0);
     for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
       uint32_t v;
       bool neg;
@@ -492,18 +501,13 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
 
   const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
 
-  // ---- residual records, in clause order (contiguous clauses per lane)
-  const uint32_t cpl = (nc + S - 1) / S;
-  const uint32_t c0 = min(nc, lane * cpl), c1 = min(nc, c0 + cpl);
-  uint32_t my_unsat = 0;
-  for (uint32_t c = c0; c < c1; c++)
-    if (!clause_satisfied(cnf, c, T, F)) my_unsat++;
+  // ---- residual records, in clause order (the same contiguous clauses)
   uint32_t n_unsat;
   uint32_t pos = tm.scan(my_unsat, &n_unsat);
   const bool cap_ok = n_unsat <= cd.nres_cap;
   if (f_ok && cap_ok) {
     for (uint32_t c = c0; c < c1; c++) {
-      if (clause_satisfied(cnf, c, T, F)) continue;
+      if (keep ? !((unsat >> (c - c0)) & 1) : clause_satisfied(cnf, c, T, F)) continue;
       uint64_t low = 0, lm = 0;
       uint32_t hp = 0, hn = 0;
       for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
