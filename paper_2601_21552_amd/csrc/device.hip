@@ -372,10 +372,12 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
     const uint32_t* cur = Q + ((r + 1) & 1) * QC;
     uint32_t* next = Q + (r & 1) * QC;
     if (lane == 0) { sh.qn[kn] = 0; sh.ovf[kn] = 0; sh.chg[kn] = 0; }
-    if (uniform_u32(sh.ovf[kp])) {
+    // both counters of the previous round are read at once
+    const uint32_t ovf_p = uniform_u32(sh.ovf[kp]), qn_p = uniform_u32(sh.qn[kp]);
+    if (ovf_p) {
       for (uint32_t c = lane; c < nc; c += S) push(visit_clause(cnf, c, T, F, k, sh), next, QC, k, sh);
     } else {
-      const uint32_t n = min(uniform_u32(sh.qn[kp]), QC);
+      const uint32_t n = min(qn_p, QC);
       for (uint32_t base = 0; wv + TW * base < n; base += 64) {
         const uint32_t j = wv + TW * (base + wl);
         uint32_t cnt = 0, start = 0;
@@ -383,13 +385,15 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
           const uint32_t e = cur[j];
           const uint32_t v = e >> 1, val = e & 1;
           const uint32_t bit = 1u << (v & 31);
+          // the literal of v that is now false is the negative one iff v = 1;
+          // its list bounds are loaded alongside the conflict test
+          const uint32_t li = 2 * v + val;
+          const uint32_t b = occ.beg(li), en = occ.end(li);
           if (T[v >> 5] & F[v >> 5] & bit) {
             sh.conflict = 1;
           } else {
-            // the literal of v that is now false is the negative one iff v = 1
-            const uint32_t li = 2 * v + val;
-            start = occ.beg(li);
-            cnt = occ.end(li) - start;
+            start = b;
+            cnt = en - b;
           }
         }
         uint32_t total;
