@@ -157,9 +157,11 @@ class _Launch:
         self._rng[key] = r
         return r
 
-    @staticmethod
-    def _width(hi):
-        return max(1, (max(hi, 1) - 1).bit_length())
+    def _width(self, hi):
+        w = max(1, (max(hi, 1) - 1).bit_length())
+        if w > 64:
+            raise FrontendError(f"{self.p.name}: an id or loop counter may exceed 64 bits")
+        return w
 
     # ---- expression trees into the query ----------------------------
     def id_var(self, b, ax):

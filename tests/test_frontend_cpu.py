@@ -136,3 +136,11 @@ def test_frontend_rejections():
     """)
     with pytest.raises(fe.FrontendError, match="negative"):
         fe.analyse(bad_div)
+    wide = P.parse("""
+        input n : 40
+        malloc A = n
+        launch k grid(n * n) block(1) args(A)
+        kernel k(a) { load a[blockIdx.x] }
+    """)
+    with pytest.raises(fe.FrontendError, match="64 bits"):
+        fe.analyse(wide)
