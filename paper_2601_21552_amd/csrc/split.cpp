@@ -565,8 +565,16 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
     }
     at_fresh_node_ = true;
   }
+  if (pending_) {
+    pending_ = false;
+    if (!finish_branch(std::move(pending_r_), out, keep_refuted)) { state_ = kExhausted; return state_; }
+    if (cubes_total() >= max_cubes_) { state_ = kBudget; return state_; }
+    at_fresh_node_ = true;
+    word_checked_ = false;
+  }
   for (;;) {
     Failure r;
+    bool leaf = false;
     if (at_fresh_node_ && !stack_.empty() && !q_.word_facts.empty() && !word_checked_) {
       word_checked_ = true;
       if (!word_check(&r.levels)) {
@@ -609,6 +617,7 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
         emit(CubeKind::kLeaf, path(), out, keep_refuted);
         produced_++;
         r.unknown = true;
+        leaf = true;
       } else {
         const int32_t lit = first_literal(v);
         stack_.push_back({lit, 0, trail_.size(), Failure{}});
@@ -617,6 +626,11 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
         emit(CubeKind::kRefuted, path(), out, keep_refuted);
       }
       at_fresh_node_ = false;
+    }
+    if (leaf && produced_ >= max_leaves) {
+      pending_r_ = std::move(r);
+      pending_ = true;
+      return kRunning;
     }
     const bool moved = finish_branch(std::move(r), out, keep_refuted);
     if (!moved) { state_ = kExhausted; return state_; }

@@ -173,6 +173,10 @@ class Splitter {
   uint32_t produced_ = 0;
   bool awaiting_ = false;
   bool started_ = false, root_conflict_ = false, at_fresh_node_ = false;
+  // the branch that a call's last leaf ended, finished by the next call
+  // (work that a query decided by that leaf never needs)
+  bool pending_ = false;
+  Failure pending_r_;
   State state_ = kRunning;
   uint64_t n_leaves_ = 0, n_refuted_ = 0, n_pruned_ = 0;
 };
