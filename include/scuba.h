@@ -2,8 +2,8 @@
  * scuba.h - C ABI of the MI355X OOB-query decision library.
  *
  * What is decided.  For every static memory access the bounds analysis
- * builds one constraint set (paper Sec. 4.1 "three kinds of constraints",
- * Sec. 5.2): thread/block ids below their dimensions (kind 1), the access
+ * builds one constraint set (paper Sec. 4.1 and Sec. 5.2, constraint kinds
+ * 1-3): thread/block ids below their dimensions (kind 1), the access
  * offset reaching the allocation or partition size (kind 2), and the
  * equalities that define offset, size, grid dimensions and asserts through
  * expression trees (kind 3, Sec. 5.1, Fig. 8, Fig. 9).  The set is

@@ -13,7 +13,9 @@ Contents
 * ``encode``          - the oracle's own Tseitin encoding (two's complement,
   widths that never overflow, full-equivalence gates): an independent
   re-derivation of the CNF route, used to decide queries at full width.
-* ``root_check``      - the oracle's word-level reasoning: every comparison
+* ``root_check``      - the oracle's word-level reasoning (the same method as
+  the library's root stage, written apart from it; only its soundness is
+  pinned, against exhaustive search): every comparison
   is brought to a polynomial normal form and the bounds asserted on the same
   polynomial are intersected; an empty intersection proves UNSAT.  Failing
   that, the root facts, their products with single atoms (kept when every

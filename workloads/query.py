@@ -1,7 +1,7 @@
 """Query DAG format and a small builder for it.
 
 A query is the constraint set that the bounds analysis emits for one static
-memory access (Sec. 4.1, "three kinds of constraints"; Sec. 5.2): thread and
+memory access (its constraint kinds 1-3, Sec. 4.1 and Sec. 5.2): thread and
 block ids below their dimensions, equalities that define offset, size, grid
 dimensions and asserts through expression trees, and the out-of-bounds test
 ``offset >= size``.  Expression trees (Sec. 5.1, Fig. 8) become one DAG per
