@@ -204,7 +204,7 @@ typedef struct {
 typedef struct {
   uint32_t k;            /* max active variables per leaf (<= 38)            */
   uint32_t scorer;       /* SCUBA_SCORER_*                                   */
-  uint64_t max_cubes;    /* per query, leaves + refuted                       */
+  uint64_t max_cubes;    /* per query, leaves + refuted (at most 2^26)        */
   uint32_t max_residual; /* a leaf must also have at most this many residual
                             clauses (0 = the device limit)                   */
   uint32_t reserved;
@@ -280,7 +280,8 @@ void scuba_trace_free(scuba_trace* t);
 typedef struct {
   uint32_t mode;             /* SCUBA_MODE_*                                  */
   uint32_t k;                /* split bound for scuba_decide (<= 38)          */
-  uint64_t max_cubes;        /* per query budget for scuba_decide             */
+  uint64_t max_cubes;        /* per query budget for scuba_decide (<= 2^26;
+                                0 = 100000)                                   */
   uint32_t leaves_per_round; /* lazily split leaves per query per round       */
   uint32_t chunk_log2;       /* leaf work item = 2^chunk_log2 blocks of 4096
                                 assignments                                   */

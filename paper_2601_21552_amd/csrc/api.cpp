@@ -125,6 +125,7 @@ constexpr uint32_t kDefaultLeavesPerRound = 4;
 constexpr uint32_t kDefaultChunkLog2 = 8;
 constexpr uint64_t kDefaultMaxCubes = 100000;
 constexpr uint32_t kMaxCubeLen = 4096;
+constexpr uint64_t kMaxCubesPerQuery = uint64_t(1) << 26;
 
 struct Opts {
   uint32_t mode, k, lpr, chunk_log2, grid, max_rounds, scorer;
@@ -150,6 +151,9 @@ Opts resolve(const scuba_solve_opts* o) {
     if (o->max_residual) r.max_res = o->max_residual;
   }
   if (r.max_res > 8192) fail(SCUBA_E_INVALID, "max_residual above 8192");
+  // the device's witness key is (cube sequence << 38) | assignment index:
+  // a query's cube sequence numbers must stay below 2^26
+  if (r.max_cubes > kMaxCubesPerQuery) fail(SCUBA_E_INVALID, "max_cubes above 2^26 per query");
   if (r.flags & ~SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "unknown solve flags");
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
@@ -614,6 +618,7 @@ scuba_status scuba_split(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_split
     const bool learned = opts->scorer == SCUBA_SCORER_LEARNED;
     uint32_t max_res = opts->max_residual ? opts->max_residual : kDefaultMaxResidual;
     uint64_t max_cubes = opts->max_cubes ? opts->max_cubes : kDefaultMaxCubes;
+    if (max_cubes > kMaxCubesPerQuery) fail(SCUBA_E_INVALID, "max_cubes above 2^26 per query");
     const size_t nq = cnf->q.size();
     std::unique_ptr<ScorerRunner> runner;
     if (learned) {

@@ -1095,9 +1095,13 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
       HIP_OK(hipEventCreateWithFlags(&graphs->ready, hipEventDisableTiming));
     }
     hipStream_t gs = graphs->stream;
-    std::vector<uint64_t> key = {uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(staging)), cl.end, nc,
-                                 rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), mode, gu, gl,
-                                 rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw};
+    // every value the captured kernels and copies bake in: pointers, the
+    // offsets of both layouts, sizes, group count and launch shapes
+    std::vector<uint64_t> key = {uint64_t(uintptr_t(ws)), uint64_t(uintptr_t(staging)),
+                                 cl.q, cl.coff, cl.lits, cl.occ_off, cl.occ, cl.qkey, cl.end,
+                                 rl.head, rl.cubes, rl.groups, rl.lits, rl.items, rl.outs, rl.res, rl.end,
+                                 up_bytes, nc, rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), n_groups,
+                                 mode, gu, gl, rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw};
     auto it = graphs->execs.find(key);
     if (it == graphs->execs.end()) {
       hipGraph_t graph;

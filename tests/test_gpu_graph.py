@@ -73,3 +73,25 @@ def test_count_graph_replays_match_eager(ctx):
         if rep == 0:
             assert total == sum(cnf_ref.count(f) for f in cnfs)
         ctx.solve(raw, cubes, mode=1)   # eager in between
+
+
+def test_graph_key_covers_cube_grouping(ctx):
+    """Two solves whose rounds have the same sizes (queries, cubes, literals,
+    work items) but group their cubes differently (300 cubes split 100/200,
+    then 102/198: 75 against 76 workgroup groups of up to four cubes of one
+    query) must not share a captured graph: each replay equals the eager
+    results of its own cube list."""
+    rng = np.random.Generator(np.random.PCG64(302))
+    f = w.random_ksat(24, 80, 3, rng)
+    raw = ctx.cnf_from_arrays(*w.concat([f, f]))
+    for split in ((100, 200), (102, 198), (100, 200)):
+        cubes = ctx.cubes_from_arrays(raw, [[[1]] * split[0], [[-1]] * split[1]])
+        eager = ctx.solve(raw, cubes, mode=1)
+        res = ctx.solve(raw, cubes, mode=1, graph=True)
+        for qi in range(2):
+            for c in range(split[qi]):
+                assert res.leaf(qi, c) == eager.leaf(qi, c), (split, qi, c)
+        ref = cnf_ref.leaf(f, [1])
+        assert eager.leaf(0, 0)["refuted"] == ref["refuted"]
+        if not ref["refuted"]:
+            assert (eager.leaf(0, 0)["f"], eager.leaf(0, 0)["count"]) == (ref["f"], ref["count"])

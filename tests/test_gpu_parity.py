@@ -299,3 +299,55 @@ def test_decide_batch_2d_one_call(ctx):
             assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars)), g.query.name
         elif i % 8 == 0:
             assert query_ref.root_check(g.query) == "UNSAT", g.query.name
+
+
+def _component_cnf(nv, rng, name):
+    """Variables 1..nv split into components of 2-4 variables, each with 1-3
+    random clauses of 2-3 literals over its own variables, every variable in
+    some clause.  Components share no variable, so the model count is the
+    product of the components' counts and the smallest satisfying index
+    (slot j = variable j + 1, all variables active) is the sum of each
+    component's smallest contribution; both are found by enumerating each
+    component's few assignments: closed forms that need no search."""
+    perm = rng.permutation(nv) + 1
+    comps, i = [], 0
+    while i < nv:
+        size = int(rng.integers(2, 5))
+        if nv - i - size == 1:
+            size += 1
+        comps.append(sorted(int(v) for v in perm[i:i + size]))
+        i += size
+    clauses, count, first = [], 1, 0
+    for vs in comps:
+        while True:
+            cl = []
+            for _ in range(int(rng.integers(1, 4))):
+                k = int(rng.integers(2, min(3, len(vs)) + 1))
+                pick = rng.choice(vs, size=k, replace=False)
+                cl.append([int(v) if rng.integers(2) else -int(v) for v in pick])
+            if {abs(l) for c in cl for l in c} == set(vs):
+                break
+        clauses += cl
+        sols = []
+        for bits in range(1 << len(vs)):
+            val = {v: (bits >> t) & 1 for t, v in enumerate(vs)}
+            if all(any((val[abs(l)] == 1) == (l > 0) for l in c) for c in cl):
+                sols.append(sum(val[v] << (v - 1) for v in vs))
+        count *= len(sols)
+        first += min(sols)
+    return w.CNF.from_clauses(nv, clauses, name=name), count, first
+
+
+@pytest.mark.parametrize("f", [31, 34, 38])
+def test_count_high_slots_closed_form(ctx, f):
+    """Leaves of 31..38 active variables reach the block-index slots 12..37
+    (block bits up to 25): COUNT over one whole-formula leaf equals the
+    closed-form count and smallest satisfying index."""
+    rng = np.random.Generator(np.random.PCG64(700 + f))
+    cnf, count, first = _component_cnf(f, rng, f"comp{f}")
+    raw = _raw(ctx, [cnf])
+    cubes = ctx.cubes_from_arrays(raw, [[[]]])
+    out = ctx.solve(raw, cubes, mode=1, chunk_log2=12)
+    lf = out.leaf(0, 0)
+    assert (lf["refuted"], lf["f"], lf["m"]) == (False, f, 0), lf
+    assert lf["count"] == count and lf["first"] == first, (lf, count, first)

@@ -381,3 +381,17 @@ def test_trace_word_candidates_and_range_label(api, ctx):
     # the word candidates are input bits at the top of their words
     tail = feats[sel][m:]
     assert np.all(tail[:, 7] == 1.0)
+
+
+def test_max_cubes_beyond_witness_key_is_rejected(api):
+    """The device witness key holds a cube sequence number below 2^26: a
+    larger per-query budget is refused before any work."""
+    from paper_2601_21552_amd import _lib
+    import workloads as w
+    ctx = api.Context(0)
+    cnf = ctx.bitblast([w.single_access("lt").query.arrays()[:2]])
+    with pytest.raises(_lib.ScubaError):
+        ctx.split(cnf, k=30, max_cubes=(1 << 26) + 1)
+    with pytest.raises(_lib.ScubaError):
+        ctx.decide_workspace(cnf, k=30, max_cubes=(1 << 26) + 1)
+    ctx.split(cnf, k=30, max_cubes=1 << 26)

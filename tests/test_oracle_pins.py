@@ -306,3 +306,15 @@ def test_guarded_2d_shapes_refuted_by_dpll():
     for mult, sep in ((1, False), (1, True), (2, False)):
         cnf, _ = query_ref.encode(oob_2d(2, "ok", mult, 2, 1, sep))
         assert cnf_ref.solve(cnf, 50_000_000)[0] == "UNSAT", (mult, sep)
+
+
+def test_component_closed_form_matches_oracle_leaf():
+    """The closed-form count and smallest index of the component formulas
+    that the GPU test uses at 31..38 active variables equal the oracle's
+    canonical leaf where #DPLL still finishes (10..18 variables)."""
+    from tests.test_gpu_parity import _component_cnf
+    for nv in (10, 12, 14, 16, 18):
+        rng = np.random.Generator(np.random.PCG64(700 + nv))
+        cnf, count, first = _component_cnf(nv, rng, f"comp{nv}")
+        lf = cnf_ref.leaf(cnf, [])
+        assert (lf["f"], lf["m"], lf["count"], lf["first"]) == (nv, 0, count, first)
