@@ -12,11 +12,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libscuba.so")
+MICRO_LIB = os.path.join(HERE, "libkmicro.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 HOST_SRCS = ["api.cpp", "encode.cpp", "split.cpp", "verify.cpp"]
 HIP_SRCS = ["device.hip", "mlp.hip"]
+MICRO_SRC = "kmicro.hip"   # microbenchmarks, a library of their own
 
 CXXFLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
             "-fvisibility=hidden"]
@@ -43,6 +45,8 @@ def build(verbose: bool = False) -> str:
     for s in HIP_SRCS:
         jobs.append([HIPCC, *HIPFLAGS, "-I", os.path.join(HERE, "..", "include"),
                      "-c", os.path.join(CSRC, s), "-o", os.path.join(OBJ, s + ".o")])
+    jobs.append([HIPCC, *HIPFLAGS, "-I", os.path.join(HERE, "..", "include"),
+                 "-c", os.path.join(CSRC, MICRO_SRC), "-o", os.path.join(OBJ, MICRO_SRC + ".o")])
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         for r in ex.map(_run, jobs):
             if verbose and (r.stdout or r.stderr):
@@ -51,6 +55,9 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    tmp = MICRO_LIB + ".tmp"
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, os.path.join(OBJ, MICRO_SRC + ".o")])
+    os.replace(tmp, MICRO_LIB)
     return LIB
 
 
