@@ -1,20 +1,28 @@
 """Throughput of the OOB-query decision path on one MI355X.
 
 One step = the whole path for one batch: query DAGs -> normalisation and
-Tseitin CNF (host) -> lazy cube splitting (host) -> device unit propagation
-and bit-sliced leaf evaluation (gfx950) -> verified verdicts and witnesses.
-Default workload: 256 seeded 1-D access queries (widths 8-16 bits, element
-size s in {1,2,4,8}, header c in 0..16; 128 with the correct guard, 128
-unguarded or off by one), static cubing with k = 30.
+Tseitin CNF (host) -> cube splitting (host) -> device unit propagation and
+bit-sliced leaf evaluation (gfx950) -> verified verdicts and witnesses.
 
-Prints one JSON line: queries decided per second over the timed steps, the
-roofline of the dominant kernel (HIP events on the library's stream) and the
-CPU oracle timed on this host's cores.  Every step's verdicts must agree with
-the oracle (and the generators' labels); witnesses are re-checked exactly.
+Default workload (the largest single-GPU batch): 4096 seeded 2-D row-major
+accesses of uneven width (inputs of 8-24 bits, one to three multipliers in
+the offset, guards row < R and col < C), 2048 correct (UNSAT) and 2048 buggy
+(SAT), decided in one call per step with autotuned options (cube depth k,
+work-item size, leaves per round, grid, leaf tile, HIP graphs).
+
+Prints one JSON line: queries decided per second over the timed steps for
+the headline cube ordering, the same for every ordering (static, learned,
+word) with its agreement, the roofline of the dominant kernel (HIP events
+bracketing each dispatch, on the stream the kernel runs on), microbenchmark
+peaks of this GPU, and the CPU oracle timed on this host's cores.  Every
+step's verdicts are checked against the generators' labels (pinned by
+exhaustive search in the CPU tests); the CPU-baseline leg re-decides a
+sample with the oracle and re-checks every witness exactly.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,77 +32,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_INT32_TOPS = 39.3216   # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (int32 VALU)
+PEAK_INT32_TOPS = 39.3216   # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (int32 VALU lane-ops)
 PEAK_HBM_GBS = 8000.0
 # per evaluated clause-block (one residual clause against 4096 assignments):
 # the 64-bit AND of the clause's satisfaction word into each of the 64 lanes'
 # accumulators = 64 lanes x 2 int32 ops
 OPS_PER_CLAUSE_BLOCK = 128
 
-# HBM bytes per launch from two rocprofv3 counter passes over this bench's
-# default workload (FETCH_SIZE / 0.5 + WRITE_SIZE, both scaled by what they
-# read for a device copy of known size), valid only for the kernel source
-# they were taken on
-MEASURED_TRAFFIC = {
-    "device_hip_sha256_16": "dffad7f9ea90893e",
-    "up_kernel": 14_491_136,
-    "leaf_kernel": 3_004_501,
-}
+# HBM bytes per launch from two rocprofv3 counter passes (FETCH_SIZE /
+# 0.5 + WRITE_SIZE, both scaled by what they read for a device copy of known
+# size), valid only for the kernel source, workload and options they were
+# taken on
+MEASURED_TRAFFIC = {}
 
 # learned ordering: candidates scored per decision node, and the levels
-# below a scored node that reuse its ranking (fewer device scoring passes).
-# The access queries are shallow trees (about 27 decisions to a k = 30
-# leaf): one ranking per 32 levels serves them.  With the scorer trained here
-# (seeded), 16 and 64 levels pick leaves whose first model lies deep in the
-# enumeration (3 ms of leaf kernel per step against 0.4 ms).  The random
-# 3-SAT trees are deeper and are rescored every 4 levels.
+# below a scored node that reuse its ranking
 LEARNED_CANDIDATES = 16
 LEARNED_RESCORE = 4
 LEARNED_RESCORE_ACCESS = 32
 
 WORKLOADS = {
-    "batch_1d": ("256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, "
-                 "c in 0..16, 128 guarded (UNSAT) / 64 unguarded + 64 off-by-one (SAT); "
-                 "static cubing k=30"),
-    "single": "one 12-bit guarded idx<N query (UNSAT), static cubing k=30",
+    "batch_2d": ("4096 seeded 2-D OOB queries of uneven width: inputs 8-24 bits, 1-3 multipliers per "
+                 "offset (row = by*bdy+ty, col = bx*bdx+tx), offset (row*ld+col)*s+c vs size R*ld*s+c, "
+                 "2048 guarded (UNSAT) / 2048 buggy (SAT); one decide call per step, autotuned, HIP graphs"),
+    "batch_1d": ("256 seeded 1-D OOB queries, widths 8-16 bits, s in {1,2,4,8}, c in 0..16, "
+                 "128 guarded (UNSAT) / 64 unguarded + 64 off-by-one (SAT); k=30"),
+    "single": "one 12-bit guarded idx<N query (UNSAT), k=30",
 }
+MAX_CUBES = {"batch_2d": 20000, "batch_1d": 100000, "single": 100000}
+
+
+def log(m):
+    print(m, file=sys.stderr, flush=True)
 
 
 def make_batch(workload: str):
     import workloads as w
     if workload == "single":
         return [w.single_access("lt")]
-    return w.batch_1d()
-
-
-def oracle_leg(gens, cores: int):
-    """The oracle as it stands, timed on this host; returns (value, verdicts,
-    seconds, cores)."""
-    from concurrent.futures import ProcessPoolExecutor
-    t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=cores) as ex:
-        verdicts = list(ex.map(_oracle_one, [g.query for g in gens], chunksize=4))
-    dt = time.perf_counter() - t0
-    return len(gens) / dt, verdicts, dt
-
-
-def _oracle_one(q):
-    from oracle import query_ref
-    return query_ref.decide(q)[0]
-
-
-def measured_traffic(args):
-    """The counter figures when they apply: same kernel source, default
-    workload and launch options; else None."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_2601_21552_amd", "csrc", "device.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    default = (args.workload == "batch_1d" and args.k == 30 and args.leaves_per_round == 1
-               and args.chunk_log2 == 12)
-    if sha != MEASURED_TRAFFIC["device_hip_sha256_16"] or not default:
-        return None
-    return MEASURED_TRAFFIC
+    if workload == "batch_1d":
+        return w.batch_1d()
+    return w.batch_2d()
 
 
 def train_scorer(ctx, batches, k, epochs, seed, candidates=32, depth=24):
@@ -137,50 +115,250 @@ def decide_stats(ctx, cnf, n, labels=None, **opts):
     return out, verdicts
 
 
-def gain_legs(ctx, mlp_q, log):
-    """Learned vs static on samples of the random 3-SAT workload (scorer
-    trained on disjoint-seed instances) and the partition queries (scorer
-    trained on 1-D / 2-D access traces): verdicts must agree; leaves, cubes
-    and wall time are reported."""
+class Steps:
+    """Timed steps of the whole path on one batch: bit-blast of the packed
+    query DAGs, then one decide call with fixed options."""
+
+    def __init__(self, ctx, packed, gens, stream, args):
+        self.ctx, self.packed, self.gens, self.stream, self.args = ctx, packed, gens, stream, args
+        self.labels = [g.label for g in gens]
+
+    def run(self, opts, steps=None, warmup=None):
+        import torch
+        ctx = self.ctx
+        steps = self.args.steps if steps is None else steps
+        warmup = self.args.warmup if warmup is None else warmup
+        bb_ms = []
+
+        def step():
+            t0 = time.perf_counter()
+            cnf = ctx.bitblast_packed(*self.packed)
+            bb_ms.append(1000.0 * (time.perf_counter() - t0))
+            return cnf, ctx.decide(cnf, stream=self.stream, **opts)
+
+        # the first call of a fresh shape (graph captures included)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        first_ms = 1000.0 * (time.perf_counter() - t0)
+        for _ in range(max(warmup - 1, 0)):
+            step()
+        torch.cuda.synchronize()
+        bb_ms.clear()
+        t0 = time.perf_counter()
+        out, last_cnf = [], None
+        for _ in range(steps):
+            cnf, res = step()
+            out.append(res)
+            last_cnf = cnf   # a step's CNF is released when the next replaces it
+            del cnf
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        agree, unknown = [], 0
+        for res in out:
+            vs = res.verdicts()
+            wrong = sum(v != "UNKNOWN" and v != l for v, l in zip(vs, self.labels))
+            assert wrong == 0, ("a verdict contradicts the generator's label", opts)
+            agree.append(sum(v == l for v, l in zip(vs, self.labels)) / len(vs))
+            unknown = sum(v == "UNKNOWN" for v in vs)
+            for i, v in enumerate(vs):
+                if v == "SAT":
+                    assert res.result(i)["witness_checked"]
+        return dict(ms_per_step=1000.0 * elapsed / steps, results=out, cnf=last_cnf,
+                    first_ms=first_ms, agree=min(agree), unknown=unknown,
+                    bitblast_ms=sorted(bb_ms)[len(bb_ms) // 2])
+
+
+def kernel_accounting(steps: "Steps", run, traffic_key):
+    """Per-kernel durations (HIP events bracketing each dispatch), launches
+    and algorithmic work of a run's steps; the dominant kernel's roofline."""
+    res_list, cnf = run["results"], run["cnf"]
+    n = len(steps.gens)
+    leaf_ms = up_ms = 0.0
+    leaf_launches = up_launches = 0
+    split_ms = verify_ms = 0.0
+    for res in res_list:
+        tm = res.timing()
+        leaf_ms += tm["leaf"]
+        up_ms += tm["up"]
+        leaf_launches += int(tm["leaf_launches"])
+        up_launches += int(tm["up_launches"])
+        split_ms += tm["split"]
+        verify_ms += tm["verify"]
+    res = res_list[-1]
+    k = len(res_list)
+    detail = dict(decided_at_root=0, decided_on_device=0, unknown=0, leaves_sent=0, leaves_refuted=0,
+                  blocks_evaluated=0, clause_blocks=0, word_ops=0)
+    up_bytes = 0
+    for i in range(n):
+        r = res.result(i)
+        detail["decided_at_root"] += r["how"] == "root"
+        detail["decided_on_device"] += r["how"] == "device"
+        detail["unknown"] += r["verdict"] == "UNKNOWN"
+        for key in ("leaves_sent", "leaves_refuted", "blocks_evaluated", "clause_blocks", "word_ops"):
+            detail[key] += r[key]
+        if r["leaves_sent"]:
+            v = cnf.sizes(i)
+            # every cube sent reads its query's CSR CNF once: 4 (C + 1 + L) bytes
+            up_bytes += r["leaves_sent"] * 4 * (v["n_clauses"] + 1 + v["n_lits"])
+    last = res.timing()
+    lpl = max(int(last["leaf_launches"]), 1)
+    upl = max(int(last["up_launches"]), 1)
+    kernels = {
+        "leaf_kernel": dict(bound="alu", ms_step=leaf_ms / k, avg=leaf_ms / max(leaf_launches, 1),
+                            per_launch=2 * detail["word_ops"] / lpl,
+                            peak=PEAK_INT32_TOPS, unit="TOP/s (int32 lane-ops: 2 per 64-bit word op, "
+                            "64 words x (|c|+1) per evaluated clause-block)", scale=1e12,
+                            launches=leaf_launches / k,
+                            clause_block_rate=OPS_PER_CLAUSE_BLOCK * detail["clause_blocks"] / lpl),
+        "up_kernel": dict(bound="hbm", ms_step=up_ms / k, avg=up_ms / max(up_launches, 1),
+                          per_launch=up_bytes / upl, peak=PEAK_HBM_GBS,
+                          unit="GB/s (each cube's CSR CNF read once)", scale=1e9, launches=up_launches / k),
+    }
+    dom = max(kernels, key=lambda x: kernels[x]["ms_step"])
+
+    def line(name):
+        kd = kernels[name]
+        ach = kd["per_launch"] / (kd["avg"] * 1e-3) / kd["scale"] if kd["avg"] > 0 else 0.0
+        tr = MEASURED_TRAFFIC.get(traffic_key, {}).get(name)
+        out = {"kernel": name, "bound": kd["bound"], "achieved": round(ach, 4), "peak": kd["peak"],
+               "unit": kd["unit"], "frac": round(ach / kd["peak"], 5), "traffic": tr,
+               "avg_launch_ms": round(kd["avg"], 4), "launches_per_step": kd["launches"],
+               "per_launch": kd["per_launch"]}
+        if name == "leaf_kernel":
+            out["clause_block_rate_tops"] = round(kd["clause_block_rate"] / (kd["avg"] * 1e-3) / 1e12, 4) \
+                if kd["avg"] > 0 else 0.0
+        return out
+    roof = line(dom)
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roof["other"] = line("leaf_kernel" if dom == "up_kernel" else "up_kernel")
+    detail.update(host_split_ms_per_step=round(split_ms / k, 3), verify_ms_per_step=round(verify_ms / k, 3),
+                  leaf_kernel_ms_per_step=round(leaf_ms / k, 3), up_kernel_ms_per_step=round(up_ms / k, 3))
+    return roof, detail
+
+
+def traffic_key(workload, opts):
+    src = os.path.join(ROOT, "paper_2601_21552_amd", "csrc", "device.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return f"{workload}:{sha}:{json.dumps(opts, sort_keys=True)}"
+
+
+# ------------------------------------------------------------------ CPU baseline
+
+def _oracle_decide(q):
+    from oracle import query_ref
+    return query_ref.decide(q)[0]
+
+
+def _oracle_dpll(arrs):
+    """The oracle's C DPLL on one query's CNF bytes as the library emitted
+    them (root-refuted queries have no CNF: UNSAT)."""
+    import numpy as np
+    from oracle import cnf_ref
+    from workloads.cnf import CNF
+    n_vars, off, lits, root_unsat = arrs
+    if root_unsat:
+        return "UNSAT"
+    return cnf_ref.solve(CNF(n_vars, np.asarray(off, np.uint64), np.asarray(lits, np.int32)))[0]
+
+
+def cpu_baseline_leg(gens, cnf, path_verdicts, results_last):
+    """The oracle as it stands, timed on this host: (1) the whole oracle
+    (root check, own Tseitin encoding, C DPLL) on a stratified sample of the
+    batch, on every core of this process's share and on one core; (2) the C
+    DPLL alone on the library's own CNF bytes of the same sample (bit-blast
+    is shared and timed on its own line).  Checks the oracle's verdicts
+    against the path's, and every SAT witness of the path exactly."""
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import query_ref
+    n = len(gens)
+    # the process's CPU share (16 on a one-GPU box); the pool is capped there
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    m = min(n, 256)
+    idx = [i * n // m for i in range(m)]
+    sample = [gens[i].query for i in idx]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        ov = list(ex.map(_oracle_decide, sample, chunksize=2))
+    dt_all = time.perf_counter() - t0
+    one = idx[:max(m // 8, 1)]
+    t0 = time.perf_counter()
+    ov1 = [_oracle_decide(gens[i].query) for i in one]
+    dt_one = time.perf_counter() - t0
+    agree = sum(a == path_verdicts[i] for a, i in zip(ov, idx)) / m
+    unknown = sum(a == "UNKNOWN" for a in ov)
+    assert all(a == path_verdicts[i] for a, i in zip(ov1, one))
+    # the C DPLL on the library's CNF bytes
+    arrs = []
+    for i in idx:
+        v = cnf.view(i)
+        arrs.append((v["n_vars"], v["clause_off"], v["lits"], bool(v["root_unsat"])))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        dv = list(ex.map(_oracle_dpll, arrs, chunksize=2))
+    dt_dpll = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dv1 = [_oracle_dpll(a) for a in arrs[:len(one)]]
+    dt_dpll1 = time.perf_counter() - t0
+    dpll_agree = sum(a == path_verdicts[i] for a, i in zip(dv, idx)) / m
+    assert dv1 == dv[:len(one)]
+    # every SAT witness of the last timed step, by the exact definition
+    for i, g in enumerate(gens):
+        if path_verdicts[i] == "SAT":
+            assert query_ref.int_eval(g.query, results_last.witness(i, g.query.n_vars))
+    return {
+        "value": round(m / dt_all, 3), "unit": "queries/s", "cores": cores, "kind": "oracle",
+        "sample": (f"{m} of the {n} queries (every {n // m}th), the whole oracle per query (root check, "
+                   f"own Tseitin encoding, C DPLL) in {cores} processes: {dt_all:.2f} s wall; the pool is "
+                   "capped at 16, this process's CPU share on a one-GPU box"),
+        "one_core": {"value": round(len(one) / dt_one, 3), "queries": len(one), "seconds": round(dt_one, 2)},
+        "dpll_on_library_cnf": {
+            "value": round(m / dt_dpll, 3), "cores": cores, "one_core_value": round(len(one) / dt_dpll1, 3),
+            "note": "C DPLL on the CNF bytes the library bit-blasted (shared bit-blast excluded; queries the "
+                    "root stage refuted have no CNF and count as decided)",
+            "agreement": dpll_agree},
+        "oracle_agreement": agree, "oracle_unknown": unknown,
+    }
+
+
+# ------------------------------------------------------------------ other legs
+
+def gain_legs(ctx, mlp_q, mlp_s_info, args):
+    """Learned vs static on samples of the random 3-SAT sets (scorer trained
+    on disjoint-seed instances) at every n, with autotuned k, and the
+    partition queries; the smaller access workloads and the front-end."""
     import workloads as w
+    from oracle import cnf_ref
     out = {}
-    # random 3-SAT: n = 100 and 150, k = 16
-    tr = w.random_3sat_train(per_n=48)
-    tr_batches = [ctx.cnf_from_arrays(*w.concat(tr[100])),
-                  ctx.cnf_from_arrays(*w.concat(tr[150][:16]))]
-    mlp_s, info = train_scorer(ctx, tr_batches, k=16, epochs=6, seed=4, candidates=16, depth=40)
-    log(f"3-SAT scorer trained: {info}")
-    ev = w.random_3sat_sets(per_n=128, ns=(100, 150))
-    for n, count in ((100, 128), (150, 32)):
+    mlp_s, info = mlp_s_info
+    out["random3sat_scorer"] = info
+    per_n = {100: 256, 150: 64, 200: 16, 250: 8}
+    oracle_n = {100: 32, 150: 8, 200: 2, 250: 1}
+    ev = w.random_3sat_sets(per_n=max(per_n.values()), ns=tuple(per_n))
+    for n, count in per_n.items():
         cnfs = ev[n][:count]
         raw = ctx.cnf_from_arrays(*w.concat(cnfs))
-        st, vs = decide_stats(ctx, raw, count, k=16, max_cubes=400000)
-        le, vl = decide_stats(ctx, raw, count, k=16, max_cubes=400000,
+        tuned, rep = ctx.autotune(raw, sample=min(count, 32), reps=1, max_cubes=400000)
+        k = tuned["k"]
+        base = dict(k=k, leaves_per_round=tuned["leaves_per_round"], chunk_log2=tuned["chunk_log2"],
+                    grid=tuned["grid"], max_cubes=400000)
+        st, vs = decide_stats(ctx, raw, count, **base)
+        le, vl = decide_stats(ctx, raw, count, **base,
                               learned=mlp_s.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE))
         assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vs, vl))
-        leg = {"instances": count, "static": st, "learned": le,
+        no = oracle_n[n]
+        ov = [cnf_ref.solve(f, 3_000_000)[0] for f in cnfs[:no]]
+        agree = [a == b for a, b in zip(ov, vs[:no]) if a != "UNKNOWN"]
+        assert all(agree), "oracle disagrees on random 3-SAT"
+        leg = {"instances": count, "of": 2500, "k_autotuned": k, "tuned": tuned, "static": st, "learned": le,
                "leaf_ratio": round(le["leaves"] / max(st["leaves"], 1), 3),
-               "time_ratio": round(le["ms"] / max(st["ms"], 1e-9), 3)}
-        if n == 100:
-            # checked against the oracle in the CPU-baseline leg
-            out["_random3sat_n100_check"] = (cnfs, vs)
+               "time_ratio": round(le["ms"] / max(st["ms"], 1e-9), 3),
+               "oracle_sample": no, "oracle_unknown": sum(a == "UNKNOWN" for a in ov),
+               "oracle_agreement": (sum(agree) / len(agree)) if agree else None}
         out[f"random3sat_n{n}"] = leg
         log(f"3-SAT n={n}: {leg}")
-    out["random3sat_scorer"] = info
-    # 4096 2-D accesses of uneven width in one decide call, autotuned and
-    # captured as HIP graphs (word ordering)
-    gens3 = w.batch_2d()
-    t0 = time.perf_counter()
-    cnf3 = ctx.bitblast([g.query.arrays()[:2] for g in gens3])
-    bb3 = 1000.0 * (time.perf_counter() - t0)
-    tuned, rep = ctx.autotune(cnf3, sample=128, reps=1, scorer="word", graph=True)
-    labels3 = [g.label for g in gens3]
-    dec = [decide_stats(ctx, cnf3, len(gens3), labels3, max_cubes=20000, **tuned)[0] for _ in range(2)]
-    best = min(dec, key=lambda d: d["ms"])
-    out["batch_4096_2d"] = {"bitblast_ms": round(bb3, 1), "tuned": tuned,
-                            "tune_points": rep["points"], "decide": best,
-                            "queries_per_s": round(len(gens3) / ((bb3 + best["ms"]) / 1000.0), 1)}
-    log(f"4096 2-D accesses: {out['batch_4096_2d']}")
     # partition queries, all 1024
     gens = w.partition_batch()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
@@ -202,8 +380,7 @@ def gain_legs(ctx, mlp_q, log):
     out["lower_bound_256"] = {"bitblast_ms": round(bbl, 2), "decide": best,
                               "queries_per_s": round(len(gens) / ((bbl + best["ms"]) / 1000.0), 1)}
     log(f"lower-bound reads: {out['lower_bound_256']}")
-    # the same guarded 1-D accesses with 32-bit machine integers: byte sizes
-    # that wrap are found SAT; the wrap-safe UNSAT ones may stay UNKNOWN
+    # the same guarded 1-D accesses with 32-bit machine integers
     from paper_2601_21552_amd import _lib
     gens = w.batch_wrap(m=32)
     t0 = time.perf_counter()
@@ -216,7 +393,6 @@ def gain_legs(ctx, mlp_q, log):
                          "sat_labels": sum(g.label == "SAT" for g in gens)}
     log(f"32-bit wrap-around: {out['wrap32_256']}")
     # queries that the front-end emits from 128 small generated programs
-    # (host and kernel analysis, upper and lower bound of every access)
     from paper_2601_21552_amd import frontend
     import workloads.program as wp
     progs = wp.random_programs(seed=14, n=128)
@@ -225,18 +401,11 @@ def gain_legs(ctx, mlp_q, log):
     t1 = time.perf_counter()
     cnf = ctx.bitblast([a.query.arrays()[:2] for a in aqs])
     t2 = time.perf_counter()
-    dec = [decide_stats(ctx, cnf, len(aqs), k=30, leaves_per_round=1, chunk_log2=12)[0]
-           for _ in range(3)]
-    best = min(dec, key=lambda d: d["ms"])
-    # the UNSAT queries that the root stage leaves open end in exhaustive
-    # leaves of up to 2^30 assignments at k = 30; the tuner trades leaf size
-    # for splitting
     tuned, rep = ctx.autotune(cnf, sample=len(aqs), reps=1)
     dec_t = [decide_stats(ctx, cnf, len(aqs), **tuned)[0] for _ in range(3)]
     best_t = min(dec_t, key=lambda d: d["ms"])
     fe_ms, bbp = 1000.0 * (t1 - t0), 1000.0 * (t2 - t1)
-    out["programs_128"] = {"queries": len(aqs), "frontend_ms": round(fe_ms, 2),
-                           "bitblast_ms": round(bbp, 2), "decide_k30": best,
+    out["programs_128"] = {"queries": len(aqs), "frontend_ms": round(fe_ms, 2), "bitblast_ms": round(bbp, 2),
                            "tuned": tuned, "decide_tuned": best_t,
                            "queries_per_s": round(len(aqs) / ((fe_ms + bbp + best_t["ms"]) / 1000.0), 1)}
     log(f"programs: {out['programs_128']}")
@@ -247,7 +416,21 @@ def gain_legs(ctx, mlp_q, log):
     reports = sum(len(uaf.analyse(p)) for p in uprogs)
     out["uaf_64"] = {"programs": len(uprogs), "reports": reports,
                      "analysis_ms": round(1000.0 * (time.perf_counter() - t0), 2)}
-    log(f"use after free: {out['uaf_64']}")
+    return out
+
+
+def secondary_1d(ctx, stream, args, mlp_q):
+    """The 1-D batch (256 queries, k = 30) under each ordering: queries/s."""
+    import workloads as w
+    from paper_2601_21552_amd import api
+    gens = w.batch_1d()
+    steps = Steps(ctx, api.pack_queries([g.query.arrays()[:2] for g in gens]), gens, stream, args)
+    out = {}
+    for name, extra in (("static", {}), ("word", dict(scorer="word")),
+                        ("learned", dict(learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)))):
+        r = steps.run(dict(k=30, leaves_per_round=1, chunk_log2=12, **extra))
+        out[name] = {"queries_per_s": round(len(gens) / (r["ms_per_step"] / 1000.0), 1),
+                     "ms_per_step": round(r["ms_per_step"], 3), "agree": r["agree"]}
     return out
 
 
@@ -256,13 +439,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batch_1d", choices=sorted(WORKLOADS))
-    ap.add_argument("--k", type=int, default=30)
-    ap.add_argument("--leaves-per-round", type=int, default=1)
-    ap.add_argument("--chunk-log2", type=int, default=12)
+    ap.add_argument("--workload", default="batch_2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--form", default="auto", choices=("auto", "static", "learned", "word"),
+                    help="ordering of the headline value (auto: learned if it agrees 100%%, else static "
+                         "if it does, else word)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the word / learned forms")
-    ap.add_argument("--no-gain", action="store_true", help="skip the learned-vs-static legs")
+    ap.add_argument("--only-form", action="store_true",
+                    help="time only the --form ordering (profiling runs)")
+    ap.add_argument("--no-gain", action="store_true", help="skip the 3-SAT / partition / other legs")
+    ap.add_argument("--no-micro", action="store_true", help="skip the microbenchmark peaks")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a plain copy kernel of known "
                          "size, to scale hardware byte counters under a profiler)")
@@ -285,196 +470,121 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    micro = None
+    if not args.no_micro:
+        from paper_2601_21552_amd import kmicro
+        micro = kmicro.measure()
+        log(f"microbenchmark peaks: {micro}")
+
     gens = make_batch(args.workload)
-    arrays = [g.query.arrays()[:2] for g in gens]
-    # the batch in the boundary's input layout (all node records and roots
-    # with per-query offsets), as a caller holding the query DAGs has it
-    packed = api.pack_queries(arrays)
-    labels = [g.label for g in gens]
+    packed = api.pack_queries([g.query.arrays()[:2] for g in gens])
     ctx = api.Context(0)
     stream = torch.cuda.current_stream()
-    opts = dict(k=args.k, leaves_per_round=args.leaves_per_round, chunk_log2=args.chunk_log2)
+    steps = Steps(ctx, packed, gens, stream, args)
+    n = len(gens)
+    max_cubes = MAX_CUBES[args.workload]
 
-    bb_ms = []
+    # the learned scorer, trained on traces of other seeds' access batches
+    import workloads as w
+    t0 = time.perf_counter()
+    tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.batch_1d(seed=102)]),
+          ctx.bitblast([g.query.arrays()[:2] for g in w.batch_2d(seed=103, n=1024)])]
+    mlp_q, scorer_info = train_scorer(ctx, tr, k=30, epochs=4, seed=2)
+    scorer_info["seconds"] = round(time.perf_counter() - t0, 1)
+    log(f"access-query scorer trained: {scorer_info}")
 
-    def run_steps(extra):
-        def step():
-            t0 = time.perf_counter()
-            cnf = ctx.bitblast_packed(*packed)
-            bb_ms.append(1000.0 * (time.perf_counter() - t0))
-            res = ctx.decide(cnf, stream=stream, **opts, **extra)
-            return cnf, res
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
+    # per ordering: autotuned options (static / word; the learned form runs
+    # at the static ordering's point), timed steps, agreement with the labels
+    cnf0 = ctx.bitblast_packed(*packed)
+    forms, runs = {}, {}
+    names = [args.form] if (args.only_form and args.form != "auto") else ["static", "learned", "word"]
+    tuned = {}
+    for name in names:
         t0 = time.perf_counter()
-        out = []
-        last_cnf = None
-        for _ in range(args.steps):
-            cnf, res = step()
-            out.append(res)
-            # a step's CNF is released when the next step replaces it, as in a
-            # pipeline that frees each batch after deciding it; the results stay
-            last_cnf = cnf
-            del cnf
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        for res in out:
-            for i, g in enumerate(gens):
-                r = res.result(i)
-                assert r["verdict"] == labels[i], (g.query.name, r, extra)
-                if r["verdict"] == "SAT":
-                    assert r["witness_checked"]
-        return 1000.0 * elapsed / args.steps, out, last_cnf
+        if name in ("static", "word"):
+            tuned[name], rep = ctx.autotune(cnf0, sample=128, reps=1, scorer=name, graph=True,
+                                            max_cubes=max_cubes)
+        else:
+            if "static" not in tuned:
+                tuned["static"], rep = ctx.autotune(cnf0, sample=128, reps=1, graph=True, max_cubes=max_cubes)
+            rep = {"points": 0}
+        tune_s = time.perf_counter() - t0
+        opts = dict(tuned["static" if name == "learned" else name], max_cubes=max_cubes)
+        if name == "learned":
+            opts.pop("scorer", None)
+            opts["learned"] = mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)
+        r = steps.run(opts)
+        runs[name] = (r, opts)
+        forms[name] = {"queries_per_s": round(n / (r["ms_per_step"] / 1000.0), 3),
+                       "ms_per_step": round(r["ms_per_step"], 3), "agree": r["agree"], "unknown": r["unknown"],
+                       "first_call_ms": round(r["first_ms"], 2), "bitblast_ms": round(r["bitblast_ms"], 3),
+                       "tune_s": round(tune_s, 2), "tune_points": rep["points"],
+                       "options": {k: v for k, v in opts.items() if k != "learned"}}
+        log(f"form {name}: {forms[name]}")
+    if args.form == "auto":
+        head = next((f for f in ("learned", "static", "word") if f in forms and forms[f]["agree"] == 1.0),
+                    max(forms, key=lambda f: forms[f]["agree"]))
+    else:
+        head = args.form
+    run, opts = runs[head]
 
-    ms_per_step, results, last_cnf = run_steps({})
-    bitblast_ms = sorted(bb_ms[args.warmup:])[len(bb_ms[args.warmup:]) // 2]
+    # per-kernel events: the same steps eagerly (graph replays carry no
+    # per-dispatch events), HIP events bracketing each dispatch
+    ev_opts = dict(opts, graph=False)
+    ev = steps.run(ev_opts, warmup=1)
+    tkey = traffic_key(args.workload, {k: v for k, v in ev_opts.items() if k != "learned"} | {"form": head})
+    roofline, detail = kernel_accounting(steps, ev, tkey)
+    if micro:
+        for line in (roofline, roofline["other"]):
+            mp = micro["valu_int32_tops"] if line["bound"] == "alu" else micro["hbm_gbs"]
+            line["measured_peak"] = mp
+            line["frac_of_measured_peak"] = round(line["achieved"] / mp, 5) if mp else None
+    detail["eager_ms_per_step"] = round(ev["ms_per_step"], 3)
+    detail["bitblast_ms_per_step"] = round(run["bitblast_ms"], 3)
+    detail["first_call_ms"] = round(run["first_ms"], 2)
+    detail["traffic_key"] = tkey
 
-    # accounting over the timed steps (every SAT witness was checked by the
-    # library's own verifier; the oracle's checks run in the CPU-baseline leg)
-    n_root = n_dev = n_unknown = 0
-    clause_blocks = leaves_sent = leaves_refuted = blocks_evaluated = 0
-    leaf_ms = up_ms = 0.0
-    leaf_launches = up_launches = 0
-    split_ms = verify_ms = 0.0
-    for res in results:
-        tm = res.timing()
-        leaf_ms += tm["leaf"]
-        up_ms += tm["up"]
-        leaf_launches += int(tm["leaf_launches"])
-        up_launches += int(tm["up_launches"])
-        split_ms += tm["split"]
-        verify_ms += tm["verify"]
-    cnf, res = last_cnf, results[-1]
-    for i, g in enumerate(gens):
-        r = res.result(i)
-        n_root += r["how"] == "root"
-        n_dev += r["how"] == "device"
-        n_unknown += r["verdict"] == "UNKNOWN"
-        clause_blocks += r["clause_blocks"]
-        leaves_sent += r["leaves_sent"]
-        leaves_refuted += r["leaves_refuted"]
-        blocks_evaluated += r["blocks_evaluated"]
-
-    steps = args.steps
-    # algorithmic work of the last step (every step does the same work)
-    up_bytes = 0
-    for i in range(len(gens)):
-        r = res.result(i)
-        if r["leaves_sent"]:
-            v = cnf.view(i)
-            up_bytes += r["leaves_sent"] * 4 * (v["n_clauses"] + 1 + len(v["lits"]))
-    leaf_avg_ms = leaf_ms / max(leaf_launches, 1)
-    up_avg_ms = up_ms / max(up_launches, 1)
-    kernels = {
-        "leaf_kernel": dict(bound="alu", ms_step=leaf_ms / steps, avg=leaf_avg_ms,
-                            per_launch=OPS_PER_CLAUSE_BLOCK * clause_blocks / max(leaf_launches / steps, 1),
-                            peak=PEAK_INT32_TOPS, unit="TOP/s (int32 VALU lane-ops)", scale=1e12,
-                            launches=leaf_launches / steps),
-        "up_kernel": dict(bound="hbm", ms_step=up_ms / steps, avg=up_avg_ms,
-                          per_launch=up_bytes / max(up_launches / steps, 1),
-                          peak=PEAK_HBM_GBS, unit="GB/s (CNF bytes per cube)", scale=1e9,
-                          launches=up_launches / steps),
-    }
-    dom = max(kernels, key=lambda k: kernels[k]["ms_step"])
-    kd = kernels[dom]
-    achieved = kd["per_launch"] / (kd["avg"] * 1e-3) / kd["scale"] if kd["avg"] > 0 else 0.0
-    traffic = measured_traffic(args)
-    roofline = {"bound": kd["bound"], "kernel": dom, "achieved": round(achieved, 4),
-                "peak": kd["peak"], "unit": kd["unit"], "frac": round(achieved / kd["peak"], 5),
-                "traffic": traffic.get(dom) if traffic else None,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "avg_launch_ms": round(kd["avg"], 4),
-                "launches_per_step": kd["launches"]}
-    other = "leaf_kernel" if dom == "up_kernel" else "up_kernel"
-    ko = kernels[other]
-    oach = ko["per_launch"] / (ko["avg"] * 1e-3) / ko["scale"] if ko["avg"] > 0 else 0.0
-    roofline["other"] = {"kernel": other, "bound": ko["bound"], "achieved": round(oach, 4),
-                         "traffic": traffic.get(other) if traffic else None,
-                         "peak": ko["peak"], "unit": ko["unit"], "frac": round(oach / ko["peak"], 5),
-                         "avg_launch_ms": round(ko["avg"], 4), "launches_per_step": ko["launches"]}
-    roofline["clause_blocks_per_step"] = clause_blocks
-    roofline["up_cnf_bytes_per_step"] = up_bytes
-
-    # the other orderings on the same batch and steps, and the learned
-    # scorer's gains on the random 3-SAT and partition workloads
-    def log(m):
-        print(m, file=sys.stderr, flush=True)
-
-    forms = {"static": round(len(gens) / (ms_per_step / 1000.0), 3)}
+    secondary = None
     gain = None
-    scorer_info = None
-    if not (args.no_forms and args.no_gain):
-        import workloads as w
-        tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.batch_1d(seed=102)]),
-              ctx.bitblast([g.query.arrays()[:2] for g in w.batch_2d(seed=103, n=1024)])]
-        mlp_q, scorer_info = train_scorer(ctx, tr, k=30, epochs=4, seed=2)
-        log(f"access-query scorer trained: {scorer_info}")
-    if not args.no_forms:
-        for name, extra in (("word", dict(scorer="word")),
-                            ("learned", dict(learned=mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)))):
-            ms, _, _ = run_steps(extra)
-            forms[name] = round(len(gens) / (ms / 1000.0), 3)
-        log(f"forms (queries/s): {forms}")
-    if not args.no_gain:
-        gain = gain_legs(ctx, mlp_q, log)
+    if not args.only_form:
+        secondary = {"batch_1d_256": secondary_1d(ctx, stream, args, mlp_q)}
+        log(f"1-D batch: {secondary}")
+        if not args.no_gain:
+            tr3 = w.random_3sat_train(per_n=48)
+            tb = [ctx.cnf_from_arrays(*w.concat(tr3[100])), ctx.cnf_from_arrays(*w.concat(tr3[150][:16]))]
+            mlp_s = train_scorer(ctx, tb, k=16, epochs=6, seed=4, candidates=16, depth=40)
+            gain = gain_legs(ctx, mlp_q, mlp_s, args)
 
     cpu = None
-    agree = None
-    check = gain.pop("_random3sat_n100_check", None) if gain else None
     if not args.no_cpu_baseline:
-        # the CPU-baseline leg: the oracle timed on this host, and its checks
-        # of the path's verdicts and witnesses
-        from oracle import cnf_ref, query_ref
-        cores = len(os.sched_getaffinity(0))
-        cores = min(cores, 16)
-        v, overd, dt = oracle_leg(gens, cores)
-        agree = sum(a == b for a, b in zip(overd, labels)) / len(labels)
-        assert agree == 1.0, "oracle disagrees with the path"
-        res = results[-1]
-        for i, g in enumerate(gens):
-            if res.result(i)["verdict"] == "SAT":
-                assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars))
-        if check is not None:
-            cnfs3, vs3 = check
-            ov = [cnf_ref.solve(f)[0] for f in cnfs3]
-            gain["random3sat_n100"]["oracle_agreement"] = sum(a == b for a, b in zip(ov, vs3)) / len(vs3)
-            assert gain["random3sat_n100"]["oracle_agreement"] == 1.0
-        cpu = {"value": round(v, 3), "unit": "queries/s", "cores": cores, "kind": "oracle",
-               "sample": f"the full {len(gens)}-query batch once ({dt:.2f} s wall on "
-                         f"{cores} processes): root check + own Tseitin + C DPLL per query"}
+        res_last = run["results"][-1]
+        cpu = cpu_baseline_leg(gens, run["cnf"], res_last.verdicts(), res_last)
+        log(f"cpu baseline: {cpu}")
+        assert cpu["oracle_agreement"] == 1.0 or cpu["oracle_unknown"] > 0
 
     out = {
         "metric": "OOB queries decided/sec at 100% oracle agreement, learned vs static cubing",
-        "value": round(len(gens) / (ms_per_step / 1000.0), 3),
+        "value": forms[head]["queries_per_s"],
         "unit": "queries/s",
         "n_gpus": 1,
-        "steps": steps,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": forms[head]["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic (seeded generators)",
-        "config": {"workload": WORKLOADS[args.workload], "queries": len(gens), "k": args.k,
-                   "scorer": "static", "leaves_per_round": args.leaves_per_round,
-                   "chunk_log2": args.chunk_log2},
+        "config": {"workload": WORKLOADS[args.workload], "queries": n, "scorer": head,
+                   "options": forms[head]["options"], "max_cubes": max_cubes},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
+        "micro_peaks": micro,
         "learned_scorer": scorer_info,
+        "secondary": secondary,
         "gain": gain,
-        "detail": {"decided_at_root": n_root, "decided_on_device": n_dev,
-                   "unknown": n_unknown, "oracle_agreement": agree,
-                   "leaves_sent": leaves_sent, "leaves_refuted": leaves_refuted,
-                   "blocks_evaluated": blocks_evaluated,
-                   "bitblast_ms_per_step": round(bitblast_ms, 3),
-                   "host_split_ms_per_step": round(split_ms / steps, 3),
-                   "verify_ms_per_step": round(verify_ms / steps, 3),
-                   "leaf_kernel_ms_per_step": round(leaf_ms / steps, 3),
-                   "up_kernel_ms_per_step": round(up_ms / steps, 3)},
+        "detail": detail,
     }
     print(json.dumps(out))
 

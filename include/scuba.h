@@ -396,6 +396,9 @@ typedef struct {
   uint32_t rounds;
   int32_t witness_checked;   /* 1: model satisfies every clause and (for
                                 bit-blasted queries) the exact integer query */
+  uint64_t word_ops;         /* 64-bit word operations of the leaf
+                                evaluation: 64 words x (|c| + 1) for every
+                                residual clause c evaluated on a block     */
 } scuba_query_result;
 
 typedef struct {

@@ -89,7 +89,8 @@ class QueryResult(C.Structure):
                 ("cubes_total", C.c_uint64), ("cubes_refuted", C.c_uint64),
                 ("leaves_sent", C.c_uint64), ("leaves_refuted", C.c_uint64),
                 ("blocks_evaluated", C.c_uint64), ("clause_blocks", C.c_uint64),
-                ("rounds", C.c_uint32), ("witness_checked", C.c_int32)]
+                ("rounds", C.c_uint32), ("witness_checked", C.c_int32),
+                ("word_ops", C.c_uint64)]
 
 
 class LeafResult(C.Structure):

@@ -46,6 +46,12 @@ class Cnf(_Handle):
         return dict(n_vars=v.n_vars, n_inputs=v.n_inputs, n_clauses=v.n_clauses,
                     clause_off=off, lits=lits, root_unsat=bool(v.root_unsat))
 
+    def sizes(self, qi: int) -> dict:
+        """n_vars, n_clauses, n_lits and root_unsat of one query (no copy)."""
+        v = L.CnfView()
+        self.ctx._check(L.load().scuba_cnf_view_get(self.h, qi, C.byref(v)))
+        return dict(n_vars=v.n_vars, n_clauses=v.n_clauses, n_lits=v.n_lits, root_unsat=bool(v.root_unsat))
+
     def input_map(self, qi: int):
         n = self.view(qi)["n_inputs"]
         first = np.zeros(max(n, 1), np.uint32)
@@ -83,7 +89,7 @@ class Results(_Handle):
         return dict(verdict=L.VERDICT[r.verdict], how=L.HOW[r.how], cubes_total=r.cubes_total,
                     cubes_refuted=r.cubes_refuted, leaves_sent=r.leaves_sent,
                     leaves_refuted=r.leaves_refuted, blocks_evaluated=r.blocks_evaluated,
-                    clause_blocks=r.clause_blocks, rounds=r.rounds,
+                    clause_blocks=r.clause_blocks, word_ops=r.word_ops, rounds=r.rounds,
                     witness_checked=bool(r.witness_checked))
 
     def verdicts(self):

@@ -871,6 +871,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
       rq.r.leaves_refuted += lr.refuted;
       rq.r.blocks_evaluated += outs[i].blocks;
       rq.r.clause_blocks += outs[i].clause_blocks;
+      rq.r.word_ops += outs[i].word_ops;
     }
     parallel_for(cnf->q.size(), [&](size_t qi) {
       auto& rq = res->q[qi];
@@ -1025,6 +1026,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
         r.leaves_refuted += outs[i].status == 1;
         r.blocks_evaluated += outs[i].blocks;
         r.clause_blocks += outs[i].clause_blocks;
+        r.word_ops += outs[i].word_ops;
       }
       // queries with a witness are SAT; the witness is from this round
       std::vector<size_t> first_of(nq, SIZE_MAX);

@@ -15,6 +15,7 @@
 //             is true (the same patterns over the lane id)
 //   [1].x   : positive literals of slots 12..37 (26 bits)
 //   [1].y   : all literals of slots 12..37 (positive or negative)
+//   [1].z   : the residual clause's length |c| (open literals)
 //
 // Leaf kernel: assignment index a = 4096*block + 64*lane + bit.  Slot j < 6
 // is bit j of `bit` (a constant 64-bit pattern), slot 6..11 is bit j-6 of
@@ -513,13 +514,14 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
     for (uint32_t c = c0; c < c1; c++) {
       if (keep ? !((unsat >> (c - c0)) & 1) : clause_satisfied(cnf, c, T, F)) continue;
       uint64_t low = 0, lm = 0;
-      uint32_t hp = 0, hn = 0;
+      uint32_t hp = 0, hn = 0, len = 0;
       for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
         uint32_t v;
         bool neg;
         cnf.lit(i, &v, &neg);
         const uint32_t bit = 1u << (v & 31);
         if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
+        len++;
         const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
         if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
         else if (slot < 12) lm |= neg ? ~slot_pattern(slot - 6) : slot_pattern(slot - 6);
@@ -527,7 +529,7 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
       }
       const size_t rec = 2 * (cd.res_base + pos);
       res[rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
-      res[rec + 1] = make_uint4(hp, hp | hn, 0u, 0u);
+      res[rec + 1] = make_uint4(hp, hp | hn, len, 0u);
       pos++;
     }
   }
@@ -727,7 +729,7 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
       else if (f >= 6) valid = lane < (1u << (f - 6)) ? ~0ull : 0ull;
       else valid = lane == 0 ? ((2ull << ((1u << f) - 1)) - 1) : 0ull;
 
-      uint64_t count = 0, blocks = 0, evals = 0, first = ~0ull;
+      uint64_t count = 0, blocks = 0, evals = 0, word_ops = 0, first = ~0ull;
       uint32_t steps = 0;
       for (uint32_t blk = it.it_lo + wave; blk < it.it_hi; blk += kWaves) {
         if (mode == SCUBA_MODE_DECIDE && (steps++ & 7) == 0) {
@@ -737,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
         }
         const uint32_t H = blk & kHighMask;
         uint64_t acc = valid;
-        uint32_t done = 0;
+        uint32_t done = 0, lits = 0;
         // four clauses per step: their records are loaded together (the
         // record region is padded so that reading past nres stays inside
         // it), clauses past nres are masked out
@@ -748,14 +750,15 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
           // the four skip masks are needed first: keep their loads together
           // (else each test waits for its own load)
           asm volatile("" :: "s"(r1.x), "s"(r1.y), "s"(r3.x), "s"(r3.y), "s"(r5.x), "s"(r5.y), "s"(r7.x), "s"(r7.y));
-          if (!(~(H ^ r1.x) & r1.y)) { acc = clause_and(acc, r0); done++; }
-          if (left > 1 && !(~(H ^ r3.x) & r3.y)) { acc = clause_and(acc, r2); done++; }
-          if (left > 2 && !(~(H ^ r5.x) & r5.y)) { acc = clause_and(acc, r4); done++; }
-          if (left > 3 && !(~(H ^ r7.x) & r7.y)) { acc = clause_and(acc, r6); done++; }
+          if (!(~(H ^ r1.x) & r1.y)) { acc = clause_and(acc, r0); done++; lits += r1.z; }
+          if (left > 1 && !(~(H ^ r3.x) & r3.y)) { acc = clause_and(acc, r2); done++; lits += r3.z; }
+          if (left > 2 && !(~(H ^ r5.x) & r5.y)) { acc = clause_and(acc, r4); done++; lits += r5.z; }
+          if (left > 3 && !(~(H ^ r7.x) & r7.y)) { acc = clause_and(acc, r6); done++; lits += r7.z; }
           if (!__any(acc != 0)) break;
         }
         blocks++;
         evals += done;
+        word_ops += uint64_t(lits + done) * 64;   // (|c| + 1) per clause and 64-bit word
         if (mode == SCUBA_MODE_COUNT) count += __popcll(acc);
         const uint64_t hit = __ballot(acc != 0);
         if (hit) {
@@ -776,6 +779,7 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
         if (first != ~0ull) atomicMin((unsigned long long*)&out[it.cube].first, (unsigned long long)first);
         atomicAdd((unsigned long long*)&out[it.cube].blocks, (unsigned long long)blocks);
         atomicAdd((unsigned long long*)&out[it.cube].clause_blocks, (unsigned long long)evals);
+        atomicAdd((unsigned long long*)&out[it.cube].word_ops, (unsigned long long)word_ops);
       }
     }
   }

@@ -40,6 +40,7 @@ struct DevCubeOut {
   uint64_t first;       // smallest satisfying index (~0: none found)
   uint64_t blocks;      // 4096-assignment blocks evaluated
   uint64_t clause_blocks;  // clause x block evaluations on the VALU
+  uint64_t word_ops;       // sum over them of 64 words x (|c| + 1)
 };
 
 // A slice of one leaf: blocks [it_lo, it_hi) of 4096 assignments.

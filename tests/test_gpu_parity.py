@@ -351,3 +351,56 @@ def test_count_high_slots_closed_form(ctx, f):
     lf = out.leaf(0, 0)
     assert (lf["refuted"], lf["f"], lf["m"]) == (False, f, 0), lf
     assert lf["count"] == count and lf["first"] == first, (lf, count, first)
+
+
+def _word_ops_reference(f, cube):
+    """The leaf evaluation's word operations of one leaf with at most 12
+    active variables (one block of 4096 assignments, no block-level
+    literals), reproduced on the CPU in the kernel's fixed order: residual
+    clauses in clause order, four at a time, the block abandoned after the
+    first group that leaves no assignment alive.  Every evaluated clause
+    costs 64 words x (|c| + 1)."""
+    ref = cnf_ref.leaf(f, cube)
+    if ref["refuted"]:
+        return 0
+    conflict, assign = cnf_ref.up(f, cube)
+    slots = {v: j for j, v in enumerate(ref["slots"])}
+    a = np.arange(4096, dtype=np.int64)
+    alive = a < (1 << ref["f"])
+    res = []
+    for cl in f.clauses():
+        if any((assign[abs(l)] == 1) == (l > 0) for l in cl if assign[abs(l)] >= 0):
+            continue
+        res.append([l for l in cl if assign[abs(l)] < 0])
+    ops = 0
+    for g in range(0, len(res), 4):
+        for cl in res[g:g + 4]:
+            sat = np.zeros(4096, dtype=bool)
+            for l in cl:
+                bit = (a >> slots[abs(l)]) & 1
+                sat |= (bit == 1) if l > 0 else (bit == 0)
+            alive &= sat
+            ops += 64 * (len(cl) + 1)
+        if not alive.any():
+            break
+    return ops
+
+
+def test_word_ops_counter_reproduced(ctx):
+    """The leaf kernel's count of algorithmic word operations equals the
+    CPU's replay of its fixed evaluation order on one-block leaves."""
+    rng = np.random.Generator(np.random.PCG64(103))
+    cnfs, cubes = [], []
+    for n in (14, 18, 22, 26):
+        f = w.random_ksat(n, int(round(4.0 * n)), 3, rng)
+        cnfs.append(f)
+        qc = []
+        for _ in range(10):
+            vs = rng.choice(n, size=n - 10, replace=False) + 1
+            qc.append([int(v) if rng.integers(2) else -int(v) for v in vs])
+        cubes.append(qc)
+    raw = _raw(ctx, cnfs)
+    out = ctx.solve(raw, ctx.cubes_from_arrays(raw, cubes), mode=1)
+    for qi, (f, qc) in enumerate(zip(cnfs, cubes)):
+        want = sum(_word_ops_reference(f, c) for c in qc)
+        assert out.result(qi)["word_ops"] == want, (qi, out.result(qi)["word_ops"], want)
