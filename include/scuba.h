@@ -321,6 +321,25 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
 scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
                           void* dev_ws, size_t ws_bytes, void* hip_stream, scuba_results** out);
 
+/* Allocation-free scuba_decide, for callers that cannot allocate: code
+ * under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same loop, kernels and results as scuba_decide, with the
+ * device workspace taken from a scratch array of the library's own
+ * (SCUBA_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process ends)
+ * and the host staging in pageable memory: the call makes no hipMalloc,
+ * hipFree, hipHostMalloc or hipHostFree (host heap memory of the splitter
+ * aside).
+ * Errors: SCUBA_E_CAPACITY when the batch needs more device bytes than the
+ * scratch holds (scuba_decide_workspace gives the need; split the batch);
+ * SCUBA_E_INVALID with SCUBA_SOLVE_GRAPH (no graphs are captured here).
+ * Every call on one GPU shares that GPU's scratch and leaves its contents
+ * there; each call uploads everything its kernels read before they run, so
+ * consecutive calls are independent, but calls that overlap in time on one
+ * GPU (two contexts on two threads) race and give wrong results.          */
+#define SCUBA_NOALLOC_SCRATCH_BYTES (128u << 20)
+scuba_status scuba_decide_noalloc(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
+                                  void* hip_stream, scuba_results** out);
+
 /* ---------------------------------------------------------------- autotune
  * Picks k, chunk_log2, leaves_per_round and grid for scuba_decide on this
  * batch.  A size-stratified sample of the queries is decided at every

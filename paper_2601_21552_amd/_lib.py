@@ -27,6 +27,7 @@ def BB_WRAP(m: int) -> int:
 
 SCORER_STATIC, SCORER_LEARNED, SCORER_WORD = 0, 1, 2
 SOLVE_GRAPH = 1
+NOALLOC_SCRATCH_BYTES = 128 << 20   # device scratch of scuba_decide_noalloc
 CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2
 BB_NO_REWRITE = 1
 
@@ -126,6 +127,7 @@ SIGNATURES = {
     "scuba_decide_workspace": (C.c_int32, [P, P, C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]),
     "scuba_solve": (C.c_int32, [P, P, P, C.POINTER(SolveOpts), P, C.c_size_t, P, C.POINTER(P)]),
     "scuba_decide": (C.c_int32, [P, P, C.POINTER(SolveOpts), P, C.c_size_t, P, C.POINTER(P)]),
+    "scuba_decide_noalloc": (C.c_int32, [P, P, C.POINTER(SolveOpts), P, C.POINTER(P)]),
     "scuba_result_get": (C.c_int32, [P, C.c_uint32, C.POINTER(QueryResult)]),
     "scuba_witness_get": (C.c_int32, [P, C.c_uint32, P, C.c_uint32]),
     "scuba_model_get": (C.c_int32, [P, C.c_uint32, P, C.c_uint32]),

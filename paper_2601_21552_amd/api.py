@@ -338,6 +338,15 @@ class Context:
                                           self._stream(stream), C.byref(h)))
         return Results(self, h, len(cnf))
 
+    def decide_noalloc(self, cnf: Cnf, stream=None, **opts) -> Results:
+        """scuba_decide on the library's own device scratch (no workspace,
+        no allocation in the call)."""
+        o = _solve_opts(**opts)
+        h = _P()
+        self._check(self.lib.scuba_decide_noalloc(self.h, cnf.h, C.byref(o), self._stream(stream),
+                                                  C.byref(h)))
+        return Results(self, h, len(cnf))
+
 
 def _tune_opts(sample=0, reps=0, max_cubes=0, scorer="static", graph=False, refresh=False):
     return L.TuneOpts(sample, reps, max_cubes, _scorer(scorer), L.SOLVE_GRAPH if graph else 0,

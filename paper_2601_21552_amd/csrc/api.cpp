@@ -29,6 +29,10 @@ struct scuba_ctx {
   void* cnf_pinned = nullptr;
   size_t cnf_pinned_bytes = 0;
   DevGraphs* graphs = nullptr;
+  // staging in pageable host memory instead of pinned (the allocation-free
+  // entry point sets it for the duration of its call)
+  bool pageable = false;
+  std::vector<char> pageable_stg, pageable_cnf_stg;
   // autotuner choices per size bucket (see scuba_autotune)
   std::map<std::vector<uint64_t>, scuba_solve_opts> tuned;
 
@@ -39,6 +43,10 @@ struct scuba_ctx {
     }
   }
   void* staging(size_t bytes) {
+    if (pageable) {
+      if (bytes > pageable_stg.size()) pageable_stg.resize(bytes);
+      return pageable_stg.data();
+    }
     if (bytes > pinned_bytes) {
       dev_pinned_free(pinned);
       pinned = nullptr;
@@ -50,6 +58,10 @@ struct scuba_ctx {
     return pinned;
   }
   void* cnf_staging(size_t bytes) {
+    if (pageable) {
+      if (bytes > pageable_cnf_stg.size()) pageable_cnf_stg.resize(bytes);
+      return pageable_cnf_stg.data();
+    }
     if (bytes > cnf_pinned_bytes) {
       dev_pinned_free(cnf_pinned);
       cnf_pinned = nullptr;
@@ -60,6 +72,8 @@ struct scuba_ctx {
     }
     return cnf_pinned;
   }
+  size_t staging_size() const { return pageable ? pageable_stg.size() : pinned_bytes; }
+  size_t cnf_staging_size() const { return pageable ? pageable_cnf_stg.size() : cnf_pinned_bytes; }
   DevGraphs* graph_cache() {
     if (!graphs) graphs = dev_graphs_create(device);
     return graphs;
@@ -850,10 +864,10 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than scuba_solve_workspace");
     void* stg = ctx->staging(std::max(cnf_b, round_b) + 4096 + rh.cubes.size() * sizeof(DevCubeOut) + h.q.size() * 8);
     RoundTimes rt;
-    dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->pinned_bytes, true);
+    dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, stg, ctx->staging_size(), true);
     std::vector<DevCubeOut> outs;
     std::vector<uint64_t> qkeys;
-    dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, o.mode, o.grid, hip_stream, stg, ctx->pinned_bytes, &outs,
+    dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, o.mode, o.grid, hip_stream, stg, ctx->staging_size(), &outs,
               &qkeys, &rt, (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr);
     auto tv = Clock::now();
     for (size_t i = 0; i < outs.size(); i++) {
@@ -963,7 +977,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     bool uploaded = false;
     if (std::find(open.begin(), open.end(), 1) != open.end()) {
       void* cstg = ctx->cnf_staging(cnf_b);
-      dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, cstg, ctx->cnf_pinned_bytes, false);
+      dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, cstg, ctx->cnf_staging_size(), false);
       uploaded = true;
     }
     RoundTimes rt;
@@ -1016,7 +1030,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       std::vector<DevCubeOut> outs;
       std::vector<uint64_t> qkeys;
       dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
-                ctx->pinned_bytes, &outs, &qkeys, &rt,
+                ctx->staging_size(), &outs, &qkeys, &rt,
                 (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr);
       auto tv = Clock::now();
       for (size_t i = 0; i < outs.size(); i++) {
@@ -1093,6 +1107,31 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
   return guard(ctx, [&] {
     Opts o = resolve(opts);
     *out = decide_impl(ctx, cnf, o, dev_ws, ws_bytes, hip_stream).release();
+  });
+}
+
+scuba_status scuba_decide_noalloc(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
+                                  void* hip_stream, scuba_results** out) {
+  if (!ctx || !cnf || !out) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    Opts o = resolve(opts);
+    if (o.flags & SCUBA_SOLVE_GRAPH)
+      fail(SCUBA_E_INVALID, "scuba_decide_noalloc captures no graphs: clear SCUBA_SOLVE_GRAPH");
+    // the same bound as scuba_decide_workspace, checked before any device work
+    CnfHost h = cnf_host(cnf, 0, true);
+    size_t need = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, o.max_res);
+    if (o.scorer == SCUBA_SCORER_LEARNED) need += scorer_bytes(scorer_rows(cnf, o.learned->candidates)) + 256;
+    if (need > kScratchBytes)
+      fail(SCUBA_E_CAPACITY, "batch needs " + std::to_string(need) + " device bytes; the allocation-free "
+           "entry point has " + std::to_string(kScratchBytes) + " (split the batch or use scuba_decide)");
+    ctx->ensure_device();
+    if (!ctx->dev.scratch || ctx->dev.scratch_bytes < need) fail(SCUBA_E_INTERNAL, "device scratch missing");
+    struct Pageable {   // restores pinned staging on every exit
+      scuba_ctx* c;
+      explicit Pageable(scuba_ctx* c_) : c(c_) { c->pageable = true; }
+      ~Pageable() { c->pageable = false; }
+    } pg(ctx);
+    *out = decide_impl(ctx, cnf, o, ctx->dev.scratch, ctx->dev.scratch_bytes, hip_stream).release();
   });
 }
 

@@ -787,6 +787,16 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+}  // namespace
+
+// Device scratch of the allocation-free decide entry point: one copy per
+// GPU that the library runs on, held until the process ends.  Host code
+// never uses this name as an address: dev_init looks up its device address
+// once per device and every user takes that pointer.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
 struct CnfLayout {
   size_t q, coff, lits, occ_off, occ, qkey, end;
 };
@@ -828,6 +838,22 @@ void dev_init(DeviceInfo* info, int device) {
   HIP_OK(hipGetDeviceProperties(&p, device));
   info->device = device;
   info->cus = p.multiProcessorCount;
+  {
+    // the scratch array's address on this device, looked up once per
+    // device with that device current
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+      void* ptr = nullptr;
+      HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+      if (!ptr) fail(SCUBA_E_DEVICE, "no device address for the scratch array");
+      it = addr.emplace(device, ptr).first;
+    }
+    info->scratch = it->second;
+    info->scratch_bytes = kScratchBytes;
+  }
   info->max_lds = p.sharedMemPerBlock;
   info->up_lds_max = info->max_lds;
   info->leaf_lds_max = info->max_lds;

@@ -63,10 +63,16 @@ struct DevGraphs;
 DevGraphs* dev_graphs_create(int device);
 void dev_graphs_destroy(DevGraphs* g);
 
+// Bytes of the per-device scratch array of the allocation-free decide
+// entry point (SCUBA_NOALLOC_SCRATCH_BYTES in the C header).
+constexpr size_t kScratchBytes = size_t(SCUBA_NOALLOC_SCRATCH_BYTES);
+
 // Device context: a device id, its CU count and events.
 struct DeviceInfo {
   int device = 0;
   int cus = 256;
+  void* scratch = nullptr;     // device address of the scratch array
+  size_t scratch_bytes = 0;
   size_t max_lds = 65536;      // dynamic LDS a kernel may use by default
   size_t up_lds_max = 65536;   // dynamic LDS the propagation kernel may use
   size_t leaf_lds_max = 65536; // dynamic LDS the leaf kernel may use

@@ -395,3 +395,23 @@ def test_max_cubes_beyond_witness_key_is_rejected(api):
     with pytest.raises(_lib.ScubaError):
         ctx.decide_workspace(cnf, k=30, max_cubes=(1 << 26) + 1)
     ctx.split(cnf, k=30, max_cubes=1 << 26)
+
+
+def test_noalloc_rejects_batches_beyond_its_scratch(ctx):
+    """The allocation-free decide refuses, before any device work, a batch
+    whose workspace bound exceeds its scratch array, and a graph request."""
+    import ctypes as C
+    from paper_2601_21552_amd import _lib
+    from paper_2601_21552_amd.api import _solve_opts
+    gens = w.batch_2d(n=256)
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    need = ctx.decide_workspace(cnf, k=30)
+    assert need > _lib.NOALLOC_SCRATCH_BYTES
+    h = C.c_void_p()
+    st = ctx.lib.scuba_decide_noalloc(ctx.h, cnf.h, C.byref(_solve_opts(k=30)), None, C.byref(h))
+    assert st == -5 and not h.value   # SCUBA_E_CAPACITY
+    assert "allocation-free" in ctx.lib.scuba_last_error(ctx.h).decode()
+    small = ctx.bitblast([g.query.arrays()[:2] for g in w.batch_1d()[:4]])
+    st = ctx.lib.scuba_decide_noalloc(ctx.h, small.h, C.byref(_solve_opts(k=30, graph=True)), None,
+                                      C.byref(h))
+    assert st == -1 and not h.value   # SCUBA_E_INVALID
