@@ -32,7 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_INT32_TOPS = 39.3216   # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz (int32 VALU lane-ops)
+# int32 VALU lane-ops/s: 256 CU x 128 lanes per clock x 2.4 GHz.  The lane
+# rate is the one the fp32 vector peak (157.3 TFLOP/s, 2 flops per FMA)
+# implies, and the microbenchmark's chains of separate v_xor_b32 / v_add_u32
+# reach 89 % of it on this GPU (a 4-SIMD x 16-lane count, 39.3 T, is below
+# what the hardware measurably issues)
+PEAK_INT32_TOPS = 78.6432
 PEAK_HBM_GBS = 8000.0
 # per evaluated clause-block (one residual clause against 4096 assignments):
 # the 64-bit AND of the clause's satisfaction word into each of the 64 lanes'
@@ -350,12 +355,14 @@ def gain_legs(ctx, mlp_q, mlp_s_info, args):
         assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vs, vl))
         no = oracle_n[n]
         ov = [cnf_ref.solve(f, 3_000_000)[0] for f in cnfs[:no]]
-        agree = [a == b for a, b in zip(ov, vs[:no]) if a != "UNKNOWN"]
+        # a query left UNKNOWN by either side (budget) is counted, not compared
+        agree = [a == b for a, b in zip(ov, vs[:no]) if "UNKNOWN" not in (a, b)]
         assert all(agree), "oracle disagrees on random 3-SAT"
         leg = {"instances": count, "of": 2500, "k_autotuned": k, "tuned": tuned, "static": st, "learned": le,
                "leaf_ratio": round(le["leaves"] / max(st["leaves"], 1), 3),
                "time_ratio": round(le["ms"] / max(st["ms"], 1e-9), 3),
                "oracle_sample": no, "oracle_unknown": sum(a == "UNKNOWN" for a in ov),
+               "path_unknown_in_sample": sum(b == "UNKNOWN" for b in vs[:no]),
                "oracle_agreement": (sum(agree) / len(agree)) if agree else None}
         out[f"random3sat_n{n}"] = leg
         log(f"3-SAT n={n}: {leg}")

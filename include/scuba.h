@@ -277,6 +277,25 @@ void scuba_trace_free(scuba_trace* t);
  * The graphs belong to the context (at most 64, least recently used
  * dropped) and are released by scuba_ctx_destroy. */
 #define SCUBA_SOLVE_GRAPH 1u
+/* scuba_decide only: split on the device instead of the host.  Each open
+ * query's root is the start node of a work stack in device memory; every
+ * step pops up to split_batch nodes, propagates each from its parent's
+ * fixpoint and one decision literal, and turns it into a refuted cube, a
+ * leaf (at most k active variables and max_residual unsatisfied clauses:
+ * evaluated by the leaf kernel in the same step) or a branching node whose
+ * two children are pushed (the branching variable is the first active one
+ * of the static or word order, its 0-branch explored first).  Sec. 4.1 and
+ * Sec. 5.2 fix what a query decides; the splitting order is the solver's.
+ * Without host word-level bounds or backjumping, the device tree holds the
+ * host tree's leaves that have models and possibly more model-free ones;
+ * verdicts are the same.  DECIDE or COUNT mode (COUNT: scuba_leaf_get gives
+ * each leaf in emission order); static or word scorer; no graphs.
+ * Steps shrink to single nodes (depth first) when the stack nears its
+ * capacity, which never runs out as long as it holds the start nodes and
+ * one path.  scuba_decide_workspace gives the bytes for the default stack
+ * (64 x split_batch nodes plus one path); a larger workspace holds a
+ * larger stack and needs fewer single-node steps.                         */
+#define SCUBA_SOLVE_DEVICE_SPLIT 2u
 typedef struct {
   uint32_t mode;             /* SCUBA_MODE_*                                  */
   uint32_t k;                /* split bound for scuba_decide (<= 38)          */
@@ -294,7 +313,10 @@ typedef struct {
   uint32_t max_residual;     /* scuba_decide: a leaf's residual clauses must
                                 fit this tile (16 B each, in LDS; 0 = 2048,
                                 at most 8192)                                 */
-  uint32_t reserved;
+  uint32_t split_batch;      /* SCUBA_SOLVE_DEVICE_SPLIT: nodes expanded per
+                                step (0 = 16384, fewer when the residual
+                                records of that many leaves would exceed
+                                512 MiB; at most 2^20)                        */
 } scuba_solve_opts;
 
 /* Device bytes scuba_solve / scuba_decide need for this batch. */

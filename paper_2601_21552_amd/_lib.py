@@ -27,6 +27,7 @@ def BB_WRAP(m: int) -> int:
 
 SCORER_STATIC, SCORER_LEARNED, SCORER_WORD = 0, 1, 2
 SOLVE_GRAPH = 1
+SOLVE_DEVICE_SPLIT = 2
 NOALLOC_SCRATCH_BYTES = 128 << 20   # device scratch of scuba_decide_noalloc
 CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2
 BB_NO_REWRITE = 1
@@ -71,7 +72,7 @@ class SolveOpts(C.Structure):
                 ("leaves_per_round", C.c_uint32), ("chunk_log2", C.c_uint32),
                 ("grid", C.c_uint32), ("max_rounds", C.c_uint32), ("scorer", C.c_uint32),
                 ("flags", C.c_uint32), ("learned", C.POINTER(LearnedScorer)),
-                ("max_residual", C.c_uint32), ("reserved", C.c_uint32)]
+                ("max_residual", C.c_uint32), ("split_batch", C.c_uint32)]
 
 
 class TuneOpts(C.Structure):

@@ -147,10 +147,11 @@ struct Opts {
   const scuba_learned_scorer* learned;
   uint32_t flags;
   uint32_t max_res;
+  uint32_t split_batch;
 };
 Opts resolve(const scuba_solve_opts* o) {
   Opts r{SCUBA_MODE_DECIDE, kDefaultK, kDefaultLeavesPerRound, kDefaultChunkLog2, 0, 0, 0, kDefaultMaxCubes,
-         nullptr, 0, kDefaultMaxResidual};
+         nullptr, 0, kDefaultMaxResidual, 0};
   if (o) {
     r.mode = o->mode;
     if (o->k) r.k = o->k;
@@ -163,12 +164,18 @@ Opts resolve(const scuba_solve_opts* o) {
     r.learned = o->learned;
     r.flags = o->flags;
     if (o->max_residual) r.max_res = o->max_residual;
+    r.split_batch = o->split_batch;
   }
   if (r.max_res > 8192) fail(SCUBA_E_INVALID, "max_residual above 8192");
   // the device's witness key is (cube sequence << 38) | assignment index:
   // a query's cube sequence numbers must stay below 2^26
   if (r.max_cubes > kMaxCubesPerQuery) fail(SCUBA_E_INVALID, "max_cubes above 2^26 per query");
-  if (r.flags & ~SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "unknown solve flags");
+  if (r.flags & ~(SCUBA_SOLVE_GRAPH | SCUBA_SOLVE_DEVICE_SPLIT)) fail(SCUBA_E_INVALID, "unknown solve flags");
+  if (r.flags & SCUBA_SOLVE_DEVICE_SPLIT) {
+    if (r.flags & SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "the device split captures no graphs");
+    if (r.scorer == SCUBA_SCORER_LEARNED) fail(SCUBA_E_INVALID, "the device split takes the static or word order");
+    if (r.split_batch > (1u << 20)) fail(SCUBA_E_INVALID, "split_batch above 2^20");
+  }
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
   if (r.chunk_log2 > 26) fail(SCUBA_E_INVALID, "chunk_log2 above 26");
@@ -327,7 +334,7 @@ size_t round_bound(const scuba_cnf* cnf, size_t n_cubes, const Opts& o, uint32_t
 // propagation of the cube again), slot j = bit j of `a`, remaining
 // unassigned variables 0.  Then the checks of the result stage: every clause
 // and the exact integer query.
-void assemble_witness(const CnfQuery& q, Splitter& sp, const Cube& cube, uint64_t a, scuba_results::Q& out) {
+void assemble_witness(const CnfQuery& q, Splitter* sp, const Cube& cube, uint64_t a, scuba_results::Q& out) {
   std::vector<int8_t> assign;
   std::vector<int32_t> active;
   if (!cube.assign.empty()) {   // the leaf's fixpoint, kept by the splitter
@@ -335,7 +342,8 @@ void assemble_witness(const CnfQuery& q, Splitter& sp, const Cube& cube, uint64_
     active = cube.active;
   } else {
     uint32_t nres = 0;
-    if (!sp.leaf_of(cube.lits, &assign, &active, &nres)) fail(SCUBA_E_INTERNAL, "witness cube conflicts on the host");
+    if (!sp || !sp->leaf_of(cube.lits, &assign, &active, &nres))
+      fail(SCUBA_E_INTERNAL, "witness cube conflicts on the host");
   }
   if (active.size() > 64 || assign.size() != size_t(q.n_vars) + 1)
     fail(SCUBA_E_INTERNAL, "leaf state does not match the query");
@@ -822,11 +830,206 @@ scuba_status scuba_solve_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const s
   });
 }
 
+// ---------------------------------------------------------------- device split
+
+namespace {
+
+// Run parameters of the device split for a batch: bitmap width and residual
+// bound from the open queries, nodes per step, and the default stack.
+SplitRun split_run(const scuba_cnf* cnf, const Opts& o, size_t* n_order) {
+  SplitRun r;
+  r.k = o.k;
+  r.max_res = o.max_res;
+  r.mode = o.mode;
+  r.chunk_log2 = o.chunk_log2;
+  r.grid = o.grid;
+  r.max_cubes = o.max_cubes;
+  uint32_t nw = 1;
+  uint64_t nc = 1;
+  *n_order = 0;
+  for (const CnfQuery& q : cnf->q) {
+    if (q.root_unsat) continue;
+    nw = std::max(nw, (q.n_vars >> 5) + 1);
+    nc = std::max<uint64_t>(nc, q.n_clauses());
+    *n_order += q.n_vars;
+  }
+  r.nw_max = nw;
+  r.nres_max = uint32_t(std::min<uint64_t>(o.max_res, nc));
+  uint64_t b = o.split_batch ? o.split_batch : 16384;
+  if (!o.split_batch) b = std::min<uint64_t>(b, std::max<uint64_t>(256, (uint64_t(512) << 20) / (32 * r.nres_max)));
+  r.batch = uint32_t(b);
+  // room for 64 wide steps, then depth-first steps within the reserve
+  uint32_t nv_max = 0;
+  for (const CnfQuery& q : cnf->q)
+    if (!q.root_unsat) nv_max = std::max(nv_max, q.n_vars);
+  r.stack_cap = 64 * size_t(b) + size_t(nv_max) + 2 + cnf->q.size();
+  return r;
+}
+
+size_t split_need(const scuba_cnf* cnf, const Opts& o) {
+  CnfHost h = cnf_host(cnf, 0, true);
+  size_t n_order;
+  SplitRun r = split_run(cnf, o, &n_order);
+  return dev_split_bytes(h, n_order, r);
+}
+
+// scuba_decide with the split on the device: branch orders on the host pool,
+// then the device loop, then the witnesses of the SAT queries built from
+// their leaves' fixpoints and checked like every witness.
+std::unique_ptr<scuba_results> decide_split_impl(scuba_ctx* ctx, const scuba_cnf* cnf, const Opts& o, void* dev_ws,
+                                                 size_t ws_bytes, void* hip_stream) {
+  auto t0 = Clock::now();
+  ctx->ensure_device();
+  const size_t nq = cnf->q.size();
+  CnfHost h = cnf_host(cnf, 0, true);
+  auto res = std::make_unique<scuba_results>();
+  res->q.resize(nq);
+  std::vector<uint32_t> start;
+  for (size_t qi = 0; qi < nq; qi++) {
+    if (cnf->q[qi].root_unsat) {
+      res->q[qi].r.verdict = SCUBA_UNSAT;
+      res->q[qi].r.how = SCUBA_HOW_ROOT;
+    } else {
+      start.push_back(uint32_t(qi));
+    }
+  }
+  auto ts = Clock::now();
+  std::vector<std::vector<int32_t>> ords(nq);
+  parallel_for(start.size(), [&](size_t j) {
+    const uint32_t qi = start[j];
+    Splitter sp(cnf->q[qi], o.k, o.max_res, o.max_cubes);
+    if (o.scorer == SCUBA_SCORER_WORD) sp.set_word_order();
+    ords[qi] = sp.branch_order();
+  });
+  std::vector<uint64_t> order_off(nq, 0);
+  size_t n_order = 0;
+  for (uint32_t qi : start) {
+    order_off[qi] = n_order;
+    n_order += cnf->q[qi].n_vars;
+    if (ords[qi].size() != cnf->q[qi].n_vars) fail(SCUBA_E_INTERNAL, "branch order misses variables");
+  }
+  std::vector<uint32_t> order(n_order);
+  for (uint32_t qi : start)
+    for (size_t i = 0; i < ords[qi].size(); i++) order[order_off[qi] + i] = uint32_t(ords[qi][i]);
+  ords.clear();
+  const double order_ms = ms_since(ts);
+  size_t n_ord;
+  SplitRun r = split_run(cnf, o, &n_ord);
+  // the stack takes what the workspace holds beyond the fixed regions
+  {
+    SplitRun r0 = r;
+    r0.stack_cap = 0;
+    const size_t fixed = dev_split_bytes(h, n_order, r0) + 1024;
+    const size_t per = dev_split_node_bytes(r.nw_max);
+    if (ws_bytes < fixed + per * 2 * size_t(r.batch))
+      fail(SCUBA_E_CAPACITY, "workspace smaller than scuba_decide_workspace");
+    // (dev_split checks the stack against the start nodes and the reserve)
+    r.stack_cap = std::min<size_t>((ws_bytes - fixed) / per, size_t(1) << 31);
+    while (r.stack_cap && dev_split_bytes(h, n_order, r) > ws_bytes) r.stack_cap -= 256;
+    if (r.stack_cap < 2 * size_t(r.batch)) fail(SCUBA_E_CAPACITY, "workspace smaller than scuba_decide_workspace");
+  }
+  SplitOutput so;
+  double verify_ms = 0;
+  if (!start.empty()) {
+    const size_t cnf_b = dev_cnf_bytes(h);
+    void* cstg = ctx->cnf_staging(cnf_b);
+    dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, cstg, ctx->cnf_staging_size(), false);
+    void* stg = ctx->staging(dev_split_staging(h, n_order, start.size(), r));
+    dev_split(ctx->dev, dev_ws, ws_bytes, h, order_off, order, start, r, hip_stream, stg, ctx->staging_size(), &so);
+    auto tv = Clock::now();
+    const size_t fw = 2 * size_t(r.nw_max);
+    parallel_for(start.size(), [&](size_t j) {
+      const uint32_t qi = start[j];
+      const CnfQuery& q = cnf->q[qi];
+      auto& rq = res->q[qi];
+      const DevSplitStat& st = so.stats[qi];
+      rq.r.cubes_total = st.cubes;
+      rq.r.cubes_refuted = st.refuted;
+      rq.r.leaves_sent = st.leaves;
+      rq.r.blocks_evaluated = st.blocks;
+      rq.r.clause_blocks = st.clause_blocks;
+      rq.r.word_ops = st.word_ops;
+      rq.r.rounds = uint32_t(std::min<uint64_t>(so.steps, UINT32_MAX));
+      rq.r.how = SCUBA_HOW_DEVICE;
+      const bool undecided = st.budget || so.stopped;
+      if (o.mode == SCUBA_MODE_COUNT) {
+        bool any = false;
+        for (const DevCubeOut& lo : so.leaves[qi]) {
+          scuba_leaf_result lr{};
+          lr.refuted = lo.status != 0;
+          lr.f = lo.f;
+          lr.m = lo.m;
+          lr.count = lo.count;
+          lr.first = lo.first == ~0ull ? -1 : int64_t(lo.first);
+          any |= lo.count != 0;
+          rq.leaves.push_back(lr);
+        }
+        rq.r.verdict = any ? SCUBA_SAT : (undecided ? SCUBA_UNKNOWN : SCUBA_UNSAT);
+        if (!any && undecided) rq.r.how = SCUBA_HOW_BUDGET;
+        return;
+      }
+      if (so.qkeys[qi] == ~0ull) {
+        rq.r.verdict = undecided ? SCUBA_UNKNOWN : SCUBA_UNSAT;
+        if (undecided) rq.r.how = SCUBA_HOW_BUDGET;
+        return;
+      }
+      // the witness leaf's fixpoint: assigned variables, then its active
+      // variables (unassigned, in an unsatisfied clause) in increasing
+      // order as slots 0.., as the device numbered them
+      const uint32_t* T = so.wit.data() + qi * fw;
+      const uint32_t* F = T + r.nw_max;
+      Cube cube;
+      cube.assign.assign(size_t(q.n_vars) + 1, -1);
+      for (uint32_t v = 1; v <= q.n_vars; v++) {
+        const bool t = (T[v >> 5] >> (v & 31)) & 1u, f = (F[v >> 5] >> (v & 31)) & 1u;
+        if (t && f) fail(SCUBA_E_DEVICE, "device split witness leaf assigns a variable both ways");
+        if (t || f) cube.assign[v] = t ? 1 : 0;
+      }
+      std::vector<uint8_t> act(size_t(q.n_vars) + 1, 0);
+      for (uint64_t c = 0; c < q.n_clauses(); c++) {
+        bool sat = false;
+        for (uint64_t i = q.off[c]; i < q.off[c + 1] && !sat; i++) {
+          const int32_t l = q.lits[i];
+          sat = cube.assign[std::abs(l)] == (l > 0 ? 1 : 0);
+        }
+        if (sat) continue;
+        for (uint64_t i = q.off[c]; i < q.off[c + 1]; i++)
+          if (cube.assign[std::abs(q.lits[i])] < 0) act[std::abs(q.lits[i])] = 1;
+      }
+      for (uint32_t v = 1; v <= q.n_vars; v++)
+        if (act[v]) cube.active.push_back(int32_t(v));
+      const uint64_t a = so.qkeys[qi] & ((uint64_t(1) << 38) - 1);
+      if (cube.active.size() > kMaxLeafVars || (cube.active.size() < 38 && (a >> cube.active.size())))
+        fail(SCUBA_E_DEVICE, "device split witness index outside its leaf");
+      rq.r.verdict = SCUBA_SAT;
+      assemble_witness(q, nullptr, cube, a, rq);
+    });
+    verify_ms = ms_since(tv);
+  }
+  res->ms[0] = order_ms;
+  res->ms[2] = so.expand_ms + so.leaf_ms;
+  res->ms[4] = verify_ms;
+  res->ms[5] = ms_since(t0);
+  res->ms[6] = so.expand_ms;
+  res->ms[7] = so.leaf_ms;
+  res->ms[8] = double(so.steps);
+  res->ms[9] = double(so.steps);
+  res->ms[16] = double(so.nodes);
+  res->ms[17] = double(so.max_stack);
+  return res;
+}
+
+}  // namespace
+
 scuba_status scuba_decide_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
                                     size_t* bytes) {
   if (!ctx || !cnf || !bytes) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     Opts o = resolve(opts);
+    if (o.flags & SCUBA_SOLVE_DEVICE_SPLIT) {
+      *bytes = split_need(cnf, o);
+      return;
+    }
     CnfHost h = cnf_host(cnf, 0, true);
     *bytes = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, o.max_res);
     if (o.scorer == SCUBA_SCORER_LEARNED)
@@ -841,6 +1044,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
   return guard(ctx, [&] {
     auto t0 = Clock::now();
     Opts o = resolve(opts);
+    if (o.flags & SCUBA_SOLVE_DEVICE_SPLIT) fail(SCUBA_E_INVALID, "scuba_solve takes given cubes: no device split");
     ctx->ensure_device();
     CnfHost h = cnf_host(cnf, up_lds_limit(ctx));
     auto res = std::make_unique<scuba_results>();
@@ -902,7 +1106,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
         Splitter sp(cnf->q[qi], 0, 0, 1);
         Cube cb;
         cb.lits = std::move(lits);
-        assemble_witness(cnf->q[qi], sp, cb, uint64_t(rq.leaves[sat_cube].first), rq);
+        assemble_witness(cnf->q[qi], &sp, cb, uint64_t(rq.leaves[sat_cube].first), rq);
       } else {
         rq.r.verdict = cubes->q[qi].complete ? SCUBA_UNSAT : SCUBA_UNKNOWN;
         if (cnf->q[qi].root_unsat) { rq.r.verdict = SCUBA_UNSAT; rq.r.how = SCUBA_HOW_ROOT; }
@@ -1062,7 +1266,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
         auto& rq = res->q[qi];
         rq.r.verdict = SCUBA_SAT;
         rq.r.how = SCUBA_HOW_DEVICE;
-        assemble_witness(cnf->q[qi], *sp[qi], *cube, a, rq);
+        assemble_witness(cnf->q[qi], sp[qi].get(), *cube, a, rq);
       });
       for (uint32_t qi : sat_q) open[qi] = 0;
       verify_ms += ms_since(tv);
@@ -1106,7 +1310,10 @@ scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solv
   if (!ctx || !cnf || !out || !dev_ws) return SCUBA_E_INVALID;
   return guard(ctx, [&] {
     Opts o = resolve(opts);
-    *out = decide_impl(ctx, cnf, o, dev_ws, ws_bytes, hip_stream).release();
+    if (o.flags & SCUBA_SOLVE_DEVICE_SPLIT)
+      *out = decide_split_impl(ctx, cnf, o, dev_ws, ws_bytes, hip_stream).release();
+    else
+      *out = decide_impl(ctx, cnf, o, dev_ws, ws_bytes, hip_stream).release();
   });
 }
 
@@ -1117,6 +1324,8 @@ scuba_status scuba_decide_noalloc(scuba_ctx* ctx, const scuba_cnf* cnf, const sc
     Opts o = resolve(opts);
     if (o.flags & SCUBA_SOLVE_GRAPH)
       fail(SCUBA_E_INVALID, "scuba_decide_noalloc captures no graphs: clear SCUBA_SOLVE_GRAPH");
+    if (o.flags & SCUBA_SOLVE_DEVICE_SPLIT)
+      fail(SCUBA_E_INVALID, "scuba_decide_noalloc splits on the host: clear SCUBA_SOLVE_DEVICE_SPLIT");
     // the same bound as scuba_decide_workspace, checked before any device work
     CnfHost h = cnf_host(cnf, 0, true);
     size_t need = dev_cnf_bytes(h) + round_bound(cnf, size_t(cnf->q.size()) * o.lpr, o, o.max_res);

@@ -31,6 +31,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <list>
 #include <map>
@@ -301,18 +302,19 @@ __device__ __forceinline__ void push(uint32_t e, uint32_t* next, uint32_t cap, u
   else sh.ovf[w] = 1;
 }
 
-// Unit propagation of one cube by one team, then its active variables,
-// slots and residual records.  Every thread of the team calls it (uniform
-// control flow within the team).
-template <int TW, class Cnf, class Occ>
-__device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
-                               uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
-                               uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
-                               uint32_t* Q, uint32_t* X, UpShared& sh) {
-  Team<TW> tm{sh};
-  constexpr uint32_t S = Team<TW>::kSize, QC = Team<TW>::kQueue;
+// Pieces of the unit propagation of one cube by one team.  Every thread of
+// the team calls each of them (uniform control flow within the team).  The
+// assignment is two LDS bitmaps, T (variable true) and F (variable false),
+// over variables 0..nv; A marks the active variables (unassigned, in an
+// unsatisfied clause) and P holds, per bitmap word, the slot of its first
+// active variable.
+
+// Clears the bitmaps, the owner marks and the counters.
+template <int TW>
+__device__ __forceinline__ void up_clear(Team<TW>& tm, uint32_t nw, uint32_t* T, uint32_t* F, uint32_t* A,
+                                         uint32_t* X, UpShared& sh) {
+  constexpr uint32_t S = Team<TW>::kSize;
   const uint32_t lane = tm.lane();
-  const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
   for (uint32_t w = lane; w < nw; w += S) { T[w] = 0; F[w] = 0; A[w] = 0; }
   for (uint32_t t = lane; t < S; t += S) X[2 * (t & ~63u) + 64 + (t & 63)] = 0;   // the owner marks
   if (lane == 0) {
@@ -320,49 +322,67 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
     sh.error = 0;
     for (uint32_t k = 0; k < 3; k++) { sh.qn[k] = 0; sh.ovf[k] = 0; sh.chg[k] = 0; }
   }
-  tm.sync();
+}
 
-  // ---- the first frontier: every literal that holds before propagation
-  // (the cube's literals and the unit clauses), as if a round -1 had set
-  // them (queue 1, counter set 2).  An empty clause is a conflict.
-  {
-    uint32_t* seed = Q + QC;
-    for (uint32_t j = lane; j < cd.n_lits; j += S) {
-      const int32_t l = cube_lits[cd.lit_off + j];
-      const uint32_t v = uint32_t(l > 0 ? l : -l);
-      if (v == 0 || v > nv) { sh.error = 1; continue; }
-      const uint32_t bit = 1u << (v & 31);
-      const uint32_t old = atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], bit);
-      if (!(old & bit)) push((v << 1) | (l > 0 ? 1u : 0u), seed, QC, 2, sh);
-    }
-    for (uint32_t c = lane; c < nc; c += S) {
-      const uint32_t b = cnf.beg(c), e = cnf.end(c);
-      if (e == b) { sh.conflict = 1; continue; }
-      if (e - b != 1) continue;
-      uint32_t v;
-      bool neg;
-      cnf.lit(b, &v, &neg);
-      const uint32_t bit = 1u << (v & 31);
-      const uint32_t old = atomicOr(neg ? &F[v >> 5] : &T[v >> 5], bit);
-      if (!(old & bit)) push((v << 1) | (neg ? 0u : 1u), seed, QC, 2, sh);
-    }
+// The first frontier: every literal that holds before propagation, as if a
+// round -1 had set it (queue 1, counter set 2).  From a literal list (a
+// cube's literals, or one decision on top of a fixpoint):
+template <int TW>
+__device__ __forceinline__ void up_seed_lits(Team<TW>& tm, const int32_t* __restrict__ lits, uint32_t n_lits,
+                                             uint32_t nv, uint32_t* T, uint32_t* F, uint32_t* Q, UpShared& sh) {
+  constexpr uint32_t S = Team<TW>::kSize, QC = Team<TW>::kQueue;
+  const uint32_t lane = tm.lane();
+  uint32_t* seed = Q + QC;
+  for (uint32_t j = lane; j < n_lits; j += S) {
+    const int32_t l = lits[j];
+    const uint32_t v = uint32_t(l > 0 ? l : -l);
+    if (v == 0 || v > nv) { sh.error = 1; continue; }
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t old = atomicOr(l > 0 ? &T[v >> 5] : &F[v >> 5], bit);
+    if (!(old & bit)) push((v << 1) | (l > 0 ? 1u : 0u), seed, QC, 2, sh);
   }
-  tm.sync();
+}
+// ... and from the unit clauses of the CNF (an empty clause is a conflict).
+template <int TW, class Cnf>
+__device__ __forceinline__ void up_seed_units(Team<TW>& tm, const Cnf& cnf, uint32_t nc, uint32_t* T, uint32_t* F,
+                                              uint32_t* Q, UpShared& sh) {
+  constexpr uint32_t S = Team<TW>::kSize, QC = Team<TW>::kQueue;
+  const uint32_t lane = tm.lane();
+  uint32_t* seed = Q + QC;
+  for (uint32_t c = lane; c < nc; c += S) {
+    const uint32_t b = cnf.beg(c), e = cnf.end(c);
+    if (e == b) { sh.conflict = 1; continue; }
+    if (e - b != 1) continue;
+    uint32_t v;
+    bool neg;
+    cnf.lit(b, &v, &neg);
+    const uint32_t bit = 1u << (v & 31);
+    const uint32_t old = atomicOr(neg ? &F[v >> 5] : &T[v >> 5], bit);
+    if (!(old & bit)) push((v << 1) | (neg ? 0u : 1u), seed, QC, 2, sh);
+  }
+}
 
-  // ---- propagation rounds.  Round r visits the clauses of the literals
-  // that round r-1 made false (its frontier); when that frontier overflowed
-  // its queue, round r scans every clause instead.  A round that sets
-  // nothing new ends at the fixpoint: every clause has been visited after
-  // its last false literal was assigned.  Every changing round sets a new
-  // bit, so at most 2*(nv+1) rounds change something.  Each wave takes
-  // every TW-th frontier entry and spreads the (entry, occurrence) pairs of
-  // up to 64 entries at a time over its lanes: a wave scan of the
-  // occurrence counts gives each entry's first pair, and a lane finds the
-  // entry of its pair: among up to four entries by comparisons with their
-  // offsets held in scalar registers, else from marks that each entry
-  // writes at its first pair of a 64-pair chunk (Xw[64..127] in LDS) and a
-  // wave max-scan over them.  The only team-wide barrier of a round is at
-  // its end.
+// Propagation rounds from the first frontier to the fixpoint, then the
+// conflict test over the bitmaps (sh.conflict / sh.error on return).
+// Round r visits the clauses of the literals that round r-1 made false (its
+// frontier); when that frontier overflowed its queue, round r scans every
+// clause instead.  A round that sets nothing new ends at the fixpoint:
+// every clause has been visited after its last false literal was assigned.
+// Every changing round sets a new bit, so at most 2*(nv+1) rounds change
+// something.  Each wave takes every TW-th frontier entry and spreads the
+// (entry, occurrence) pairs of up to 64 entries at a time over its lanes: a
+// wave scan of the occurrence counts gives each entry's first pair, and a
+// lane finds the entry of its pair: among up to four entries by comparisons
+// with their offsets held in scalar registers, else from marks that each
+// entry writes at its first pair of a 64-pair chunk (Xw[64..127] in LDS)
+// and a wave max-scan over them.  The only team-wide barrier of a round is
+// at its end.
+template <int TW, class Cnf, class Occ>
+__device__ __forceinline__ void up_rounds(Team<TW>& tm, const Cnf& cnf, const Occ& occ, uint32_t nv, uint32_t nc,
+                                          uint32_t* T, uint32_t* F, uint32_t* Q, uint32_t* X, UpShared& sh) {
+  constexpr uint32_t S = Team<TW>::kSize, QC = Team<TW>::kQueue;
+  const uint32_t lane = tm.lane();
+  const uint32_t nw = (nv >> 5) + 1;
   const uint32_t wl = threadIdx.x & 63, wv = TW == 1 ? 0u : uniform_u32(lane >> 6);
   uint32_t* Xw = X + wv * 128;
   uint32_t mark_tag = 0;   // tags of the owner marks; 0 (the cleared marks) never matches
@@ -456,27 +476,32 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   for (uint32_t w = lane; w < nw; w += S)
     if (T[w] & F[w]) sh.conflict = 1;
   tm.sync();
-  if (uniform_u32(sh.conflict) || uniform_u32(sh.error)) {
-    if (lane == 0) {
-      out[ci].status = sh.error ? 2 : 1;
-      out[ci].f = out[ci].m = out[ci].nres = 0;
-    }
-    tm.sync();
-    return;
-  }
+}
 
-  // ---- active variables, over contiguous clauses per lane; a lane with at
-  // most 64 clauses keeps which of them are unsatisfied for the residual
-  // records below (others test them again there)
+// Active variables into A, over contiguous clauses per lane.  A lane with
+// at most 64 clauses keeps which of them are unsatisfied, in a register
+// mask that also serves the residual records.
+struct ActiveScan {
+  uint32_t c0, c1, my_unsat;
+  bool keep;
+  uint64_t unsat;
+};
+template <int TW, class Cnf>
+__device__ __forceinline__ ActiveScan up_active(Team<TW>& tm, const Cnf& cnf, uint32_t nc, const uint32_t* T,
+                                                const uint32_t* F, uint32_t* A) {
+  constexpr uint32_t S = Team<TW>::kSize;
+  const uint32_t lane = tm.lane();
+  ActiveScan as;
   const uint32_t cpl = (nc + S - 1) / S;
-  const uint32_t c0 = min(nc, lane * cpl), c1 = min(nc, c0 + cpl);
-  const bool keep = cpl <= 64;
-  uint64_t unsat = 0;
-  uint32_t my_unsat = 0;
-  for (uint32_t c = c0; c < c1; c++) {
+  as.c0 = min(nc, lane * cpl);
+  as.c1 = min(nc, as.c0 + cpl);
+  as.keep = cpl <= 64;
+  as.unsat = 0;
+  as.my_unsat = 0;
+  for (uint32_t c = as.c0; c < as.c1; c++) {
     if (clause_satisfied(cnf, c, T, F)) continue;
-    my_unsat++;
-    if (keep) unsat |= uint64_t(1) << (c - c0);
+    as.my_unsat++;
+    if (as.keep) as.unsat |= uint64_t(1) << (c - as.c0);
     for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
       uint32_t v;
       bool neg;
@@ -485,9 +510,18 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
       if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
     }
   }
-  tm.sync();
+  return as;
+}
 
-  // ---- slot prefix per bitmap word (contiguous words per lane)
+// Slot prefix per bitmap word (contiguous words per lane) into P, and the
+// team totals of active (f) and unassigned variables.  A must be complete
+// (a team barrier after up_active).
+template <int TW>
+__device__ __forceinline__ void up_prefix(Team<TW>& tm, uint32_t nv, const uint32_t* T, const uint32_t* F,
+                                          const uint32_t* A, uint32_t* P, uint32_t* f_total, uint32_t* free_total) {
+  constexpr uint32_t S = Team<TW>::kSize;
+  const uint32_t lane = tm.lane();
+  const uint32_t nw = (nv >> 5) + 1;
   const uint32_t wpl = (nw + S - 1) / S;
   const uint32_t w0 = min(nw, lane * wpl), w1 = min(nw, w0 + wpl);
   uint32_t my_act = 0, my_free = 0;
@@ -498,41 +532,77 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
     my_act += __popc(A[w]);
     my_free += __popc(~(T[w] | F[w]) & valid);
   }
-  uint32_t f_total, free_total;
-  uint32_t base = tm.scan(my_act, &f_total);
-  tm.scan(my_free, &free_total);
+  uint32_t base = tm.scan(my_act, f_total);
+  tm.scan(my_free, free_total);
   for (uint32_t w = w0; w < w1; w++) { P[w] = base; base += __popc(A[w]); }
+}
+
+// The residual records of the lane's unsatisfied clauses, in clause order,
+// at records res_base + pos.. (pos: the team scan of my_unsat).  P must be
+// complete (a team barrier after up_prefix).
+template <class Cnf>
+__device__ __forceinline__ void up_records(const Cnf& cnf, const ActiveScan& as, const uint32_t* T,
+                                           const uint32_t* F, const uint32_t* A, const uint32_t* P,
+                                           uint4* __restrict__ res, uint64_t res_base, uint32_t pos) {
+  for (uint32_t c = as.c0; c < as.c1; c++) {
+    if (as.keep ? !((as.unsat >> (c - as.c0)) & 1) : clause_satisfied(cnf, c, T, F)) continue;
+    uint64_t low = 0, lm = 0;
+    uint32_t hp = 0, hn = 0, len = 0;
+    for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+      uint32_t v;
+      bool neg;
+      cnf.lit(i, &v, &neg);
+      const uint32_t bit = 1u << (v & 31);
+      if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
+      len++;
+      const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
+      if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
+      else if (slot < 12) lm |= neg ? ~slot_pattern(slot - 6) : slot_pattern(slot - 6);
+      else (neg ? hn : hp) |= 1u << (slot - 12);
+    }
+    const size_t rec = 2 * (res_base + pos);
+    res[rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
+    res[rec + 1] = make_uint4(hp, hp | hn, len, 0u);
+    pos++;
+  }
+}
+
+// Unit propagation of one cube by one team from the empty assignment (the
+// cube's literals and the unit clauses), then its active variables, slots
+// and residual records.
+template <int TW, class Cnf, class Occ>
+__device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
+                               uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
+                               uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
+                               uint32_t* Q, uint32_t* X, UpShared& sh) {
+  Team<TW> tm{sh};
+  const uint32_t lane = tm.lane();
+  const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
+  up_clear<TW>(tm, nw, T, F, A, X, sh);
+  tm.sync();
+  up_seed_lits<TW>(tm, cube_lits + cd.lit_off, cd.n_lits, nv, T, F, Q, sh);
+  up_seed_units<TW>(tm, cnf, nc, T, F, Q, sh);
+  tm.sync();
+  up_rounds<TW>(tm, cnf, occ, nv, nc, T, F, Q, X, sh);
+  if (uniform_u32(sh.conflict) || uniform_u32(sh.error)) {
+    if (lane == 0) {
+      out[ci].status = sh.error ? 2 : 1;
+      out[ci].f = out[ci].m = out[ci].nres = 0;
+    }
+    tm.sync();
+    return;
+  }
+  const ActiveScan as = up_active<TW>(tm, cnf, nc, T, F, A);
+  tm.sync();
+  uint32_t f_total, free_total;
+  up_prefix<TW>(tm, nv, T, F, A, P, &f_total, &free_total);
   tm.sync();
 
   const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
-
-  // ---- residual records, in clause order (the same contiguous clauses)
   uint32_t n_unsat;
-  uint32_t pos = tm.scan(my_unsat, &n_unsat);
+  const uint32_t pos = tm.scan(as.my_unsat, &n_unsat);
   const bool cap_ok = n_unsat <= cd.nres_cap;
-  if (f_ok && cap_ok) {
-    for (uint32_t c = c0; c < c1; c++) {
-      if (keep ? !((unsat >> (c - c0)) & 1) : clause_satisfied(cnf, c, T, F)) continue;
-      uint64_t low = 0, lm = 0;
-      uint32_t hp = 0, hn = 0, len = 0;
-      for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
-        uint32_t v;
-        bool neg;
-        cnf.lit(i, &v, &neg);
-        const uint32_t bit = 1u << (v & 31);
-        if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
-        len++;
-        const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
-        if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
-        else if (slot < 12) lm |= neg ? ~slot_pattern(slot - 6) : slot_pattern(slot - 6);
-        else (neg ? hn : hp) |= 1u << (slot - 12);
-      }
-      const size_t rec = 2 * (cd.res_base + pos);
-      res[rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
-      res[rec + 1] = make_uint4(hp, hp | hn, len, 0u);
-      pos++;
-    }
-  }
+  if (f_ok && cap_ok) up_records(cnf, as, T, F, A, P, res, cd.res_base, pos);
   if (lane == 0) {
     out[ci].status = !f_ok ? 2 : (!cap_ok ? 3 : 0);
     out[ci].f = int32_t(f_total);
@@ -674,8 +744,11 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
                                                      DevCubeOut* __restrict__ out,
                                                      const uint4* __restrict__ res,
                                                      unsigned long long* __restrict__ qkey,
-                                                     uint32_t* head, uint32_t mode) {
+                                                     uint32_t* head, uint32_t mode,
+                                                     const uint32_t* __restrict__ n_items_dev) {
   __shared__ uint32_t s_base, s_skip;
+  // the item count from device memory when the host does not know it
+  if (n_items_dev) n_items = *n_items_dev;
   // the wave index is the same for all lanes of a wave: make that explicit so
   // that block indices, the skip tests and the clause loop stay scalar
   const uint32_t tid = threadIdx.x, lane = tid & 63, wave = uniform_u32(tid >> 6);
@@ -785,6 +858,339 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
   }
 }
 
+
+// ---------------------------------------------------------------- device split
+// Counters of the split loop (u32 words of one 256-byte block).
+constexpr uint32_t kSpExpandHead = 0;   // expansion: next popped node
+constexpr uint32_t kSpChildren = 1;     // children pushed by this step
+constexpr uint32_t kSpLeaves = 2;       // leaves emitted by this step
+constexpr uint32_t kSpRes = 3;          // their residual records
+constexpr uint32_t kSpItems = 4;        // their work items
+constexpr uint32_t kSpError = 5;        // a propagation error (a broken invariant)
+constexpr uint32_t kSpLeafHead = 6;     // leaf kernel's head (it claims at head + 1)
+
+// Work items of a leaf with f active variables: blocks of 4096 assignments
+// in chunks of 2^chunk_log2 blocks, at most kSplitItemsPerLeaf chunks.
+__device__ __forceinline__ uint32_t split_items_of(int32_t f, uint32_t chunk_log2, uint32_t* chunk) {
+  const uint32_t blocks = f >= 12 ? (1u << (f - 12)) : 1u;
+  uint32_t c = chunk_log2 >= 26 ? (1u << 26) : (1u << chunk_log2);
+  const uint32_t need = (blocks + kSplitItemsPerLeaf - 1) / kSplitItemsPerLeaf;
+  if (c < need) c = need;
+  *chunk = c;
+  return (blocks + c - 1) / c;
+}
+
+// One popped node per wave: the parent's fixpoint plus the decision literal
+// (or a start node from the empty assignment), propagation to the new
+// fixpoint, then: a conflict is a refuted cube; at most k active variables
+// and at most max_res unsatisfied clauses make a leaf; else the first
+// active variable of the query's branch order is the branching variable
+// (its negative literal is the branch explored first).  The fixpoint of a
+// leaf or branching node goes to fix_out.  Nodes of queries already decided
+// or out of budget are dropped.
+__global__ __launch_bounds__(kBlock) void split_expand_kernel(
+    const DevQueryDesc* __restrict__ qd, const uint32_t* __restrict__ coff, const int32_t* __restrict__ lits,
+    const uint32_t* __restrict__ occ_offs, const uint32_t* __restrict__ occs,
+    const unsigned long long* __restrict__ order_off, const uint32_t* __restrict__ order,
+    const DevSplitNode* __restrict__ nodes, const uint32_t* __restrict__ node_fix, uint32_t first, uint32_t b,
+    const int32_t* __restrict__ start_lits, const unsigned long long* __restrict__ qkey,
+    DevSplitStat* __restrict__ stats, DevSplitOut* __restrict__ sout, uint32_t* __restrict__ fix_out,
+    uint32_t* __restrict__ ctr, uint32_t nw_max, uint32_t k, uint32_t max_res, unsigned long long max_cubes) {
+  extern __shared__ uint32_t smem[];
+  __shared__ UpShared sh[kUpWaves];
+  __shared__ uint32_t s_claim[kUpWaves];
+  const uint32_t lane = threadIdx.x & 63, wave = uniform_u32(threadIdx.x >> 6);
+  const size_t per_team = size_t(nw_max) * 4 + 2 * Team<1>::kQueue + 2 * Team<1>::kSize;
+  uint32_t* T = smem + wave * per_team;
+  uint32_t* F = T + nw_max;
+  uint32_t* A = F + nw_max;
+  uint32_t* P = A + nw_max;
+  uint32_t* Q = P + nw_max;
+  uint32_t* X = Q + 2 * Team<1>::kQueue;
+  Team<1> tm{sh[wave]};
+  for (;;) {
+    // the claimed node index goes through LDS: a value that only lane 0
+    // sets and a readfirstlane broadcasts lets the compiler fold the other
+    // lanes' placeholder into a constant on a path of its own, after which
+    // those lanes work on another node than lane 0
+    if (lane == 0) s_claim[wave] = atomicAdd(&ctr[kSpExpandHead], 1u);
+    wave_sync();
+    const uint32_t i = uniform_u32(s_claim[wave]);
+    wave_sync();
+    if (i >= b) break;
+    const DevSplitNode nd = nodes[first + i];
+    const uint32_t qid = uniform_u32(nd.qid);
+    DevSplitOut so{};
+    so.qid = qid;
+    // both read once for the wave, so that the drop is a uniform branch
+    const unsigned long long key =
+        uniform_u64(__hip_atomic_load(&qkey[qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    const unsigned long long spent =
+        uniform_u64(__hip_atomic_load(&stats[qid].cubes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (key != ~0ull || spent >= max_cubes) {
+      if (lane == 0) {
+        if (key == ~0ull) stats[qid].budget = 1;
+        sout[i] = so;   // kind 0: dropped
+      }
+      // every path back to the claim passes a wave barrier after its lane-0
+      // stores: without one here the compiler sends lanes 1..63 back to the
+      // loop head on a path of their own, around lane 0's claim
+      tm.sync();
+      continue;
+    }
+    const DevQueryDesc q = qd[qid];
+    const uint32_t nv = q.n_vars, nc = q.n_clauses, nw = (nv >> 5) + 1;
+    const GlobalCnf cnf{coff + q.coff_base, lits + q.lit_base};
+    const GlobalOcc occ{occ_offs + q.occ_off_base, occs + q.occ_base};
+    up_clear<1>(tm, nw, T, F, A, X, sh[wave]);
+    tm.sync();
+    const bool start = nd.lit == 0;
+    if (!start) {
+      const uint32_t* fx = node_fix + size_t(first + i) * 2 * nw_max;
+      for (uint32_t w = lane; w < nw; w += 64) { T[w] = fx[w]; F[w] = fx[nw_max + w]; }
+      tm.sync();
+      up_seed_lits<1>(tm, &nodes[first + i].lit, 1, nv, T, F, Q, sh[wave]);
+    } else {
+      up_seed_lits<1>(tm, start_lits + nd.lit_off, nd.n_lits, nv, T, F, Q, sh[wave]);
+      up_seed_units<1>(tm, cnf, nc, T, F, Q, sh[wave]);
+    }
+    tm.sync();
+    up_rounds<1>(tm, cnf, occ, nv, nc, T, F, Q, X, sh[wave]);
+    if (uniform_u32(sh[wave].conflict) || uniform_u32(sh[wave].error)) {
+      if (lane == 0) {
+        if (sh[wave].error) ctr[kSpError] = 1;
+        atomicAdd(&stats[qid].cubes, 1ull);
+        atomicAdd(&stats[qid].refuted, 1ull);
+        so.kind = kSplitRefuted;
+        sout[i] = so;
+      }
+      tm.sync();
+      continue;
+    }
+    const ActiveScan as = up_active<1>(tm, cnf, nc, T, F, A);
+    tm.sync();
+    uint32_t f_total, free_total, n_unsat;
+    up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
+    tm.scan(as.my_unsat, &n_unsat);
+    so.f = int32_t(f_total);
+    so.m = int32_t(free_total - f_total);
+    so.nres = n_unsat;
+    if (f_total <= k && n_unsat <= max_res) {
+      so.kind = kSplitLeaf;
+      if (lane == 0) atomicAdd(&stats[qid].cubes, 1ull);
+    } else {
+      // the first active variable of the branch order, 64 candidates at a time
+      const uint32_t* ord = order + order_off[qid];
+      uint32_t v = 0;
+      for (uint32_t j0 = 0; j0 < nv; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const uint32_t x = j < nv ? ord[j] : 0u;
+        const bool act = x != 0 && x <= nv && ((A[x >> 5] >> (x & 31)) & 1u);
+        const uint64_t m = __ballot(act);
+        if (m) {
+          v = uint32_t(__builtin_amdgcn_readlane(int(x), int(__builtin_ctzll(m))));
+          break;
+        }
+      }
+      if (v == 0) {   // f > 0 has an active variable: cannot happen
+        if (lane == 0) ctr[kSpError] = 1;
+        so.kind = kSplitDropped;
+      } else {
+        so.kind = kSplitBranch;
+        so.lit = -int32_t(v);
+      }
+    }
+    uint32_t* fo = fix_out + size_t(i) * 2 * nw_max;
+    for (uint32_t w = lane; w < nw; w += 64) { fo[w] = T[w]; fo[nw_max + w] = F[w]; }
+    if (lane == 0) sout[i] = so;
+    tm.sync();
+  }
+}
+
+// Exclusive scan over the workgroup (1024 threads) of one value per thread.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total, uint32_t* part) {
+  const uint32_t wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  uint32_t wt;
+  const uint32_t x = wave_exclusive_scan(v, &wt);
+  if ((threadIdx.x & 63) == 0) part[wv] = wt;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+  for (uint32_t w = 0; w < nwv; w++) {
+    if (w < wv) base += part[w];
+    tot += part[w];
+  }
+  __syncthreads();   // part is rewritten by the next scan
+  *total = tot;
+  return base + x;
+}
+
+// One workgroup: positions of this step's children, leaves, residual
+// records and work items (exclusive scans over the popped nodes, in their
+// order, so the layout is deterministic), the step totals, and the heads
+// of the next kernels reset.
+__global__ __launch_bounds__(1024) void split_scan_kernel(const DevSplitOut* __restrict__ sout, uint32_t b,
+                                                          uint32_t chunk_log2, uint32_t* __restrict__ child_off,
+                                                          uint32_t* __restrict__ leaf_idx,
+                                                          uint32_t* __restrict__ res_off,
+                                                          uint32_t* __restrict__ item_off,
+                                                          uint32_t* __restrict__ ctr) {
+  __shared__ uint32_t part[16];
+  const uint32_t per = (b + blockDim.x - 1) / blockDim.x;
+  const uint32_t i0 = min(b, threadIdx.x * per), i1 = min(b, i0 + per);
+  uint32_t c = 0, l = 0, r = 0, it = 0;
+  for (uint32_t i = i0; i < i1; i++) {
+    const DevSplitOut so = sout[i];
+    uint32_t ch;
+    c += so.kind == kSplitBranch ? 2u : 0u;
+    if (so.kind == kSplitLeaf) {
+      l++;
+      r += so.nres;
+      it += split_items_of(so.f, chunk_log2, &ch);
+    }
+  }
+  uint32_t tc, tl, tr, ti;
+  uint32_t bc = block_exclusive_scan(c, &tc, part);
+  uint32_t bl = block_exclusive_scan(l, &tl, part);
+  uint32_t br = block_exclusive_scan(r, &tr, part);
+  uint32_t bi = block_exclusive_scan(it, &ti, part);
+  for (uint32_t i = i0; i < i1; i++) {
+    const DevSplitOut so = sout[i];
+    uint32_t ch;
+    child_off[i] = bc;
+    leaf_idx[i] = bl;
+    res_off[i] = br;
+    item_off[i] = bi;
+    bc += so.kind == kSplitBranch ? 2u : 0u;
+    if (so.kind == kSplitLeaf) {
+      bl++;
+      br += so.nres;
+      bi += split_items_of(so.f, chunk_log2, &ch);
+    }
+  }
+  if (threadIdx.x == 0) {
+    ctr[kSpChildren] = tc;
+    ctr[kSpLeaves] = tl;
+    ctr[kSpRes] = tr;
+    ctr[kSpItems] = ti;
+    ctr[kSpExpandHead] = 0;
+    ctr[kSpLeafHead + 1] = 0;
+  }
+}
+
+// One popped node per wave: a branching node's two children are pushed at
+// its scanned position (the branch explored first on top, so that it is
+// popped first when steps are short), each with a copy of the node's
+// fixpoint; a leaf gets its cube descriptor, initial results, residual
+// records (rebuilt from its fixpoint, as the propagation kernel builds
+// them) and work items.
+__global__ __launch_bounds__(kBlock) void split_scatter_kernel(
+    const DevQueryDesc* __restrict__ qd, const uint32_t* __restrict__ coff, const int32_t* __restrict__ lits,
+    const DevSplitOut* __restrict__ sout, const uint32_t* __restrict__ fix_out, uint32_t first, uint32_t b,
+    const uint32_t* __restrict__ child_off, const uint32_t* __restrict__ leaf_idx,
+    const uint32_t* __restrict__ res_off, const uint32_t* __restrict__ item_off, DevSplitNode* __restrict__ nodes,
+    uint32_t* __restrict__ node_fix, DevCubeDesc* __restrict__ descs, DevCubeOut* __restrict__ louts,
+    uint32_t* __restrict__ leaf_src, DevItem* __restrict__ items, uint4* __restrict__ res, uint32_t seq_base,
+    uint32_t nw_max, uint32_t chunk_log2) {
+  extern __shared__ uint32_t smem[];
+  __shared__ UpShared sh[kUpWaves];
+  const uint32_t lane = threadIdx.x & 63, wave = uniform_u32(threadIdx.x >> 6);
+  uint32_t* T = smem + wave * size_t(nw_max) * 4;
+  uint32_t* F = T + nw_max;
+  uint32_t* A = F + nw_max;
+  uint32_t* P = A + nw_max;
+  Team<1> tm{sh[wave]};
+  for (uint32_t i = blockIdx.x * kUpWaves + wave; i < b; i += gridDim.x * kUpWaves) {
+    const DevSplitOut so = sout[i];
+    const uint32_t kind = uniform_u32(so.kind);
+    const uint32_t* fx = fix_out + size_t(i) * 2 * nw_max;
+    if (kind == kSplitBranch) {
+      const uint32_t s = first + child_off[i];
+      if (lane == 0) {
+        nodes[s] = DevSplitNode{so.qid, -so.lit, 0u, 0u};
+        nodes[s + 1] = DevSplitNode{so.qid, so.lit, 0u, 0u};
+      }
+      uint32_t* d0 = node_fix + size_t(s) * 2 * nw_max;
+      uint32_t* d1 = d0 + 2 * nw_max;
+      const uint32_t nw = (qd[so.qid].n_vars >> 5) + 1;
+      for (uint32_t w = lane; w < nw; w += 64) {
+        const uint32_t t = fx[w], f = fx[nw_max + w];
+        d0[w] = t;
+        d0[nw_max + w] = f;
+        d1[w] = t;
+        d1[nw_max + w] = f;
+      }
+      tm.sync();   // the whole wave reaches the next node together
+    } else if (kind == kSplitLeaf) {
+      const uint32_t j = leaf_idx[i];
+      const DevQueryDesc q = qd[so.qid];
+      const uint32_t nv = q.n_vars, nc = q.n_clauses, nw = (nv >> 5) + 1;
+      const GlobalCnf cnf{coff + q.coff_base, lits + q.lit_base};
+      for (uint32_t w = lane; w < nw; w += 64) { T[w] = fx[w]; F[w] = fx[nw_max + w]; A[w] = 0; }
+      tm.sync();
+      const ActiveScan as = up_active<1>(tm, cnf, nc, T, F, A);
+      tm.sync();
+      uint32_t f_total, free_total, n_unsat;
+      up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
+      tm.sync();
+      const uint32_t pos = tm.scan(as.my_unsat, &n_unsat);
+      up_records(cnf, as, T, F, A, P, res, res_off[i], pos);
+      uint32_t chunk;
+      const uint32_t n_it = split_items_of(so.f, chunk_log2, &chunk);
+      const uint32_t blocks = so.f >= 12 ? (1u << (so.f - 12)) : 1u;
+      for (uint32_t t = lane; t < n_it; t += 64) {
+        const uint32_t lo = t * chunk;
+        items[item_off[i] + t] = DevItem{j, lo, min(blocks, lo + chunk), 0u};
+      }
+      if (lane == 0) {
+        DevCubeDesc d{};
+        d.qid = so.qid;
+        d.seq = seq_base + j;
+        d.f_expect = so.f;
+        d.nres_cap = so.nres;
+        d.res_base = res_off[i];
+        descs[j] = d;
+        DevCubeOut o{};
+        // a rebuilt fixpoint that disagrees with the expansion is a mismatch
+        o.status = (f_total == uint32_t(so.f) && n_unsat == so.nres) ? 0 : 2;
+        o.f = so.f;
+        o.m = so.m;
+        o.nres = int32_t(so.nres);
+        o.first = ~0ull;
+        louts[j] = o;
+        leaf_src[j] = i;
+      }
+      tm.sync();
+    }
+  }
+}
+
+// After the leaf kernel: per-query counters from this step's leaves, and
+// the fixpoint of the leaf that holds a query's witness key (DECIDE).
+__global__ __launch_bounds__(kBlock) void split_capture_kernel(
+    const DevCubeDesc* __restrict__ descs, const DevCubeOut* __restrict__ louts,
+    const uint32_t* __restrict__ leaf_src, const uint32_t* __restrict__ fix_out,
+    uint32_t* __restrict__ ctr, const unsigned long long* __restrict__ qkey,
+    DevSplitStat* __restrict__ stats, uint32_t* __restrict__ wit, uint32_t nw_max, uint32_t mode) {
+  const uint32_t n = ctr[kSpLeaves];
+  for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const DevCubeDesc d = descs[j];
+    const DevCubeOut o = louts[j];
+    if (o.status != 0) atomicOr(&ctr[kSpError], 2u);
+    atomicAdd(&stats[d.qid].leaves, 1ull);
+    atomicAdd(&stats[d.qid].blocks, (unsigned long long)o.blocks);
+    atomicAdd(&stats[d.qid].clause_blocks, (unsigned long long)o.clause_blocks);
+    atomicAdd(&stats[d.qid].word_ops, (unsigned long long)o.word_ops);
+    if (mode == SCUBA_MODE_DECIDE) {
+      const unsigned long long key = qkey[d.qid];
+      if (key != ~0ull && uint32_t(key >> 38) == d.seq) {
+        const uint32_t* fx = fix_out + size_t(leaf_src[j]) * 2 * nw_max;
+        uint32_t* wq = wit + size_t(d.qid) * 2 * nw_max;
+        for (uint32_t w = 0; w < 2 * nw_max; w++) wq[w] = fx[w];
+      }
+    }
+  }
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
@@ -827,6 +1233,40 @@ RoundLayout round_layout(size_t base, size_t n_cubes, size_t n_lits, size_t n_it
   return l;
 }
 
+struct SplitLayout {
+  size_t order_off, order, ctr, stats, wit, nodes, node_fix, sout, fix_out, child_off, leaf_idx, res_off, item_off,
+      descs, louts, leaf_src, items, res, end;
+};
+SplitLayout split_layout(size_t base, size_t nq, size_t n_order, const SplitRun& r) {
+  const size_t B = r.batch, N = r.stack_cap, fw = 2 * size_t(r.nw_max) * 4;
+  SplitLayout l;
+  l.order_off = base;
+  l.order = align256(l.order_off + nq * 8);
+  l.ctr = align256(l.order + n_order * 4);
+  l.stats = align256(l.ctr + 256);
+  l.wit = align256(l.stats + nq * sizeof(DevSplitStat));
+  l.nodes = align256(l.wit + nq * fw);
+  l.node_fix = align256(l.nodes + N * sizeof(DevSplitNode));
+  l.sout = align256(l.node_fix + N * fw);
+  l.fix_out = align256(l.sout + B * sizeof(DevSplitOut));
+  l.child_off = align256(l.fix_out + B * fw);
+  l.leaf_idx = align256(l.child_off + B * 4);
+  l.res_off = align256(l.leaf_idx + B * 4);
+  l.item_off = align256(l.res_off + B * 4);
+  l.descs = align256(l.item_off + B * 4);
+  l.louts = align256(l.descs + B * sizeof(DevCubeDesc));
+  l.leaf_src = align256(l.louts + B * sizeof(DevCubeOut));
+  l.items = align256(l.leaf_src + B * 4);
+  l.res = align256(l.items + B * kSplitItemsPerLeaf * sizeof(DevItem));
+  l.end = align256(l.res + (B * size_t(r.nres_max) + 4) * 32);   // + look-ahead of the leaf kernel
+  return l;
+}
+// dynamic LDS of the split kernels
+size_t split_expand_lds(uint32_t nw_max) {
+  return kUpWaves * (size_t(nw_max) * 4 + 2 * Team<1>::kQueue + 2 * Team<1>::kSize) * 4;
+}
+size_t split_scatter_lds(uint32_t nw_max) { return kUpWaves * size_t(nw_max) * 4 * 4; }
+
 }  // namespace
 
 void dev_init(DeviceInfo* info, int device) {
@@ -866,6 +1306,10 @@ void dev_init(DeviceInfo* info, int device) {
     if (hipFuncSetAttribute(reinterpret_cast<const void*>(&up_kernel<1>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&up_kernel<4>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&split_expand_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&split_scatter_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
       info->up_lds_max = want;
     else
@@ -1095,7 +1539,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                             reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
                             reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
                             reinterpret_cast<unsigned long long*>(w + cl.qkey),
-                            reinterpret_cast<uint32_t*>(w + rl.head), mode);
+                            reinterpret_cast<uint32_t*>(w + rl.head), mode, (const uint32_t*)nullptr);
       HIP_OK(hipGetLastError());
     }
     if (ev) HIP_OK(hipEventRecord(ev[6], q));
@@ -1172,6 +1616,176 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   std::memcpy(outs->data(), s, nc * sizeof(DevCubeOut));
   qkeys->resize(cnf.q.size());
   std::memcpy(qkeys->data(), s + align256(nc * sizeof(DevCubeOut)), cnf.q.size() * 8);
+}
+
+size_t dev_split_node_bytes(uint32_t nw_max) { return sizeof(DevSplitNode) + 2 * size_t(nw_max) * 4; }
+
+size_t dev_split_bytes(const CnfHost& cnf, size_t n_order, const SplitRun& r) {
+  const CnfLayout cl = cnf_layout(cnf);
+  return split_layout(cl.end, cnf.q.size(), n_order, r).end;
+}
+
+void dev_split(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
+               const std::vector<uint64_t>& order_off, const std::vector<uint32_t>& order,
+               const std::vector<uint32_t>& start, const SplitRun& r, void* stream, void* staging,
+               size_t staging_bytes, SplitOutput* out) {
+  HIP_OK(hipSetDevice(info.device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t nq = cnf.q.size();
+  const CnfLayout cl = cnf_layout(cnf);
+  const SplitLayout sl = split_layout(cl.end, nq, order.size(), r);
+  if (sl.end > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the device split");
+  // host-side checks of what the kernels assume
+  if (r.batch == 0 || r.batch > (1u << 20) || r.stack_cap < 2 * size_t(r.batch))
+    fail(SCUBA_E_INTERNAL, "device split batch or stack out of range");
+  if (start.size() > r.stack_cap) fail(SCUBA_E_CAPACITY, "more start nodes than the device split stack holds");
+  if (order_off.size() != nq) fail(SCUBA_E_INTERNAL, "branch orders do not match the batch");
+  for (uint32_t q : start) {
+    if (q >= nq || (cnf.skip_root_unsat && cnf.src->q[q].root_unsat)) fail(SCUBA_E_INTERNAL, "start node out of range");
+    if ((cnf.q[q].n_vars >> 5) + 1 > r.nw_max) fail(SCUBA_E_INTERNAL, "query wider than the split bitmaps");
+    if (order_off[q] + cnf.q[q].n_vars > order.size()) fail(SCUBA_E_INTERNAL, "branch order out of range");
+    if (cnf.q[q].n_clauses > r.nres_max && r.max_res > r.nres_max)
+      fail(SCUBA_E_INTERNAL, "residual bound below a query's clause count");
+  }
+  if (r.k > kMaxLeafVars || r.chunk_log2 > 26) fail(SCUBA_E_INTERNAL, "split options out of range");
+  const size_t e_lds = split_expand_lds(r.nw_max), s_lds = split_scatter_lds(r.nw_max);
+  if (e_lds > info.up_lds_max || s_lds > info.up_lds_max)
+    fail(SCUBA_E_CAPACITY, "query too large for the device split's LDS");
+  const size_t B = r.batch;
+  const size_t up_b = sl.nodes + start.size() * sizeof(DevSplitNode) - sl.order_off;
+  const size_t fin_b = align256(nq * 8) + align256(nq * sizeof(DevSplitStat)) + nq * 2 * size_t(r.nw_max) * 4;
+  const size_t cnt_b = align256(B * sizeof(DevCubeDesc)) + B * sizeof(DevCubeOut);
+  if (std::max({up_b, fin_b, cnt_b, size_t(256)}) > staging_bytes) fail(SCUBA_E_INTERNAL, "staging too small");
+
+  char* s = static_cast<char*>(staging);
+  std::memset(s, 0, up_b);   // counters, statistics and witness fixpoints start at 0
+  std::memcpy(s + (sl.order_off - sl.order_off), order_off.data(), nq * 8);
+  std::memcpy(s + (sl.order - sl.order_off), order.data(), order.size() * 4);
+  DevSplitNode* sn = reinterpret_cast<DevSplitNode*>(s + (sl.nodes - sl.order_off));
+  for (size_t i = 0; i < start.size(); i++) sn[i] = DevSplitNode{start[i], 0, 0u, 0u};
+  char* w = static_cast<char*>(ws);
+  HIP_OK(hipMemcpyAsync(w + sl.order_off, s, up_b, hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));   // the staging buffer is reused below
+
+  const auto* qd = reinterpret_cast<const DevQueryDesc*>(w + cl.q);
+  const auto* coff = reinterpret_cast<const uint32_t*>(w + cl.coff);
+  const auto* lits = reinterpret_cast<const int32_t*>(w + cl.lits);
+  const auto* occ_off = reinterpret_cast<const uint32_t*>(w + cl.occ_off);
+  const auto* occ = reinterpret_cast<const uint32_t*>(w + cl.occ);
+  auto* qkey = reinterpret_cast<unsigned long long*>(w + cl.qkey);
+  auto* ctr = reinterpret_cast<uint32_t*>(w + sl.ctr);
+  auto* stats = reinterpret_cast<DevSplitStat*>(w + sl.stats);
+  auto* nodes = reinterpret_cast<DevSplitNode*>(w + sl.nodes);
+  auto* node_fix = reinterpret_cast<uint32_t*>(w + sl.node_fix);
+  auto* sout = reinterpret_cast<DevSplitOut*>(w + sl.sout);
+  auto* fix_out = reinterpret_cast<uint32_t*>(w + sl.fix_out);
+  auto* descs = reinterpret_cast<DevCubeDesc*>(w + sl.descs);
+  auto* louts = reinterpret_cast<DevCubeOut*>(w + sl.louts);
+  const uint32_t g = r.grid ? r.grid : uint32_t(info.cus) * 8;
+  hipEvent_t ev[4];
+  for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 4; i++) (void)hipEventDestroy(e[i]); }
+  } eg{ev};
+  if (r.mode == SCUBA_MODE_COUNT) out->leaves.assign(nq, {});
+  // Steps pop at most the headroom above a reserve of (largest variable
+  // count + 2) nodes; within the reserve they pop one node.  A one-node step
+  // is depth-first: the nodes it leaves above the current stack are at most
+  // one per decision of the current path, and a path decides at most every
+  // variable once, so the stack never exceeds its capacity.
+  uint64_t reserve = 2;
+  for (uint32_t q : start) reserve = std::max<uint64_t>(reserve, uint64_t(cnf.q[q].n_vars) + 2);
+  if (r.stack_cap < start.size() + reserve)
+    fail(SCUBA_E_CAPACITY, "device split stack smaller than the start nodes and one depth-first path");
+  uint64_t top = start.size(), seq_base = 0;
+  while (top > 0) {
+    const uint64_t head = r.stack_cap - top;
+    uint64_t b = std::min<uint64_t>({uint64_t(B), top, head > reserve ? head - reserve : 1});
+    if (top + b > r.stack_cap) fail(SCUBA_E_INTERNAL, "device split stack bound broken");
+    const uint64_t first = top - b;
+    const uint32_t gw = uint32_t(std::min<uint64_t>(g, (b + kUpWaves - 1) / kUpWaves));
+    launch(split_expand_kernel, dim3(gw), dim3(kBlock), e_lds, st, ev[0], ev[1], qd, coff, lits, occ_off, occ,
+           reinterpret_cast<const unsigned long long*>(w + sl.order_off),
+           reinterpret_cast<const uint32_t*>(w + sl.order), (const DevSplitNode*)nodes, (const uint32_t*)node_fix,
+           uint32_t(first), uint32_t(b), (const int32_t*)nullptr, (const unsigned long long*)qkey, stats, sout,
+           fix_out, ctr, r.nw_max, r.k, r.max_res, (unsigned long long)r.max_cubes);
+    HIP_OK(hipGetLastError());
+    launch(split_scan_kernel, dim3(1), dim3(1024), 0, st, nullptr, nullptr, (const DevSplitOut*)sout, uint32_t(b),
+           r.chunk_log2, reinterpret_cast<uint32_t*>(w + sl.child_off), reinterpret_cast<uint32_t*>(w + sl.leaf_idx),
+           reinterpret_cast<uint32_t*>(w + sl.res_off), reinterpret_cast<uint32_t*>(w + sl.item_off), ctr);
+    HIP_OK(hipGetLastError());
+    launch(split_scatter_kernel, dim3(gw), dim3(kBlock), s_lds, st, nullptr, nullptr, qd, coff, lits,
+           (const DevSplitOut*)sout, (const uint32_t*)fix_out, uint32_t(first), uint32_t(b),
+           reinterpret_cast<const uint32_t*>(w + sl.child_off), reinterpret_cast<const uint32_t*>(w + sl.leaf_idx),
+           reinterpret_cast<const uint32_t*>(w + sl.res_off), reinterpret_cast<const uint32_t*>(w + sl.item_off),
+           nodes, node_fix, descs, louts, reinterpret_cast<uint32_t*>(w + sl.leaf_src),
+           reinterpret_cast<DevItem*>(w + sl.items), reinterpret_cast<uint4*>(w + sl.res), uint32_t(seq_base),
+           r.nw_max, r.chunk_log2);
+    HIP_OK(hipGetLastError());
+    launch(leaf_kernel, dim3(g), dim3(kBlock), 0, st, ev[2], ev[3], reinterpret_cast<const DevItem*>(w + sl.items),
+           0u, (const DevCubeDesc*)descs, louts, reinterpret_cast<const uint4*>(w + sl.res), qkey,
+           ctr + kSpLeafHead, r.mode, (const uint32_t*)(ctr + kSpItems));
+    HIP_OK(hipGetLastError());
+    launch(split_capture_kernel, dim3(std::min<uint64_t>(g, (b + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+           nullptr, nullptr, (const DevCubeDesc*)descs, (const DevCubeOut*)louts,
+           reinterpret_cast<const uint32_t*>(w + sl.leaf_src), (const uint32_t*)fix_out, ctr,
+           (const unsigned long long*)qkey, stats, reinterpret_cast<uint32_t*>(w + sl.wit), r.nw_max, r.mode);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipMemcpyAsync(s, ctr, 256, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    uint32_t c[64];
+    std::memcpy(c, s, 256);
+    if (c[kSpError] & 1) fail(SCUBA_E_DEVICE, "device split: propagation error");
+    if (c[kSpError] & 2) fail(SCUBA_E_DEVICE, "device split: a leaf's rebuilt fixpoint disagrees with its expansion");
+    if (c[kSpChildren] > 2 * b || c[kSpLeaves] > b) fail(SCUBA_E_DEVICE, "device split: step totals out of range");
+    float ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    out->expand_ms += ms;
+    HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3]));
+    out->leaf_ms += ms;
+    if (r.mode == SCUBA_MODE_COUNT && c[kSpLeaves]) {
+      const size_t nl = c[kSpLeaves];
+      HIP_OK(hipMemcpyAsync(s, descs, nl * sizeof(DevCubeDesc), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(s + align256(B * sizeof(DevCubeDesc)), louts, nl * sizeof(DevCubeOut),
+                            hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      const DevCubeDesc* dh = reinterpret_cast<const DevCubeDesc*>(s);
+      const DevCubeOut* oh = reinterpret_cast<const DevCubeOut*>(s + align256(B * sizeof(DevCubeDesc)));
+      for (size_t j = 0; j < nl; j++) out->leaves[dh[j].qid].push_back(oh[j]);
+    }
+    top = first + c[kSpChildren];
+    seq_base += c[kSpLeaves];
+    out->steps++;
+    out->nodes += b;
+    out->max_stack = std::max<uint64_t>(out->max_stack, top);
+    // the witness key holds leaf sequence numbers below 2^26
+    if (top > 0 && seq_base + B >= (uint64_t(1) << 26)) {
+      out->stopped = true;
+      break;
+    }
+  }
+  HIP_OK(hipMemcpyAsync(s, qkey, nq * 8, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(s + align256(nq * 8), stats, nq * sizeof(DevSplitStat), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(s + align256(nq * 8) + align256(nq * sizeof(DevSplitStat)), w + sl.wit,
+                        nq * 2 * size_t(r.nw_max) * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  out->qkeys.resize(nq);
+  std::memcpy(out->qkeys.data(), s, nq * 8);
+  out->stats.resize(nq);
+  std::memcpy(out->stats.data(), s + align256(nq * 8), nq * sizeof(DevSplitStat));
+  out->wit.resize(nq * 2 * size_t(r.nw_max));
+  std::memcpy(out->wit.data(), s + align256(nq * 8) + align256(nq * sizeof(DevSplitStat)),
+              out->wit.size() * 4);
+}
+
+size_t dev_split_staging(const CnfHost& cnf, size_t n_order, size_t n_start, const SplitRun& r) {
+  const size_t nq = cnf.q.size();
+  const SplitLayout sl = split_layout(0, nq, n_order, r);
+  const size_t up_b = sl.nodes + n_start * sizeof(DevSplitNode);
+  const size_t fin_b = align256(nq * 8) + align256(nq * sizeof(DevSplitStat)) + nq * 2 * size_t(r.nw_max) * 4;
+  const size_t cnt_b = align256(size_t(r.batch) * sizeof(DevCubeDesc)) + size_t(r.batch) * sizeof(DevCubeOut);
+  return std::max({up_b, fin_b, cnt_b, size_t(256)});
 }
 
 }  // namespace scuba

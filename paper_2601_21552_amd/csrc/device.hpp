@@ -136,4 +136,72 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                size_t staging_bytes, std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys,
                RoundTimes* times, DevGraphs* graphs = nullptr);
 
+// ---------------------------------------------------------------- device split
+// Splitting on the device (scuba_decide with SCUBA_SOLVE_DEVICE_SPLIT): a
+// work stack of nodes in device memory.  A node is a query, the fixpoint of
+// its parent (two bitmaps of nw_max words, T then F, stored beside the
+// stack) and the decision literal to add; a start node (lit = 0) is
+// propagated from the empty assignment with its literals
+// [lit_off, lit_off + n_lits) of the start-literal array.
+struct DevSplitNode {
+  uint32_t qid;
+  int32_t lit;
+  uint32_t lit_off, n_lits;
+};
+// What the expansion of one popped node found.
+struct DevSplitOut {
+  uint32_t kind;        // kSplit* below
+  int32_t lit;          // branch: the literal of the branch explored first
+  int32_t f, m;         // active / other unassigned variables
+  uint32_t nres, qid, pad0, pad1;
+};
+constexpr uint32_t kSplitDropped = 0;   // its query is decided or out of budget
+constexpr uint32_t kSplitLeaf = 1;
+constexpr uint32_t kSplitBranch = 2;
+constexpr uint32_t kSplitRefuted = 3;
+// A leaf's blocks are cut into at most this many work items.
+constexpr uint32_t kSplitItemsPerLeaf = 64;
+// Per-query counters of the device split.
+struct DevSplitStat {
+  unsigned long long cubes;    // leaves + refuted nodes
+  unsigned long long refuted;
+  unsigned long long leaves;   // leaves evaluated
+  unsigned long long blocks, clause_blocks, word_ops;
+  uint32_t budget;             // 1: a node was dropped for the cube budget
+  uint32_t pad;
+};
+
+struct SplitRun {
+  uint32_t k = 30, max_res = 2048, mode = 0, chunk_log2 = 8, grid = 0;
+  uint32_t batch = 0;          // nodes expanded per step
+  uint64_t max_cubes = 0;
+  uint32_t nw_max = 1;         // bitmap words of the largest query
+  uint32_t nres_max = 1;       // residual records a leaf may need
+  size_t stack_cap = 0;        // nodes the stack holds
+};
+struct SplitOutput {
+  std::vector<uint64_t> qkeys;              // per query: smallest (leaf sequence << 38 | index), ~0 none
+  std::vector<DevSplitStat> stats;          // per query
+  std::vector<uint32_t> wit;                // per query 2*nw_max words: T, F of the witness leaf
+  std::vector<std::vector<DevCubeOut>> leaves;   // COUNT mode: each query's leaves, in emission order
+  bool stopped = false;                     // the leaf sequence space ran out: open queries undecided
+  uint64_t steps = 0, nodes = 0, max_stack = 0;
+  double expand_ms = 0, leaf_ms = 0, other_ms = 0;
+};
+// Device bytes of the split region (after the CNF) for `cnf`, an order
+// array of n_order entries and the run's batch, residual bound and stack.
+size_t dev_split_bytes(const CnfHost& cnf, size_t n_order, const SplitRun& r);
+// Bytes of one stack node (record and fixpoint).
+size_t dev_split_node_bytes(uint32_t nw_max);
+// Host staging bytes dev_split needs.
+size_t dev_split_staging(const CnfHost& cnf, size_t n_order, size_t n_start, const SplitRun& r);
+// The whole split-and-evaluate loop for the start queries `start` (one start
+// node each, from the root).  order_off[q] indexes the concatenated branch
+// orders (variables, first choice first).  The CNF must already be uploaded
+// (dev_upload_cnf); the stream is synchronised on return.
+void dev_split(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
+               const std::vector<uint64_t>& order_off, const std::vector<uint32_t>& order,
+               const std::vector<uint32_t>& start, const SplitRun& r, void* stream, void* staging,
+               size_t staging_bytes, SplitOutput* out);
+
 }  // namespace scuba

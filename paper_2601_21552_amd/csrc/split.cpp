@@ -473,6 +473,16 @@ int32_t Splitter::choose_word() const {
   return choose_static();
 }
 
+std::vector<int32_t> Splitter::branch_order() const {
+  if (!word_) return order_;
+  // choose_word takes the first active input bit of word_order_, else the
+  // first active variable of the static order, which is then no input bit
+  std::vector<int32_t> out = word_order_;
+  for (int32_t v : order_)
+    if (!bit_width_[v]) out.push_back(v);
+  return out;
+}
+
 int32_t Splitter::choose_static() const {
   for (int32_t v : order_)
     if (assign_[v] < 0 && act_cnt_[v] > 0) return v;

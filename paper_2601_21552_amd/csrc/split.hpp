@@ -61,6 +61,10 @@ class Splitter {
   // to the lowest variable), which halves an input's value range per
   // decision; then the static order for the remaining (auxiliary) variables.
   void set_word_order();
+  // The fixed branch order of the static or word ordering: every variable,
+  // the one a node branches on being the first of them that is active
+  // there (the word ordering's active input bits, then the static order).
+  std::vector<int32_t> branch_order() const;
   // Leaves carry their fixpoint (Cube::assign, Cube::active).
   void set_keep_leaf_state() { keep_leaf_state_ = true; }
   // Trace mode (static ordering): at every `every`-th decision node above

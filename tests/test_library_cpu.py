@@ -415,3 +415,28 @@ def test_noalloc_rejects_batches_beyond_its_scratch(ctx):
     st = ctx.lib.scuba_decide_noalloc(ctx.h, small.h, C.byref(_solve_opts(k=30, graph=True)), None,
                                       C.byref(h))
     assert st == -1 and not h.value   # SCUBA_E_INVALID
+
+
+def test_device_split_options_are_checked(ctx):
+    """The device split's option checks run before any device work: no
+    graphs, no learned scorer, no given cubes, no allocation-free form, and
+    a bounded step; its workspace grows with the step size."""
+    import ctypes as C
+    from paper_2601_21552_amd import _lib
+    from paper_2601_21552_amd.api import _solve_opts
+    rng = np.random.Generator(np.random.PCG64(5))
+    cnf = ctx.cnf_from_arrays(*w.concat([w.random_ksat(60, 256, 3, rng) for _ in range(8)]))
+    small = ctx.decide_workspace(cnf, k=16, device_split=True, split_batch=256)
+    big = ctx.decide_workspace(cnf, k=16, device_split=True, split_batch=4096)
+    assert 0 < small < big
+    for bad in (dict(graph=True), dict(split_batch=(1 << 20) + 1)):
+        with pytest.raises(_lib.ScubaError):
+            ctx.decide_workspace(cnf, k=16, device_split=True, **bad)
+    h = C.c_void_p()
+    st = ctx.lib.scuba_decide_noalloc(ctx.h, cnf.h, C.byref(_solve_opts(k=16, device_split=True)), None,
+                                      C.byref(h))
+    assert st == -1 and not h.value   # SCUBA_E_INVALID
+    cubes = ctx.split(cnf, k=16)
+    st = ctx.lib.scuba_solve(ctx.h, cnf.h, cubes.h, C.byref(_solve_opts(k=16, device_split=True)),
+                             C.c_void_p(1), 1 << 20, None, C.byref(h))
+    assert st == -1 and not h.value
