@@ -254,6 +254,12 @@ uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint
   d.qid = qid;
   d.lit_off = uint32_t(rh.cube_lits.size());
   d.n_lits = uint32_t(c.lits.size());
+  // a leaf whose fixpoint the splitter kept goes as that fixpoint (two
+  // bitmaps), so the device confirms it instead of propagating the cube
+  // again; 2 * (n_vars/32 + 1) words fit the literal bound of a round
+  const bool fix = !c.refuted() && c.assign.size() == size_t(n_vars) + 1 && n_vars >= 2 &&
+                   2 * ((n_vars >> 5) + 1) <= kMaxCubeLen;
+  if (fix) d.n_lits = kCubeFixpoint | (2 * ((n_vars >> 5) + 1));
   d.seq = seq;
   d.f_expect = c.refuted() ? -1 : c.f;
   d.nres_cap = c.refuted() ? 0 : c.nres;
@@ -261,7 +267,16 @@ uint32_t add_cube(RoundHost& rh, uint32_t qid, uint32_t seq, const Cube& c, uint
   rh.res_records += d.nres_cap;
   rh.tile_max = std::max(rh.tile_max, d.nres_cap);
   rh.nw_max = std::max(rh.nw_max, (n_vars >> 5) + 1);
-  rh.cube_lits.insert(rh.cube_lits.end(), c.lits.begin(), c.lits.end());
+  if (fix) {
+    const uint32_t nw = (n_vars >> 5) + 1;
+    const size_t base = rh.cube_lits.size();
+    rh.cube_lits.resize(base + 2 * size_t(nw), 0);
+    uint32_t* words = reinterpret_cast<uint32_t*>(rh.cube_lits.data() + base);
+    for (uint32_t v = 1; v <= n_vars; v++)
+      if (c.assign[v] >= 0) words[(c.assign[v] ? 0 : nw) + (v >> 5)] |= 1u << (v & 31);
+  } else {
+    rh.cube_lits.insert(rh.cube_lits.end(), c.lits.begin(), c.lits.end());
+  }
   uint32_t ci = uint32_t(rh.cubes.size());
   rh.cubes.push_back(d);
   return ci;

@@ -580,8 +580,16 @@ __device__ void propagate_cube(const Cnf& cnf, const Occ& occ, const DevCubeDesc
   const uint32_t nw = (nv >> 5) + 1;   // bits 0..nv
   up_clear<TW>(tm, nw, T, F, A, X, sh);
   tm.sync();
-  up_seed_lits<TW>(tm, cube_lits + cd.lit_off, cd.n_lits, nv, T, F, Q, sh);
-  up_seed_units<TW>(tm, cnf, nc, T, F, Q, sh);
+  if (cd.n_lits & kCubeFixpoint) {
+    // the host's fixpoint: round 0 visits every clause (as after a queue
+    // overflow), which confirms it or propagates on from it
+    const uint32_t* fw = reinterpret_cast<const uint32_t*>(cube_lits + cd.lit_off);
+    for (uint32_t w = lane; w < nw; w += Team<TW>::kSize) { T[w] = fw[w]; F[w] = fw[nw + w]; }
+    if (lane == 0) sh.ovf[2] = 1;
+  } else {
+    up_seed_lits<TW>(tm, cube_lits + cd.lit_off, cd.n_lits, nv, T, F, Q, sh);
+    up_seed_units<TW>(tm, cnf, nc, T, F, Q, sh);
+  }
   tm.sync();
   up_rounds<TW>(tm, cnf, occ, nv, nc, T, F, Q, X, sh);
   if (uniform_u32(sh.conflict) || uniform_u32(sh.error)) {
@@ -627,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
                                                    const int32_t* __restrict__ cube_lits,
                                                    const uint2* __restrict__ groups, uint32_t n_groups,
                                                    DevCubeOut* __restrict__ out, uint4* __restrict__ res,
-                                                   uint32_t* head, uint32_t nw_max) {
+                                                   uint32_t* head, uint32_t nw_max, uint32_t occ_in_memory) {
   // LDS: per team four bitmaps of nw_max words, two frontier queues and
   // the scan space, then the staged CNF
   constexpr uint32_t kTeams = kUpWaves / TW;
@@ -685,18 +693,18 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
         for (uint32_t u = 0; u < kStageUnroll; u++) {
           const uint32_t i = b + u * kBlock;
           x[u] = i < nl ? L[i] : 0;
-          y[u] = i < nl ? oc[i] : 0u;
+          y[u] = i < nl && !occ_in_memory ? oc[i] : 0u;
         }
 #pragma unroll
         for (uint32_t u = 0; u < kStageUnroll; u++) {
           const uint32_t i = b + u * kBlock;
           if (i < nl) {
             sl[i] = uint16_t((uint32_t(x[u] > 0 ? x[u] : -x[u]) << 1) | (x[u] < 0 ? 1u : 0u));
-            soc[i] = uint16_t(y[u]);
+            if (!occ_in_memory) soc[i] = uint16_t(y[u]);
           }
         }
       }
-      for (uint32_t b = tid; b <= nli; b += kStageUnroll * kBlock) {
+      for (uint32_t b = tid; !occ_in_memory && b <= nli; b += kStageUnroll * kBlock) {
         uint32_t x[kStageUnroll];
 #pragma unroll
         for (uint32_t u = 0; u < kStageUnroll; u++) {
@@ -712,8 +720,12 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
       __syncthreads();
       if (team < g.y) {
         const uint32_t ci = g.x + team;
-        propagate_cube<TW>(LdsCnf{sco, sl}, LdsOcc{soo, soc}, cubes[ci], ci, q.n_vars, q.n_clauses, cube_lits,
-                           out, res, T, F, A, P, Q, X, sh[team]);
+        if (occ_in_memory)   // (only a host fixpoint that is not one needs them)
+          propagate_cube<TW>(LdsCnf{sco, sl}, GlobalOcc{oo, oc}, cubes[ci], ci, q.n_vars, q.n_clauses,
+                             cube_lits, out, res, T, F, A, P, Q, X, sh[team]);
+        else
+          propagate_cube<TW>(LdsCnf{sco, sl}, LdsOcc{soo, soc}, cubes[ci], ci, q.n_vars, q.n_clauses,
+                             cube_lits, out, res, T, F, A, P, Q, X, sh[team]);
       }
     } else if (team < g.y) {
       const uint32_t ci = g.x + team;
@@ -1454,16 +1466,32 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   if (up_bytes > staging_bytes || align256(nc * sizeof(DevCubeOut)) + cnf.q.size() * 8 > staging_bytes)
     fail(SCUBA_E_INTERNAL, "staging too small");
   // host-side checks of what the kernels assume
-  // a round with at most one cube per CU gives each cube a whole workgroup
-  // (team of four waves); larger rounds give each cube one wave
-  const uint32_t tw = nc <= uint32_t(info.cus) ? 4 : 1;
+  // a round with at most one cube per CU, or whose queries mostly send one
+  // cube (so that a workgroup of one-wave teams would hold one busy wave),
+  // gives each cube a whole workgroup (team of four waves); other rounds
+  // give each cube one wave and put up to four cubes of a query in a
+  // workgroup, sharing its staged CNF
+  uint32_t groups_of_four = 0;
+  for (uint32_t i = 0; i < nc;) {
+    uint32_t j = i + 1;
+    while (j < nc && j - i < kUpWaves && rh.cubes[j].qid == rh.cubes[i].qid) j++;
+    groups_of_four++;
+    i = j;
+  }
+  const uint32_t tw = (nc <= uint32_t(info.cus) || 2 * groups_of_four > nc) ? 4 : 1;
   const size_t team_bytes = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 + 2 * 64 * size_t(tw) * 4;
   const size_t up_lds = (kUpWaves / tw) * team_bytes + cnf.stage_bytes;
   const size_t leaf_lds = 0;   // the leaf kernel reads its records from memory
   if (up_lds > info.up_lds_max) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
 
+  uint32_t occ_in_memory = nc ? 1u : 0u;
   for (const DevCubeDesc& c : rh.cubes) {
-    if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + c.n_lits > rh.cube_lits.size() ||
+    const bool fix = c.n_lits & kCubeFixpoint;
+    const uint32_t n = c.n_lits & ~kCubeFixpoint;
+    if (!fix) occ_in_memory = 0;
+    if (fix && c.qid < cnf.q.size() && n != 2 * ((cnf.q[c.qid].n_vars >> 5) + 1))
+      fail(SCUBA_E_INTERNAL, "cube fixpoint of the wrong size");
+    if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + n > rh.cube_lits.size() ||
         c.res_base + c.nres_cap > rh.res_records || c.nres_cap > rh.tile_max ||
         (cnf.q[c.qid].n_vars >> 5) + 1 > rh.nw_max ||
         (cnf.skip_root_unsat && cnf.src->q[c.qid].root_unsat))
@@ -1529,7 +1557,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                             reinterpret_cast<const int32_t*>(w + rl.lits),
                             reinterpret_cast<const uint2*>(w + rl.groups), n_groups,
                             reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
-                            reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
+                            reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max, occ_in_memory);
       HIP_OK(hipGetLastError());
     }
     if (gl) {
@@ -1575,7 +1603,8 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                                  cl.q, cl.coff, cl.lits, cl.occ_off, cl.occ, cl.qkey, cl.end,
                                  rl.head, rl.cubes, rl.groups, rl.lits, rl.items, rl.outs, rl.res, rl.end,
                                  up_bytes, nc, rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), n_groups,
-                                 mode, gu, gl, rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw};
+                                 mode, gu, gl, rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw,
+                                 occ_in_memory};
     auto it = graphs->execs.find(key);
     if (it == graphs->execs.end()) {
       hipGraph_t graph;

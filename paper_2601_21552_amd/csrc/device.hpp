@@ -21,11 +21,16 @@ struct DevQueryDesc {
   uint32_t pad;
 };
 
-// One cube to evaluate.
+// One cube to evaluate.  Either its literals (propagated from the empty
+// assignment) or, with kCubeFixpoint set in n_lits, a fixpoint the host has
+// already propagated: 2*nw words at lit_off, the bitmaps T then F (variable
+// true / false) of nw = n_vars/32 + 1 words each, which the device checks by
+// visiting every clause once (and propagates further should any be unit).
+constexpr uint32_t kCubeFixpoint = 1u << 31;
 struct DevCubeDesc {
   uint32_t qid;
   uint32_t lit_off;     // into the round's cube literal array
-  uint32_t n_lits;
+  uint32_t n_lits;      // literals, or kCubeFixpoint | 2*nw words
   uint32_t seq;         // position of the cube in its query's cube order
   int32_t f_expect;     // host propagation's active count (-1: unknown)
   uint32_t nres_cap;    // residual records reserved for this cube
