@@ -50,6 +50,9 @@ OPS_PER_CLAUSE_BLOCK = 128
 # taken on
 MEASURED_TRAFFIC = {}
 
+# leaf-evaluation variants of the leaf profile (solve options)
+LEAF_VARIANTS = {"scalar": {}, "vector": {"leaf": "vector"}, "lds": {"leaf": "lds"}}
+
 # learned ordering: candidates scored per decision node, and the levels
 # below a scored node that reuse its ranking
 LEARNED_CANDIDATES = 16
@@ -441,6 +444,69 @@ def secondary_1d(ctx, stream, args, mlp_q):
     return out
 
 
+def leaf_profile(args):
+    """Exhaustive leaf evaluation, the leaf kernel's own roof: COUNT mode
+    over every leaf of 64 seeded uniform random 3-SAT formulas (n = 64,
+    m = 273, the ratio 4.26 of the 3-SAT sets), split on the host to at most
+    28 active variables (about 700 leaves, 10 M blocks of 4096 assignments
+    per call).  Prints one JSON line: the leaf kernel's word operations
+    (64 x (|c| + 1) per evaluated clause-block, two int32 ops each) per
+    second against the int32 VALU peak, per leaf-evaluation variant."""
+    import numpy as np
+    import torch
+    from oracle import cnf_ref
+    from paper_2601_21552_amd import api
+    import workloads as w
+    ctx = api.Context(0)
+    rng = np.random.Generator(np.random.PCG64(401))
+    cnfs = [w.random_ksat(64, 273, 3, rng) for _ in range(64)]
+    raw = ctx.cnf_from_arrays(*w.concat(cnfs))
+    cubes = ctx.split(raw, k=args.leaf_k)
+    out = {"metric": "leaf kernel int32 lane-ops/s (exhaustive COUNT leaves)", "unit": "TOP/s",
+           "peak": PEAK_INT32_TOPS, "workload": f"64 random 3-SAT n=64 m=273 seed 401, k={args.leaf_k}",
+           "variants": {}}
+    # the oracle's exact model counts for a few formulas: the leaves must add up
+    check = {qi: cnf_ref.count(cnfs[qi]) for qi in range(4)}
+    for name, extra in LEAF_VARIANTS.items():
+        if args.leaf_variant and name != args.leaf_variant:
+            continue
+        opts = dict(mode=1, **extra)
+        for _ in range(args.warmup):
+            res = ctx.solve(raw, cubes, **opts)
+        for qi, want in check.items():
+            r = res.result(qi)
+            cv = cubes.view(qi)
+            got = sum(res.leaf(qi, c)["count"] << res.leaf(qi, c)["m"]
+                      for c in range(len(cv["kind"])) if not res.leaf(qi, c)["refuted"])
+            assert got == want, (name, qi, got, want)
+        torch.cuda.synchronize()
+        leaf_ms = launches = 0.0
+        word_ops = clause_blocks = blocks = 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = ctx.solve(raw, cubes, **opts)
+            tm = res.timing()
+            leaf_ms += tm["leaf"]
+            launches += tm["leaf_launches"]
+            for qi in range(len(cnfs)):
+                r = res.result(qi)
+                word_ops += r["word_ops"]
+                clause_blocks += r["clause_blocks"]
+                blocks += r["blocks_evaluated"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        avg = leaf_ms / max(launches, 1)
+        ach = 2 * word_ops / launches / (avg * 1e-3) / 1e12
+        out["variants"][name] = {
+            "avg_launch_ms": round(avg, 4), "launches": launches, "wall_ms_per_call": round(1000 * wall / args.steps, 3),
+            "word_ops_per_launch": word_ops / launches, "clause_blocks_per_launch": clause_blocks / launches,
+            "blocks_per_launch": blocks / launches, "achieved_tops": round(ach, 4),
+            "frac": round(ach / PEAK_INT32_TOPS, 5),
+            "clause_block_tops": round(OPS_PER_CLAUSE_BLOCK * clause_blocks / launches / (avg * 1e-3) / 1e12, 4)}
+        log(f"leaf variant {name}: {out['variants'][name]}")
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,6 +521,10 @@ def main():
                     help="time only the --form ordering (profiling runs)")
     ap.add_argument("--no-gain", action="store_true", help="skip the 3-SAT / partition / other legs")
     ap.add_argument("--no-micro", action="store_true", help="skip the microbenchmark peaks")
+    ap.add_argument("--leaf-profile", action="store_true",
+                    help="only the exhaustive leaf-evaluation workload (the leaf kernel's roof)")
+    ap.add_argument("--leaf-k", type=int, default=28)
+    ap.add_argument("--leaf-variant", default="", help="one variant of the leaf profile")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device 3 times (a plain copy kernel of known "
                          "size, to scale hardware byte counters under a profiler)")
@@ -464,6 +534,10 @@ def main():
               "(queries are independent: a multi-GPU run would shard the batch "
               "with no collective)", file=sys.stderr)
         sys.exit(2)
+
+    if args.leaf_profile:
+        leaf_profile(args)
+        return
 
     import torch
     from paper_2601_21552_amd import api

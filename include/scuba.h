@@ -296,6 +296,15 @@ void scuba_trace_free(scuba_trace* t);
  * (64 x split_batch nodes plus one path); a larger workspace holds a
  * larger stack and needs fewer single-node steps.                         */
 #define SCUBA_SOLVE_DEVICE_SPLIT 2u
+/* Leaf evaluation with the block-level skip test on the vector unit: 64
+ * clauses per test and ballot, each clause that no block-level literal
+ * satisfies broadcast to the wave; without this flag the test runs per
+ * clause on the scalar unit.  Same counts, witnesses and verdicts.        */
+#define SCUBA_SOLVE_LEAF_VECTOR 4u
+/* With SCUBA_SOLVE_LEAF_VECTOR: each work item's clause records are staged
+ * in LDS by the whole workgroup first (when they fit), instead of every
+ * wave reading them through the caches (not with the device split).     */
+#define SCUBA_SOLVE_LEAF_LDS 8u
 typedef struct {
   uint32_t mode;             /* SCUBA_MODE_*                                  */
   uint32_t k;                /* split bound for scuba_decide (<= 38)          */

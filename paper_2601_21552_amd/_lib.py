@@ -28,6 +28,8 @@ def BB_WRAP(m: int) -> int:
 SCORER_STATIC, SCORER_LEARNED, SCORER_WORD = 0, 1, 2
 SOLVE_GRAPH = 1
 SOLVE_DEVICE_SPLIT = 2
+SOLVE_LEAF_VECTOR = 4
+SOLVE_LEAF_LDS = 8
 NOALLOC_SCRATCH_BYTES = 128 << 20   # device scratch of scuba_decide_noalloc
 CUBE_LEAF, CUBE_REFUTED, CUBE_PRUNED = 0, 1, 2
 BB_NO_REWRITE = 1

@@ -152,16 +152,19 @@ def _scorer(scorer) -> int:
 
 def _solve_opts(mode=L.MODE_DECIDE, k=0, max_cubes=0, leaves_per_round=0, chunk_log2=0,
                 grid=0, max_rounds=0, learned=None, scorer="static", graph=False, max_residual=0,
-                device_split=False, split_batch=0):
+                device_split=False, split_batch=0, leaf="scalar"):
     """learned: an L.LearnedScorer (Mlp.scorer()) selects the learned
     ordering; otherwise scorer is "static" or "word".  device_split: split
-    on the device (scuba_decide only), split_batch nodes per step."""
+    on the device (scuba_decide only), split_batch nodes per step.  leaf:
+    the leaf-evaluation variant, "scalar", "vector" or "lds"."""
     o = L.SolveOpts()
     o.mode, o.k, o.max_cubes = mode, k, max_cubes
     o.leaves_per_round, o.chunk_log2, o.grid = leaves_per_round, chunk_log2, grid
     o.max_rounds = max_rounds
     o.scorer = _scorer(scorer)
     o.flags = (L.SOLVE_GRAPH if graph else 0) | (L.SOLVE_DEVICE_SPLIT if device_split else 0)
+    o.flags |= {"scalar": 0, "vector": L.SOLVE_LEAF_VECTOR,
+                "lds": L.SOLVE_LEAF_VECTOR | L.SOLVE_LEAF_LDS}[leaf]
     o.max_residual = max_residual
     o.split_batch = split_batch
     if learned is not None:

@@ -170,11 +170,15 @@ Opts resolve(const scuba_solve_opts* o) {
   // the device's witness key is (cube sequence << 38) | assignment index:
   // a query's cube sequence numbers must stay below 2^26
   if (r.max_cubes > kMaxCubesPerQuery) fail(SCUBA_E_INVALID, "max_cubes above 2^26 per query");
-  if (r.flags & ~(SCUBA_SOLVE_GRAPH | SCUBA_SOLVE_DEVICE_SPLIT)) fail(SCUBA_E_INVALID, "unknown solve flags");
+  if (r.flags & ~(SCUBA_SOLVE_GRAPH | SCUBA_SOLVE_DEVICE_SPLIT | SCUBA_SOLVE_LEAF_VECTOR | SCUBA_SOLVE_LEAF_LDS))
+    fail(SCUBA_E_INVALID, "unknown solve flags");
+  if ((r.flags & SCUBA_SOLVE_LEAF_LDS) && !(r.flags & SCUBA_SOLVE_LEAF_VECTOR))
+    fail(SCUBA_E_INVALID, "SCUBA_SOLVE_LEAF_LDS needs SCUBA_SOLVE_LEAF_VECTOR");
   if (r.flags & SCUBA_SOLVE_DEVICE_SPLIT) {
     if (r.flags & SCUBA_SOLVE_GRAPH) fail(SCUBA_E_INVALID, "the device split captures no graphs");
     if (r.scorer == SCUBA_SCORER_LEARNED) fail(SCUBA_E_INVALID, "the device split takes the static or word order");
     if (r.split_batch > (1u << 20)) fail(SCUBA_E_INVALID, "split_batch above 2^20");
+    if (r.flags & SCUBA_SOLVE_LEAF_LDS) fail(SCUBA_E_INVALID, "the device split reads leaf records from memory");
   }
   if (r.mode > SCUBA_MODE_COUNT) fail(SCUBA_E_INVALID, "unknown mode");
   if (r.k > kMaxLeafVars) fail(SCUBA_E_INVALID, "k above the leaf limit of 38 variables");
@@ -194,6 +198,11 @@ Opts resolve(const scuba_solve_opts* o) {
 // Device image of the CNF batch.  A query whose CNF fits the LDS left over
 // by the propagation kernel's bitmaps (16-bit literals and offsets) is
 // marked for staging; lds_limit = 0 disables staging.
+uint32_t leaf_variant(const Opts& o) {
+  if (!(o.flags & SCUBA_SOLVE_LEAF_VECTOR)) return kLeafScalar;
+  return (o.flags & SCUBA_SOLVE_LEAF_LDS) ? kLeafVectorLds : kLeafVector;
+}
+
 // Device descriptors of a CNF batch.  With skip_root_unsat, the queries
 // decided at the root get empty descriptors and are not uploaded (DECIDE
 // sends them no cube).
@@ -827,6 +836,7 @@ SolveRound solve_round(const scuba_cnf* cnf, const scuba_cubes* cubes, const Opt
     }
   }
   make_items(sr.rh, o.mode, o.chunk_log2, grid);
+  sr.rh.leaf_variant = leaf_variant(o);
   return sr;
 }
 
@@ -859,6 +869,7 @@ SplitRun split_run(const scuba_cnf* cnf, const Opts& o, size_t* n_order) {
   r.chunk_log2 = o.chunk_log2;
   r.grid = o.grid;
   r.max_cubes = o.max_cubes;
+  r.leaf_variant = leaf_variant(o);
   uint32_t nw = 1;
   uint64_t nc = 1;
   *n_order = 0;
@@ -1241,6 +1252,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
         }
       }
       make_items(rh, SCUBA_MODE_DECIDE, o.chunk_log2, grid);
+      rh.leaf_variant = leaf_variant(o);
       split_ms += ms_since(ts);
       if (rh.cubes.empty()) break;
       size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);

@@ -816,15 +816,24 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
 
       uint64_t count = 0, blocks = 0, evals = 0, word_ops = 0, first = ~0ull;
       uint32_t steps = 0;
-      for (uint32_t blk = it.it_lo + wave; blk < it.it_hi; blk += kWaves) {
-        if (mode == SCUBA_MODE_DECIDE && (steps++ & 7) == 0) {
+      bool stop = false;
+      // two blocks per pass over the records (blk and blk + kWaves, the
+      // wave's next two): one set of record loads, two independent
+      // dependency chains.  Each block keeps its own clause sequence and
+      // dead-block test (after every group of four records), exactly as if
+      // it were evaluated alone.
+      for (uint32_t blk = it.it_lo + wave; blk < it.it_hi && !stop; blk += 2 * kWaves) {
+        if (mode == SCUBA_MODE_DECIDE && (steps++ & 3) == 0) {
           const uint64_t k = uniform_u64(
               __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
           if (k <= key_base + (uint64_t(blk) << 12)) break;
         }
-        const uint32_t H = blk & kHighMask;
-        uint64_t acc = valid;
-        uint32_t done = 0, lits = 0;
+        const uint32_t blk1 = blk + kWaves;
+        const bool two = blk1 < it.it_hi;
+        const uint32_t H0 = blk & kHighMask, H1 = blk1 & kHighMask;
+        uint64_t acc0 = valid, acc1 = two ? valid : 0ull;
+        bool live0 = true, live1 = two;
+        uint32_t done0 = 0, lits0 = 0, done1 = 0, lits1 = 0;
         // four clauses per step: their records are loaded together (the
         // record region is padded so that reading past nres stays inside
         // it), clauses past nres are masked out
@@ -835,26 +844,43 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
           // the four skip masks are needed first: keep their loads together
           // (else each test waits for its own load)
           asm volatile("" :: "s"(r1.x), "s"(r1.y), "s"(r3.x), "s"(r3.y), "s"(r5.x), "s"(r5.y), "s"(r7.x), "s"(r7.y));
-          if (!(~(H ^ r1.x) & r1.y)) { acc = clause_and(acc, r0); done++; lits += r1.z; }
-          if (left > 1 && !(~(H ^ r3.x) & r3.y)) { acc = clause_and(acc, r2); done++; lits += r3.z; }
-          if (left > 2 && !(~(H ^ r5.x) & r5.y)) { acc = clause_and(acc, r4); done++; lits += r5.z; }
-          if (left > 3 && !(~(H ^ r7.x) & r7.y)) { acc = clause_and(acc, r6); done++; lits += r7.z; }
-          if (!__any(acc != 0)) break;
+          if (live0) {
+            if (!(~(H0 ^ r1.x) & r1.y)) { acc0 = clause_and(acc0, r0); done0++; lits0 += r1.z; }
+            if (left > 1 && !(~(H0 ^ r3.x) & r3.y)) { acc0 = clause_and(acc0, r2); done0++; lits0 += r3.z; }
+            if (left > 2 && !(~(H0 ^ r5.x) & r5.y)) { acc0 = clause_and(acc0, r4); done0++; lits0 += r5.z; }
+            if (left > 3 && !(~(H0 ^ r7.x) & r7.y)) { acc0 = clause_and(acc0, r6); done0++; lits0 += r7.z; }
+          }
+          if (live1) {
+            if (!(~(H1 ^ r1.x) & r1.y)) { acc1 = clause_and(acc1, r0); done1++; lits1 += r1.z; }
+            if (left > 1 && !(~(H1 ^ r3.x) & r3.y)) { acc1 = clause_and(acc1, r2); done1++; lits1 += r3.z; }
+            if (left > 2 && !(~(H1 ^ r5.x) & r5.y)) { acc1 = clause_and(acc1, r4); done1++; lits1 += r5.z; }
+            if (left > 3 && !(~(H1 ^ r7.x) & r7.y)) { acc1 = clause_and(acc1, r6); done1++; lits1 += r7.z; }
+          }
+          live0 = live0 && __any(acc0 != 0);
+          live1 = live1 && __any(acc1 != 0);
+          if (!live0 && !live1) break;
         }
-        blocks++;
-        evals += done;
-        word_ops += uint64_t(lits + done) * 64;   // (|c| + 1) per clause and 64-bit word
-        if (mode == SCUBA_MODE_COUNT) count += __popcll(acc);
-        const uint64_t hit = __ballot(acc != 0);
-        if (hit) {
+        blocks += two ? 2 : 1;
+        evals += done0 + done1;
+        word_ops += uint64_t(lits0 + done0 + lits1 + done1) * 64;   // (|c| + 1) per clause and 64-bit word
+        if (mode == SCUBA_MODE_COUNT) count += __popcll(acc0) + __popcll(acc1);
+        // satisfying assignments, the earlier block first
+        for (uint32_t h = 0; h < (two ? 2u : 1u); h++) {
+          const uint64_t acc = h ? acc1 : acc0;
+          const uint64_t hit = __ballot(acc != 0);
+          if (!hit) continue;
           const uint32_t fl = __builtin_ctzll(hit);
           const uint64_t acc_fl = __shfl(acc, int(fl), 64);
-          const uint64_t a = (uint64_t(blk) << 12) | (uint64_t(fl) << 6) | uint64_t(__builtin_ctzll(acc_fl));
+          const uint64_t a = (uint64_t(h ? blk1 : blk) << 12) | (uint64_t(fl) << 6) |
+                             uint64_t(__builtin_ctzll(acc_fl));
           if (lane == 0) {
             if (a < first) first = a;
             if (mode == SCUBA_MODE_DECIDE) atomicMin(&qkey[cd.qid], (unsigned long long)(key_base | a));
           }
-          if (mode == SCUBA_MODE_DECIDE) break;
+          if (mode == SCUBA_MODE_DECIDE) {
+            stop = true;
+            break;
+          }
         }
       }
       // wave totals
@@ -870,6 +896,154 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
   }
 }
 
+
+// The same evaluation with the skip test on the vector unit.  Per block,
+// a wave takes the leaf's clauses 64 at a time, lane i holding the record
+// of clause g + i: one vector test per lane finds the clauses that no
+// block-level literal satisfies, a ballot collects them, and each of those
+// is broadcast to the wave (v_readlane of its pattern word and lane mask)
+// and ANDed in as above.  A clause satisfied at block level costs no scalar
+// instruction.  The word-operation counters are per-lane sums (corrected
+// for the clauses a dead block did not reach), so they count exactly the
+// clauses evaluated.  kLds: a work item's records are first staged in LDS
+// by the whole workgroup (coalesced 16-byte loads) when they fit
+// lds_records; else every wave reads them from memory.
+template <bool kLds>
+__global__ __launch_bounds__(kBlock) void leaf_kernel_v(const DevItem* __restrict__ items, uint32_t n_items,
+                                                       const DevCubeDesc* __restrict__ cubes,
+                                                       DevCubeOut* __restrict__ out,
+                                                       const uint4* __restrict__ res,
+                                                       unsigned long long* __restrict__ qkey, uint32_t* head,
+                                                       uint32_t mode, const uint32_t* __restrict__ n_items_dev,
+                                                       uint32_t lds_records) {
+  extern __shared__ uint4 tile[];
+  __shared__ uint32_t s_base, s_skip;
+  if (n_items_dev) n_items = *n_items_dev;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wave = uniform_u32(tid >> 6);
+  constexpr uint32_t kWaves = kBlock / 64;
+  constexpr uint32_t kClaim = 8;
+  for (;;) {
+    if (wave == 0) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(head + 1, kClaim);
+      base = uniform_u32(__shfl(base, 0, 64));
+      bool skip = true;
+      const uint32_t i = base + lane;
+      if (lane < kClaim && i < n_items) {
+        const DevItem it0 = items[i];
+        skip = out[it0.cube].status != 0;
+        if (!skip && mode == SCUBA_MODE_DECIDE) {
+          const DevCubeDesc c0 = cubes[it0.cube];
+          const uint64_t k = __hip_atomic_load(&qkey[c0.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          skip = k <= (uint64_t(c0.seq) << 38) + (uint64_t(it0.it_lo) << 12);
+        }
+      }
+      const uint64_t mask = __ballot(skip);
+      if (lane == 0) {
+        s_base = base;
+        s_skip = uint32_t(mask);
+      }
+    }
+    __syncthreads();
+    const uint32_t base = uniform_u32(s_base), skip_mask = uniform_u32(s_skip);
+    __syncthreads();
+    if (base >= n_items) break;
+    for (uint32_t t = 0; t < kClaim; t++) {
+      const uint32_t item = base + t;
+      if (item >= n_items) break;
+      if ((skip_mask >> t) & 1) continue;
+      const DevItem it = items[item];
+      const DevCubeDesc cd = cubes[it.cube];
+      const uint32_t f = uniform_u32(uint32_t(out[it.cube].f));
+      const uint32_t nres = uniform_u32(uint32_t(out[it.cube].nres));
+      const uint64_t key_base = uint64_t(cd.seq) << 38;
+      const uint4* __restrict__ src = res + 2 * uniform_u64(cd.res_base);
+      const bool staged = kLds && nres <= lds_records;
+      if (kLds) {
+        __syncthreads();   // the previous item's tile is no longer read
+        if (staged)
+          for (uint32_t x = tid; x < 2 * nres; x += kBlock) tile[x] = src[x];
+        __syncthreads();
+      }
+      uint64_t valid;
+      if (f >= 12) valid = ~0ull;
+      else if (f >= 6) valid = lane < (1u << (f - 6)) ? ~0ull : 0ull;
+      else valid = lane == 0 ? ((2ull << ((1u << f) - 1)) - 1) : 0ull;
+
+      uint64_t count = 0, first = ~0ull;
+      uint32_t blocks = 0, evals = 0, word_lanes = 0, steps = 0;
+      for (uint32_t blk = it.it_lo + wave; blk < it.it_hi; blk += kWaves) {
+        if (mode == SCUBA_MODE_DECIDE && (steps++ & 7) == 0) {
+          const uint64_t k = uniform_u64(
+              __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          if (k <= key_base + (uint64_t(blk) << 12)) break;
+        }
+        const uint32_t H = blk & kHighMask;
+        uint64_t acc = valid;
+        for (uint32_t g = 0; g < nres; g += 64) {
+          const uint32_t c = g + lane;
+          uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = make_uint4(0u, 0u, 0u, 0u);
+          if (c < nres) {
+            if (staged) {
+              r0 = tile[2 * c];
+              r1 = tile[2 * c + 1];
+            } else {
+              r0 = src[2 * c];
+              r1 = src[2 * c + 1];
+            }
+          }
+          const bool ap = c < nres && !(~(H ^ r1.x) & r1.y);
+          uint64_t m = __ballot(ap);
+          const uint32_t n_ap = uint32_t(__popcll(m));
+          evals += n_ap;
+          if (ap) word_lanes += r1.z + 1;
+          uint32_t n_done = 0;
+          while (m) {
+            const uint32_t j = uint32_t(__builtin_ctzll(m));
+            m &= m - 1;
+            const uint4 r = make_uint4(uint32_t(__builtin_amdgcn_readlane(int(r0.x), int(j))),
+                                       uint32_t(__builtin_amdgcn_readlane(int(r0.y), int(j))),
+                                       uint32_t(__builtin_amdgcn_readlane(int(r0.z), int(j))),
+                                       uint32_t(__builtin_amdgcn_readlane(int(r0.w), int(j))));
+            acc = clause_and(acc, r);
+            if ((++n_done & 3) == 0 && m && !__any(acc != 0)) break;
+          }
+          if (m) {
+            // the block died before the clauses still in m: not evaluated
+            evals -= uint32_t(__popcll(m));
+            if (ap && ((m >> lane) & 1)) word_lanes -= r1.z + 1;
+          }
+          if (!__any(acc != 0)) break;
+        }
+        blocks++;
+        if (mode == SCUBA_MODE_COUNT) count += __popcll(acc);
+        const uint64_t hit = __ballot(acc != 0);
+        if (hit) {
+          const uint32_t fl = __builtin_ctzll(hit);
+          const uint64_t acc_fl = __shfl(acc, int(fl), 64);
+          const uint64_t a = (uint64_t(blk) << 12) | (uint64_t(fl) << 6) | uint64_t(__builtin_ctzll(acc_fl));
+          if (lane == 0) {
+            if (a < first) first = a;
+            if (mode == SCUBA_MODE_DECIDE) atomicMin(&qkey[cd.qid], (unsigned long long)(key_base | a));
+          }
+          if (mode == SCUBA_MODE_DECIDE) break;
+        }
+      }
+      uint64_t wl = word_lanes;
+      for (uint32_t d = 32; d >= 1; d >>= 1) {
+        count += __shfl_xor(count, int(d), 64);
+        wl += __shfl_xor(wl, int(d), 64);
+      }
+      if (lane == 0) {
+        if (mode == SCUBA_MODE_COUNT && count) atomicAdd((unsigned long long*)&out[it.cube].count, (unsigned long long)count);
+        if (first != ~0ull) atomicMin((unsigned long long*)&out[it.cube].first, (unsigned long long)first);
+        atomicAdd((unsigned long long*)&out[it.cube].blocks, (unsigned long long)blocks);
+        atomicAdd((unsigned long long*)&out[it.cube].clause_blocks, (unsigned long long)evals);
+        atomicAdd((unsigned long long*)&out[it.cube].word_ops, (unsigned long long)(wl * 64));
+      }
+    }
+  }
+}
 
 // ---------------------------------------------------------------- device split
 // Counters of the split loop (u32 words of one 256-byte block).
@@ -1326,8 +1500,8 @@ void dev_init(DeviceInfo* info, int device) {
       info->up_lds_max = want;
     else
       (void)hipGetLastError();
-    // and the leaf kernel (no dynamic LDS at present; kept for larger tiles)
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel),
+    // and the leaf kernel whose records are staged in LDS
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&leaf_kernel_v<true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess)
       info->leaf_lds_max = want;
     else
@@ -1481,7 +1655,15 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
   const uint32_t tw = (nc <= uint32_t(info.cus) || 2 * groups_of_four > nc) ? 4 : 1;
   const size_t team_bytes = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 + 2 * 64 * size_t(tw) * 4;
   const size_t up_lds = (kUpWaves / tw) * team_bytes + cnf.stage_bytes;
-  const size_t leaf_lds = 0;   // the leaf kernel reads its records from memory
+  // the LDS variant stages a work item's records when the round's largest
+  // residual fits the kernel's LDS (else all items read from memory)
+  uint32_t lds_records = 0;
+  if (rh.leaf_variant == kLeafVectorLds) {
+    const size_t cap = (info.leaf_lds_max - 64) / 32;
+    lds_records = uint32_t(std::min<size_t>(rh.tile_max, cap));
+  }
+  const size_t leaf_lds = size_t(lds_records) * 32;
+  if (rh.leaf_variant > kLeafVectorLds) fail(SCUBA_E_INTERNAL, "unknown leaf variant");
   if (up_lds > info.up_lds_max) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
 
   uint32_t occ_in_memory = nc ? 1u : 0u;
@@ -1561,13 +1743,22 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
       HIP_OK(hipGetLastError());
     }
     if (gl) {
-      launch(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, q, ev ? ev[4] : nullptr,
-                            ev ? ev[5] : nullptr,
-                            reinterpret_cast<const DevItem*>(w + rl.items), uint32_t(ni),
-                            reinterpret_cast<const DevCubeDesc*>(w + rl.cubes),
-                            reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<const uint4*>(w + rl.res),
-                            reinterpret_cast<unsigned long long*>(w + cl.qkey),
-                            reinterpret_cast<uint32_t*>(w + rl.head), mode, (const uint32_t*)nullptr);
+      const auto* items = reinterpret_cast<const DevItem*>(w + rl.items);
+      const auto* cubes = reinterpret_cast<const DevCubeDesc*>(w + rl.cubes);
+      auto* outs_d = reinterpret_cast<DevCubeOut*>(w + rl.outs);
+      const auto* res = reinterpret_cast<const uint4*>(w + rl.res);
+      auto* qkey = reinterpret_cast<unsigned long long*>(w + cl.qkey);
+      auto* head = reinterpret_cast<uint32_t*>(w + rl.head);
+      hipEvent_t e0 = ev ? ev[4] : nullptr, e1 = ev ? ev[5] : nullptr;
+      if (rh.leaf_variant == kLeafScalar)
+        launch(leaf_kernel, dim3(gl), dim3(kBlock), leaf_lds, q, e0, e1, items, uint32_t(ni), cubes, outs_d, res,
+               qkey, head, mode, (const uint32_t*)nullptr);
+      else if (rh.leaf_variant == kLeafVector)
+        launch(leaf_kernel_v<false>, dim3(gl), dim3(kBlock), leaf_lds, q, e0, e1, items, uint32_t(ni), cubes,
+               outs_d, res, qkey, head, mode, (const uint32_t*)nullptr, 0u);
+      else
+        launch(leaf_kernel_v<true>, dim3(gl), dim3(kBlock), leaf_lds, q, e0, e1, items, uint32_t(ni), cubes,
+               outs_d, res, qkey, head, mode, (const uint32_t*)nullptr, lds_records);
       HIP_OK(hipGetLastError());
     }
     if (ev) HIP_OK(hipEventRecord(ev[6], q));
@@ -1604,7 +1795,7 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                                  rl.head, rl.cubes, rl.groups, rl.lits, rl.items, rl.outs, rl.res, rl.end,
                                  up_bytes, nc, rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), n_groups,
                                  mode, gu, gl, rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw,
-                                 occ_in_memory};
+                                 occ_in_memory, rh.leaf_variant, lds_records};
     auto it = graphs->execs.find(key);
     if (it == graphs->execs.end()) {
       hipGraph_t graph;
@@ -1752,9 +1943,15 @@ void dev_split(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
            reinterpret_cast<DevItem*>(w + sl.items), reinterpret_cast<uint4*>(w + sl.res), uint32_t(seq_base),
            r.nw_max, r.chunk_log2);
     HIP_OK(hipGetLastError());
-    launch(leaf_kernel, dim3(g), dim3(kBlock), 0, st, ev[2], ev[3], reinterpret_cast<const DevItem*>(w + sl.items),
-           0u, (const DevCubeDesc*)descs, louts, reinterpret_cast<const uint4*>(w + sl.res), qkey,
-           ctr + kSpLeafHead, r.mode, (const uint32_t*)(ctr + kSpItems));
+    if (r.leaf_variant == kLeafScalar)
+      launch(leaf_kernel, dim3(g), dim3(kBlock), 0, st, ev[2], ev[3], reinterpret_cast<const DevItem*>(w + sl.items),
+             0u, (const DevCubeDesc*)descs, louts, reinterpret_cast<const uint4*>(w + sl.res), qkey,
+             ctr + kSpLeafHead, r.mode, (const uint32_t*)(ctr + kSpItems));
+    else
+      launch(leaf_kernel_v<false>, dim3(g), dim3(kBlock), 0, st, ev[2], ev[3],
+             reinterpret_cast<const DevItem*>(w + sl.items), 0u, (const DevCubeDesc*)descs, louts,
+             reinterpret_cast<const uint4*>(w + sl.res), qkey, ctr + kSpLeafHead, r.mode,
+             (const uint32_t*)(ctr + kSpItems), 0u);
     HIP_OK(hipGetLastError());
     launch(split_capture_kernel, dim3(std::min<uint64_t>(g, (b + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
            nullptr, nullptr, (const DevCubeDesc*)descs, (const DevCubeOut*)louts,

@@ -92,7 +92,13 @@ struct RoundHost {
   uint64_t res_records = 0;   // residual records to reserve
   uint32_t tile_max = 0;      // largest residual of a cube
   uint32_t nw_max = 0;        // largest bitmap (32-bit words) of a query
+  uint32_t leaf_variant = 0;  // kLeafScalar / kLeafVector / kLeafVectorLds
 };
+// Leaf-evaluation variants: the per-clause block-level skip test on the
+// scalar unit (records read with scalar loads), on the vector unit (64
+// clauses per test, records read with vector loads), or on the vector unit
+// with each work item's records staged in LDS first.
+constexpr uint32_t kLeafScalar = 0, kLeafVector = 1, kLeafVectorLds = 2;
 
 // Device image of a CNF batch: descriptors and array sizes.  The arrays
 // (query-relative clause offsets, literals, per-literal occurrence offsets
@@ -183,6 +189,7 @@ struct SplitRun {
   uint32_t nw_max = 1;         // bitmap words of the largest query
   uint32_t nres_max = 1;       // residual records a leaf may need
   size_t stack_cap = 0;        // nodes the stack holds
+  uint32_t leaf_variant = 0;   // kLeaf*
 };
 struct SplitOutput {
   std::vector<uint64_t> qkeys;              // per query: smallest (leaf sequence << 38 | index), ~0 none

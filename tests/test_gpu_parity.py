@@ -50,7 +50,13 @@ def _check_leaves(cnfs, cubes_per_query, out, complete=True, kinds=None):
             assert total == cnf_ref.count(f), f.name
 
 
-def test_count_mode_split_cubes(ctx):
+LEAF_VARIANTS = ["scalar", "vector", "lds"]
+
+
+@pytest.mark.parametrize("leaf", LEAF_VARIANTS)
+def test_count_mode_split_cubes(ctx, leaf):
+    """Every leaf of complete splits (k = 8, 14, 20: one block to 256
+    blocks of 4096 assignments) under each leaf-evaluation variant."""
     rng = np.random.Generator(np.random.PCG64(101))
     cnfs = []
     for n, ratio in ((24, 3.0), (30, 4.26), (40, 4.26), (48, 3.5), (36, 2.0), (60, 4.26)):
@@ -58,7 +64,7 @@ def test_count_mode_split_cubes(ctx):
     raw = _raw(ctx, cnfs)
     for k in (8, 14, 20):
         cubes = ctx.split(raw, k=k)
-        out = ctx.solve(raw, cubes, mode=1)
+        out = ctx.solve(raw, cubes, mode=1, leaf=leaf)
         per_q = [cubes.view(i)["cubes"] for i in range(len(cnfs))]
         kinds = [cubes.view(i)["kind"] for i in range(len(cnfs))]
         for i in range(len(cnfs)):
@@ -153,7 +159,9 @@ def test_decide_single_access(ctx):
     dict(k=30),                                             # the library's defaults
     dict(k=30, leaves_per_round=1, chunk_log2=12),          # the launch point bench.py times
     dict(k=30, leaves_per_round=1, chunk_log2=12, scorer="word"),
-], ids=["defaults", "bench_point", "word"])
+    dict(k=30, leaves_per_round=1, chunk_log2=12, leaf="vector"),
+    dict(k=30, leaves_per_round=1, chunk_log2=12, leaf="lds"),
+], ids=["defaults", "bench_point", "word", "leaf_vector", "leaf_lds"])
 def test_decide_batch_1d_full(ctx, opts):
     gens = w.batch_1d()
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
@@ -338,8 +346,9 @@ def _component_cnf(nv, rng, name):
     return w.CNF.from_clauses(nv, clauses, name=name), count, first
 
 
+@pytest.mark.parametrize("leaf", LEAF_VARIANTS)
 @pytest.mark.parametrize("f", [31, 34, 38])
-def test_count_high_slots_closed_form(ctx, f):
+def test_count_high_slots_closed_form(ctx, f, leaf):
     """Leaves of 31..38 active variables reach the block-index slots 12..37
     (block bits up to 25): COUNT over one whole-formula leaf equals the
     closed-form count and smallest satisfying index."""
@@ -347,7 +356,7 @@ def test_count_high_slots_closed_form(ctx, f):
     cnf, count, first = _component_cnf(f, rng, f"comp{f}")
     raw = _raw(ctx, [cnf])
     cubes = ctx.cubes_from_arrays(raw, [[[]]])
-    out = ctx.solve(raw, cubes, mode=1, chunk_log2=12)
+    out = ctx.solve(raw, cubes, mode=1, chunk_log2=12, leaf=leaf)
     lf = out.leaf(0, 0)
     assert (lf["refuted"], lf["f"], lf["m"]) == (False, f, 0), lf
     assert lf["count"] == count and lf["first"] == first, (lf, count, first)
@@ -386,9 +395,13 @@ def _word_ops_reference(f, cube):
     return ops
 
 
-def test_word_ops_counter_reproduced(ctx):
+@pytest.mark.parametrize("leaf", LEAF_VARIANTS)
+def test_word_ops_counter_reproduced(ctx, leaf):
     """The leaf kernel's count of algorithmic word operations equals the
-    CPU's replay of its fixed evaluation order on one-block leaves."""
+    CPU's replay of its fixed evaluation order on one-block leaves (each
+    variant tests for a dead block after every fourth clause it evaluates
+    and at the end of the clauses, which on a one-block leaf, where every
+    clause is evaluated, is the replay's rule)."""
     rng = np.random.Generator(np.random.PCG64(103))
     cnfs, cubes = [], []
     for n in (14, 18, 22, 26):
@@ -400,7 +413,7 @@ def test_word_ops_counter_reproduced(ctx):
             qc.append([int(v) if rng.integers(2) else -int(v) for v in vs])
         cubes.append(qc)
     raw = _raw(ctx, cnfs)
-    out = ctx.solve(raw, ctx.cubes_from_arrays(raw, cubes), mode=1)
+    out = ctx.solve(raw, ctx.cubes_from_arrays(raw, cubes), mode=1, leaf=leaf)
     for qi, (f, qc) in enumerate(zip(cnfs, cubes)):
         want = sum(_word_ops_reference(f, c) for c in qc)
         assert out.result(qi)["word_ops"] == want, (qi, out.result(qi)["word_ops"], want)
