@@ -378,7 +378,8 @@ scuba_status scuba_decide_noalloc(scuba_ctx* ctx, const scuba_cnf* cnf, const sc
  * best point before the next: k in {16, 20, 24, 28, 30}, chunk_log2 in
  * {4, 6, 8, 10, 12}, leaves_per_round in {1, 2, 4, 8, 16}, grid in
  * {2, 4, 8, 16} workgroups per CU, leaf tile (max_residual) in {1024,
- * 2048, 4096, 8192} clauses; a point's time is the best wall time of
+ * 2048, 4096, 8192} clauses, leaf variant (scalar skip test, vector skip
+ * test, vector with LDS-staged records); a point's time is the best wall time of
  * `reps` runs.  Every point must give the same decided verdicts (UNKNOWN is
  * compatible with SAT and UNSAT); a contradiction is SCUBA_E_INTERNAL.  The
  * choice is cached in the context per bucket (log2 of the mean clause
@@ -402,6 +403,15 @@ typedef struct {
 } scuba_tune_report;
 scuba_status scuba_autotune_workspace(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tune_opts* opts,
                                       size_t* bytes);
+/* The autotuner's cache of a context, persisted: scuba_tune_cache_save
+ * writes one JSON object per line (the device's architecture name, the
+ * bucket and the chosen options); scuba_tune_cache_load adds the lines of
+ * the device this context runs on and reports how many (lines of another
+ * architecture are skipped; a malformed line or options the library would
+ * reject are SCUBA_E_INVALID).  A context without a device keys its lines
+ * "no-device".                                                            */
+scuba_status scuba_tune_cache_save(scuba_ctx* ctx, const char* path);
+scuba_status scuba_tune_cache_load(scuba_ctx* ctx, const char* path, uint32_t* loaded);
 /* best: a complete scuba_solve_opts for scuba_decide on this batch. */
 scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tune_opts* opts, void* dev_ws,
                             size_t ws_bytes, void* hip_stream, scuba_solve_opts* best,

@@ -131,6 +131,8 @@ SIGNATURES = {
     "scuba_solve": (C.c_int32, [P, P, P, C.POINTER(SolveOpts), P, C.c_size_t, P, C.POINTER(P)]),
     "scuba_decide": (C.c_int32, [P, P, C.POINTER(SolveOpts), P, C.c_size_t, P, C.POINTER(P)]),
     "scuba_decide_noalloc": (C.c_int32, [P, P, C.POINTER(SolveOpts), P, C.POINTER(P)]),
+    "scuba_tune_cache_save": (C.c_int32, [P, C.c_char_p]),
+    "scuba_tune_cache_load": (C.c_int32, [P, C.c_char_p, C.POINTER(C.c_uint32)]),
     "scuba_result_get": (C.c_int32, [P, C.c_uint32, C.POINTER(QueryResult)]),
     "scuba_witness_get": (C.c_int32, [P, C.c_uint32, P, C.c_uint32]),
     "scuba_model_get": (C.c_int32, [P, C.c_uint32, P, C.c_uint32]),

@@ -6,6 +6,7 @@ workspace and the stream."""
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -343,6 +344,16 @@ class Context:
         self._check(self.lib.scuba_decide(self.h, cnf.h, C.byref(o), _P(ws.data_ptr()), ws.numel(),
                                           self._stream(stream), C.byref(h)))
         return Results(self, h, len(cnf))
+
+    def tune_cache_save(self, path: str) -> None:
+        """Persist this context's autotuner choices (JSON lines)."""
+        self._check(self.lib.scuba_tune_cache_save(self.h, os.fsencode(path)))
+
+    def tune_cache_load(self, path: str) -> int:
+        """Add the choices of `path` made on this device's architecture."""
+        n = C.c_uint32()
+        self._check(self.lib.scuba_tune_cache_load(self.h, os.fsencode(path), C.byref(n)))
+        return n.value
 
     def decide_noalloc(self, cnf: Cnf, stream=None, **opts) -> Results:
         """scuba_decide on the library's own device scratch (no workspace,

@@ -1,5 +1,8 @@
 // C ABI of the library: handles, the split/solve/decide drivers and results.
 #include <algorithm>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <limits>
 #include <cmath>
@@ -1380,6 +1383,9 @@ constexpr uint32_t kTuneChunk[] = {4, 6, 8, 10, 12};
 constexpr uint32_t kTuneLpr[] = {1, 2, 4, 8, 16};
 constexpr uint32_t kTuneGridPerCu[] = {2, 4, 8, 16};
 constexpr uint32_t kTuneTile[] = {1024, 2048, 4096, 8192};
+// leaf-evaluation variants: scalar skip test, vector skip test, vector
+// skip test with the records staged in LDS
+constexpr uint32_t kTuneLeaf[] = {0, SCUBA_SOLVE_LEAF_VECTOR, SCUBA_SOLVE_LEAF_VECTOR | SCUBA_SOLVE_LEAF_LDS};
 
 struct TuneSetup {
   uint32_t sample, reps, scorer, flags;
@@ -1422,8 +1428,8 @@ std::vector<uint64_t> tune_bucket(const scuba_cnf* cnf, const TuneSetup& ts) {
 }
 
 Opts tune_point(const TuneSetup& ts, uint32_t k, uint32_t chunk, uint32_t lpr, uint32_t grid,
-                uint32_t tile = kDefaultMaxResidual) {
-  Opts o{SCUBA_MODE_DECIDE, k, lpr, chunk, grid, 0, ts.scorer, ts.max_cubes, nullptr, ts.flags, tile};
+                uint32_t tile = kDefaultMaxResidual, uint32_t leaf = 0) {
+  Opts o{SCUBA_MODE_DECIDE, k, lpr, chunk, grid, 0, ts.scorer, ts.max_cubes, nullptr, ts.flags | leaf, tile, 0};
   return o;
 }
 
@@ -1488,15 +1494,15 @@ scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tu
       return bestt;
     };
     uint32_t k = kDefaultK, chunk = kDefaultChunkLog2, lpr = kDefaultLeavesPerRound, gpc = 8;
-    uint32_t tile = kDefaultMaxResidual;
-    double cur = measure(tune_point(ts, k, chunk, lpr, gpc * cus, tile));
+    uint32_t tile = kDefaultMaxResidual, leaf = 0;
+    double cur = measure(tune_point(ts, k, chunk, lpr, gpc * cus, tile, leaf));
     rep.default_ms = cur;
     auto sweep = [&](uint32_t* var, const uint32_t* vals, size_t n) {
       for (size_t i = 0; i < n; i++) {
         if (vals[i] == *var) continue;
         const uint32_t keep = *var;
         *var = vals[i];
-        double t = measure(tune_point(ts, k, chunk, lpr, gpc * cus, tile));
+        double t = measure(tune_point(ts, k, chunk, lpr, gpc * cus, tile, leaf));
         if (t < cur) cur = t;
         else *var = keep;
       }
@@ -1506,6 +1512,7 @@ scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tu
     sweep(&lpr, kTuneLpr, std::size(kTuneLpr));
     sweep(&gpc, kTuneGridPerCu, std::size(kTuneGridPerCu));
     sweep(&tile, kTuneTile, std::size(kTuneTile));
+    sweep(&leaf, kTuneLeaf, std::size(kTuneLeaf));
     if (!std::isfinite(cur)) fail(SCUBA_E_CAPACITY, "no tuning point fits the workspace");
     scuba_solve_opts b{};
     b.mode = SCUBA_MODE_DECIDE;
@@ -1515,12 +1522,105 @@ scuba_status scuba_autotune(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_tu
     b.chunk_log2 = chunk;
     b.grid = gpc * cus;
     b.scorer = ts.scorer;
-    b.flags = ts.flags;
+    b.flags = ts.flags | leaf;
     b.max_residual = tile;
     ctx->tuned[bucket] = b;
     *best = b;
     rep.best_ms = cur;
     if (report) *report = rep;
+  });
+}
+
+// One cache line: {"gpu":"<arch>","bucket":[b0,b1,b2,b3],"k":..,"chunk_log2":..,
+// "leaves_per_round":..,"grid":..,"scorer":..,"flags":..,"max_residual":..}
+namespace {
+std::string device_key(scuba_ctx* ctx) {
+  try {
+    ctx->ensure_device();
+    return ctx->dev.arch;
+  } catch (const Error&) {
+    return "no-device";   // a context without a device (the cache still round-trips)
+  }
+}
+bool json_u64(const std::string& line, const char* key, uint64_t* out) {
+  const std::string k = std::string("\"") + key + "\":";
+  const size_t p = line.find(k);
+  if (p == std::string::npos) return false;
+  const char* s = line.c_str() + p + k.size();
+  char* e = nullptr;
+  const unsigned long long v = std::strtoull(s, &e, 10);
+  if (e == s) return false;
+  *out = v;
+  return true;
+}
+}  // namespace
+
+scuba_status scuba_tune_cache_save(scuba_ctx* ctx, const char* path) {
+  if (!ctx || !path) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    const std::string gpu = device_key(ctx);
+    FILE* f = std::fopen(path, "w");
+    if (!f) fail(SCUBA_E_INVALID, std::string("cannot write ") + path);
+    for (const auto& [b, o] : ctx->tuned) {
+      if (b.size() != 4) continue;
+      std::fprintf(f,
+                   "{\"gpu\":\"%s\",\"bucket\":[%llu,%llu,%llu,%llu],\"k\":%u,\"chunk_log2\":%u,"
+                   "\"leaves_per_round\":%u,\"grid\":%u,\"scorer\":%u,\"flags\":%u,\"max_residual\":%u}\n",
+                   gpu.c_str(), (unsigned long long)b[0], (unsigned long long)b[1], (unsigned long long)b[2],
+                   (unsigned long long)b[3], o.k, o.chunk_log2, o.leaves_per_round, o.grid, o.scorer, o.flags,
+                   o.max_residual);
+    }
+    if (std::fclose(f) != 0) fail(SCUBA_E_INVALID, std::string("cannot write ") + path);
+  });
+}
+
+scuba_status scuba_tune_cache_load(scuba_ctx* ctx, const char* path, uint32_t* loaded) {
+  if (!ctx || !path) return SCUBA_E_INVALID;
+  return guard(ctx, [&] {
+    const std::string gpu = device_key(ctx);
+    FILE* f = std::fopen(path, "r");
+    if (!f) fail(SCUBA_E_INVALID, std::string("cannot read ") + path);
+    uint32_t n = 0;
+    char buf[1024];
+    while (std::fgets(buf, sizeof buf, f)) {
+      std::string line;   // without whitespace (JSON writers differ in spacing)
+      for (const char* c = buf; *c; c++)
+        if (!std::isspace(static_cast<unsigned char>(*c))) line.push_back(*c);
+      if (line.find("\"gpu\":\"" + gpu + "\"") == std::string::npos) continue;   // another GPU's choice
+      const size_t bp = line.find("\"bucket\":[");
+      if (bp == std::string::npos) continue;
+      std::vector<uint64_t> b(4);
+      const char* s = line.c_str() + bp + 10;
+      bool ok = true;
+      for (int i = 0; i < 4 && ok; i++) {
+        char* e = nullptr;
+        b[i] = std::strtoull(s, &e, 10);
+        ok = e != s && (*e == ',' || *e == ']');
+        s = e + 1;
+      }
+      uint64_t k, c, l, g, sc, fl, mr;
+      ok = ok && json_u64(line, "k", &k) && json_u64(line, "chunk_log2", &c) &&
+           json_u64(line, "leaves_per_round", &l) && json_u64(line, "grid", &g) && json_u64(line, "scorer", &sc) &&
+           json_u64(line, "flags", &fl) && json_u64(line, "max_residual", &mr);
+      if (!ok) {
+        std::fclose(f);
+        fail(SCUBA_E_INVALID, std::string("malformed tune cache line in ") + path);
+      }
+      scuba_solve_opts o{};
+      o.mode = SCUBA_MODE_DECIDE;
+      o.k = uint32_t(k);
+      o.chunk_log2 = uint32_t(c);
+      o.leaves_per_round = uint32_t(l);
+      o.grid = uint32_t(g);
+      o.scorer = uint32_t(sc);
+      o.flags = uint32_t(fl);
+      o.max_residual = uint32_t(mr);
+      resolve(&o);   // a line whose options the library would reject is an error
+      ctx->tuned[b] = o;
+      n++;
+    }
+    std::fclose(f);
+    if (loaded) *loaded = n;
   });
 }
 

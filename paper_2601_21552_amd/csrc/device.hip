@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <list>
 #include <map>
@@ -1464,6 +1465,7 @@ void dev_init(DeviceInfo* info, int device) {
   HIP_OK(hipGetDeviceProperties(&p, device));
   info->device = device;
   info->cus = p.multiProcessorCount;
+  std::snprintf(info->arch, sizeof(info->arch), "%s", p.gcnArchName);
   {
     // the scratch array's address on this device, looked up once per
     // device with that device current

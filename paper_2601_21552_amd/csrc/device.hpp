@@ -81,6 +81,7 @@ struct DeviceInfo {
   size_t max_lds = 65536;      // dynamic LDS a kernel may use by default
   size_t up_lds_max = 65536;   // dynamic LDS the propagation kernel may use
   size_t leaf_lds_max = 65536; // dynamic LDS the leaf kernel may use
+  char arch[64] = "";          // gcnArchName of the device
 };
 
 // Host staging for one launch pair; the layout inside the workspace is

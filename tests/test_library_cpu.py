@@ -440,3 +440,30 @@ def test_device_split_options_are_checked(ctx):
     st = ctx.lib.scuba_solve(ctx.h, cnf.h, cubes.h, C.byref(_solve_opts(k=16, device_split=True)),
                              C.c_void_p(1), 1 << 20, None, C.byref(h))
     assert st == -1 and not h.value
+
+
+def test_tune_cache_round_trip(ctx, tmp_path):
+    """The autotuner's cache persists as JSON lines keyed by the device's
+    architecture: lines of this device load (a context without a device
+    keys them "no-device"), lines of another architecture are skipped, a
+    save writes back what was loaded, and a malformed line or options the
+    library rejects are errors."""
+    import json
+    from paper_2601_21552_amd import _lib
+    mine = {"gpu": "no-device", "bucket": [11, 8, 2, 1], "k": 20, "chunk_log2": 8, "leaves_per_round": 1,
+            "grid": 2048, "scorer": 2, "flags": 5, "max_residual": 4096}
+    other = dict(mine, gpu="gfx90a", k=16)
+    p = tmp_path / "tune.jsonl"
+    p.write_text(json.dumps(mine) + "\n" + json.dumps(other) + "\n")
+    assert ctx.tune_cache_load(str(p)) == 1
+    out = tmp_path / "saved.jsonl"
+    ctx.tune_cache_save(str(out))
+    lines = [json.loads(x) for x in out.read_text().splitlines()]
+    assert mine in lines and all(x["gpu"] == "no-device" for x in lines)
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"gpu":"no-device","bucket":[1,2,3,4],"k":20}\n')
+    with pytest.raises(_lib.ScubaError):
+        ctx.tune_cache_load(str(bad))
+    bad.write_text(json.dumps(dict(mine, k=50)) + "\n")    # k above the leaf limit of 38
+    with pytest.raises(_lib.ScubaError):
+        ctx.tune_cache_load(str(bad))
