@@ -577,6 +577,11 @@ class Encoder {
         if (nodes_[i].op == SCUBA_OP_VAR && nodes_[i].width > wrap)
           fail(SCUBA_E_WIDTH, "node " + std::to_string(i) + ": input wider than the wrap-around width");
       out_.wrap_bits = wrap;
+      if (wrap_abstraction_unsat(wrap)) {
+        out_.root_unsat = true;
+        g_.clause(std::vector<int32_t>{});  // the empty clause
+        return;
+      }
       run_wrap(wrap);
     } else if (flags_ & SCUBA_BB_NO_REWRITE) {
       run_structural();
@@ -1040,6 +1045,119 @@ class Encoder {
   // Every integer node is an unsigned m-bit word: ADD, SUB, MUL and SHL are
   // taken modulo 2^m, UDIV / UREM by a constant are the unsigned quotient
   // and remainder, comparisons are unsigned (machine integers of m bits).
+  // Machine-integer queries refuted by the exact method.  An arithmetic node
+  // whose exact value provably stays in [0, 2^m) computes the same m-bit
+  // word as the exact integer (it never wraps); every other arithmetic node
+  // is replaced by a fresh m-bit input (its wrapped value is some m-bit
+  // word).  The resulting exact-integer query has every behaviour of the
+  // machine-integer one (comparisons of values in [0, 2^m) are the unsigned
+  // ones), so refuting it at the root (normalisation, bounds, relaxation)
+  // refutes the machine-integer query.  Value ranges start from the input
+  // widths and are narrowed, to a fixpoint, by the comparisons that the
+  // roots assert: a guard idx < N bounds even a wrapping idx, which is what
+  // shows that idx * s and N * s cannot wrap.  A root comparison that no
+  // value pair can meet refutes the query directly.
+  bool wrap_abstraction_unsat(uint32_t m) {
+    const BigInt top = BigInt::pow2(m) - BigInt(1);
+    const Range full{BigInt(0), top};
+    // the comparisons the roots assert (through conjunctions)
+    struct Fact { uint32_t op, a, b; };
+    std::vector<Fact> facts;
+    std::vector<uint32_t> todo(roots_, roots_ + nr_);
+    while (!todo.empty()) {
+      const uint32_t i = todo.back();
+      todo.pop_back();
+      const scuba_node& x = nodes_[i];
+      if (x.op == SCUBA_OP_AND) { todo.push_back(x.a); todo.push_back(x.b); }
+      else if (x.op >= SCUBA_OP_LT && x.op <= SCUBA_OP_EQ) facts.push_back({x.op, x.a, x.b});
+    }
+    std::vector<Range> nar(n_, full);     // narrowing of each integer node by the facts
+    std::vector<Range> r(n_);
+    std::vector<char> exact(n_, 1);
+    for (uint32_t iter = 0; iter < 16; iter++) {
+      for (uint64_t i = 0; i < n_; i++) {
+        const scuba_node& x = nodes_[i];
+        Range e;
+        bool arith = false;
+        switch (x.op) {
+          case SCUBA_OP_VAR: e = {BigInt(0), BigInt::pow2(x.width) - BigInt(1)}; break;
+          case SCUBA_OP_CONST: {
+            BigInt c;
+            BigInt::floor_divmod(BigInt::from_u64(x.imm), BigInt::pow2(m), nullptr, &c);
+            e = {c, c};
+            break;
+          }
+          case SCUBA_OP_ADD: e = range_add(r[x.a], r[x.b]); arith = true; break;
+          case SCUBA_OP_SUB: e = {r[x.a].lo - r[x.b].hi, r[x.a].hi - r[x.b].lo}; arith = true; break;
+          case SCUBA_OP_MUL: e = range_mul(r[x.a], r[x.b]); arith = true; break;
+          case SCUBA_OP_SHL: e = range_scale(r[x.a], BigInt::pow2(uint32_t(x.imm))); arith = true; break;
+          case SCUBA_OP_UDIV: {
+            const BigInt k = BigInt::from_u64(x.imm);
+            BigInt lo, hi;
+            BigInt::floor_divmod(r[x.a].lo, k, &lo, nullptr);
+            BigInt::floor_divmod(r[x.a].hi, k, &hi, nullptr);
+            e = {lo, hi};
+            break;
+          }
+          case SCUBA_OP_UREM: {
+            const BigInt k = BigInt::from_u64(x.imm);
+            e = r[x.a].hi < k ? r[x.a] : Range{BigInt(0), k - BigInt(1)};
+            break;
+          }
+          default: continue;   // boolean nodes
+        }
+        exact[i] = !arith || (e.lo >= BigInt(0) && e.hi <= top);
+        if (!exact[i]) e = full;
+        // the facts' narrowing
+        if (nar[i].lo > e.lo) e.lo = nar[i].lo;
+        if (nar[i].hi < e.hi) e.hi = nar[i].hi;
+        if (e.lo > e.hi) return true;   // no value of this node meets the roots
+        r[i] = e;
+      }
+      bool changed = false;
+      auto tighten = [&](uint32_t i, const BigInt* lo, const BigInt* hi) {
+        if (lo && *lo > nar[i].lo) { nar[i].lo = *lo; changed = true; }
+        if (hi && *hi < nar[i].hi) { nar[i].hi = *hi; changed = true; }
+      };
+      for (const Fact& f : facts) {
+        uint32_t a = f.a, b = f.b;
+        uint32_t op = f.op;
+        if (op == SCUBA_OP_GT) { std::swap(a, b); op = SCUBA_OP_LT; }
+        if (op == SCUBA_OP_GE) { std::swap(a, b); op = SCUBA_OP_LE; }
+        const BigInt d = op == SCUBA_OP_LT ? BigInt(1) : BigInt(0);
+        if (op == SCUBA_OP_EQ) {
+          tighten(a, &r[b].lo, &r[b].hi);
+          tighten(b, &r[a].lo, &r[a].hi);
+        } else {   // a + d <= b
+          const BigInt ahi = r[b].hi - d, blo = r[a].lo + d;
+          tighten(a, nullptr, &ahi);
+          tighten(b, &blo, nullptr);
+        }
+      }
+      if (!changed) break;
+    }
+    // the exact-integer query: wrapping nodes become fresh m-bit inputs
+    std::vector<scuba_node> nodes(nodes_, nodes_ + n_);
+    uint32_t nv = 0;
+    bool any_abstract = false;
+    for (uint64_t i = 0; i < n_; i++) {
+      scuba_node& x = nodes[i];
+      if (x.op == SCUBA_OP_VAR) {
+        x.imm = nv++;
+      } else if (x.op == SCUBA_OP_CONST) {
+        x.imm = x.imm & (m == 64 ? ~0ull : ((uint64_t(1) << m) - 1));
+      } else if (!exact[i]) {
+        x = scuba_node{SCUBA_OP_VAR, 0, 0, m, nv++};
+        any_abstract = true;
+      }
+    }
+    (void)any_abstract;
+    CnfQuery probe;
+    Encoder e(nodes.data(), n_, roots_, nr_, 0, probe);
+    e.run();
+    return probe.root_unsat;
+  }
+
   void run_wrap(uint32_t m) {
     std::vector<BitVec> bv(n_);
     std::vector<int32_t> bl(n_, kFalse);

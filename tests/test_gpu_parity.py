@@ -209,11 +209,9 @@ def test_decide_lower_bound_batch(ctx):
 def test_decide_wrap32_batch(ctx):
     """256 guarded accesses with 32-bit machine integers (SCUBA_BB_WRAP(32)).
     Those whose byte size N*s can wrap are found SAT, with a witness that
-    goes out of bounds under 32-bit arithmetic.  With s = 1 the offset and
-    the size are the guard's own words, and propagation refutes the query at
-    the root.  The rest are UNSAT by construction but need a proof through
-    the multipliers that cubing alone cannot give: within the cube budget
-    they may stay UNKNOWN, never SAT."""
+    goes out of bounds under 32-bit arithmetic.  The others are refuted at
+    the root: the guard bounds the (possibly wrapping) index, so index and
+    size times s cannot wrap, and the exact root check applies."""
     from paper_2601_21552_amd import _lib
     gens = w.batch_wrap(m=32)
     cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens], flags=_lib.BB_WRAP(32))
@@ -225,7 +223,7 @@ def test_decide_wrap32_batch(ctx):
             assert r["verdict"] == "SAT", g.query.name
             assert r["witness_checked"]
             assert query_ref.wrap_eval(g.query, res.witness(i, g.query.n_vars), 32)
-        elif g.query.name.endswith("_s1"):
+        else:
             assert r["verdict"] == "UNSAT" and r["how"] == "root", g.query.name
 
 

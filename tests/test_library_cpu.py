@@ -72,8 +72,48 @@ def test_wrap_cnf_counts_equal_machine_solutions(ctx, m):
     cnf = ctx.bitblast([q.arrays()[:2] for q in qs], flags=_lib.BB_WRAP(m))
     for i, q in enumerate(qs):
         v = cnf.view(i)
-        assert not v["root_unsat"]
-        assert cnf_ref.count(_cnf(v)) == query_ref.wrap_bruteforce(q, m)[1], q.nodes
+        want = query_ref.wrap_bruteforce(q, m)[1]
+        if v["root_unsat"]:   # refuted by the no-wrap abstraction: no m-bit model
+            assert want == 0, q.nodes
+        else:
+            assert cnf_ref.count(_cnf(v)) == want, q.nodes
+
+
+@pytest.mark.parametrize("m", [3, 4, 5, 6])
+def test_wrap_root_refutation_is_sound(ctx, m):
+    """Machine-integer queries refuted at the root (arithmetic that cannot
+    wrap kept exact, the rest abstracted, then the exact root check) have no
+    satisfying input tuple under m-bit arithmetic, by exhaustive search; and
+    the refutation does happen on guarded accesses that cannot wrap."""
+    from paper_2601_21552_amd import _lib
+    rng = np.random.Generator(np.random.PCG64(911 + m))
+    qs = [random_query(rng, max_bits=9, n_ops=8, name=f"s{m}_{i}") for i in range(300)]
+    qs = [q for q in qs if max(q.var_widths) <= m]
+    # guarded accesses idx*s >= N*s under idx < N, with and without room
+    # for N*s in m bits (the bit-level pins of these shapes are in the
+    # oracle tests)
+    for wd in range(1, m + 1):
+        for s_ in (1, 2, 4):
+            qs.append(w.oob_1d(wd, "lt", scale=s_, header=0, name=f"g{m}_{wd}_{s_}"))
+    qs = [q for q in qs if sum(q.var_widths) <= 16]
+    cnf = ctx.bitblast([q.arrays()[:2] for q in qs], flags=_lib.BB_WRAP(m))
+    refuted = 0
+    for i, q in enumerate(qs):
+        if cnf.view(i)["root_unsat"]:
+            refuted += 1
+            assert query_ref.wrap_bruteforce(q, m)[0] == "UNSAT", (m, q.name, q.nodes)
+    assert refuted > 0
+
+
+def test_wrap_batch_refuted_at_the_root(ctx):
+    """In the 32-bit batch every guarded access whose size cannot wrap is
+    refuted at the root (its label is pinned by the oracle tests) and no
+    access whose size wraps is."""
+    from paper_2601_21552_amd import _lib
+    gens = w.batch_wrap(m=32)
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens], flags=_lib.BB_WRAP(32))
+    for i, g in enumerate(gens):
+        assert bool(cnf.view(i)["root_unsat"]) == (g.label == "UNSAT"), g.query.name
 
 
 def test_wrap_rejects_inputs_wider_than_the_machine_word(api, ctx):
