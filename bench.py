@@ -260,16 +260,26 @@ def _oracle_decide(q):
     return query_ref.decide(q)[0]
 
 
+def _oracle_3sat(f):
+    """The oracle's DPLL verdict on one raw formula (node budget 3e8)."""
+    from oracle import cnf_ref
+    return cnf_ref.solve(f, 300_000_000)[0]
+
+
+DPLL_CNF_NODES = 20_000
+
+
 def _oracle_dpll(arrs):
     """The oracle's C DPLL on one query's CNF bytes as the library emitted
-    them (root-refuted queries have no CNF: UNSAT)."""
+    them (root-refuted queries have no CNF: UNSAT), with a node budget."""
     import numpy as np
     from oracle import cnf_ref
     from workloads.cnf import CNF
     n_vars, off, lits, root_unsat = arrs
     if root_unsat:
         return "UNSAT"
-    return cnf_ref.solve(CNF(n_vars, np.asarray(off, np.uint64), np.asarray(lits, np.int32)))[0]
+    return cnf_ref.solve(CNF(n_vars, np.asarray(off, np.uint64), np.asarray(lits, np.int32)),
+                         DPLL_CNF_NODES)[0]
 
 
 def cpu_baseline_leg(gens, cnf, path_verdicts, results_last):
@@ -291,27 +301,36 @@ def cpu_baseline_leg(gens, cnf, path_verdicts, results_last):
     with ProcessPoolExecutor(max_workers=cores) as ex:
         ov = list(ex.map(_oracle_decide, sample, chunksize=2))
     dt_all = time.perf_counter() - t0
+    log(f"cpu baseline: whole oracle on {m} queries, {cores} processes: {dt_all:.2f} s")
     one = idx[:max(m // 8, 1)]
     t0 = time.perf_counter()
     ov1 = [_oracle_decide(gens[i].query) for i in one]
     dt_one = time.perf_counter() - t0
+    log(f"cpu baseline: whole oracle on {len(one)} queries, one core: {dt_one:.2f} s")
     agree = sum(a == path_verdicts[i] for a, i in zip(ov, idx)) / m
     unknown = sum(a == "UNKNOWN" for a in ov)
     assert all(a == path_verdicts[i] for a, i in zip(ov1, one))
     # the C DPLL on the library's CNF bytes
+    # its own smaller sample (every n/64-th query)
+    md = min(n, 64)
+    idx_d = [i * n // md for i in range(md)]
+    one_d = idx_d[:max(md // 8, 1)]
     arrs = []
-    for i in idx:
+    for i in idx_d:
         v = cnf.view(i)
         arrs.append((v["n_vars"], v["clause_off"], v["lits"], bool(v["root_unsat"])))
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=cores) as ex:
         dv = list(ex.map(_oracle_dpll, arrs, chunksize=2))
     dt_dpll = time.perf_counter() - t0
+    log(f"cpu baseline: DPLL on the library's CNF bytes, {md} queries, {cores} processes: {dt_dpll:.2f} s")
     t0 = time.perf_counter()
-    dv1 = [_oracle_dpll(a) for a in arrs[:len(one)]]
+    dv1 = [_oracle_dpll(a) for a in arrs[:len(one_d)]]
     dt_dpll1 = time.perf_counter() - t0
-    dpll_agree = sum(a == path_verdicts[i] for a, i in zip(dv, idx)) / m
-    assert dv1 == dv[:len(one)]
+    log(f"cpu baseline: DPLL on the library's CNF bytes, {len(one_d)} queries, one core: {dt_dpll1:.2f} s")
+    decided = [(a, i) for a, i in zip(dv, idx_d) if a != "UNKNOWN"]
+    dpll_agree = (sum(a == path_verdicts[i] for a, i in decided) / len(decided)) if decided else None
+    assert dv1 == dv[:len(one_d)]
     # every SAT witness of the last timed step, by the exact definition
     for i, g in enumerate(gens):
         if path_verdicts[i] == "SAT":
@@ -323,9 +342,13 @@ def cpu_baseline_leg(gens, cnf, path_verdicts, results_last):
                    "capped at 16, this process's CPU share on a one-GPU box"),
         "one_core": {"value": round(len(one) / dt_one, 3), "queries": len(one), "seconds": round(dt_one, 2)},
         "dpll_on_library_cnf": {
-            "value": round(m / dt_dpll, 3), "cores": cores, "one_core_value": round(len(one) / dt_dpll1, 3),
-            "note": "C DPLL on the CNF bytes the library bit-blasted (shared bit-blast excluded; queries the "
-                    "root stage refuted have no CNF and count as decided)",
+            "value": round(md / dt_dpll, 3), "cores": cores, "one_core_value": round(len(one_d) / dt_dpll1, 3),
+            "queries": md, "one_core_queries": len(one_d),
+            "note": f"C DPLL on the CNF bytes the library bit-blasted (shared bit-blast excluded; queries the "
+                    f"root stage refuted have no CNF and count as decided), at most {DPLL_CNF_NODES} nodes per "
+                    "query (static MOMs branching without the word-level bounds can run for minutes on one "
+                    "SAT query); agreement over the queries it decided",
+            "unknown": sum(a == "UNKNOWN" for a in dv),
             "agreement": dpll_agree},
         "oracle_agreement": agree, "oracle_unknown": unknown,
     }
@@ -342,30 +365,53 @@ def gain_legs(ctx, mlp_q, mlp_s_info, args):
     out = {}
     mlp_s, info = mlp_s_info
     out["random3sat_scorer"] = info
-    per_n = {100: 256, 150: 64, 200: 16, 250: 8}
-    oracle_n = {100: 32, 150: 8, 200: 2, 250: 1}
+    # seeded samples of the 2500 instances per n; the static ordering split
+    # on the device and on the host, the learned ordering on the host (its
+    # scorer runs between host decisions); k autotuned on the sample
+    per_n = {100: 256, 150: 128, 200: 32, 250: 16}
+    learned_n = {100: 256, 150: 64, 200: 8, 250: 4}
+    host_n = {100: 256, 150: 64, 200: 8, 250: 4}
+    oracle_n = {100: 32, 150: 8, 200: 4, 250: 2}
+    budget = {100: 400000, 150: 400000, 200: 1 << 22, 250: 1 << 22}
     ev = w.random_3sat_sets(per_n=max(per_n.values()), ns=tuple(per_n))
+    from concurrent.futures import ProcessPoolExecutor
+    cores = min(len(os.sched_getaffinity(0)), 16)
     for n, count in per_n.items():
         cnfs = ev[n][:count]
         raw = ctx.cnf_from_arrays(*w.concat(cnfs))
         tuned, rep = ctx.autotune(raw, sample=min(count, 32), reps=1, max_cubes=400000)
         k = tuned["k"]
         base = dict(k=k, leaves_per_round=tuned["leaves_per_round"], chunk_log2=tuned["chunk_log2"],
-                    grid=tuned["grid"], max_cubes=400000)
-        st, vs = decide_stats(ctx, raw, count, **base)
-        le, vl = decide_stats(ctx, raw, count, **base,
+                    grid=tuned["grid"], max_cubes=budget[n])
+        dv, vd = decide_stats(ctx, raw, count, k=k, max_cubes=budget[n], device_split=True)
+        nh = host_n[n]
+        raw_h = raw if nh == count else ctx.cnf_from_arrays(*w.concat(cnfs[:nh]))
+        st, vs = decide_stats(ctx, raw_h, nh, **base)
+        nl = learned_n[n]
+        raw_l = raw if nl == count else ctx.cnf_from_arrays(*w.concat(cnfs[:nl]))
+        le, vl = decide_stats(ctx, raw_l, nl, **base,
                               learned=mlp_s.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE))
-        assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vs, vl))
+        assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vd, vs))
+        assert all(a == b or "UNKNOWN" in (a, b) for a, b in zip(vd, vl))
         no = oracle_n[n]
-        ov = [cnf_ref.solve(f, 3_000_000)[0] for f in cnfs[:no]]
+        t0 = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=min(cores, no)) as ex:
+            ov = list(ex.map(_oracle_3sat, cnfs[:no]))
+        oracle_s = time.perf_counter() - t0
         # a query left UNKNOWN by either side (budget) is counted, not compared
-        agree = [a == b for a, b in zip(ov, vs[:no]) if "UNKNOWN" not in (a, b)]
+        agree = [a == b for a, b in zip(ov, vd[:no]) if "UNKNOWN" not in (a, b)]
         assert all(agree), "oracle disagrees on random 3-SAT"
-        leg = {"instances": count, "of": 2500, "k_autotuned": k, "tuned": tuned, "static": st, "learned": le,
-               "leaf_ratio": round(le["leaves"] / max(st["leaves"], 1), 3),
-               "time_ratio": round(le["ms"] / max(st["ms"], 1e-9), 3),
-               "oracle_sample": no, "oracle_unknown": sum(a == "UNKNOWN" for a in ov),
-               "path_unknown_in_sample": sum(b == "UNKNOWN" for b in vs[:no]),
+        st_same = decide_stats(ctx, raw_l, nl, **base)[0] if nl != nh else st
+        leg = {"instances": count, "of": 2500, "k_autotuned": k, "tuned": tuned,
+               "static_device_split": dv, "static_host_split": dict(st, instances=nh),
+               "learned_host_split": dict(le, instances=nl),
+               "learned_vs_static_host": {"instances": nl,
+                                          "leaf_ratio": round(le["leaves"] / max(st_same["leaves"], 1), 3),
+                                          "time_ratio": round(le["ms"] / max(st_same["ms"], 1e-9), 3)},
+               "device_vs_host_static_ms_per_instance": [round(dv["ms"] / count, 3), round(st["ms"] / nh, 3)],
+               "oracle_sample": no, "oracle_seconds": round(oracle_s, 1),
+               "oracle_unknown": sum(a == "UNKNOWN" for a in ov),
+               "path_unknown_in_sample": sum(b == "UNKNOWN" for b in vd[:no]),
                "oracle_agreement": (sum(agree) / len(agree)) if agree else None}
         out[f"random3sat_n{n}"] = leg
         log(f"3-SAT n={n}: {leg}")
@@ -594,12 +640,17 @@ def main():
         if name == "learned":
             opts.pop("scorer", None)
             opts["learned"] = mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)
-        r = steps.run(opts)
+        # a form below 100% agreement cannot give the headline: one timed call
+        r = steps.run(opts, steps=1, warmup=1)
+        timed_steps = 1
+        if r["agree"] == 1.0 and r["unknown"] == 0:
+            r = steps.run(opts)
+            timed_steps = args.steps
         runs[name] = (r, opts)
         forms[name] = {"queries_per_s": round(n / (r["ms_per_step"] / 1000.0), 3),
                        "ms_per_step": round(r["ms_per_step"], 3), "agree": r["agree"], "unknown": r["unknown"],
                        "first_call_ms": round(r["first_ms"], 2), "bitblast_ms": round(r["bitblast_ms"], 3),
-                       "tune_s": round(tune_s, 2), "tune_points": rep["points"],
+                       "tune_s": round(tune_s, 2), "tune_points": rep["points"], "timed_steps": timed_steps,
                        "options": {k: v for k, v in opts.items() if k != "learned"}}
         log(f"form {name}: {forms[name]}")
     if args.form == "auto":

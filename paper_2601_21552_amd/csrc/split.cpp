@@ -87,19 +87,24 @@ void Splitter::set_trace(uint32_t candidates, uint32_t every, uint32_t depth) {
 }
 
 // The first m active variables of the static order.
-std::vector<int32_t> Splitter::candidates(uint32_t m) const {
+std::vector<int32_t> Splitter::candidates(uint32_t m, std::set<int32_t>* words) const {
   std::vector<int32_t> c;
   for (int32_t v : order_) {
     if (c.size() >= m) break;
     if (assign_[v] < 0 && act_cnt_[v] > 0) c.push_back(v);
   }
-  // and the most significant active bit of each input word
+  // and the most significant active bit of each input word (these stand
+  // for their words, see choose_learned)
   const size_t n_static = c.size();
+  if (words) words->clear();
   for (size_t i = 0; i < q_.in_first.size(); i++)
     for (uint32_t b = q_.in_width[i]; b-- > 0;) {
       const int32_t v = int32_t(q_.in_first[i] + b);
       if (assign_[v] >= 0 || act_cnt_[v] == 0) continue;
-      if (std::find(c.begin(), c.begin() + n_static, v) == c.begin() + n_static) c.push_back(v);
+      if (std::find(c.begin(), c.begin() + n_static, v) == c.begin() + n_static) {
+        c.push_back(v);
+        if (words) words->insert(v);
+      }
       break;
     }
   return c;
@@ -182,17 +187,24 @@ float Splitter::input_range_bits() {
 }
 
 // One-step lookahead after propagating v = 0 and v = 1: the reduction of
-// the active variable count (a conflicting branch counts as reducing it
-// to 0), log2(1 + reduction) summed over the two branches, plus the
-// reduction of the inputs' range width in bits (a word-level view of the
-// same progress: deciding a high input bit halves that input's range).
+// the active variable count (a branch that conflicts, or that the
+// word-level bounds refute, counts as reducing it to 0), log2(1 +
+// reduction) summed over the two branches, plus the reduction of the
+// inputs' range width in bits (a word-level view of the same progress:
+// deciding a high input bit halves that input's range).
 float Splitter::lookahead_label(int32_t v) {
   const size_t pos = trail_.size();
   const uint32_t f = f_;
   const float r = input_range_bits();
   float dr = 0.f;
   auto branch = [&](int32_t lit) {
-    const bool ok = propagate(lit);
+    bool ok = propagate(lit);
+    if (ok && !q_.word_facts.empty()) {
+      // a branch the word-level bounds refute is closed, as the walk would
+      // find at that node
+      std::vector<uint32_t> lv;
+      ok = word_check(&lv);
+    }
     const uint32_t fb = ok ? f_ : 0;
     dr += r - (ok ? input_range_bits() : 0.f);
     undo_to(pos);
@@ -215,12 +227,34 @@ void Splitter::provide_scores(const float* scores) {
   have_scores_ = true;
 }
 
-// The best-ranked active variable while the last ranking applies (the node
-// it was made at and `rescore` levels below), else 0.
+// The most significant unassigned active bit of the input word that holds
+// variable v, or 0.
+int32_t Splitter::word_top_bit(int32_t v) const {
+  const uint32_t w = bit_width_[v];
+  if (!w) return 0;
+  const uint32_t first = uint32_t(v) - bit_pos_[v];
+  for (uint32_t b = w; b-- > 0;) {
+    const int32_t u = int32_t(first + b);
+    if (assign_[u] < 0 && act_cnt_[u] > 0) return u;
+  }
+  return 0;
+}
+
+// The best-ranked candidate while the last ranking applies (the node it was
+// made at and `rescore` levels below), else 0.  A candidate that was the top
+// active bit of an input word stands for that word: once its bit is
+// assigned, the word's next active bit takes its place in the ranking (so a
+// ranking that puts input words first descends through their bits the way
+// the word ordering does).
 int32_t Splitter::choose_learned() {
   if (!rank_valid_ || stack_.size() < rank_depth_ || stack_.size() >= rank_depth_ + rescore_) return 0;
-  for (int32_t v : ranking_)
+  for (int32_t v : ranking_) {
     if (assign_[v] < 0 && act_cnt_[v] > 0) return v;
+    if (rank_words_.count(v)) {
+      const int32_t u = word_top_bit(v);
+      if (u) return u;
+    }
+  }
   return 0;
 }
 
@@ -603,7 +637,7 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
             rank_depth_ = stack_.size();
             v = choose_learned();
           } else if (!v) {
-            req_vars_ = candidates(n_cands_);
+            req_vars_ = candidates(n_cands_, &rank_words_);
             if (req_vars_.size() > 1) {
               features(req_vars_, &req_feats_);
               awaiting_ = true;

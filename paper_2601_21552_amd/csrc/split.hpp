@@ -21,6 +21,7 @@
 // failures that depend on every decision (their outcome is not known here).
 #pragma once
 #include <cstdint>
+#include <set>
 #include <vector>
 
 #include "common.hpp"
@@ -122,7 +123,8 @@ class Splitter {
   bool finish_branch(Failure r, std::vector<Cube>& out, bool keep);
   void reset_state();
   bool root_propagate();
-  std::vector<int32_t> candidates(uint32_t m) const;
+  std::vector<int32_t> candidates(uint32_t m, std::set<int32_t>* words = nullptr) const;
+  int32_t word_top_bit(int32_t v) const;
   void features(const std::vector<int32_t>& cands, std::vector<float>* out) const;
   float lookahead_label(int32_t v);
   float input_range_bits();
@@ -167,6 +169,7 @@ class Splitter {
   bool learned_ = false, have_scores_ = false, rank_valid_ = false;
   uint32_t n_cands_ = 32, rescore_ = 1;
   std::vector<int32_t> req_vars_, ranking_;
+  std::set<int32_t> rank_words_;   // candidates that stand for their input word
   std::vector<float> req_feats_;
   size_t rank_depth_ = 0;
   // traces
