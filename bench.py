@@ -611,20 +611,23 @@ def main():
     n = len(gens)
     max_cubes = MAX_CUBES[args.workload]
 
-    # the learned scorer, trained on traces of other seeds' access batches
     import workloads as w
-    t0 = time.perf_counter()
-    tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.batch_1d(seed=102)]),
-          ctx.bitblast([g.query.arrays()[:2] for g in w.batch_2d(seed=103, n=1024)])]
-    mlp_q, scorer_info = train_scorer(ctx, tr, k=30, epochs=4, seed=2)
-    scorer_info["seconds"] = round(time.perf_counter() - t0, 1)
-    log(f"access-query scorer trained: {scorer_info}")
+    names = [args.form] if (args.only_form and args.form != "auto") else ["static", "learned", "word"]
+    # the learned scorer, trained on traces of other seeds' access batches
+    # (when a leg uses it)
+    mlp_q, scorer_info = None, None
+    if "learned" in names or not args.only_form:
+        t0 = time.perf_counter()
+        tr = [ctx.bitblast([g.query.arrays()[:2] for g in w.batch_1d(seed=102)]),
+              ctx.bitblast([g.query.arrays()[:2] for g in w.batch_2d(seed=103, n=1024)])]
+        mlp_q, scorer_info = train_scorer(ctx, tr, k=30, epochs=4, seed=2)
+        scorer_info["seconds"] = round(time.perf_counter() - t0, 1)
+        log(f"access-query scorer trained: {scorer_info}")
 
     # per ordering: autotuned options (static / word; the learned form runs
     # at the static ordering's point), timed steps, agreement with the labels
     cnf0 = ctx.bitblast_packed(*packed)
     forms, runs = {}, {}
-    names = [args.form] if (args.only_form and args.form != "auto") else ["static", "learned", "word"]
     tuned = {}
     for name in names:
         t0 = time.perf_counter()

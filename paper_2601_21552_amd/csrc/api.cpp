@@ -35,7 +35,11 @@ struct scuba_ctx {
   // staging in pageable host memory instead of pinned (the allocation-free
   // entry point sets it for the duration of its call)
   bool pageable = false;
-  std::vector<char> pageable_stg, pageable_cnf_stg;
+  std::vector<char> pageable_stg, pageable_cnf_stg, pageable_score_stg;
+  // the learned scorer's own staging: its passes run while a round, which
+  // owns the round staging until it ends, is on the device
+  void* score_pinned = nullptr;
+  size_t score_pinned_bytes = 0;
   // autotuner choices per size bucket (see scuba_autotune)
   std::map<std::vector<uint64_t>, scuba_solve_opts> tuned;
 
@@ -75,6 +79,20 @@ struct scuba_ctx {
     }
     return cnf_pinned;
   }
+  void* score_staging(size_t bytes) {
+    if (pageable) {
+      if (bytes > pageable_score_stg.size()) pageable_score_stg.resize(bytes);
+      return pageable_score_stg.data();
+    }
+    if (bytes > score_pinned_bytes) {
+      dev_pinned_free(score_pinned);
+      score_pinned = nullptr;
+      score_pinned_bytes = 0;
+      score_pinned = dev_pinned(bytes);
+      score_pinned_bytes = bytes;
+    }
+    return score_pinned;
+  }
   size_t staging_size() const { return pageable ? pageable_stg.size() : pinned_bytes; }
   size_t cnf_staging_size() const { return pageable ? pageable_cnf_stg.size() : cnf_pinned_bytes; }
   DevGraphs* graph_cache() {
@@ -85,6 +103,7 @@ struct scuba_ctx {
     dev_graphs_destroy(graphs);
     dev_pinned_free(pinned);
     dev_pinned_free(cnf_pinned);
+    dev_pinned_free(score_pinned);
   }
 };
 
@@ -453,7 +472,7 @@ struct ScorerRunner {
         j++;
       }
       if (j == i) fail(SCUBA_E_CAPACITY, "scorer workspace smaller than one request");
-      void* stg = ctx->staging(std::max(rows * kMlpF * 2, rows * 4) + 256);
+      void* stg = ctx->score_staging(std::max(rows * kMlpF * 2, rows * 4) + 256);
       uint16_t* xh = static_cast<uint16_t*>(stg);
       // each request's rows at their offset, converted on the host pool
       std::vector<size_t> at(j - i + 1, 0);
@@ -1215,11 +1234,20 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     }
     RoundTimes rt;
     const uint32_t grid = grid_of(ctx, o);
-    for (uint32_t round = 0; o.max_rounds == 0 || round < o.max_rounds; round++) {
+    // One round's leaves as the walks produced them, with each walk's
+    // counters at that point.
+    struct Batch {
+      std::vector<std::vector<Cube>> leaves;
+      std::vector<Splitter::State> state;
+      std::vector<uint64_t> cubes_total, cubes_refuted;
+    };
+    // every open query's walk advances on the host pool
+    auto split_round = [&](Batch& b) {
       ts = Clock::now();
-      // each open query's walk advances on the host pool
-      std::vector<std::vector<Cube>> leaves(nq);
-      std::vector<Splitter::State> state(nq, Splitter::kRunning);
+      b.leaves.assign(nq, {});
+      b.state.assign(nq, Splitter::kRunning);
+      b.cubes_total.assign(nq, 0);
+      b.cubes_refuted.assign(nq, 0);
       std::vector<Splitter*> walks;
       std::vector<size_t> wq;
       for (size_t qi = 0; qi < nq; qi++)
@@ -1231,27 +1259,40 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       std::vector<Splitter::State> ws(walks.size(), Splitter::kRunning);
       run_walks(walks, o.lpr, wl, false, ws, runner.get());
       for (size_t i = 0; i < wq.size(); i++) {
-        leaves[wq[i]].swap(wl[i]);
-        state[wq[i]] = ws[i];
+        b.leaves[wq[i]].swap(wl[i]);
+        b.state[wq[i]] = ws[i];
+        b.cubes_total[wq[i]] = sp[wq[i]]->cubes_total();
+        b.cubes_refuted[wq[i]] = sp[wq[i]]->cubes_refuted();
       }
+      split_ms += ms_since(ts);
+    };
+    // Rounds overlap with the host: while the device evaluates round r, the
+    // walks of the queries still open produce round r + 1's leaves; a query
+    // that round r decides drops them (its walk is released at the end).
+    DevRoundPending pend;
+    Batch next;
+    split_round(next);
+    for (uint32_t round = 0; o.max_rounds == 0 || round < o.max_rounds; round++) {
+      ts = Clock::now();
       RoundHost rh;
       std::vector<std::pair<uint32_t, Cube>> sent;
       for (size_t qi = 0; qi < nq; qi++) {
         if (!open[qi]) continue;
         auto& r = res->q[qi].r;
         r.rounds++;
-        for (Cube& c : leaves[qi]) {
+        for (Cube& c : next.leaves[qi]) {
           add_cube(rh, uint32_t(qi), seq[qi]++, c, cnf->q[qi].n_vars);
           sent.push_back({uint32_t(qi), std::move(c)});
         }
-        r.cubes_total = sp[qi]->cubes_total();
-        r.cubes_refuted = sp[qi]->cubes_refuted();
-        if (leaves[qi].empty()) {
+        r.cubes_total = next.cubes_total[qi];
+        r.cubes_refuted = next.cubes_refuted[qi];
+        if (next.leaves[qi].empty()) {
           // nothing left for the device: the tree is done or cut
           open[qi] = 0;
-          r.verdict = state[qi] == Splitter::kExhausted ? SCUBA_UNSAT : SCUBA_UNKNOWN;
-          r.how = state[qi] == Splitter::kExhausted ? (r.leaves_sent ? SCUBA_HOW_DEVICE : SCUBA_HOW_ROOT)
-                                                     : SCUBA_HOW_BUDGET;
+          const Splitter::State st = next.state[qi];
+          r.verdict = st == Splitter::kExhausted ? SCUBA_UNSAT : SCUBA_UNKNOWN;
+          r.how = st == Splitter::kExhausted ? (r.leaves_sent ? SCUBA_HOW_DEVICE : SCUBA_HOW_ROOT)
+                                             : SCUBA_HOW_BUDGET;
         }
       }
       make_items(rh, SCUBA_MODE_DECIDE, o.chunk_log2, grid);
@@ -1261,11 +1302,15 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       size_t round_b = dev_round_bytes(rh.cubes.size(), rh.cube_lits.size(), rh.items.size(), rh.res_records);
       if (cnf_b + round_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace smaller than this round needs");
       void* stg = ctx->staging(std::max(cnf_b, round_b) + 4096 + rh.cubes.size() * sizeof(DevCubeOut) + nq * 8);
+      dev_round_begin(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
+                      ctx->staging_size(), &rt, (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr,
+                      &pend);
+      // the next round's leaves while this one runs
+      Batch after;
+      if (o.max_rounds == 0 || round + 1 < o.max_rounds) split_round(after);
       std::vector<DevCubeOut> outs;
       std::vector<uint64_t> qkeys;
-      dev_round(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
-                ctx->staging_size(), &outs, &qkeys, &rt,
-                (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr);
+      dev_round_end(&pend, &outs, &qkeys, &rt);
       auto tv = Clock::now();
       for (size_t i = 0; i < outs.size(); i++) {
         check_out(outs[i], sent[i].second);
@@ -1300,6 +1345,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       });
       for (uint32_t qi : sat_q) open[qi] = 0;
       verify_ms += ms_since(tv);
+      next = std::move(after);
     }
     for (size_t qi = 0; qi < nq; qi++)
       if (open[qi]) {  // round limit reached

@@ -1628,10 +1628,9 @@ void launch(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t q, hipEvent
   else hipLaunchKernelGGL(kernel, grid, block, lds, q, args...);
 }
 
-void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
-               uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
-               std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys, RoundTimes* times,
-               DevGraphs* graphs) {
+void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
+                     uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
+                     RoundTimes* times, DevGraphs* graphs, DevRoundPending* pend) {
   HIP_OK(hipSetDevice(info.device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   CnfLayout cl = cnf_layout(cnf);
@@ -1772,18 +1771,21 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
 
   times->cubes += nc;
   times->items += ni;
-  hipEvent_t ev[9];
-  for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+  if (pend->active) fail(SCUBA_E_INTERNAL, "a round is already in flight");
+  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(pend->ev);
+  pend->active = true;   // (release destroys whichever events exist)
+  pend->sync_stream = st;
+  for (int i = 0; i < 9; i++) HIP_OK(hipEventCreate(&ev[i]));
+  pend->device = info.device;
+  pend->gu = gu;
+  pend->gl = gl;
+  pend->nc = nc;
+  pend->nq = cnf.q.size();
+  pend->staging = staging;
   if (!graphs) {
     enqueue(st, ev);
-    HIP_OK(hipStreamSynchronize(st));
-    float ms;
-    HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1])); times->h2d_ms += ms;
-    if (gu) { HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->up_ms += ms; }
-    if (gl) { HIP_OK(hipEventElapsedTime(&ms, ev[4], ev[5])); times->leaf_ms += ms; }
-    HIP_OK(hipEventElapsedTime(&ms, ev[6], ev[7])); times->d2h_ms += ms;
-    times->up_launches += gu != 0;
-    times->leaf_launches += gl != 0;
+    pend->graph = false;
+    pend->sync_stream = st;
   } else {
     if (!graphs->stream) {
       HIP_OK(hipStreamCreateWithFlags(&graphs->stream, hipStreamNonBlocking));
@@ -1827,17 +1829,57 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
     HIP_OK(hipEventRecord(ev[0], gs));
     HIP_OK(hipGraphLaunch(it->second, gs));
     HIP_OK(hipEventRecord(ev[1], gs));
-    HIP_OK(hipStreamSynchronize(gs));
-    float ms;
+    pend->graph = true;
+    pend->sync_stream = gs;
+  }
+}
+
+void dev_round_end(DevRoundPending* pend, std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys,
+                   RoundTimes* times) {
+  if (!pend->active) fail(SCUBA_E_INTERNAL, "no round in flight");
+  HIP_OK(hipSetDevice(pend->device));
+  hipEvent_t* ev = reinterpret_cast<hipEvent_t*>(pend->ev);
+  HIP_OK(hipStreamSynchronize(static_cast<hipStream_t>(pend->sync_stream)));
+  float ms;
+  if (!pend->graph) {
+    HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1])); times->h2d_ms += ms;
+    if (pend->gu) { HIP_OK(hipEventElapsedTime(&ms, ev[2], ev[3])); times->up_ms += ms; }
+    if (pend->gl) { HIP_OK(hipEventElapsedTime(&ms, ev[4], ev[5])); times->leaf_ms += ms; }
+    HIP_OK(hipEventElapsedTime(&ms, ev[6], ev[7])); times->d2h_ms += ms;
+    times->up_launches += pend->gu != 0;
+    times->leaf_launches += pend->gl != 0;
+  } else {
     HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));
     times->graph_ms += ms;
     times->graph_launches++;
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
-  outs->resize(nc);
-  std::memcpy(outs->data(), s, nc * sizeof(DevCubeOut));
-  qkeys->resize(cnf.q.size());
-  std::memcpy(qkeys->data(), s + align256(nc * sizeof(DevCubeOut)), cnf.q.size() * 8);
+  const char* s = static_cast<const char*>(pend->staging);
+  outs->resize(pend->nc);
+  std::memcpy(outs->data(), s, pend->nc * sizeof(DevCubeOut));
+  qkeys->resize(pend->nq);
+  std::memcpy(qkeys->data(), s + align256(pend->nc * sizeof(DevCubeOut)), pend->nq * 8);
+  dev_round_release(pend);
+}
+
+void dev_round_release(DevRoundPending* pend) {
+  if (!pend->active) return;
+  pend->active = false;
+  (void)hipSetDevice(pend->device);
+  (void)hipStreamSynchronize(static_cast<hipStream_t>(pend->sync_stream));
+  for (int i = 0; i < 9; i++)
+    if (pend->ev[i]) (void)hipEventDestroy(static_cast<hipEvent_t>(pend->ev[i]));
+  for (auto& e : pend->ev) e = nullptr;
+}
+
+DevRoundPending::~DevRoundPending() { dev_round_release(this); }
+
+void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
+               uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
+               std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys, RoundTimes* times,
+               DevGraphs* graphs) {
+  DevRoundPending pend;
+  dev_round_begin(info, ws, ws_bytes, cnf, rh, mode, grid, stream, staging, staging_bytes, times, graphs, &pend);
+  dev_round_end(&pend, outs, qkeys, times);
 }
 
 size_t dev_split_node_bytes(uint32_t nw_max) { return sizeof(DevSplitNode) + 2 * size_t(nw_max) * 4; }

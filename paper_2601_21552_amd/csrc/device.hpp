@@ -148,6 +148,31 @@ void dev_round(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
                size_t staging_bytes, std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys,
                RoundTimes* times, DevGraphs* graphs = nullptr);
 
+// The same round in two halves, so that the host can work while it runs:
+// dev_round_begin enqueues it (the staging buffer and the workspace's round
+// region belong to it until dev_round_end), dev_round_end waits for it and
+// fills outs and qkeys.  A pending round that is never ended is waited for
+// and released by the destructor.
+struct DevRoundPending {
+  bool active = false, graph = false;
+  int device = 0;
+  void* sync_stream = nullptr;
+  void* ev[9] = {};
+  uint32_t gu = 0, gl = 0;
+  size_t nc = 0, nq = 0;
+  void* staging = nullptr;
+  DevRoundPending() = default;
+  DevRoundPending(const DevRoundPending&) = delete;
+  DevRoundPending& operator=(const DevRoundPending&) = delete;
+  ~DevRoundPending();
+};
+void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, const RoundHost& rh,
+                     uint32_t mode, uint32_t grid, void* stream, void* staging, size_t staging_bytes,
+                     RoundTimes* times, DevGraphs* graphs, DevRoundPending* pend);
+void dev_round_end(DevRoundPending* pend, std::vector<DevCubeOut>* outs, std::vector<uint64_t>* qkeys,
+                   RoundTimes* times);
+void dev_round_release(DevRoundPending* pend);
+
 // ---------------------------------------------------------------- device split
 // Splitting on the device (scuba_decide with SCUBA_SOLVE_DEVICE_SPLIT): a
 // work stack of nodes in device memory.  A node is a query, the fixpoint of
