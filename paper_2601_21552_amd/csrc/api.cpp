@@ -1266,12 +1266,16 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       }
       split_ms += ms_since(ts);
     };
-    // Rounds overlap with the host: while the device evaluates round r, the
-    // walks of the queries still open produce round r + 1's leaves; a query
-    // that round r decides drops them (its walk is released at the end).
+    // Rounds overlap with the host when the device bounds them: while the
+    // device evaluates round r, the walks of the queries still open produce
+    // round r + 1's leaves, and a query that round r decides drops them.
+    // Speculation costs the walks of queries the round decides (a walk whose
+    // leaf decides its query never finishes the branch otherwise), so it
+    // runs only after a round whose kernels took longer than its split.
     DevRoundPending pend;
     Batch next;
     split_round(next);
+    double last_split_ms = split_ms, last_dev_ms = 0;
     for (uint32_t round = 0; o.max_rounds == 0 || round < o.max_rounds; round++) {
       ts = Clock::now();
       RoundHost rh;
@@ -1305,12 +1309,18 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       dev_round_begin(ctx->dev, dev_ws, ws_bytes, h, rh, SCUBA_MODE_DECIDE, o.grid, hip_stream, stg,
                       ctx->staging_size(), &rt, (o.flags & SCUBA_SOLVE_GRAPH) ? ctx->graph_cache() : nullptr,
                       &pend);
-      // the next round's leaves while this one runs
+      // the next round's leaves while this one runs, when rounds are
+      // bound by the device
       Batch after;
-      if (o.max_rounds == 0 || round + 1 < o.max_rounds) split_round(after);
+      const bool more = o.max_rounds == 0 || round + 1 < o.max_rounds;
+      const bool speculate = more && last_dev_ms > last_split_ms;
+      const double split_before = split_ms;
+      if (speculate) split_round(after);
       std::vector<DevCubeOut> outs;
       std::vector<uint64_t> qkeys;
+      const double dev_before = rt.up_ms + rt.leaf_ms + rt.graph_ms;
       dev_round_end(&pend, &outs, &qkeys, &rt);
+      last_dev_ms = rt.up_ms + rt.leaf_ms + rt.graph_ms - dev_before;
       auto tv = Clock::now();
       for (size_t i = 0; i < outs.size(); i++) {
         check_out(outs[i], sent[i].second);
@@ -1345,6 +1355,8 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       });
       for (uint32_t qi : sat_q) open[qi] = 0;
       verify_ms += ms_since(tv);
+      if (!speculate && more) split_round(after);   // only the queries still open
+      last_split_ms = split_ms - split_before;
       next = std::move(after);
     }
     for (size_t qi = 0; qi < nq; qi++)

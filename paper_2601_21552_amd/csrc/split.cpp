@@ -187,24 +187,17 @@ float Splitter::input_range_bits() {
 }
 
 // One-step lookahead after propagating v = 0 and v = 1: the reduction of
-// the active variable count (a branch that conflicts, or that the
-// word-level bounds refute, counts as reducing it to 0), log2(1 +
-// reduction) summed over the two branches, plus the reduction of the
-// inputs' range width in bits (a word-level view of the same progress:
-// deciding a high input bit halves that input's range).
+// the active variable count (a conflicting branch counts as reducing it
+// to 0), log2(1 + reduction) summed over the two branches, plus the
+// reduction of the inputs' range width in bits (a word-level view of the
+// same progress: deciding a high input bit halves that input's range).
 float Splitter::lookahead_label(int32_t v) {
   const size_t pos = trail_.size();
   const uint32_t f = f_;
   const float r = input_range_bits();
   float dr = 0.f;
   auto branch = [&](int32_t lit) {
-    bool ok = propagate(lit);
-    if (ok && !q_.word_facts.empty()) {
-      // a branch the word-level bounds refute is closed, as the walk would
-      // find at that node
-      std::vector<uint32_t> lv;
-      ok = word_check(&lv);
-    }
+    const bool ok = propagate(lit);
     const uint32_t fb = ok ? f_ : 0;
     dr += r - (ok ? input_range_bits() : 0.f);
     undo_to(pos);
