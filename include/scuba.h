@@ -486,7 +486,8 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube,
  * replays, [12] graph captures; with the learned scorer (scuba_decide):
  * [13] ms in the scoring passes' copies, kernel and wait, [14] passes,
  * [15] candidate rows scored; [16] cubes and [17] leaf work items sent to
- * the kernels.  n <= 18.                                                    */
+ * the kernels; [18] propagation launches whose cubes all carried the
+ * host's fixpoint (fix_kernel, counted in [8] too).  n <= 19.               */
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n);
 void scuba_results_free(scuba_results* r);
 

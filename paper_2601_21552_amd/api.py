@@ -112,11 +112,11 @@ class Results(_Handle):
         return dict(refuted=bool(r.refuted), f=r.f, m=r.m, count=int(r.count), first=int(r.first))
 
     def timing(self) -> dict:
-        ms = np.zeros(18, np.float64)
-        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 18))
+        ms = np.zeros(19, np.float64)
+        self.ctx._check(L.load().scuba_results_timing(self.h, _ptr(ms), 19))
         keys = ["split", "h2d", "kernels", "d2h", "verify", "total", "up", "leaf",
                 "up_launches", "leaf_launches", "graph", "graph_launches", "graph_captures",
-                "score_device", "score_passes", "score_rows", "cubes_sent", "items_sent"]
+                "score_device", "score_passes", "score_rows", "cubes_sent", "items_sent", "fix_launches"]
         return dict(zip(keys, ms.tolist()))
 
 

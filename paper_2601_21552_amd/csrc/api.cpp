@@ -126,7 +126,7 @@ struct scuba_results {
     std::vector<scuba_leaf_result> leaves;
   };
   std::vector<Q> q;
-  double ms[18] = {};
+  double ms[19] = {};
 };
 
 namespace {
@@ -1174,6 +1174,7 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
     res->ms[12] = rt.graph_captures;
     res->ms[16] = double(rt.cubes);
     res->ms[17] = double(rt.items);
+    res->ms[18] = rt.fix_launches;
     *out = res.release();
   });
 }
@@ -1389,6 +1390,7 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
     res->ms[12] = rt.graph_captures;
     res->ms[16] = double(rt.cubes);
     res->ms[17] = double(rt.items);
+    res->ms[18] = rt.fix_launches;
     return res;
   }
 }
@@ -1758,7 +1760,7 @@ scuba_status scuba_leaf_get(const scuba_results* r, uint32_t qi, uint64_t cube, 
 }
 
 scuba_status scuba_results_timing(const scuba_results* r, double* ms, uint32_t n) {
-  if (!r || !ms || n > 18) return SCUBA_E_INVALID;
+  if (!r || !ms || n > 19) return SCUBA_E_INVALID;
   std::copy(r->ms, r->ms + n, ms);
   return SCUBA_OK;
 }

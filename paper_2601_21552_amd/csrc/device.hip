@@ -538,6 +538,30 @@ __device__ __forceinline__ void up_prefix(Team<TW>& tm, uint32_t nv, const uint3
   for (uint32_t w = w0; w < w1; w++) { P[w] = base; base += __popc(A[w]); }
 }
 
+// The residual record of unsatisfied clause c (slots from A and P) at
+// record index rec.
+template <class Cnf>
+__device__ __forceinline__ void up_record(const Cnf& cnf, uint32_t c, const uint32_t* T, const uint32_t* F,
+                                          const uint32_t* A, const uint32_t* P, uint4* __restrict__ res,
+                                          uint64_t rec) {
+  uint64_t low = 0, lm = 0;
+  uint32_t hp = 0, hn = 0, len = 0;
+  for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
+    uint32_t v;
+    bool neg;
+    cnf.lit(i, &v, &neg);
+    const uint32_t bit = 1u << (v & 31);
+    if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
+    len++;
+    const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
+    if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
+    else if (slot < 12) lm |= neg ? ~slot_pattern(slot - 6) : slot_pattern(slot - 6);
+    else (neg ? hn : hp) |= 1u << (slot - 12);
+  }
+  res[2 * rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
+  res[2 * rec + 1] = make_uint4(hp, hp | hn, len, 0u);
+}
+
 // The residual records of the lane's unsatisfied clauses, in clause order,
 // at records res_base + pos.. (pos: the team scan of my_unsat).  P must be
 // complete (a team barrier after up_prefix).
@@ -547,25 +571,222 @@ __device__ __forceinline__ void up_records(const Cnf& cnf, const ActiveScan& as,
                                            uint4* __restrict__ res, uint64_t res_base, uint32_t pos) {
   for (uint32_t c = as.c0; c < as.c1; c++) {
     if (as.keep ? !((as.unsat >> (c - as.c0)) & 1) : clause_satisfied(cnf, c, T, F)) continue;
-    uint64_t low = 0, lm = 0;
-    uint32_t hp = 0, hn = 0, len = 0;
-    for (uint32_t i = cnf.beg(c), e = cnf.end(c); i < e; i++) {
-      uint32_t v;
-      bool neg;
-      cnf.lit(i, &v, &neg);
-      const uint32_t bit = 1u << (v & 31);
-      if ((T[v >> 5] | F[v >> 5]) & bit) continue;     // false literal
-      len++;
-      const uint32_t slot = P[v >> 5] + __popc(A[v >> 5] & (bit - 1));
-      if (slot < 6) low |= neg ? ~slot_pattern(slot) : slot_pattern(slot);
-      else if (slot < 12) lm |= neg ? ~slot_pattern(slot - 6) : slot_pattern(slot - 6);
-      else (neg ? hn : hp) |= 1u << (slot - 12);
-    }
-    const size_t rec = 2 * (res_base + pos);
-    res[rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
-    res[rec + 1] = make_uint4(hp, hp | hn, len, 0u);
+    up_record(cnf, c, T, F, A, P, res, res_base + pos);
     pos++;
   }
+}
+
+// A host fixpoint in one pass over the clauses in HBM.  The pass confirms
+// that no clause is unit or empty under the assignment, marks the active
+// variables in A and lists the unsatisfied clauses.  Wave wv of the team
+// takes the clauses [c0, c1) of fix_range, 64 at a time with lane j on
+// clause base + j, so consecutive lanes read consecutive clause offsets and
+// literals, kFixUnroll chunks at a time (the first four literals of a
+// clause with the chunk, longer clauses' rest when evaluated).  The wave's unsatisfied clauses go to list[]
+// in clause order (ballot ranks), the first cap of them.  Returns the
+// wave's count of unsatisfied clauses; *bad is set (wave-uniform) when a
+// clause is unit or empty, so the assignment is not a fixpoint.
+constexpr uint32_t kFixUnroll = 3;
+constexpr uint32_t kFixList = 512;   // listed unsatisfied clauses per wave
+
+// Element i of a 32-bit array whose indexes stay below 2^30: the byte
+// offset is a 32-bit value, so a uniform base takes the scalar-base form of
+// the load.
+template <class T>
+__device__ __forceinline__ T ld32(const T* base, uint32_t i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (i << 2));
+}
+
+template <int TW>
+__device__ __forceinline__ void fix_range(uint32_t nc, uint32_t wv, uint32_t* c0, uint32_t* c1) {
+  const uint32_t per = ((nc + TW - 1) / TW + 63) & ~63u;
+  *c0 = min(nc, wv * per);
+  *c1 = min(nc, *c0 + per);
+}
+
+__device__ __forceinline__ void fix_lit(int32_t l, const uint32_t* T, const uint32_t* F, bool* sat, uint32_t* open) {
+  const uint32_t v = uint32_t(l > 0 ? l : -l), bit = 1u << (v & 31);
+  const uint32_t t = T[v >> 5], f = F[v >> 5];
+  if (((l > 0) ? t : f) & bit) *sat = true;
+  else if (!((t | f) & bit)) (*open)++;
+}
+__device__ __forceinline__ void fix_mark(int32_t l, const uint32_t* T, const uint32_t* F, uint32_t* A) {
+  const uint32_t v = uint32_t(l > 0 ? l : -l), bit = 1u << (v & 31);
+  if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
+}
+
+template <int TW>
+__device__ __forceinline__ uint32_t fix_scan(const GlobalCnf& cnf, uint32_t nc, uint32_t wv, const uint32_t* T,
+                                             const uint32_t* F, uint32_t* A, uint32_t* list, uint32_t cap,
+                                             uint32_t* bad) {
+  constexpr uint32_t G = 64 * kFixUnroll;   // clauses per group
+  const uint32_t wl = threadIdx.x & 63;
+  uint32_t c0, c1;
+  fix_range<TW>(nc, wv, &c0, &c1);
+  uint32_t n = 0;
+  bool wrong = false;
+  // Software pipeline over groups of kFixUnroll chunks: while group g is
+  // evaluated, the literals of group g + 1 and the clause starts of group
+  // g + 2 are in flight.  A clause's end is the next lane's start, the
+  // next chunk's first start, or the group's end offset (one uniform
+  // load); a lane past the range gets an empty clause.  Literals come four
+  // at a time in one 16-byte load from the clause's start (what lies past
+  // a shorter clause is read, within the CNF's regions, and ignored).
+  auto starts = [&](uint32_t base, uint32_t* bb, uint32_t* last) {
+#pragma unroll
+    for (uint32_t u = 0; u < kFixUnroll; u++) {
+      const uint32_t c = base + 64 * u + wl;
+      bb[u] = c < c1 ? ld32(cnf.co, c) : 0u;
+    }
+    *last = base < c1 ? ld32(cnf.co, min(base + G, c1)) : 0u;
+  };
+  auto ends = [&](uint32_t base, const uint32_t* bb, uint32_t last, uint32_t* ee) {
+#pragma unroll
+    for (uint32_t u = 0; u < kFixUnroll; u++) {
+      const uint32_t nx = u + 1 < kFixUnroll ? uint32_t(__builtin_amdgcn_readlane(int(bb[u + 1]), 0)) : last;
+      const uint32_t dn = uint32_t(__shfl_down(int(bb[u]), 1));
+      const uint32_t c = base + 64 * u + wl;
+      ee[u] = c >= c1 ? 0u : c + 1 == c1 ? last : (wl < 63 ? dn : nx);
+    }
+  };
+  auto lits = [&](const uint32_t* bb, const uint32_t* ee, int4* xx) {
+#pragma unroll
+    for (uint32_t u = 0; u < kFixUnroll; u++) {
+      xx[u] = make_int4(0, 0, 0, 0);
+      if (bb[u] < ee[u]) __builtin_memcpy(&xx[u], reinterpret_cast<const char*>(cnf.L) + (bb[u] << 2), 16);
+    }
+  };
+  uint32_t b[kFixUnroll], e[kFixUnroll], nb[kFixUnroll], last, nlast;
+  int4 x[kFixUnroll];
+  starts(c0, b, &last);
+  ends(c0, b, last, e);
+  lits(b, e, x);
+  starts(c0 + G, nb, &nlast);
+  for (uint32_t base = c0; base < c1; base += G) {
+    uint32_t ne[kFixUnroll], bb[kFixUnroll], blast;
+    int4 nx[kFixUnroll];
+    ends(base + G, nb, nlast, ne);
+    lits(nb, ne, nx);                  // group g + 1
+    starts(base + 2 * G, bb, &blast);  // group g + 2
+#pragma unroll
+    for (uint32_t u = 0; u < kFixUnroll; u++) {
+      const uint32_t c = base + 64 * u + wl;
+      const int32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+      bool sat = false;
+      uint32_t open = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++)
+        if (b[u] + j < e[u]) fix_lit(xs[j], T, F, &sat, &open);
+      for (uint32_t i = b[u] + 4; i < e[u]; i++) fix_lit(ld32(cnf.L, i), T, F, &sat, &open);
+      const bool unsat = c < c1 && !sat;
+      if (unsat) {
+        wrong |= open < 2;
+#pragma unroll
+        for (uint32_t j = 0; j < 4; j++)
+          if (b[u] + j < e[u]) fix_mark(xs[j], T, F, A);
+        for (uint32_t i = b[u] + 4; i < e[u]; i++) fix_mark(ld32(cnf.L, i), T, F, A);
+      }
+      const uint64_t m = __ballot(unsat);
+      if (unsat) {
+        const uint32_t r = n + __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+        if (r < cap) list[r] = c;
+      }
+      n += uint32_t(__popcll(m));
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kFixUnroll; u++) {
+      b[u] = nb[u];
+      e[u] = ne[u];
+      x[u] = nx[u];
+      nb[u] = bb[u];
+    }
+    nlast = blast;
+  }
+  *bad = __ballot(wrong) != 0;
+  return n;
+}
+
+// Records of the wave's unsatisfied clauses at res_base + pos.., in clause
+// order: from the wave's list when it holds them all, else by a second pass
+// over the wave's clauses.
+template <int TW>
+__device__ __forceinline__ void fix_records(const GlobalCnf& cnf, uint32_t nc, uint32_t wv, uint32_t n,
+                                            const uint32_t* list, uint32_t cap, const uint32_t* T,
+                                            const uint32_t* F, const uint32_t* A, const uint32_t* P,
+                                            uint4* __restrict__ res, uint64_t res_base, uint32_t pos) {
+  const uint32_t wl = threadIdx.x & 63;
+  if (n <= cap) {
+    for (uint32_t i = wl; i < n; i += 64) up_record(cnf, list[i], T, F, A, P, res, res_base + pos + i);
+    return;
+  }
+  uint32_t c0, c1;
+  fix_range<TW>(nc, wv, &c0, &c1);
+  for (uint32_t base = c0; base < c1; base += 64) {
+    const uint32_t c = base + wl;
+    const bool unsat = c < c1 && !clause_satisfied(cnf, c, T, F);
+    const uint64_t m = __ballot(unsat);
+    if (unsat)
+      up_record(cnf, c, T, F, A, P, res,
+                res_base + pos + __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+    pos += uint32_t(__popcll(m));
+  }
+}
+
+// A cube that carries the host's fixpoint, from the CNF in HBM: the
+// bitmaps from the cube's record, one pass (fix_scan), then slots and
+// records.  The host's fixpoint is the unit-propagation fixpoint of the
+// same clauses, so a clause that is unit or empty under it (or a variable
+// set both ways) means the two sides disagree: the cube's status is 2, an
+// error the host reports.
+template <int TW>
+__device__ void fix_cube(Team<TW>& tm, const GlobalCnf& cnf, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
+                         uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
+                         uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
+                         uint32_t* lists) {
+  constexpr uint32_t S = Team<TW>::kSize;
+  const uint32_t lane = tm.lane(), wv = TW == 1 ? 0u : uniform_u32(lane >> 6);
+  const uint32_t nw = (nv >> 5) + 1;
+  const uint32_t* fw = reinterpret_cast<const uint32_t*>(cube_lits + cd.lit_off);
+  uint32_t clash = 0;
+  for (uint32_t w = lane; w < nw; w += S) {
+    const uint32_t t = fw[w], f = fw[nw + w];
+    T[w] = t;
+    F[w] = f;
+    A[w] = 0;
+    clash |= t & f;
+  }
+  tm.sync();
+  uint32_t* list = lists + wv * kFixList;
+  uint32_t bad;
+  const uint32_t n = fix_scan<TW>(cnf, nc, wv, T, F, A, list, kFixList, &bad);
+  bad |= __ballot(clash != 0) != 0;
+  const bool lead = (threadIdx.x & 63) == 0;
+  uint32_t n_bad, n_unsat;
+  tm.scan(lead ? bad : 0u, &n_bad);
+  // lane 0 of a wave holds the count of the waves before it
+  const uint32_t pos = uniform_u32(tm.scan(lead ? n : 0u, &n_unsat));
+  tm.sync();
+  if (n_bad) {
+    if (lane == 0) {
+      out[ci].status = 2;
+      out[ci].f = out[ci].m = out[ci].nres = 0;
+    }
+    tm.sync();
+    return;
+  }
+  uint32_t f_total, free_total;
+  up_prefix<TW>(tm, nv, T, F, A, P, &f_total, &free_total);
+  tm.sync();
+  const bool f_ok = (cd.f_expect < 0 || uint32_t(cd.f_expect) == f_total) && f_total <= kMaxLeafVars;
+  const bool cap_ok = n_unsat <= cd.nres_cap;
+  if (f_ok && cap_ok) fix_records<TW>(cnf, nc, wv, n, list, kFixList, T, F, A, P, res, cd.res_base, pos);
+  if (lane == 0) {
+    out[ci].status = !f_ok ? 2 : (!cap_ok ? 3 : 0);
+    out[ci].f = int32_t(f_total);
+    out[ci].m = int32_t(free_total - f_total);
+    out[ci].nres = int32_t(n_unsat);
+  }
+  tm.sync();
 }
 
 // Unit propagation of one cube by one team from the empty assignment (the
@@ -636,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
                                                    const int32_t* __restrict__ cube_lits,
                                                    const uint2* __restrict__ groups, uint32_t n_groups,
                                                    DevCubeOut* __restrict__ out, uint4* __restrict__ res,
-                                                   uint32_t* head, uint32_t nw_max, uint32_t occ_in_memory) {
+                                                   uint32_t* head, uint32_t nw_max) {
   // LDS: per team four bitmaps of nw_max words, two frontier queues and
   // the scan space, then the staged CNF
   constexpr uint32_t kTeams = kUpWaves / TW;
@@ -694,18 +915,18 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
         for (uint32_t u = 0; u < kStageUnroll; u++) {
           const uint32_t i = b + u * kBlock;
           x[u] = i < nl ? L[i] : 0;
-          y[u] = i < nl && !occ_in_memory ? oc[i] : 0u;
+          y[u] = i < nl ? oc[i] : 0u;
         }
 #pragma unroll
         for (uint32_t u = 0; u < kStageUnroll; u++) {
           const uint32_t i = b + u * kBlock;
           if (i < nl) {
             sl[i] = uint16_t((uint32_t(x[u] > 0 ? x[u] : -x[u]) << 1) | (x[u] < 0 ? 1u : 0u));
-            if (!occ_in_memory) soc[i] = uint16_t(y[u]);
+            soc[i] = uint16_t(y[u]);
           }
         }
       }
-      for (uint32_t b = tid; !occ_in_memory && b <= nli; b += kStageUnroll * kBlock) {
+      for (uint32_t b = tid; b <= nli; b += kStageUnroll * kBlock) {
         uint32_t x[kStageUnroll];
 #pragma unroll
         for (uint32_t u = 0; u < kStageUnroll; u++) {
@@ -721,12 +942,8 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
       __syncthreads();
       if (team < g.y) {
         const uint32_t ci = g.x + team;
-        if (occ_in_memory)   // (only a host fixpoint that is not one needs them)
-          propagate_cube<TW>(LdsCnf{sco, sl}, GlobalOcc{oo, oc}, cubes[ci], ci, q.n_vars, q.n_clauses,
-                             cube_lits, out, res, T, F, A, P, Q, X, sh[team]);
-        else
-          propagate_cube<TW>(LdsCnf{sco, sl}, LdsOcc{soo, soc}, cubes[ci], ci, q.n_vars, q.n_clauses,
-                             cube_lits, out, res, T, F, A, P, Q, X, sh[team]);
+        propagate_cube<TW>(LdsCnf{sco, sl}, LdsOcc{soo, soc}, cubes[ci], ci, q.n_vars, q.n_clauses, cube_lits,
+                           out, res, T, F, A, P, Q, X, sh[team]);
       }
     } else if (team < g.y) {
       const uint32_t ci = g.x + team;
@@ -734,6 +951,51 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
                          out, res, T, F, A, P, Q, X, sh[team]);
     }
     __syncthreads();   // the staged CNF is replaced by the next group
+  }
+}
+
+// Persistent kernel for launches whose cubes all carry the host's
+// fixpoint.  A workgroup takes a group of up to kUpWaves / TW cubes of one
+// query, as up_kernel does, and each team checks one cube with fix_cube.
+// Nothing is staged: the one pass reads the CNF from HBM, and the launch
+// asks only for the teams' bitmaps and lists, so more workgroups share a CU
+// than with staging.
+template <int TW>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : 5))) void fix_kernel(const DevQueryDesc* __restrict__ qd,
+                                                    const uint32_t* __restrict__ coff,
+                                                    const int32_t* __restrict__ lits,
+                                                    const DevCubeDesc* __restrict__ cubes,
+                                                    const int32_t* __restrict__ cube_lits,
+                                                    const uint2* __restrict__ groups, uint32_t n_groups,
+                                                    DevCubeOut* __restrict__ out, uint4* __restrict__ res,
+                                                    uint32_t* head, uint32_t nw_max) {
+  // LDS per team: T, F, A, P of nw_max words, then kFixList per wave
+  constexpr uint32_t kTeams = kUpWaves / TW;
+  extern __shared__ uint32_t smem[];
+  __shared__ UpShared sh[kTeams];
+  __shared__ uint32_t s_group;
+  // the group, the cube and its query are wave-uniform (scalar loads, and
+  // CNF bases in scalar registers)
+  const uint32_t tid = threadIdx.x, team = uniform_u32((tid >> 6) / TW);
+  uint32_t* T = smem + team * (size_t(nw_max) * 4 + TW * kFixList);
+  uint32_t* F = T + nw_max;
+  uint32_t* A = F + nw_max;
+  uint32_t* P = A + nw_max;
+  uint32_t* lists = P + nw_max;
+  for (;;) {
+    if (tid == 0) s_group = atomicAdd(head, 1u);
+    __syncthreads();
+    const uint32_t gi = uniform_u32(s_group);
+    __syncthreads();
+    if (gi >= n_groups) break;
+    const uint2 g = groups[gi];
+    if (team < g.y) {
+      const uint32_t ci = g.x + team;
+      const DevQueryDesc q = qd[cubes[ci].qid];
+      Team<TW> tm{sh[team]};
+      fix_cube<TW>(tm, GlobalCnf{coff + q.coff_base, lits + q.lit_base}, cubes[ci], ci, q.n_vars, q.n_clauses,
+                   cube_lits, out, res, T, F, A, P, lists);
+    }
   }
 }
 
@@ -1495,6 +1757,10 @@ void dev_init(DeviceInfo* info, int device) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&up_kernel<4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<4>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&split_expand_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&split_scatter_kernel),
@@ -1654,8 +1920,20 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
     i = j;
   }
   const uint32_t tw = (nc <= uint32_t(info.cus) || 2 * groups_of_four > nc) ? 4 : 1;
-  const size_t team_bytes = size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 + 2 * 64 * size_t(tw) * 4;
-  const size_t up_lds = (kUpWaves / tw) * team_bytes + cnf.stage_bytes;
+  // every cube with the host's fixpoint: fix_kernel (one pass from HBM,
+  // nothing staged); else up_kernel
+  // (its loads take 32-bit byte offsets: clauses and literals below 2^30)
+  uint32_t fix_only = nc ? 1u : 0u;
+  for (const DevCubeDesc& c : rh.cubes) {
+    if (!(c.n_lits & kCubeFixpoint)) fix_only = 0;
+    if (c.qid < cnf.q.size() && (cnf.src->q[c.qid].lits.size() >= (size_t(1) << 30) ||
+                                 cnf.src->q[c.qid].n_clauses() >= (uint64_t(1) << 30)))
+      fix_only = 0;
+  }
+  const size_t team_bytes = fix_only ? (size_t(rh.nw_max) * 4 + size_t(tw) * kFixList) * 4
+                                     : size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 +
+                                           2 * 64 * size_t(tw) * 4;
+  const size_t up_lds = (kUpWaves / tw) * team_bytes + (fix_only ? 0 : cnf.stage_bytes);
   // the LDS variant stages a work item's records when the round's largest
   // residual fits the kernel's LDS (else all items read from memory)
   uint32_t lds_records = 0;
@@ -1667,11 +1945,9 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
   if (rh.leaf_variant > kLeafVectorLds) fail(SCUBA_E_INTERNAL, "unknown leaf variant");
   if (up_lds > info.up_lds_max) fail(SCUBA_E_CAPACITY, "query too large for the propagation kernel's LDS");
 
-  uint32_t occ_in_memory = nc ? 1u : 0u;
   for (const DevCubeDesc& c : rh.cubes) {
     const bool fix = c.n_lits & kCubeFixpoint;
     const uint32_t n = c.n_lits & ~kCubeFixpoint;
-    if (!fix) occ_in_memory = 0;
     if (fix && c.qid < cnf.q.size() && n != 2 * ((cnf.q[c.qid].n_vars >> 5) + 1))
       fail(SCUBA_E_INTERNAL, "cube fixpoint of the wrong size");
     if (c.qid >= cnf.q.size() || uint64_t(c.lit_off) + n > rh.cube_lits.size() ||
@@ -1687,7 +1963,10 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
   const size_t b = rl.head;
   std::memset(s + (rl.head - b), 0, 256);
   std::memcpy(s + (rl.cubes - b), rh.cubes.data(), nc * sizeof(DevCubeDesc));
-  // groups of up to kUpWaves consecutive cubes of one query
+  // groups of up to kUpWaves consecutive cubes of one query, the largest
+  // CNFs first: a group's time grows with its query's clauses and literals,
+  // and workgroups take groups in this order, so the long ones do not start
+  // last
   uint32_t n_groups = 0;
   {
     uint2* gp = reinterpret_cast<uint2*>(s + (rl.groups - b));
@@ -1697,6 +1976,11 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
       gp[n_groups++] = make_uint2(i, j - i);
       i = j;
     }
+    auto size_of = [&](const uint2& g) {
+      const CnfQuery& q = cnf.src->q[rh.cubes[g.x].qid];
+      return q.lits.size() + q.off.size();
+    };
+    std::stable_sort(gp, gp + n_groups, [&](const uint2& x, const uint2& y) { return size_of(x) > size_of(y); });
   }
   std::memcpy(s + (rl.lits - b), rh.cube_lits.data(), rh.cube_lits.size() * 4);
   std::memcpy(s + (rl.items - b), rh.items.data(), ni * sizeof(DevItem));
@@ -1728,7 +2012,15 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
     } else {
       HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
     }
-    if (gu) {
+    if (gu && fix_only) {
+      launch(tw == 4 ? fix_kernel<4> : fix_kernel<1>, dim3(gu), dim3(kBlock), up_lds, q, ev ? ev[2] : nullptr,
+             ev ? ev[3] : nullptr, reinterpret_cast<const DevQueryDesc*>(w + cl.q),
+             reinterpret_cast<const uint32_t*>(w + cl.coff), reinterpret_cast<const int32_t*>(w + cl.lits),
+             reinterpret_cast<const DevCubeDesc*>(w + rl.cubes), reinterpret_cast<const int32_t*>(w + rl.lits),
+             reinterpret_cast<const uint2*>(w + rl.groups), n_groups, reinterpret_cast<DevCubeOut*>(w + rl.outs),
+             reinterpret_cast<uint4*>(w + rl.res), reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
+      HIP_OK(hipGetLastError());
+    } else if (gu) {
       launch(tw == 4 ? up_kernel<4> : up_kernel<1>, dim3(gu), dim3(kBlock), up_lds, q,
                             ev ? ev[2] : nullptr, ev ? ev[3] : nullptr,
                             reinterpret_cast<const DevQueryDesc*>(w + cl.q),
@@ -1740,7 +2032,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
                             reinterpret_cast<const int32_t*>(w + rl.lits),
                             reinterpret_cast<const uint2*>(w + rl.groups), n_groups,
                             reinterpret_cast<DevCubeOut*>(w + rl.outs), reinterpret_cast<uint4*>(w + rl.res),
-                            reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max, occ_in_memory);
+                            reinterpret_cast<uint32_t*>(w + rl.head), rh.nw_max);
       HIP_OK(hipGetLastError());
     }
     if (gl) {
@@ -1779,6 +2071,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
   pend->device = info.device;
   pend->gu = gu;
   pend->gl = gl;
+  pend->fix_only = fix_only;
   pend->nc = nc;
   pend->nq = cnf.q.size();
   pend->staging = staging;
@@ -1799,7 +2092,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
                                  rl.head, rl.cubes, rl.groups, rl.lits, rl.items, rl.outs, rl.res, rl.end,
                                  up_bytes, nc, rh.cube_lits.size(), ni, rh.res_records, cnf.q.size(), n_groups,
                                  mode, gu, gl, rh.nw_max, up_lds, leaf_lds, uint64_t(info.device), tw,
-                                 occ_in_memory, rh.leaf_variant, lds_records};
+                                 fix_only, rh.leaf_variant, lds_records};
     auto it = graphs->execs.find(key);
     if (it == graphs->execs.end()) {
       hipGraph_t graph;
@@ -1847,6 +2140,7 @@ void dev_round_end(DevRoundPending* pend, std::vector<DevCubeOut>* outs, std::ve
     if (pend->gl) { HIP_OK(hipEventElapsedTime(&ms, ev[4], ev[5])); times->leaf_ms += ms; }
     HIP_OK(hipEventElapsedTime(&ms, ev[6], ev[7])); times->d2h_ms += ms;
     times->up_launches += pend->gu != 0;
+    times->fix_launches += pend->gu != 0 && pend->fix_only;
     times->leaf_launches += pend->gl != 0;
   } else {
     HIP_OK(hipEventElapsedTime(&ms, ev[0], ev[1]));

@@ -56,6 +56,7 @@ struct DevItem {
 struct RoundTimes {
   double up_ms = 0, leaf_ms = 0, h2d_ms = 0, d2h_ms = 0;
   uint32_t up_launches = 0, leaf_launches = 0;
+  uint32_t fix_launches = 0;      // propagation launches of the host-fixpoint kernel
   double graph_ms = 0;            // replays of captured rounds (copies included)
   uint32_t graph_launches = 0, graph_captures = 0;
   uint64_t cubes = 0, items = 0;  // sent to the kernels
@@ -158,7 +159,7 @@ struct DevRoundPending {
   int device = 0;
   void* sync_stream = nullptr;
   void* ev[9] = {};
-  uint32_t gu = 0, gl = 0;
+  uint32_t gu = 0, gl = 0, fix_only = 0;
   size_t nc = 0, nq = 0;
   void* staging = nullptr;
   DevRoundPending() = default;
