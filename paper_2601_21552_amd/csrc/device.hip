@@ -120,7 +120,7 @@ struct UpShared {
   // r % 3: a set is read in the round after it is written and cleared in
   // the round after that, so one barrier per round separates all three
   uint32_t qn[3], ovf[3], chg[3];
-  uint32_t scan[2][kBlock / 64];   // alternating, so one barrier per scan
+  uint32_t scan[2][16];            // per wave (teams of up to 16), alternating: one barrier per scan
 };
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -588,6 +588,7 @@ __device__ __forceinline__ void up_records(const Cnf& cnf, const ActiveScan& as,
 // clause is unit or empty, so the assignment is not a fixpoint.
 constexpr uint32_t kFixUnroll = 3;
 constexpr uint32_t kFixList = 512;   // listed unsatisfied clauses per wave
+constexpr uint64_t kFixWideClauses = 16384;
 
 // Element i of a 32-bit array whose indexes stay below 2^30: the byte
 // offset is a 32-bit value, so a uniform base takes the scalar-base form of
@@ -955,13 +956,19 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
 }
 
 // Persistent kernel for launches whose cubes all carry the host's
-// fixpoint.  A workgroup takes a group of up to kUpWaves / TW cubes of one
-// query, as up_kernel does, and each team checks one cube with fix_cube.
-// Nothing is staged: the one pass reads the CNF from HBM, and the launch
-// asks only for the teams' bitmaps and lists, so more workgroups share a CU
-// than with staging.
+// fixpoint.  A workgroup takes a group of cubes of one query (up to four
+// one-wave teams, else one cube), as up_kernel does, and each team checks
+// one cube with fix_cube.  Nothing is staged: the one pass reads the CNF
+// from HBM, and the launch asks only for the teams' bitmaps and lists, so
+// more workgroups share a CU than with staging.  TW = 16 (workgroups of
+// 1024 threads) is for rounds with large CNFs: a cube's pass is a chain of
+// dependent loads per wave, so sixteen waves finish a large cube four
+// times sooner than four.
 template <int TW>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : 5))) void fix_kernel(const DevQueryDesc* __restrict__ qd,
+constexpr int fix_threads() { return TW == 16 ? 1024 : kBlock; }
+template <int TW>
+__global__ __launch_bounds__(fix_threads<TW>())
+__attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : TW == 1 ? 5 : 4))) void fix_kernel(const DevQueryDesc* __restrict__ qd,
                                                     const uint32_t* __restrict__ coff,
                                                     const int32_t* __restrict__ lits,
                                                     const DevCubeDesc* __restrict__ cubes,
@@ -970,7 +977,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TW == 4 
                                                     DevCubeOut* __restrict__ out, uint4* __restrict__ res,
                                                     uint32_t* head, uint32_t nw_max) {
   // LDS per team: T, F, A, P of nw_max words, then kFixList per wave
-  constexpr uint32_t kTeams = kUpWaves / TW;
+  constexpr uint32_t kTeams = fix_threads<TW>() / 64 / TW;
   extern __shared__ uint32_t smem[];
   __shared__ UpShared sh[kTeams];
   __shared__ uint32_t s_group;
@@ -1761,6 +1768,8 @@ void dev_init(DeviceInfo* info, int device) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&split_expand_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&split_scatter_kernel),
@@ -1919,7 +1928,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
     groups_of_four++;
     i = j;
   }
-  const uint32_t tw = (nc <= uint32_t(info.cus) || 2 * groups_of_four > nc) ? 4 : 1;
+  const uint32_t tw_up = (nc <= uint32_t(info.cus) || 2 * groups_of_four > nc) ? 4 : 1;
   // every cube with the host's fixpoint: fix_kernel (one pass from HBM,
   // nothing staged); else up_kernel
   // (its loads take 32-bit byte offsets: clauses and literals below 2^30)
@@ -1930,10 +1939,18 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
                                  cnf.src->q[c.qid].n_clauses() >= (uint64_t(1) << 30)))
       fix_only = 0;
   }
+  // a fix launch whose largest CNF has kFixWideClauses clauses or more
+  // gives each cube sixteen waves (one 1024-thread workgroup)
+  uint64_t max_clauses = 0;
+  for (const DevCubeDesc& c : rh.cubes)
+    if (c.qid < cnf.q.size()) max_clauses = std::max<uint64_t>(max_clauses, cnf.q[c.qid].n_clauses);
+  const uint32_t tw = fix_only && max_clauses >= kFixWideClauses ? 16 : tw_up;
+  const uint32_t teams = tw == 16 ? 1 : kUpWaves / tw;
+  const uint32_t block = tw == 16 ? 1024 : kBlock;
   const size_t team_bytes = fix_only ? (size_t(rh.nw_max) * 4 + size_t(tw) * kFixList) * 4
                                      : size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 +
                                            2 * 64 * size_t(tw) * 4;
-  const size_t up_lds = (kUpWaves / tw) * team_bytes + (fix_only ? 0 : cnf.stage_bytes);
+  const size_t up_lds = teams * team_bytes + (fix_only ? 0 : cnf.stage_bytes);
   // the LDS variant stages a work item's records when the round's largest
   // residual fits the kernel's LDS (else all items read from memory)
   uint32_t lds_records = 0;
@@ -1972,7 +1989,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
     uint2* gp = reinterpret_cast<uint2*>(s + (rl.groups - b));
     for (uint32_t i = 0; i < nc;) {
       uint32_t j = i + 1;
-      while (j < nc && j - i < kUpWaves / tw && rh.cubes[j].qid == rh.cubes[i].qid) j++;
+      while (j < nc && j - i < teams && rh.cubes[j].qid == rh.cubes[i].qid) j++;
       gp[n_groups++] = make_uint2(i, j - i);
       i = j;
     }
@@ -2013,7 +2030,8 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
       HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
     }
     if (gu && fix_only) {
-      launch(tw == 4 ? fix_kernel<4> : fix_kernel<1>, dim3(gu), dim3(kBlock), up_lds, q, ev ? ev[2] : nullptr,
+      launch(tw == 16 ? fix_kernel<16> : tw == 4 ? fix_kernel<4> : fix_kernel<1>, dim3(gu), dim3(block), up_lds,
+             q, ev ? ev[2] : nullptr,
              ev ? ev[3] : nullptr, reinterpret_cast<const DevQueryDesc*>(w + cl.q),
              reinterpret_cast<const uint32_t*>(w + cl.coff), reinterpret_cast<const int32_t*>(w + cl.lits),
              reinterpret_cast<const DevCubeDesc*>(w + rl.cubes), reinterpret_cast<const int32_t*>(w + rl.lits),
