@@ -47,8 +47,12 @@ OPS_PER_CLAUSE_BLOCK = 128
 # HBM bytes per launch from two rocprofv3 counter passes (FETCH_SIZE /
 # 0.5 + WRITE_SIZE, both scaled by what they read for a device copy of known
 # size), valid only for the kernel source, workload and options they were
-# taken on
-MEASURED_TRAFFIC = {}
+# taken on (profiles/fix_kernel_batch2d_4096q.md)
+MEASURED_TRAFFIC = {
+    'batch_2d:b5a9d8c52c0e1fea:{"chunk_log2": 8, "form": "word", "graph": false, "grid": 4096, "k": 30, '
+    '"leaves_per_round": 1, "max_cubes": 20000, "max_residual": 4096, "scorer": "word"}': {
+        "fix_kernel": 930777411, "leaf_kernel": 2082846},
+}
 
 # The autotuner's choices for this bench's batches on MI355X (gfx950), as
 # scuba_tune_cache_save wrote them after a tuning run of this script; loaded
