@@ -903,14 +903,28 @@ SplitRun split_run(const scuba_cnf* cnf, const Opts& o, size_t* n_order) {
   }
   r.nw_max = nw;
   r.nres_max = uint32_t(std::min<uint64_t>(o.max_res, nc));
+  // a batch with a wide query (kSplitWideClauses clauses or more) expands
+  // one node per open query per step, so that every query's walk goes
+  // depth-first; else up to 16384 nodes, fewer when leaves are large
+  size_t n_open = 0;
+  bool wide = false;
+  for (const CnfQuery& q : cnf->q)
+    if (!q.root_unsat) {
+      n_open++;
+      wide |= q.n_clauses() >= kSplitWideClauses;
+    }
   uint64_t b = o.split_batch ? o.split_batch : 16384;
-  if (!o.split_batch) b = std::min<uint64_t>(b, std::max<uint64_t>(256, (uint64_t(512) << 20) / (32 * r.nres_max)));
+  if (!o.split_batch) {
+    b = std::min<uint64_t>(b, std::max<uint64_t>(256, (uint64_t(512) << 20) / (32 * r.nres_max)));
+    if (wide) b = std::min<uint64_t>(std::max<uint64_t>(64, n_open), uint64_t(1) << 20);
+  }
   r.batch = uint32_t(b);
-  // room for 64 wide steps, then depth-first steps within the reserve
+  // room for 64 breadth-limited steps (256 depth-first levels of every
+  // query when wide), then depth-first steps within the reserve
   uint32_t nv_max = 0;
   for (const CnfQuery& q : cnf->q)
     if (!q.root_unsat) nv_max = std::max(nv_max, q.n_vars);
-  r.stack_cap = 64 * size_t(b) + size_t(nv_max) + 2 + cnf->q.size();
+  r.stack_cap = (wide ? 256 : 64) * size_t(b) + size_t(nv_max) + 2 + cnf->q.size();
   return r;
 }
 

@@ -514,6 +514,14 @@ __device__ __forceinline__ ActiveScan up_active(Team<TW>& tm, const Cnf& cnf, ui
   return as;
 }
 
+// The bits of bitmap word w that are variables 1..nv.
+__device__ __forceinline__ uint32_t var_mask(uint32_t w, uint32_t nv) {
+  uint32_t valid = 0xFFFFFFFFu;
+  if (w == 0) valid &= ~1u;   // no variable 0
+  if (w == (nv >> 5)) valid &= (nv & 31) == 31 ? 0xFFFFFFFFu : ((2u << (nv & 31)) - 1);
+  return valid;
+}
+
 // Slot prefix per bitmap word (contiguous words per lane) into P, and the
 // team totals of active (f) and unassigned variables.  A must be complete
 // (a team barrier after up_active).
@@ -527,11 +535,8 @@ __device__ __forceinline__ void up_prefix(Team<TW>& tm, uint32_t nv, const uint3
   const uint32_t w0 = min(nw, lane * wpl), w1 = min(nw, w0 + wpl);
   uint32_t my_act = 0, my_free = 0;
   for (uint32_t w = w0; w < w1; w++) {
-    uint32_t valid = 0xFFFFFFFFu;
-    if (w == 0) valid &= ~1u;                      // no variable 0
-    if (w == (nv >> 5)) valid &= (nv & 31) == 31 ? 0xFFFFFFFFu : ((2u << (nv & 31)) - 1);
     my_act += __popc(A[w]);
-    my_free += __popc(~(T[w] | F[w]) & valid);
+    my_free += __popc(~(T[w] | F[w]) & var_mask(w, nv));
   }
   uint32_t base = tm.scan(my_act, f_total);
   tm.scan(my_free, free_total);
@@ -1423,11 +1428,28 @@ __global__ __launch_bounds__(kBlock) void split_expand_kernel(
       tm.sync();
       continue;
     }
-    const ActiveScan as = up_active<1>(tm, cnf, nc, T, F, A);
-    tm.sync();
-    uint32_t f_total, free_total, n_unsat;
-    up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
-    tm.scan(as.my_unsat, &n_unsat);
+    // A query of kSplitWideClauses clauses or more takes its unassigned
+    // variables as the node's slots (m = 0), counted from the bitmaps; the
+    // unsatisfied clauses are counted by a pass over the clauses only when
+    // that could make a leaf.  Smaller queries count the active variables
+    // (unassigned, in an unsatisfied clause) exactly.
+    const bool wide = nc >= kSplitWideClauses;
+    uint32_t f_total, free_total, n_unsat = 0;
+    if (wide) {
+      uint32_t my_free = 0;
+      for (uint32_t w = lane; w < nw; w += 64) my_free += __popc(~(T[w] | F[w]) & var_mask(w, nv));
+      tm.scan(my_free, &free_total);
+      f_total = free_total;
+      if (f_total <= k && f_total > 0) {
+        uint32_t bad;
+        n_unsat = fix_scan<1>(cnf, nc, 0, T, F, A, nullptr, 0, &bad);
+      }
+    } else {
+      const ActiveScan as = up_active<1>(tm, cnf, nc, T, F, A);
+      tm.sync();
+      up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
+      tm.scan(as.my_unsat, &n_unsat);
+    }
     so.f = int32_t(f_total);
     so.m = int32_t(free_total - f_total);
     so.nres = n_unsat;
@@ -1435,13 +1457,16 @@ __global__ __launch_bounds__(kBlock) void split_expand_kernel(
       so.kind = kSplitLeaf;
       if (lane == 0) atomicAdd(&stats[qid].cubes, 1ull);
     } else {
-      // the first active variable of the branch order, 64 candidates at a time
+      // the first variable of the branch order that is active (unassigned
+      // for a wide query), 64 candidates at a time
       const uint32_t* ord = order + order_off[qid];
       uint32_t v = 0;
       for (uint32_t j0 = 0; j0 < nv; j0 += 64) {
         const uint32_t j = j0 + lane;
         const uint32_t x = j < nv ? ord[j] : 0u;
-        const bool act = x != 0 && x <= nv && ((A[x >> 5] >> (x & 31)) & 1u);
+        const uint32_t bit = 1u << (x & 31);
+        const bool act = x != 0 && x <= nv &&
+                         (wide ? !((T[x >> 5] | F[x >> 5]) & bit) : ((A[x >> 5] & bit) != 0));
         const uint64_t m = __ballot(act);
         if (m) {
           v = uint32_t(__builtin_amdgcn_readlane(int(x), int(__builtin_ctzll(m))));
@@ -1533,12 +1558,13 @@ __global__ __launch_bounds__(1024) void split_scan_kernel(const DevSplitOut* __r
   }
 }
 
-// One popped node per wave: a branching node's two children are pushed at
-// its scanned position (the branch explored first on top, so that it is
-// popped first when steps are short), each with a copy of the node's
-// fixpoint; a leaf gets its cube descriptor, initial results, residual
-// records (rebuilt from its fixpoint, as the propagation kernel builds
-// them) and work items.
+// One popped node per wave.  A branching node of rank r among the step's
+// nb branching nodes pushes its second branch at r and its first branch at
+// nb + r, each with a copy of the node's fixpoint: the first branches of
+// the whole step lie on top, so a step of nb nodes continues every query's
+// walk depth-first.  A leaf gets its cube descriptor, initial results,
+// residual records (rebuilt from its fixpoint, as the propagation kernels
+// build them) and work items.
 __global__ __launch_bounds__(kBlock) void split_scatter_kernel(
     const DevQueryDesc* __restrict__ qd, const uint32_t* __restrict__ coff, const int32_t* __restrict__ lits,
     const DevSplitOut* __restrict__ sout, const uint32_t* __restrict__ fix_out, uint32_t first, uint32_t b,
@@ -1546,27 +1572,30 @@ __global__ __launch_bounds__(kBlock) void split_scatter_kernel(
     const uint32_t* __restrict__ res_off, const uint32_t* __restrict__ item_off, DevSplitNode* __restrict__ nodes,
     uint32_t* __restrict__ node_fix, DevCubeDesc* __restrict__ descs, DevCubeOut* __restrict__ louts,
     uint32_t* __restrict__ leaf_src, DevItem* __restrict__ items, uint4* __restrict__ res, uint32_t seq_base,
-    uint32_t nw_max, uint32_t chunk_log2) {
+    uint32_t nw_max, uint32_t chunk_log2, const uint32_t* __restrict__ ctr) {
   extern __shared__ uint32_t smem[];
   __shared__ UpShared sh[kUpWaves];
   const uint32_t lane = threadIdx.x & 63, wave = uniform_u32(threadIdx.x >> 6);
-  uint32_t* T = smem + wave * size_t(nw_max) * 4;
+  uint32_t* T = smem + wave * (size_t(nw_max) * 4 + kFixList);
   uint32_t* F = T + nw_max;
   uint32_t* A = F + nw_max;
   uint32_t* P = A + nw_max;
+  uint32_t* list = P + nw_max;
+  const uint32_t nb = ctr[kSpChildren] / 2;   // branching nodes of this step
   Team<1> tm{sh[wave]};
   for (uint32_t i = blockIdx.x * kUpWaves + wave; i < b; i += gridDim.x * kUpWaves) {
     const DevSplitOut so = sout[i];
     const uint32_t kind = uniform_u32(so.kind);
     const uint32_t* fx = fix_out + size_t(i) * 2 * nw_max;
     if (kind == kSplitBranch) {
-      const uint32_t s = first + child_off[i];
+      const uint32_t r = child_off[i] / 2;
+      const uint32_t s0 = first + r, s1 = first + nb + r;
       if (lane == 0) {
-        nodes[s] = DevSplitNode{so.qid, -so.lit, 0u, 0u};
-        nodes[s + 1] = DevSplitNode{so.qid, so.lit, 0u, 0u};
+        nodes[s0] = DevSplitNode{so.qid, -so.lit, 0u, 0u};
+        nodes[s1] = DevSplitNode{so.qid, so.lit, 0u, 0u};
       }
-      uint32_t* d0 = node_fix + size_t(s) * 2 * nw_max;
-      uint32_t* d1 = d0 + 2 * nw_max;
+      uint32_t* d0 = node_fix + size_t(s0) * 2 * nw_max;
+      uint32_t* d1 = node_fix + size_t(s1) * 2 * nw_max;
       const uint32_t nw = (qd[so.qid].n_vars >> 5) + 1;
       for (uint32_t w = lane; w < nw; w += 64) {
         const uint32_t t = fx[w], f = fx[nw_max + w];
@@ -1581,15 +1610,34 @@ __global__ __launch_bounds__(kBlock) void split_scatter_kernel(
       const DevQueryDesc q = qd[so.qid];
       const uint32_t nv = q.n_vars, nc = q.n_clauses, nw = (nv >> 5) + 1;
       const GlobalCnf cnf{coff + q.coff_base, lits + q.lit_base};
-      for (uint32_t w = lane; w < nw; w += 64) { T[w] = fx[w]; F[w] = fx[nw_max + w]; A[w] = 0; }
+      const bool wide = nc >= kSplitWideClauses;
+      // a wide query's slots are its unassigned variables
+      for (uint32_t w = lane; w < nw; w += 64) {
+        const uint32_t t = fx[w], f = fx[nw_max + w];
+        T[w] = t;
+        F[w] = f;
+        A[w] = wide ? ~(t | f) & var_mask(w, nv) : 0u;
+      }
       tm.sync();
-      const ActiveScan as = up_active<1>(tm, cnf, nc, T, F, A);
-      tm.sync();
-      uint32_t f_total, free_total, n_unsat;
-      up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
-      tm.sync();
-      const uint32_t pos = tm.scan(as.my_unsat, &n_unsat);
-      up_records(cnf, as, T, F, A, P, res, res_off[i], pos);
+      uint32_t f_total, free_total, n_unsat = 0;
+      if (wide) {
+        // the listing pass only when the leaf has unsatisfied clauses (its
+        // marks fall on variables that A already holds)
+        uint32_t n = 0, bad = 0;
+        if (so.nres) n = fix_scan<1>(cnf, nc, 0, T, F, A, list, kFixList, &bad);
+        tm.sync();
+        up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
+        tm.sync();
+        if (n) fix_records<1>(cnf, nc, 0, n, list, kFixList, T, F, A, P, res, res_off[i], 0);
+        n_unsat = n;
+      } else {
+        const ActiveScan as = up_active<1>(tm, cnf, nc, T, F, A);
+        tm.sync();
+        up_prefix<1>(tm, nv, T, F, A, P, &f_total, &free_total);
+        tm.sync();
+        const uint32_t pos = tm.scan(as.my_unsat, &n_unsat);
+        up_records(cnf, as, T, F, A, P, res, res_off[i], pos);
+      }
       uint32_t chunk;
       const uint32_t n_it = split_items_of(so.f, chunk_log2, &chunk);
       const uint32_t blocks = so.f >= 12 ? (1u << (so.f - 12)) : 1u;
@@ -1721,7 +1769,7 @@ SplitLayout split_layout(size_t base, size_t nq, size_t n_order, const SplitRun&
 size_t split_expand_lds(uint32_t nw_max) {
   return kUpWaves * (size_t(nw_max) * 4 + 2 * Team<1>::kQueue + 2 * Team<1>::kSize) * 4;
 }
-size_t split_scatter_lds(uint32_t nw_max) { return kUpWaves * size_t(nw_max) * 4 * 4; }
+size_t split_scatter_lds(uint32_t nw_max) { return kUpWaves * (size_t(nw_max) * 4 + kFixList) * 4; }
 
 }  // namespace
 
@@ -2222,6 +2270,9 @@ void dev_split(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
     if (order_off[q] + cnf.q[q].n_vars > order.size()) fail(SCUBA_E_INTERNAL, "branch order out of range");
     if (cnf.q[q].n_clauses > r.nres_max && r.max_res > r.nres_max)
       fail(SCUBA_E_INTERNAL, "residual bound below a query's clause count");
+    // the clause pass of wide queries takes 32-bit byte offsets
+    if (cnf.src->q[q].lits.size() >= (size_t(1) << 30) || cnf.q[q].n_clauses >= (uint32_t(1) << 30))
+      fail(SCUBA_E_CAPACITY, "a query of 2^30 or more clauses or literals for the device split");
   }
   if (r.k > kMaxLeafVars || r.chunk_log2 > 26) fail(SCUBA_E_INTERNAL, "split options out of range");
   const size_t e_lds = split_expand_lds(r.nw_max), s_lds = split_scatter_lds(r.nw_max);
@@ -2297,7 +2348,7 @@ void dev_split(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost&
            reinterpret_cast<const uint32_t*>(w + sl.res_off), reinterpret_cast<const uint32_t*>(w + sl.item_off),
            nodes, node_fix, descs, louts, reinterpret_cast<uint32_t*>(w + sl.leaf_src),
            reinterpret_cast<DevItem*>(w + sl.items), reinterpret_cast<uint4*>(w + sl.res), uint32_t(seq_base),
-           r.nw_max, r.chunk_log2);
+           r.nw_max, r.chunk_log2, (const uint32_t*)ctr);
     HIP_OK(hipGetLastError());
     if (r.leaf_variant == kLeafScalar)
       launch(leaf_kernel, dim3(g), dim3(kBlock), 0, st, ev[2], ev[3], reinterpret_cast<const DevItem*>(w + sl.items),

@@ -199,6 +199,11 @@ constexpr uint32_t kSplitBranch = 2;
 constexpr uint32_t kSplitRefuted = 3;
 // A leaf's blocks are cut into at most this many work items.
 constexpr uint32_t kSplitItemsPerLeaf = 64;
+// A query with this many clauses or more is split "wide": a node's slots are
+// its unassigned variables (no active-set scan per node), the branch is the
+// first unassigned variable of the order, and the batch is one node per
+// query (each query's walk goes depth-first).
+constexpr uint64_t kSplitWideClauses = 16384;
 // Per-query counters of the device split.
 struct DevSplitStat {
   unsigned long long cubes;    // leaves + refuted nodes

@@ -137,3 +137,55 @@ def test_budget_leaves_unknown(ctx):
     r = res.result(0)
     assert r["verdict"] == "UNKNOWN" and r["how"] == "budget", r
     assert r["cubes_total"] >= 50
+
+
+def _dense_planted(n, m, rng, name):
+    """m random clauses of 3..6 distinct variables over n variables, each
+    keeping a literal that a hidden assignment makes true: satisfiable,
+    with few models, and more clauses than the wide-split threshold."""
+    from workloads.cnf import CNF
+    hidden = rng.integers(0, 2, size=n + 1).astype(bool)
+    offs, lits = [0], []
+    for _ in range(m):
+        k = int(rng.integers(3, 7))
+        vs = rng.choice(n, size=k, replace=False) + 1
+        sg = rng.integers(0, 2, size=k).astype(bool)
+        if not any(hidden[v] == s for v, s in zip(vs, sg)):
+            j = int(rng.integers(0, k))
+            sg[j] = hidden[vs[j]]
+        lits.extend(int(v) if s else -int(v) for v, s in zip(vs, sg))
+        offs.append(len(lits))
+    return CNF(n, np.array(offs, np.uint64), np.array(lits, np.int32), name=name)
+
+
+@pytest.mark.parametrize("k", [6, 14])
+def test_wide_count_totals_match_oracle(ctx, k):
+    """Queries of 16,384 clauses or more split wide: a node's slots are its
+    unassigned variables, one node per query and step.  The leaves still
+    add up to the oracle's exact model count; one small query rides along in
+    the same batch."""
+    rng = np.random.Generator(np.random.PCG64(214 + k))
+    cnfs = [_dense_planted(26, 17000 + 1000 * i, rng, f"wide{i}") for i in range(3)]
+    cnfs += _formulas(215, ((22, 3.0),))
+    assert max(f.n_clauses for f in cnfs) >= 16384
+    _count_totals(ctx, cnfs, k)
+
+
+def test_wide_decide_access_batch(ctx):
+    """Full-width 2-D accesses (their CNFs reach 80,000 clauses): every
+    verdict is the label or UNKNOWN, every SAT witness passes the exact
+    integer query, and the host split agrees where both decide."""
+    gens = w.batch_2d(seed=35, n=192)
+    cnf = ctx.bitblast([g.query.arrays()[:2] for g in gens])
+    res = ctx.decide(cnf, k=30, device_split=True, scorer="word", max_cubes=20000)
+    host = ctx.decide(cnf, k=30, scorer="word", max_cubes=20000)
+    unknown = 0
+    for i, g in enumerate(gens):
+        r, h = res.result(i), host.result(i)
+        assert r["verdict"] in (g.label, "UNKNOWN"), (g.query.name, r)
+        assert "UNKNOWN" in (r["verdict"], h["verdict"]) or r["verdict"] == h["verdict"], (g.query.name, r, h)
+        unknown += r["verdict"] == "UNKNOWN"
+        if r["verdict"] == "SAT":
+            assert r["witness_checked"]
+            assert query_ref.int_eval(g.query, res.witness(i, g.query.n_vars)), g.query.name
+    assert unknown <= len(gens) // 16, unknown
