@@ -16,6 +16,7 @@
 //   [1].x   : positive literals of slots 12..37 (26 bits)
 //   [1].y   : all literals of slots 12..37 (positive or negative)
 //   [1].z   : the residual clause's length |c| (open literals)
+//   [1].w   : 2^20 + |c| + 1, the leaf kernel's packed counter increment
 //
 // Leaf kernel: assignment index a = 4096*block + 64*lane + bit.  Slot j < 6
 // is bit j of `bit` (a constant 64-bit pattern), slot 6..11 is bit j-6 of
@@ -54,6 +55,12 @@ namespace scuba {
 namespace {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 waves)
+// A record's packed counter: clauses in bits 20..31, |c| + 1 summed in bits
+// 0..19.  Within 4096 records neither field overflows (|c| <= 38).
+constexpr uint32_t kRecCount = 1u << 20;
+constexpr uint32_t kRecRun = 4096;
+// leaf_kernel: blocks evaluated together per pass over a leaf's records
+constexpr uint32_t kPass = 8;
 constexpr uint32_t kHighMask = (1u << 26) - 1;
 
 __device__ __forceinline__ uint64_t slot_pattern(uint32_t j) {
@@ -544,7 +551,9 @@ __device__ __forceinline__ void up_prefix(Team<TW>& tm, uint32_t nv, const uint3
 }
 
 // The residual record of unsatisfied clause c (slots from A and P) at
-// record index rec.
+// record index rec.  Its last word is the leaf kernel's counter increment
+// for one evaluated clause: kRecCount (one clause) plus |c| + 1 (its word
+// operations per 64-bit word).
 template <class Cnf>
 __device__ __forceinline__ void up_record(const Cnf& cnf, uint32_t c, const uint32_t* T, const uint32_t* F,
                                           const uint32_t* A, const uint32_t* P, uint4* __restrict__ res,
@@ -564,7 +573,7 @@ __device__ __forceinline__ void up_record(const Cnf& cnf, uint32_t c, const uint
     else (neg ? hn : hp) |= 1u << (slot - 12);
   }
   res[2 * rec] = make_uint4(uint32_t(low), uint32_t(low >> 32), uint32_t(lm), uint32_t(lm >> 32));
-  res[2 * rec + 1] = make_uint4(hp, hp | hn, len, 0u);
+  res[2 * rec + 1] = make_uint4(hp, hp | hn, len, kRecCount | (len + 1));
 }
 
 // The residual records of the lane's unsatisfied clauses, in clause order,
@@ -1092,61 +1101,105 @@ __global__ __launch_bounds__(kBlock) void leaf_kernel(const DevItem* __restrict_
       uint64_t count = 0, blocks = 0, evals = 0, word_ops = 0, first = ~0ull;
       uint32_t steps = 0;
       bool stop = false;
-      // two blocks per pass over the records (blk and blk + kWaves, the
-      // wave's next two): one set of record loads, two independent
+      // kPass blocks per pass over the records (blk, blk + kWaves, ..., the
+      // wave's next kPass): one set of record loads, kPass independent
       // dependency chains.  Each block keeps its own clause sequence and
       // dead-block test (after every group of four records), exactly as if
       // it were evaluated alone.
-      for (uint32_t blk = it.it_lo + wave; blk < it.it_hi && !stop; blk += 2 * kWaves) {
+      for (uint32_t blk = it.it_lo + wave; blk < it.it_hi && !stop; blk += kPass * kWaves) {
         if (mode == SCUBA_MODE_DECIDE && (steps++ & 3) == 0) {
           const uint64_t k = uniform_u64(
               __hip_atomic_load(&qkey[cd.qid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
           if (k <= key_base + (uint64_t(blk) << 12)) break;
         }
-        const uint32_t blk1 = blk + kWaves;
-        const bool two = blk1 < it.it_hi;
-        const uint32_t H0 = blk & kHighMask, H1 = blk1 & kHighMask;
-        uint64_t acc0 = valid, acc1 = two ? valid : 0ull;
-        bool live0 = true, live1 = two;
-        uint32_t done0 = 0, lits0 = 0, done1 = 0, lits1 = 0;
-        // four clauses per step: their records are loaded together (the
-        // record region is padded so that reading past nres stays inside
-        // it), clauses past nres are masked out
-        for (uint32_t c = 0; c < nres; c += 4) {
-          const uint4 r0 = rec[2 * c], r1 = rec[2 * c + 1], r2 = rec[2 * c + 2], r3 = rec[2 * c + 3];
-          const uint4 r4 = rec[2 * c + 4], r5 = rec[2 * c + 5], r6 = rec[2 * c + 6], r7 = rec[2 * c + 7];
-          const uint32_t left = nres - c;
-          // the four skip masks are needed first: keep their loads together
-          // (else each test waits for its own load)
-          asm volatile("" :: "s"(r1.x), "s"(r1.y), "s"(r3.x), "s"(r3.y), "s"(r5.x), "s"(r5.y), "s"(r7.x), "s"(r7.y));
-          if (live0) {
-            if (!(~(H0 ^ r1.x) & r1.y)) { acc0 = clause_and(acc0, r0); done0++; lits0 += r1.z; }
-            if (left > 1 && !(~(H0 ^ r3.x) & r3.y)) { acc0 = clause_and(acc0, r2); done0++; lits0 += r3.z; }
-            if (left > 2 && !(~(H0 ^ r5.x) & r5.y)) { acc0 = clause_and(acc0, r4); done0++; lits0 += r5.z; }
-            if (left > 3 && !(~(H0 ^ r7.x) & r7.y)) { acc0 = clause_and(acc0, r6); done0++; lits0 += r7.z; }
-          }
-          if (live1) {
-            if (!(~(H1 ^ r1.x) & r1.y)) { acc1 = clause_and(acc1, r0); done1++; lits1 += r1.z; }
-            if (left > 1 && !(~(H1 ^ r3.x) & r3.y)) { acc1 = clause_and(acc1, r2); done1++; lits1 += r3.z; }
-            if (left > 2 && !(~(H1 ^ r5.x) & r5.y)) { acc1 = clause_and(acc1, r4); done1++; lits1 += r5.z; }
-            if (left > 3 && !(~(H1 ^ r7.x) & r7.y)) { acc1 = clause_and(acc1, r6); done1++; lits1 += r7.z; }
-          }
-          live0 = live0 && __any(acc0 != 0);
-          live1 = live1 && __any(acc1 != 0);
-          if (!live0 && !live1) break;
+        uint32_t H[kPass], live[kPass], done[kPass], lits[kPass];
+        uint64_t acc[kPass];
+        uint32_t n_in = 0, any = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < kPass; p++) {
+          const uint32_t b = blk + p * kWaves;
+          const bool in = b < it.it_hi;
+          H[p] = b & kHighMask;
+          acc[p] = in ? valid : 0ull;
+          live[p] = in ? 1u : 0u;   // wave-uniform 0 / 1 (a plain scalar)
+          done[p] = lits[p] = 0;
+          n_in += in;
+          any |= live[p];
         }
-        blocks += two ? 2 : 1;
-        evals += done0 + done1;
-        word_ops += uint64_t(lits0 + done0 + lits1 + done1) * 64;   // (|c| + 1) per clause and 64-bit word
-        if (mode == SCUBA_MODE_COUNT) count += __popcll(acc0) + __popcll(acc1);
+        // runs of at most kRecRun records: an evaluated clause adds its
+        // record's packed counter (one scalar add), unpacked after each run
+        for (uint32_t c0 = 0; c0 < nres && any; c0 += kRecRun) {
+          const uint32_t cend = min(nres, c0 + kRecRun);
+          uint32_t pk[kPass];
+#pragma unroll
+          for (uint32_t p = 0; p < kPass; p++) pk[p] = 0;
+          // four clauses per step: their records are loaded together (the
+          // record region is padded so that reading past nres stays inside
+          // it); full groups first, then the last partial group
+          uint32_t c = c0;
+          for (; c + 4 <= cend; c += 4) {
+            const uint4 r0 = rec[2 * c], r1 = rec[2 * c + 1], r2 = rec[2 * c + 2], r3 = rec[2 * c + 3];
+            const uint4 r4 = rec[2 * c + 4], r5 = rec[2 * c + 5], r6 = rec[2 * c + 6], r7 = rec[2 * c + 7];
+            // the four skip masks are needed first; the length words are
+            // named too, so that each record pair stays one 32-byte load
+            asm volatile("" :: "s"(r1.x), "s"(r1.y), "s"(r3.x), "s"(r3.y), "s"(r5.x), "s"(r5.y), "s"(r7.x), "s"(r7.y));
+            asm volatile("" :: "s"(r1.z), "s"(r3.z), "s"(r5.z), "s"(r7.z));
+            any = 0;
+#pragma unroll
+            for (uint32_t p = 0; p < kPass; p++) {
+              if (live[p]) {
+                const uint32_t h = H[p];
+                if (!(~(h ^ r1.x) & r1.y)) { acc[p] = clause_and(acc[p], r0); pk[p] += r1.w; }
+                if (!(~(h ^ r3.x) & r3.y)) { acc[p] = clause_and(acc[p], r2); pk[p] += r3.w; }
+                if (!(~(h ^ r5.x) & r5.y)) { acc[p] = clause_and(acc[p], r4); pk[p] += r5.w; }
+                if (!(~(h ^ r7.x) & r7.y)) { acc[p] = clause_and(acc[p], r6); pk[p] += r7.w; }
+                live[p] = uint32_t(__any(acc[p] != 0));
+              }
+              any |= live[p];
+            }
+            if (!any) break;
+          }
+          if (c < cend && any) {
+            const uint4 r0 = rec[2 * c], r1 = rec[2 * c + 1], r2 = rec[2 * c + 2], r3 = rec[2 * c + 3];
+            const uint4 r4 = rec[2 * c + 4], r5 = rec[2 * c + 5];
+            const uint32_t left = cend - c;   // 1..3
+            any = 0;
+#pragma unroll
+            for (uint32_t p = 0; p < kPass; p++) {
+              if (live[p]) {
+                const uint32_t h = H[p];
+                if (!(~(h ^ r1.x) & r1.y)) { acc[p] = clause_and(acc[p], r0); pk[p] += r1.w; }
+                if (left > 1 && !(~(h ^ r3.x) & r3.y)) { acc[p] = clause_and(acc[p], r2); pk[p] += r3.w; }
+                if (left > 2 && !(~(h ^ r5.x) & r5.y)) { acc[p] = clause_and(acc[p], r4); pk[p] += r5.w; }
+                live[p] = uint32_t(__any(acc[p] != 0));
+              }
+              any |= live[p];
+            }
+          }
+#pragma unroll
+          for (uint32_t p = 0; p < kPass; p++) {
+            done[p] += pk[p] >> 20;
+            lits[p] += pk[p] & (kRecCount - 1);
+          }
+        }
+        blocks += n_in;
+#pragma unroll
+        for (uint32_t p = 0; p < kPass; p++) {
+          evals += done[p];
+          word_ops += uint64_t(lits[p]) * 64;   // (|c| + 1) per clause and 64-bit word
+          if (mode == SCUBA_MODE_COUNT) count += __popcll(acc[p]);
+        }
         // satisfying assignments, the earlier block first
-        for (uint32_t h = 0; h < (two ? 2u : 1u); h++) {
-          const uint64_t acc = h ? acc1 : acc0;
-          const uint64_t hit = __ballot(acc != 0);
+        for (uint32_t h = 0; h < n_in; h++) {
+          uint64_t a_acc = acc[0];
+#pragma unroll
+          for (uint32_t p = 1; p < kPass; p++)
+            if (h == p) a_acc = acc[p];
+          const uint64_t hit = __ballot(a_acc != 0);
           if (!hit) continue;
           const uint32_t fl = __builtin_ctzll(hit);
-          const uint64_t acc_fl = __shfl(acc, int(fl), 64);
-          const uint64_t a = (uint64_t(h ? blk1 : blk) << 12) | (uint64_t(fl) << 6) |
+          const uint64_t acc_fl = __shfl(a_acc, int(fl), 64);
+          const uint64_t a = (uint64_t(blk + h * kWaves) << 12) | (uint64_t(fl) << 6) |
                              uint64_t(__builtin_ctzll(acc_fl));
           if (lane == 0) {
             if (a < first) first = a;
