@@ -630,10 +630,10 @@ __device__ __forceinline__ void fix_mark(int32_t l, const uint32_t* T, const uin
   if (!((T[v >> 5] | F[v >> 5]) & bit)) atomicOr(&A[v >> 5], bit);
 }
 
-template <int TW>
+template <int TW, bool kTF = false>
 __device__ __forceinline__ uint32_t fix_scan(const GlobalCnf& cnf, uint32_t nc, uint32_t wv, const uint32_t* T,
                                              const uint32_t* F, uint32_t* A, uint32_t* list, uint32_t cap,
-                                             uint32_t* bad) {
+                                             uint32_t* bad, const uint2* TF = nullptr) {
   constexpr uint32_t G = 64 * kFixUnroll;   // clauses per group
   const uint32_t wl = threadIdx.x & 63;
   uint32_t c0, c1;
@@ -687,11 +687,35 @@ __device__ __forceinline__ uint32_t fix_scan(const GlobalCnf& cnf, uint32_t nc, 
     for (uint32_t u = 0; u < kFixUnroll; u++) {
       const uint32_t c = base + 64 * u + wl;
       const int32_t xs[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+      // branch-free over the four loaded literals: one past the clause's end
+      // reads variable 0 (never assigned) and is masked out; the bitmap
+      // words of all four are read before any is used (one 64-bit read
+      // each from the interleaved copy, when there is one)
+      uint32_t bit4[4], t4[4], f4[4];
+      bool ok4[4], pos4[4];
+#pragma unroll
+      for (uint32_t j = 0; j < 4; j++) {
+        ok4[j] = b[u] + j < e[u];
+        const int32_t l = ok4[j] ? xs[j] : 0;
+        const uint32_t v = uint32_t(l > 0 ? l : -l);
+        pos4[j] = l > 0;
+        bit4[j] = 1u << (v & 31);
+        if (kTF) {
+          const uint2 tf = TF[v >> 5];
+          t4[j] = tf.x;
+          f4[j] = tf.y;
+        } else {
+          t4[j] = T[v >> 5];
+          f4[j] = F[v >> 5];
+        }
+      }
       bool sat = false;
       uint32_t open = 0;
 #pragma unroll
-      for (uint32_t j = 0; j < 4; j++)
-        if (b[u] + j < e[u]) fix_lit(xs[j], T, F, &sat, &open);
+      for (uint32_t j = 0; j < 4; j++) {
+        sat |= ok4[j] && ((pos4[j] ? t4[j] : f4[j]) & bit4[j]) != 0;
+        open += (ok4[j] && !((t4[j] | f4[j]) & bit4[j])) ? 1u : 0u;
+      }
       for (uint32_t i = b[u] + 4; i < e[u]; i++) fix_lit(ld32(cnf.L, i), T, F, &sat, &open);
       const bool unsat = c < c1 && !sat;
       if (unsat) {
@@ -757,7 +781,7 @@ template <int TW>
 __device__ void fix_cube(Team<TW>& tm, const GlobalCnf& cnf, const DevCubeDesc& cd, uint32_t ci, uint32_t nv,
                          uint32_t nc, const int32_t* __restrict__ cube_lits, DevCubeOut* __restrict__ out,
                          uint4* __restrict__ res, uint32_t* T, uint32_t* F, uint32_t* A, uint32_t* P,
-                         uint32_t* lists) {
+                         uint2* TF, uint32_t* lists) {
   constexpr uint32_t S = Team<TW>::kSize;
   const uint32_t lane = tm.lane(), wv = TW == 1 ? 0u : uniform_u32(lane >> 6);
   const uint32_t nw = (nv >> 5) + 1;
@@ -767,13 +791,14 @@ __device__ void fix_cube(Team<TW>& tm, const GlobalCnf& cnf, const DevCubeDesc& 
     const uint32_t t = fw[w], f = fw[nw + w];
     T[w] = t;
     F[w] = f;
+    TF[w] = make_uint2(t, f);
     A[w] = 0;
     clash |= t & f;
   }
   tm.sync();
   uint32_t* list = lists + wv * kFixList;
   uint32_t bad;
-  const uint32_t n = fix_scan<TW>(cnf, nc, wv, T, F, A, list, kFixList, &bad);
+  const uint32_t n = fix_scan<TW, true>(cnf, nc, wv, T, F, A, list, kFixList, &bad, TF);
   bad |= __ballot(clash != 0) != 0;
   const bool lead = (threadIdx.x & 63) == 0;
   uint32_t n_bad, n_unsat;
@@ -990,7 +1015,8 @@ __attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : TW == 1 ? 5 : 4))) void fix_ker
                                                     const uint2* __restrict__ groups, uint32_t n_groups,
                                                     DevCubeOut* __restrict__ out, uint4* __restrict__ res,
                                                     uint32_t* head, uint32_t nw_max) {
-  // LDS per team: T, F, A, P of nw_max words, then kFixList per wave
+  // LDS per team: T, F, A, P of nw_max words, T and F interleaved (2 nw_max
+  // words), then kFixList per wave
   constexpr uint32_t kTeams = fix_threads<TW>() / 64 / TW;
   extern __shared__ uint32_t smem[];
   __shared__ UpShared sh[kTeams];
@@ -998,11 +1024,12 @@ __attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : TW == 1 ? 5 : 4))) void fix_ker
   // the group, the cube and its query are wave-uniform (scalar loads, and
   // CNF bases in scalar registers)
   const uint32_t tid = threadIdx.x, team = uniform_u32((tid >> 6) / TW);
-  uint32_t* T = smem + team * (size_t(nw_max) * 4 + TW * kFixList);
+  uint32_t* T = smem + team * (size_t(nw_max) * 6 + TW * kFixList);
   uint32_t* F = T + nw_max;
   uint32_t* A = F + nw_max;
   uint32_t* P = A + nw_max;
-  uint32_t* lists = P + nw_max;
+  uint2* TF = reinterpret_cast<uint2*>(P + nw_max);
+  uint32_t* lists = P + 3 * size_t(nw_max);
   for (;;) {
     if (tid == 0) s_group = atomicAdd(head, 1u);
     __syncthreads();
@@ -1015,7 +1042,7 @@ __attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : TW == 1 ? 5 : 4))) void fix_ker
       const DevQueryDesc q = qd[cubes[ci].qid];
       Team<TW> tm{sh[team]};
       fix_cube<TW>(tm, GlobalCnf{coff + q.coff_base, lits + q.lit_base}, cubes[ci], ci, q.n_vars, q.n_clauses,
-                   cube_lits, out, res, T, F, A, P, lists);
+                   cube_lits, out, res, T, F, A, P, TF, lists);
     }
   }
 }
@@ -2048,7 +2075,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
   const uint32_t tw = fix_only && max_clauses >= kFixWideClauses ? 16 : tw_up;
   const uint32_t teams = tw == 16 ? 1 : kUpWaves / tw;
   const uint32_t block = tw == 16 ? 1024 : kBlock;
-  const size_t team_bytes = fix_only ? (size_t(rh.nw_max) * 4 + size_t(tw) * kFixList) * 4
+  const size_t team_bytes = fix_only ? (size_t(rh.nw_max) * 6 + size_t(tw) * kFixList) * 4
                                      : size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 +
                                            2 * 64 * size_t(tw) * 4;
   const size_t up_lds = teams * team_bytes + (fix_only ? 0 : cnf.stage_bytes);
