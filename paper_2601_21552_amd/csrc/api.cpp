@@ -1240,11 +1240,22 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
                                     hip_stream});
     }
     if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
-    // the CNF upload does not depend on the split: it runs while the walks do
+    // the CNF upload does not depend on the split: it runs while the walks do.
+    // Every leaf goes to the device as its host fixpoint when the fixpoint
+    // fits a cube and the query fits the host-fixpoint kernel; then only
+    // that kernel runs and the occurrence lists stay on the host.
     bool uploaded = false;
+    h.no_occ = true;
+    for (size_t qi = 0; qi < nq; qi++)
+      if (open[qi]) {
+        const CnfQuery& q = cnf->q[qi];
+        if (q.n_vars < 2 || 2 * ((q.n_vars >> 5) + 1) > kMaxCubeLen || q.lits.size() >= (size_t(1) << 30) ||
+            q.n_clauses() >= (uint64_t(1) << 30))
+          h.no_occ = false;
+      }
     if (std::find(open.begin(), open.end(), 1) != open.end()) {
       void* cstg = ctx->cnf_staging(cnf_b);
-      dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, cstg, ctx->cnf_staging_size(), false);
+      dev_upload_cnf(ctx->dev, dev_ws, ws_bytes, h, hip_stream, cstg, ctx->cnf_staging_size(), false, !h.no_occ);
       uploaded = true;
     }
     RoundTimes rt;

@@ -1795,10 +1795,12 @@ CnfLayout cnf_layout(const CnfHost& c) {
   l.q = 0;
   l.coff = align256(l.q + c.q.size() * sizeof(DevQueryDesc));
   l.lits = align256(l.coff + c.n_coff * 4);
-  l.occ_off = align256(l.lits + c.n_lits * 4);
+  // the witness keys, then the occurrence lists last: an upload for
+  // host-fixpoint rounds only stops before them
+  l.qkey = align256(l.lits + c.n_lits * 4);
+  l.occ_off = align256(l.qkey + c.q.size() * 8);
   l.occ = align256(l.occ_off + c.n_occ_off * 4);
-  l.qkey = align256(l.occ + c.n_occ * 4);
-  l.end = align256(l.qkey + c.q.size() * 8);
+  l.end = align256(l.occ + c.n_occ * 4);
   return l;
 }
 struct RoundLayout {
@@ -1939,7 +1941,7 @@ size_t dev_round_bytes(size_t n_cubes, size_t n_cube_lits, size_t n_items, uint6
 }
 
 void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf, void* stream,
-                    void* staging, size_t staging_bytes, bool wait) {
+                    void* staging, size_t staging_bytes, bool wait, bool with_occ) {
   HIP_OK(hipSetDevice(info.device));
   CnfLayout l = cnf_layout(cnf);
   if (l.end > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
@@ -1959,6 +1961,7 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
     if (cnf.skip_root_unsat && q.root_unsat) return;   // an empty descriptor
     for (size_t c = 0; c < q.off.size(); c++) coff[d.coff_base + c] = uint32_t(q.off[c]);
     std::memcpy(lits + d.lit_base, q.lits.data(), q.lits.size() * 4);
+    if (!with_occ) return;
     uint32_t* oo = occ_off + d.occ_off_base;
     const size_t nli = 2 * (size_t(q.n_vars) + 1);
     uint32_t* oc = occ + d.occ_base;
@@ -1979,7 +1982,7 @@ void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cnf
   });
   std::memset(s + l.qkey, 0xFF, cnf.q.size() * 8);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_OK(hipMemcpyAsync(ws, s, l.end, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(ws, s, with_occ ? l.end : l.occ_off, hipMemcpyHostToDevice, st));
   if (wait) HIP_OK(hipStreamSynchronize(st));
 }
 
@@ -2067,6 +2070,8 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
                                  cnf.src->q[c.qid].n_clauses() >= (uint64_t(1) << 30)))
       fix_only = 0;
   }
+  if (nc && !fix_only && cnf.no_occ)
+    fail(SCUBA_E_INTERNAL, "a propagation round needs occurrence lists that were not uploaded");
   // a fix launch whose largest CNF has kFixWideClauses clauses or more
   // gives each cube sixteen waves (one 1024-thread workgroup)
   uint64_t max_clauses = 0;

@@ -113,6 +113,7 @@ struct CnfHost {
   size_t n_occ = 0;           // per query: the clauses of each literal
   size_t stage_bytes = 0;     // LDS for the largest staged CNF (16-bit form)
   bool skip_root_unsat = false;   // queries decided at the root are not uploaded
+  bool no_occ = false;            // uploaded without occurrence lists (host-fixpoint rounds only)
 };
 
 void dev_init(DeviceInfo* info, int device);
@@ -136,9 +137,11 @@ size_t dev_round_bytes(size_t n_cubes, size_t n_cube_lits, size_t n_items, uint6
 
 // Upload the CNF and reset the per-query witness keys (stream-ordered).
 // With wait false the copy may still run on return: the staging buffer must
-// stay untouched until the stream has passed it.
+// stay untouched until the stream has passed it.  Without with_occ the
+// occurrence lists are neither written nor copied: only rounds whose cubes
+// all carry host fixpoints (fix_kernel) may follow.
 void dev_upload_cnf(const DeviceInfo& info, void* ws, size_t ws_bytes, const CnfHost& cnf,
-                    void* stream, void* staging, size_t staging_bytes, bool wait);
+                    void* stream, void* staging, size_t staging_bytes, bool wait, bool with_occ = true);
 
 // Run one round: upload, unit propagation kernel, leaf kernel, download.
 // outs (n_cubes) and qkeys (nq) are filled; the stream is synchronised.
