@@ -636,7 +636,7 @@ def main():
     max_cubes = MAX_CUBES[args.workload]
 
     import workloads as w
-    names = [args.form] if (args.only_form and args.form != "auto") else ["static", "learned", "word"]
+    names = [args.form] if (args.only_form and args.form != "auto") else ["static", "word", "learned"]
     # the learned scorer, trained on traces of other seeds' access batches
     # (when a leg uses it)
     mlp_q, scorer_info = None, None
@@ -649,7 +649,8 @@ def main():
         log(f"access-query scorer trained: {scorer_info}")
 
     # per ordering: autotuned options (static / word; the learned form runs
-    # at the static ordering's point), timed steps, agreement with the labels
+    # at the word ordering's point, since on access queries it also walks
+    # input words by their top bits), timed steps, agreement with the labels
     cnf0 = ctx.bitblast_packed(*packed)
     forms, runs = {}, {}
     tuned = {}
@@ -659,11 +660,12 @@ def main():
             tuned[name], rep = ctx.autotune(cnf0, sample=128, reps=1, scorer=name, graph=True,
                                             max_cubes=max_cubes)
         else:
-            if "static" not in tuned:
-                tuned["static"], rep = ctx.autotune(cnf0, sample=128, reps=1, graph=True, max_cubes=max_cubes)
+            if "word" not in tuned:
+                tuned["word"], rep = ctx.autotune(cnf0, sample=128, reps=1, scorer="word", graph=True,
+                                                  max_cubes=max_cubes)
             rep = {"points": 0}
         tune_s = time.perf_counter() - t0
-        opts = dict(tuned["static" if name == "learned" else name], max_cubes=max_cubes)
+        opts = dict(tuned["word" if name == "learned" else name], max_cubes=max_cubes)
         if name == "learned":
             opts.pop("scorer", None)
             opts["learned"] = mlp_q.scorer(LEARNED_CANDIDATES, LEARNED_RESCORE_ACCESS)

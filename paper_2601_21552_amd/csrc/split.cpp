@@ -75,6 +75,7 @@ void Splitter::set_word_order() {
 
 void Splitter::set_learned(uint32_t candidates, uint32_t rescore) {
   learned_ = true;
+  words_first_ = true;
   n_cands_ = std::max<uint32_t>(candidates, 1);
   rescore_ = std::max<uint32_t>(rescore, 1);
 }
@@ -86,27 +87,35 @@ void Splitter::set_trace(uint32_t candidates, uint32_t every, uint32_t depth) {
   trace_depth_ = depth;
 }
 
-// The first m active variables of the static order.
+// The first m active variables of the static order and the input words'
+// top bits; with words_first_, the words alone while one of them is open.
 std::vector<int32_t> Splitter::candidates(uint32_t m, std::set<int32_t>* words) const {
   std::vector<int32_t> c;
+  // the most significant active bit of each input word (these stand for
+  // their words, see choose_learned); with words_first_ and an input bit
+  // active, the words are the only candidates
+  auto word_tops = [&](size_t n_static) {
+    if (words) words->clear();
+    for (size_t i = 0; i < q_.in_first.size(); i++)
+      for (uint32_t b = q_.in_width[i]; b-- > 0;) {
+        const int32_t v = int32_t(q_.in_first[i] + b);
+        if (assign_[v] >= 0 || act_cnt_[v] == 0) continue;
+        if (std::find(c.begin(), c.begin() + n_static, v) == c.begin() + n_static) {
+          c.push_back(v);
+          if (words) words->insert(v);
+        }
+        break;
+      }
+  };
+  if (words_first_) {
+    word_tops(0);
+    if (!c.empty()) return c;
+  }
   for (int32_t v : order_) {
     if (c.size() >= m) break;
     if (assign_[v] < 0 && act_cnt_[v] > 0) c.push_back(v);
   }
-  // and the most significant active bit of each input word (these stand
-  // for their words, see choose_learned)
-  const size_t n_static = c.size();
-  if (words) words->clear();
-  for (size_t i = 0; i < q_.in_first.size(); i++)
-    for (uint32_t b = q_.in_width[i]; b-- > 0;) {
-      const int32_t v = int32_t(q_.in_first[i] + b);
-      if (assign_[v] >= 0 || act_cnt_[v] == 0) continue;
-      if (std::find(c.begin(), c.begin() + n_static, v) == c.begin() + n_static) {
-        c.push_back(v);
-        if (words) words->insert(v);
-      }
-      break;
-    }
+  word_tops(c.size());
   return c;
 }
 

@@ -52,11 +52,13 @@ class Splitter {
   Splitter(const CnfQuery& q, uint32_t k, uint32_t max_residual, uint64_t max_cubes);
 
   // Learned ordering: at a decision node the walk stops with kNeedScore and
-  // asks for scores of the top `candidates` active variables of the static
-  // order and of the most significant active bit of each input word; the
-  // ranking by score then orders the decisions of that node and of its
-  // descendants up to `rescore` levels below.  Non-finite scores fall back
-  // to the static order.
+  // asks for scores of its candidates: while an input word has an active
+  // bit, the most significant active bit of each input word (each stands
+  // for its word, so a decision halves one input's range); after that, the
+  // top `candidates` active variables of the static order.  The ranking by
+  // score then orders the decisions of that node and of its descendants up
+  // to `rescore` levels below.  Non-finite scores fall back to the static
+  // order.
   void set_learned(uint32_t candidates, uint32_t rescore);
   // Word ordering: among active input bits the most significant first (ties
   // to the lowest variable), which halves an input's value range per
@@ -143,6 +145,7 @@ class Splitter {
   std::vector<int32_t> order_;      // static branching order
   std::vector<int32_t> word_order_; // input bits by significance (word ordering)
   bool word_ = false;
+  bool words_first_ = false;   // learned: input words only while one is open
   bool keep_leaf_state_ = false;
   // search state
   std::vector<int8_t> assign_;
