@@ -67,7 +67,7 @@ LEAF_VARIANTS = {"scalar": {}, "vector": {"leaf": "vector"}, "lds": {"leaf": "ld
 # below a scored node that reuse its ranking
 LEARNED_CANDIDATES = 16
 LEARNED_RESCORE = 4
-LEARNED_RESCORE_ACCESS = 32
+LEARNED_RESCORE_ACCESS = 128
 
 WORKLOADS = {
     "batch_2d": ("4096 seeded 2-D OOB queries of uneven width: inputs 8-24 bits, 1-3 multipliers per "
