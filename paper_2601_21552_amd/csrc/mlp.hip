@@ -153,20 +153,60 @@ __global__ __launch_bounds__(512) void mlp_bwd_dz_kernel(const uint16_t* __restr
   }
 }
 
-// Weight gradients, one wave per 16x16 tile, the batch reduced inside the
-// wave in a fixed order: tiles 0..63 -> dW2 = A1^T dZ2, tiles 64..71 ->
-// dW1 = X^T dZ1.  Extra waves: bias and w3 gradients.
-__global__ __launch_bounds__(64) void mlp_bwd_dw_kernel(const uint16_t* __restrict__ X,
-                                                       const uint16_t* __restrict__ A1,
-                                                       const uint16_t* __restrict__ A2,
-                                                       const float* __restrict__ y,
-                                                       const float* __restrict__ target, uint32_t B,
-                                                       const uint16_t* __restrict__ dZ1,
-                                                       const uint16_t* __restrict__ dZ2,
-                                                       float* __restrict__ grad) {
-  const uint32_t lane = threadIdx.x, tile = blockIdx.x;
-  const uint32_t li = lane % 16, lk = 4 * (lane / 16);
+// Weight and bias gradients, one 512-thread workgroup per output block.
+// Workgroups 0..63: 16x16 tiles of dW2 = A1^T dZ2; 64..71: tiles of
+// dW1 = X^T dZ1.  Wave w of a tile reduces the batch rows 16(w + 8i) .. +15
+// on the matrix cores; the eight waves' tiles are then added in wave order.
+// Workgroups 72..75: b1 = sum_r dZ1[r], b2 = sum_r dZ2[r],
+// w3 = sum_r A2[r] dy[r], b3 = sum_r dy[r]; thread t takes column t % H and
+// the rows of slice t / H, and the slices' sums are added in slice order.
+// Every sum is taken in an order fixed by B alone.
+constexpr uint32_t kDwWaves = 8;
+constexpr uint32_t kBiasSlices = 4;
+
+// Sum over rows [r0, r1) of column h of one bias or w3 gradient term, in
+// eight interleaved partial sums (eight loads in flight) added pairwise.
+// W selects the term, so the loop body has no branch between a load and
+// its use.
+template <int W>
+__device__ __forceinline__ float bias_rows(const uint16_t* __restrict__ M, const float* __restrict__ y,
+                                           const float* __restrict__ target, uint32_t B, uint32_t h,
+                                           uint32_t r0, uint32_t r1) {
+  auto term = [&](uint32_t r) -> float {
+    if constexpr (W < 2) return bf2f(M[size_t(r) * H + h]);
+    const float dy = 2.f * (y[r] - target[r]) / float(B);
+    if constexpr (W == 2) return bf2f(M[size_t(r) * H + h]) * dy;
+    return dy;
+  };
+  float s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
+  uint32_t r = r0;
+  for (; r + 8 <= r1; r += 8) {
+    s0 += term(r);
+    s1 += term(r + 1);
+    s2 += term(r + 2);
+    s3 += term(r + 3);
+    s4 += term(r + 4);
+    s5 += term(r + 5);
+    s6 += term(r + 6);
+    s7 += term(r + 7);
+  }
+  for (; r < r1; r++) s0 += term(r);
+  return ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
+}
+__global__ __launch_bounds__(512) void mlp_bwd_dw_kernel(const uint16_t* __restrict__ X,
+                                                        const uint16_t* __restrict__ A1,
+                                                        const uint16_t* __restrict__ A2,
+                                                        const float* __restrict__ y,
+                                                        const float* __restrict__ target, uint32_t B,
+                                                        const uint16_t* __restrict__ dZ1,
+                                                        const uint16_t* __restrict__ dZ2,
+                                                        float* __restrict__ grad) {
+  static_assert(kDwWaves * 64 == 512 && kBiasSlices * H == 512, "one 512-thread workgroup");
+  __shared__ float part[kDwWaves * 64 * 4];
+  const uint32_t tile = blockIdx.x;
   if (tile < 72) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t li = lane % 16, lk = 4 * (lane / 16);
     const bool w2 = tile < 64;
     const uint32_t ti = w2 ? tile / 8 : 0, tj = w2 ? tile % 8 : tile - 64;
     const uint16_t* L = w2 ? A1 : X;      // left operand, row-major [B x (H or F)]
@@ -174,33 +214,51 @@ __global__ __launch_bounds__(64) void mlp_bwd_dw_kernel(const uint16_t* __restri
     const uint16_t* R = w2 ? dZ2 : dZ1;   // right operand [B x H]
     f32x4 c = {0, 0, 0, 0};
     bf16x4 a, b;
-    for (uint32_t k0 = 0; k0 < B; k0 += 16) {
+    uint32_t k0 = 16 * wave;
+#pragma unroll 2
+    for (; k0 + 16 <= B; k0 += 16 * kDwWaves) {   // full 16-row chunks
       for (int e = 0; e < 4; e++) {
         const uint32_t k = k0 + lk + e;   // batch index
-        a[e] = k < B ? short(L[size_t(k) * ld + ti * 16 + li]) : short(0);   // (L^T)[i][k]
+        a[e] = short(L[size_t(k) * ld + ti * 16 + li]);   // (L^T)[i][k]
+        b[e] = short(R[size_t(k) * H + tj * 16 + li]);
+      }
+      c = mma(a, b, c);
+    }
+    if (k0 < B) {   // the ragged last chunk, at most one per wave
+      for (int e = 0; e < 4; e++) {
+        const uint32_t k = k0 + lk + e;
+        a[e] = k < B ? short(L[size_t(k) * ld + ti * 16 + li]) : short(0);
         b[e] = k < B ? short(R[size_t(k) * H + tj * 16 + li]) : short(0);
       }
       c = mma(a, b, c);
     }
-    for (int e = 0; e < 4; e++) {
-      const uint32_t i = ti * 16 + lk + e, j = tj * 16 + li;
-      grad[(w2 ? kOffW2 : kOffW1) + i * H + j] = c[e];
+    for (int e = 0; e < 4; e++) part[(wave * 64 + lane) * 4 + e] = c[e];
+    __syncthreads();
+    if (wave == 0) {
+      for (int e = 0; e < 4; e++) {
+        float sum = 0.f;
+        for (uint32_t w = 0; w < kDwWaves; w++) sum += part[(w * 64 + lane) * 4 + e];
+        const uint32_t i = ti * 16 + lk + e, j = tj * 16 + li;
+        grad[(w2 ? kOffW2 : kOffW1) + i * H + j] = sum;
+      }
     }
     return;
   }
-  // tile 72: b1, 73: b2, 74: w3, 75: b3 (64 lanes x 2 columns each)
-  const uint32_t which = tile - 72;
-  for (uint32_t h = lane; h < uint32_t(which == 3 ? 1 : H); h += 64) {
-    float acc = 0.f;
-    for (uint32_t r = 0; r < B; r++) {
-      const float dy = 2.f * (y[r] - target[r]) / float(B);
-      if (which == 0) acc += bf2f(dZ1[size_t(r) * H + h]);
-      else if (which == 1) acc += bf2f(dZ2[size_t(r) * H + h]);
-      else if (which == 2) acc += bf2f(A2[size_t(r) * H + h]) * dy;
-      else acc += dy;
-    }
+  const uint32_t which = tile - 72, h = threadIdx.x % H, slice = threadIdx.x / H;
+  const uint32_t per = (B + kBiasSlices - 1) / kBiasSlices;
+  const uint32_t r0 = min(B, slice * per), r1 = min(B, r0 + per);
+  float v;
+  if (which == 0) v = bias_rows<0>(dZ1, y, target, B, h, r0, r1);
+  else if (which == 1) v = bias_rows<1>(dZ2, y, target, B, h, r0, r1);
+  else if (which == 2) v = bias_rows<2>(A2, y, target, B, h, r0, r1);
+  else v = bias_rows<3>(A2, y, target, B, h, r0, r1);
+  part[slice * H + h] = v;
+  __syncthreads();
+  if (slice == 0 && (which != 3 || h == 0)) {
+    float sum = 0.f;
+    for (uint32_t k = 0; k < kBiasSlices; k++) sum += part[k * H + h];
     const uint32_t off = which == 0 ? kOffB1 : which == 1 ? kOffB2 : which == 2 ? kOffW3 : kOffB3;
-    grad[off + h] = acc;
+    grad[off + h] = sum;
   }
 }
 
@@ -250,7 +308,7 @@ void mlp_backward(const uint16_t* wb, const uint16_t* X, const uint16_t* A1, con
   hipLaunchKernelGGL(mlp_bwd_dz_kernel, dim3((B + 15) / 16), dim3(512), 0, st, A1, A2, y, target, B, wb, dZ1,
                      dZ2);
   HIP_OK(hipGetLastError());
-  hipLaunchKernelGGL(mlp_bwd_dw_kernel, dim3(76), dim3(64), 0, st, X, A1, A2, y, target, B, dZ1, dZ2, grad);
+  hipLaunchKernelGGL(mlp_bwd_dw_kernel, dim3(76), dim3(512), 0, st, X, A1, A2, y, target, B, dZ1, dZ2, grad);
   HIP_OK(hipGetLastError());
 }
 

@@ -36,7 +36,7 @@ def _case(seed, B):
     return p, X, t
 
 
-@pytest.mark.parametrize("B", [1, 16, 37, 100, 513])
+@pytest.mark.parametrize("B", [1, 16, 37, 100, 513, 1024])
 def test_forward_and_backward_match_reference(env, B):
     torch, api, ctx = env
     p, X, t = _case(40 + B, B)
