@@ -645,6 +645,9 @@ Splitter::State Splitter::next(uint32_t max_leaves, std::vector<Cube>& out, bool
               awaiting_ = true;
               return kNeedScore;
             }
+            // one candidate needs no scores: with input words first, it is
+            // the top active bit of the one open word
+            if (req_vars_.size() == 1) v = req_vars_[0];
           }
         }
         if (!v) v = word_ ? choose_word() : choose_static();
