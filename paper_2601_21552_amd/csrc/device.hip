@@ -595,12 +595,16 @@ __device__ __forceinline__ void up_records(const Cnf& cnf, const ActiveScan& as,
 // variables in A and lists the unsatisfied clauses.  Wave wv of the team
 // takes the clauses [c0, c1) of fix_range, 64 at a time with lane j on
 // clause base + j, so consecutive lanes read consecutive clause offsets and
-// literals, kFixUnroll chunks at a time (the first four literals of a
+// literals, fix_unroll chunks at a time (the first four literals of a
 // clause with the chunk, longer clauses' rest when evaluated).  The wave's unsatisfied clauses go to list[]
 // in clause order (ballot ranks), the first cap of them.  Returns the
 // wave's count of unsatisfied clauses; *bad is set (wave-uniform) when a
 // clause is unit or empty, so the assignment is not a fixpoint.
-constexpr uint32_t kFixUnroll = 3;
+// Chunks per group: two for the eight-wave teams, whose registers then
+// fit three workgroups per CU (more teams in flight per CU beat deeper
+// pipelines per wave there), three for the others.
+template <int TW>
+constexpr uint32_t fix_unroll() { return TW == 8 ? 2 : 3; }
 constexpr uint32_t kFixList = 512;   // listed unsatisfied clauses per wave
 constexpr uint64_t kFixWideClauses = 16384;
 
@@ -634,6 +638,7 @@ template <int TW, bool kTF = false>
 __device__ __forceinline__ uint32_t fix_scan(const GlobalCnf& cnf, uint32_t nc, uint32_t wv, const uint32_t* T,
                                              const uint32_t* F, uint32_t* A, uint32_t* list, uint32_t cap,
                                              uint32_t* bad, const uint2* TF = nullptr) {
+  constexpr uint32_t kFixUnroll = fix_unroll<TW>();
   constexpr uint32_t G = 64 * kFixUnroll;   // clauses per group
   const uint32_t wl = threadIdx.x & 63;
   uint32_t c0, c1;
@@ -999,15 +1004,16 @@ __global__ __launch_bounds__(kBlock) void up_kernel(const DevQueryDesc* __restri
 // one-wave teams, else one cube), as up_kernel does, and each team checks
 // one cube with fix_cube.  Nothing is staged: the one pass reads the CNF
 // from HBM, and the launch asks only for the teams' bitmaps and lists, so
-// more workgroups share a CU than with staging.  TW = 16 (workgroups of
-// 1024 threads) is for rounds with large CNFs: a cube's pass is a chain of
-// dependent loads per wave, so sixteen waves finish a large cube four
-// times sooner than four.
+// more workgroups share a CU than with staging.  TW = 8 (workgroups of
+// 512 threads, one cube each, three per CU) is for rounds with large CNFs:
+// eight waves finish a large cube about twice as soon as four, and while
+// one workgroup of a CU waits on the loads that start its next cube (the
+// group claim, the descriptors, the fixpoint), the others stream clauses.
 template <int TW>
-constexpr int fix_threads() { return TW == 16 ? 1024 : kBlock; }
+constexpr int fix_threads() { return TW == 8 ? 512 : kBlock; }
 template <int TW>
 __global__ __launch_bounds__(fix_threads<TW>())
-__attribute__((amdgpu_waves_per_eu(TW == 4 ? 6 : TW == 1 ? 5 : 4))) void fix_kernel(const DevQueryDesc* __restrict__ qd,
+__attribute__((amdgpu_waves_per_eu(TW == 1 ? 5 : 6))) void fix_kernel(const DevQueryDesc* __restrict__ qd,
                                                     const uint32_t* __restrict__ coff,
                                                     const int32_t* __restrict__ lits,
                                                     const DevCubeDesc* __restrict__ cubes,
@@ -1898,7 +1904,7 @@ void dev_init(DeviceInfo* info, int device) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<4>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<16>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&fix_kernel<8>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&split_expand_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, int(want)) == hipSuccess &&
@@ -2073,13 +2079,13 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
   if (nc && !fix_only && cnf.no_occ)
     fail(SCUBA_E_INTERNAL, "a propagation round needs occurrence lists that were not uploaded");
   // a fix launch whose largest CNF has kFixWideClauses clauses or more
-  // gives each cube sixteen waves (one 1024-thread workgroup)
+  // gives each cube eight waves (one 512-thread workgroup)
   uint64_t max_clauses = 0;
   for (const DevCubeDesc& c : rh.cubes)
     if (c.qid < cnf.q.size()) max_clauses = std::max<uint64_t>(max_clauses, cnf.q[c.qid].n_clauses);
-  const uint32_t tw = fix_only && max_clauses >= kFixWideClauses ? 16 : tw_up;
-  const uint32_t teams = tw == 16 ? 1 : kUpWaves / tw;
-  const uint32_t block = tw == 16 ? 1024 : kBlock;
+  const uint32_t tw = fix_only && max_clauses >= kFixWideClauses ? 8 : tw_up;
+  const uint32_t teams = tw >= 8 ? 1 : kUpWaves / tw;
+  const uint32_t block = tw >= 8 ? 64 * tw : kBlock;
   const size_t team_bytes = fix_only ? (size_t(rh.nw_max) * 6 + size_t(tw) * kFixList) * 4
                                      : size_t(rh.nw_max) * 4 * 4 + 2 * size_t(kUpQueue) * tw * 4 +
                                            2 * 64 * size_t(tw) * 4;
@@ -2163,7 +2169,7 @@ void dev_round_begin(const DeviceInfo& info, void* ws, size_t ws_bytes, const Cn
       HIP_OK(hipMemcpyAsync(w + rl.head, s, up_bytes, hipMemcpyHostToDevice, q));
     }
     if (gu && fix_only) {
-      launch(tw == 16 ? fix_kernel<16> : tw == 4 ? fix_kernel<4> : fix_kernel<1>, dim3(gu), dim3(block), up_lds,
+      launch(tw == 8 ? fix_kernel<8> : tw == 4 ? fix_kernel<4> : fix_kernel<1>, dim3(gu), dim3(block), up_lds,
              q, ev ? ev[2] : nullptr,
              ev ? ev[3] : nullptr, reinterpret_cast<const DevQueryDesc*>(w + cl.q),
              reinterpret_cast<const uint32_t*>(w + cl.coff), reinterpret_cast<const int32_t*>(w + cl.lits),

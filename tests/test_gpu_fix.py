@@ -10,7 +10,7 @@ records.  These formulas keep most clauses open at their leaves, so:
   records come from the second pass over its clauses;
 * clauses of up to ten literals take the path past the four literals that
   are loaded with the clause;
-* CNFs from 4,000 to 24,000 clauses run with four-wave and sixteen-wave
+* CNFs from 4,000 to 24,000 clauses run with four-wave and eight-wave
   teams.
 
 Verdicts equal the oracle's DPLL verdicts, and every SAT model satisfies
