@@ -69,3 +69,29 @@ def test_dense_leaves_match_oracle(ctx, m):
         if want == "SAT":
             assert r["witness_checked"]
             assert cnf_ref.check_model(f, res.model(qi, f.n_vars)), f.name
+
+
+def test_small_cnfs_in_a_wide_launch(ctx):
+    """One CNF of 20,000 clauses makes the launch give every cube an
+    eight-wave team; the other CNFs have 1 to 70 clauses, so most of their
+    team's waves get empty clause ranges and the rest end inside a 64-clause
+    chunk.  Verdicts equal the oracle's."""
+    rng = np.random.Generator(np.random.PCG64(4242))
+    cnfs = [_dense(18, 20000, rng, True, "wide")]
+    for m in (1, 2, 3, 17, 63, 64, 65, 70):
+        cnfs.append(_dense(12, m, rng, m % 2 == 1, f"small{m}"))
+    # every sign pattern of two variables (UNSAT with no unit clause: the
+    # whole formula is one leaf), and a clashing pair of units
+    cnfs.append(CNF(2, np.array([0, 2, 4, 6, 8], np.uint64),
+                    np.array([1, 2, 1, -2, -1, 2, -1, -2], np.int32), name="all4"))
+    cnfs.append(CNF(1, np.array([0, 1, 2], np.uint64), np.array([1, -1], np.int32), name="clash"))
+    raw = ctx.cnf_from_arrays(*w.concat(cnfs))
+    res = ctx.decide(raw, k=14, max_residual=8192, max_cubes=1 << 16)
+    assert res.timing()["fix_launches"] >= 1
+    for qi, f in enumerate(cnfs):
+        want = cnf_ref.solve(f)[0]
+        r = res.result(qi)
+        assert r["verdict"] == want, (f.name, r, want)
+        if want == "SAT":
+            assert r["witness_checked"]
+            assert cnf_ref.check_model(f, res.model(qi, f.n_vars)), f.name
