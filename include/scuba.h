@@ -348,7 +348,11 @@ scuba_status scuba_solve(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_cubes
 /* The whole path for a batch: split lazily (leaves_per_round per query per
  * round, DFS order), evaluate each round's leaves on the device, drop the
  * queries that are decided, repeat until every query is decided, its tree
- * is exhausted, or its budget is spent.                                    */
+ * is exhausted, or its budget is spent.  With a learned scorer the scoring
+ * passes run on a library-owned stream ordered after the caller's stream
+ * (so after its earlier work, such as scuba_mlp_sync of the weights), and
+ * do not wait for the CNF upload that this call queues on the caller's
+ * stream.                                                                  */
 scuba_status scuba_decide(scuba_ctx* ctx, const scuba_cnf* cnf, const scuba_solve_opts* opts,
                           void* dev_ws, size_t ws_bytes, void* hip_stream, scuba_results** out);
 

@@ -1236,8 +1236,11 @@ std::unique_ptr<scuba_results> decide_impl(scuba_ctx* ctx, const scuba_cnf* cnf,
       if (sb + 256 + cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the scorer");
       uintptr_t base = (reinterpret_cast<uintptr_t>(dev_ws) + ws_bytes - sb) & ~uintptr_t(255);
       ws_bytes = base - reinterpret_cast<uintptr_t>(dev_ws);
+      // the passes run on the library's scoring stream, ordered after the
+      // caller's stream as it stands now: they do not queue behind the CNF
+      // upload enqueued next, which the walks overlap
       runner.reset(new ScorerRunner{ctx, o.learned, reinterpret_cast<char*>(base), rows,
-                                    hip_stream});
+                                    dev_score_stream(ctx->dev.device, hip_stream)});
     }
     if (cnf_b > ws_bytes) fail(SCUBA_E_CAPACITY, "workspace too small for the CNF batch");
     // the CNF upload does not depend on the split: it runs while the walks do.

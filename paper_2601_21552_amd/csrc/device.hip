@@ -1861,6 +1861,8 @@ size_t split_scatter_lds(uint32_t nw_max) { return kUpWaves * (size_t(nw_max) * 
 
 }  // namespace
 
+void score_stream_init(int device);
+
 void dev_init(DeviceInfo* info, int device) {
   int n = 0;
   HIP_OK(hipGetDeviceCount(&n));
@@ -1870,6 +1872,7 @@ void dev_init(DeviceInfo* info, int device) {
   HIP_OK(hipGetDeviceProperties(&p, device));
   info->device = device;
   info->cus = p.multiProcessorCount;
+  score_stream_init(device);
   std::snprintf(info->arch, sizeof(info->arch), "%s", p.gcnArchName);
   {
     // the scratch array's address on this device, looked up once per
@@ -2028,6 +2031,35 @@ hipStream_t copy_stream(int device) {
   HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   streams.emplace(device, cs);
   return cs;
+}
+
+// The learned scorer's stream and ordering event per device, created by
+// dev_init (library set-up), so that taking the stream allocates nothing.
+std::mutex score_mu;
+std::map<int, std::pair<hipStream_t, hipEvent_t>> score_streams;
+
+void score_stream_init(int device) {
+  std::lock_guard<std::mutex> g(score_mu);
+  if (score_streams.count(device)) return;
+  hipStream_t ss;
+  hipEvent_t ev;
+  HIP_OK(hipStreamCreateWithFlags(&ss, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  score_streams.emplace(device, std::make_pair(ss, ev));
+}
+
+// The scoring stream, ordered after the work that `after` (the caller's
+// stream) holds so far.  The scoring passes then wait for the caller's
+// earlier work (the weights' sync) but not for what the call enqueues on
+// `after` later: the CNF upload.
+void* dev_score_stream(int device, void* after) {
+  std::lock_guard<std::mutex> g(score_mu);
+  auto it = score_streams.find(device);
+  if (it == score_streams.end()) fail(SCUBA_E_INTERNAL, "scoring stream used before device set-up");
+  HIP_OK(hipSetDevice(device));
+  HIP_OK(hipEventRecord(it->second.second, static_cast<hipStream_t>(after)));
+  HIP_OK(hipStreamWaitEvent(it->second.first, it->second.second, 0));
+  return it->second.first;
 }
 
 // A kernel launch; with events, the events bracket the dispatch itself (so

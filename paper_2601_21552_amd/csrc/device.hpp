@@ -120,6 +120,7 @@ void dev_init(DeviceInfo* info, int device);
 void dev_copy_h2d(void* dst, const void* src, size_t bytes, void* stream);
 void dev_copy_d2h(void* dst, const void* src, size_t bytes, void* stream);
 void dev_sync(void* stream);
+void* dev_score_stream(int device, void* after);
 void* dev_pinned(size_t bytes);          // pinned host memory (or throws)
 void dev_pinned_free(void* p);
 
