@@ -193,6 +193,7 @@ __device__ __forceinline__ float bias_rows(const uint16_t* __restrict__ M, const
   for (; r < r1; r++) s0 += term(r);
   return ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7));
 }
+
 __global__ __launch_bounds__(512) void mlp_bwd_dw_kernel(const uint16_t* __restrict__ X,
                                                         const uint16_t* __restrict__ A1,
                                                         const uint16_t* __restrict__ A2,
